@@ -1,0 +1,187 @@
+/*
+ * rcr.h — C-ABI of the rake-compress tree-LQR solver for AMD MI355X (gfx950).
+ *
+ * The solver computes the unique saddle point of the branched
+ * dual-regularised LQR problem of Sec. II-A (Lagrangian eq. (lagrangian),
+ * saddle problem eq. (saddle); unique by Prop. 1) on a rooted tree, and the
+ * Riccati data of its factorisation: it returns the KKT solution (x, u, y)
+ * of eq. (kkt), the subtree Hessians P_i (Thm. 1) and the feedback gains
+ * K_e (eq. (factor-local)).  It follows Algorithm 1 (Sec. VI): a reusable
+ * topology plan (Sec. VII), local control condensation (eq. (edge-components)),
+ * rake/compress contraction and reverse expansion of the conditional
+ * quadratics (Sec. IV), local factors (eqs. (FW), (factor-local)), then the
+ * affine solve and state recovery (Sec. V).
+ *
+ * Conventions (all calls):
+ *  - Nodes are 0..N-1 in the caller's order; parent[root] = -1, exactly one
+ *    root.  The edge e = (parent[j], j) lives in "edge slot j"; the root's
+ *    edge slot is ignored on input and written as zero on output.
+ *  - Problem and solution arrays are DEVICE pointers to float64, row-major,
+ *    one contiguous block per node or edge slot:
+ *      per node    Q[N][n][n]  q[N][n]  c[N][n]  Delta[N][n][n]
+ *      per edge    R[N][m][m]  S[N][n][m]  r[N][m]  A[N][n][n]  B[N][n][m]
+ *      outputs     K[N][m][n] (edge)  P[N][n][n]  x[N][n]  u[N][m] (edge)
+ *                  lam[N][n]  (lam = the node multipliers y_i)
+ *    S is the cross term M_e of eq. (lagrangian) (x_i^T M_e u_e); c_root is
+ *    the root constraint of eq. (kkt-root), c_j the offset of the dynamics
+ *    into j (eq. (kkt-dyn)); Delta_i is the dual regulariser of node i.
+ *  - The caller owns every problem/solution buffer and the stream; inputs are
+ *    never modified.  The library owns the plan, its device copy and (unless
+ *    the caller supplies one) a workspace cached in the plan.
+ *  - The caller guarantees the standing convexity assumptions of
+ *    Definition 1 (R_e > 0, Delta_i >= 0, Q_i - sum_out M R^-1 M^T >= 0); the
+ *    solver only reports pivot breakdowns it meets (RCR_SINGULAR, RCR_NOT_PD).
+ *  - Return value: 0 on success, a negative RCR_* status otherwise.
+ *    rcr_status_string() names it.  Calls are thread-safe for distinct plans;
+ *    concurrent rcr_solve calls that share a plan and its cached workspace
+ *    race unless each passes its own workspace.
+ */
+#ifndef RCR_H
+#define RCR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ----------------------------------------------------------------- status */
+#define RCR_OK 0
+#define RCR_INVALID_TREE (-1) /* no root, several roots, a cycle, an index out of range   */
+#define RCR_BAD_DIMS (-2)     /* n or m < 1, or above RCR_MAX_DIM, or N < 1               */
+#define RCR_NULL_ARG (-3)     /* a required pointer is NULL                                */
+#define RCR_NOT_PD (-4)       /* Cholesky of R_e or G_e broke down                         */
+#define RCR_SINGULAR (-5)     /* zero pivot in I + C U, S, or F (excluded by Definition 1) */
+#define RCR_NONFINITE (-6)    /* a NaN or Inf reached an output                            */
+#define RCR_OOM (-7)          /* host or device allocation failed                          */
+#define RCR_HIP_ERROR (-8)    /* a HIP runtime call failed                                 */
+#define RCR_BAD_OPTION (-9)   /* an option value is out of range                           */
+#define RCR_SMALL_WORKSPACE (-10) /* caller workspace smaller than rcr_workspace_size()    */
+#define RCR_NO_DEVICE (-11)   /* no usable GPU                                             */
+
+#define RCR_MAX_DIM 16 /* largest n and m the kernels are compiled for */
+
+/* ---------------------------------------------------------------- planning */
+typedef struct rcr_plan rcr_plan; /* opaque, immutable after creation */
+
+#define RCR_SELECT_GREEDY_INDEX 0 /* greedy in increasing node id (Sec. VII-A, as the paper) */
+#define RCR_SELECT_LIST_RANK 1    /* alternate positions along each maximal unary path       */
+
+typedef struct {
+  int32_t selection;   /* RCR_SELECT_*; any maximal non-adjacent set is valid (Lemma 2) */
+  int32_t reserved[7]; /* zero */
+} rcr_plan_options;
+
+typedef struct {
+  int64_t N;
+  int32_t n, m;
+  int64_t root;
+  int64_t height;        /* longest root-to-leaf path, edges                             */
+  int64_t leaves;
+  int64_t max_degree;
+  int64_t rounds;        /* structural rounds (Lemma 2: <= ceil(log_{3/2} N))            */
+  int64_t levels;        /* nonempty dependency levels of the contraction (Lemma 4)     */
+  int64_t expand_levels; /* levels of the reverse (expansion) graph                      */
+  int64_t state_levels;  /* levels of the state-map contraction (compressions only)      */
+  int64_t sexp_levels;   /* levels of the state expansion                                */
+  int64_t n_rake, n_compress, n_combine, n_absorb;
+  int64_t depth_bound;   /* D_N of eq. (dependency-level-bound)                          */
+  int64_t crew_ok;       /* 1 if every datum has one writer and is read only at a later level */
+  int64_t workspace_bytes_fp64;  /* device scratch of one FP64 solve                    */
+  int64_t workspace_bytes_mixed; /* device scratch of one MIXED32 solve                 */
+} rcr_plan_stats;
+
+/* Build the topology plan of Sec. VII from a HOST parent array (int64, N
+ * entries).  Host-only work: structural rounds, readiness-weighted sibling
+ * reductions (eq. (readiness-code-data)), earliest-start dependency levels
+ * (eq. (earliest-level)) and static slot indices.  n, m are the state and
+ * control dimensions the plan's workspace is sized for (1..RCR_MAX_DIM).
+ * The device copy is made lazily by the first solve.  *out receives the plan;
+ * release it with rcr_plan_destroy.  Errors: RCR_NULL_ARG, RCR_BAD_DIMS,
+ * RCR_INVALID_TREE, RCR_BAD_OPTION, RCR_OOM. */
+int rcr_plan_create(const int64_t *parent, int64_t N, int32_t n, int32_t m,
+                    const rcr_plan_options *opt, rcr_plan **out);
+
+/* Summary of a plan (host only).  Errors: RCR_NULL_ARG. */
+int rcr_plan_info(const rcr_plan *plan, rcr_plan_stats *out);
+
+/* Copy the plan's primitive operations to HOST arrays, for inspection and
+ * tests.  Each op is 8 int32 words:
+ *   {kind, round, level, a, b, c, d, e}
+ * kind 0 rake     a = node j, b = edge slot into j, c = contribution slot, d = parent
+ * kind 1 combine  a, b = input contribution slots (left, right), c = output slot, d = parent
+ * kind 2 absorb   a = node i, b = aggregate contribution slot
+ * kind 3 compress a = node j, b = edge slot into j, c = edge slot out of j,
+ *                 d = new edge slot, e = child node k
+ * Ops are sorted by (level, kind).  With ops == NULL only *count is written.
+ * Errors: RCR_NULL_ARG, RCR_SMALL_WORKSPACE (capacity < count). */
+int rcr_plan_export(const rcr_plan *plan, int32_t *ops, int64_t capacity, int64_t *count);
+
+void rcr_plan_destroy(rcr_plan *plan);
+
+/* ------------------------------------------------------------------ solving */
+typedef struct {
+  const double *Q, *q, *c, *Delta; /* node data   */
+  const double *R, *S, *r, *A, *B; /* edge data   */
+} rcr_problem;
+
+typedef struct {
+  double *K, *P, *x, *u, *lam;
+} rcr_solution;
+
+#define RCR_FP64 0    /* all arithmetic in float64                                        */
+#define RCR_MIXED32 1 /* float32 bulk, float64 R/G Cholesky and compress (I + C P) solve, */
+                      /* float64 KKT residual and refinement_steps correction solves        */
+
+#define RCR_EXEC_LEVELS 0 /* one launch per dependency level                              */
+#define RCR_EXEC_GRAPH 1  /* the same launches captured once into a hipGraph and replayed */
+
+typedef struct {
+  int32_t precision;        /* RCR_FP64 (default) or RCR_MIXED32                           */
+  int32_t refine_steps;     /* MIXED32: iterative-refinement steps (default 1 when < 0)    */
+  int32_t executor;         /* RCR_EXEC_LEVELS or RCR_EXEC_GRAPH                           */
+  int32_t check;            /* nonzero: synchronise the stream and report device flags     */
+  void *workspace;          /* optional caller device workspace (NULL: plan-owned)         */
+  int64_t workspace_bytes;  /* its size                                                    */
+  double *kkt_residual;     /* optional HOST out: max-abs KKT residual of eq. (kkt) over   */
+                            /* all four blocks (forces a synchronisation)                  */
+  float *kernel_ms;         /* optional HOST out[RCR_NUM_KERNEL_CLASSES]: per kernel class */
+                            /* device time of this call from HIP events (synchronises)     */
+  int32_t reserved[4];      /* zero */
+} rcr_solve_options;
+
+/* Kernel classes reported in rcr_solve_options.kernel_ms */
+#define RCR_K_CONDENSE 0
+#define RCR_K_QUAD_CONTRACT 1
+#define RCR_K_QUAD_EXPAND 2
+#define RCR_K_LOCAL_FACTOR 3
+#define RCR_K_TCOMPOSE 4
+#define RCR_K_RHS_INIT 5
+#define RCR_K_AFF_CONTRACT 6
+#define RCR_K_AFF_EXPAND 7
+#define RCR_K_LOCAL_AFFINE 8
+#define RCR_K_STATE_CONTRACT 9
+#define RCR_K_STATE_EXPAND 10
+#define RCR_K_RECOVER 11
+#define RCR_K_RESIDUAL 12
+#define RCR_NUM_KERNEL_CLASSES 13
+
+/* Device scratch one rcr_solve needs for this plan and precision. */
+int64_t rcr_workspace_size(const rcr_plan *plan, int32_t precision);
+
+/* Factor and solve one tree-LQR instance (Algorithm 1, Steps 2-6) on
+ * `stream` (a hipStream_t; NULL = the default stream).  Asynchronous and
+ * stream-ordered unless options request a synchronisation.  opt may be NULL
+ * (FP64, per-level executor, no check).  Errors: RCR_NULL_ARG, RCR_BAD_OPTION,
+ * RCR_SMALL_WORKSPACE, RCR_OOM, RCR_HIP_ERROR, RCR_NO_DEVICE and, when
+ * opt->check is set, RCR_SINGULAR, RCR_NOT_PD, RCR_NONFINITE. */
+int rcr_solve(const rcr_plan *plan, const rcr_problem *in, rcr_solution *out,
+              const rcr_solve_options *opt, void *stream);
+
+/* Static name of a status code. */
+const char *rcr_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RCR_H */

@@ -1,0 +1,66 @@
+// Device-side executor interface: plan upload, workspace layout, and the
+// launch sequence of one factor + solve (Algorithm 1, Steps 2-6).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "../../include/rcr.h"
+#include "plan.hpp"
+
+namespace rcr {
+
+// Device copy of a plan's integer arrays.
+struct PlanDev {
+  int device = -1;
+  OpRec *ops = nullptr;
+  Op4 *exp_ops = nullptr, *tc_ops = nullptr, *sx_ops = nullptr;
+  int32_t *parent = nullptr;
+  int32_t *child_off = nullptr, *child_idx = nullptr;  // children in increasing id (residual)
+  size_t bytes = 0;
+};
+
+// Element offsets (in units of the working type) of the solver's scratch arrays.
+struct WsLayout {
+  size_t U, EA, EC, EP, CT, PW, Finv, W, Ginv, Acl, Tm, Kw;  // matrices
+  size_t h, cv, z, p, kff, b, xw, uw, yw;                     // vectors
+  size_t rq, rr, rc;                                          // right-hand side copies (mixed)
+  size_t d_x, d_u, d_y;                                       // FP64 iterate (mixed), in doubles
+  size_t total_bytes;
+};
+
+WsLayout workspace_layout(const PlanHost &ph, int precision);
+
+struct GraphKey {
+  const void *p[16];
+  bool operator<(const GraphKey &o) const {
+    for (int i = 0; i < 16; ++i)
+      if (p[i] != o.p[i]) return p[i] < o.p[i];
+    return false;
+  }
+};
+
+struct PlanObj {
+  PlanHost host;
+  PlanDev dev;
+  std::mutex mu;
+  void *ws[2] = {nullptr, nullptr};  // plan-owned workspace per precision
+  size_t ws_bytes[2] = {0, 0};
+  int *status = nullptr;             // device status words
+  double *resid = nullptr;           // device residual accumulator
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  std::vector<hipEvent_t> events;
+};
+
+int plan_upload(PlanObj &P);
+void plan_release_device(PlanObj &P);
+
+int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_options &opt,
+          hipStream_t stream);
+
+}  // namespace rcr

@@ -1,0 +1,447 @@
+// Host planner: structural rounds, readiness-weighted sibling reductions,
+// earliest-start dependency levels and static slots (Sec. VII).
+//
+// Round (Sec. VII-A): rake every non-root leaf; then, in the post-rake tree,
+// compress a maximal set of pairwise non-adjacent non-root unary nodes
+// (greedy in increasing node id as in the paper, or alternate positions along
+// each maximal unary path — any maximal set satisfies Lemma 2).
+// Sibling reductions (Lemma 3): the order-preserving binary tree given by the
+// alphabetic Shannon-Fano-Elias code on the weights 2^{level}
+// (eq. (readiness-code-data)), with unary trie vertices suppressed.
+// Levels (eq. (earliest-level)): 1 + the largest producer level of the inputs.
+//
+// Slots: node data U_i is updated in place at slot i; every compression
+// appends a new edge slot (original edge into j is slot j), so an edge record
+// is never overwritten and the compress "tape" (A_r, C_r, P_r + U_j) of
+// eq. (quadratic-compress) is simply the retained records; rake and combine
+// outputs each get their own contribution slot.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cstring>
+
+#include "../../include/rcr.h"
+
+namespace rcr {
+namespace {
+
+typedef unsigned __int128 u128;
+
+struct Builder {
+  const int64_t *parent;
+  int64_t N;
+  PlanHost &P;
+
+  std::vector<int32_t> cur_par, lvlU, lvlE, edge_slot, sib_key, cnt, one_child;
+  std::vector<uint8_t> alive, sel;
+  std::vector<int32_t> contrib_level;
+  // removal records
+  std::vector<int32_t> rem_slot, rem_par, comp_r, comp_k;
+  std::vector<uint8_t> rem_kind;  // 0 none, 1 rake, 2 compress
+  std::vector<int32_t> removal_seq;
+  std::vector<OpRec> raw;  // forward op sequence before level sorting
+  int32_t next_slot = 0, next_contrib = 0;
+
+  explicit Builder(const int64_t *p, int64_t n, PlanHost &out) : parent(p), N(n), P(out) {}
+
+  int32_t new_contrib(int32_t level) {
+    contrib_level.push_back(level);
+    return next_contrib++;
+  }
+
+  // ---- readiness-weighted reduction (Lemma 3) -----------------------------
+  struct Code {
+    u128 r;
+    int d;
+  };
+  std::vector<Code> codes;
+  std::vector<int32_t> g_slot, g_lvl;
+  int32_t g_parent = 0, g_round = 0;
+
+  int bit(int j, int pos) const { return (int)((codes[j].r >> (codes[j].d - 1 - pos)) & 1); }
+
+  // returns contribution slot of the aggregate of [lo, hi] and sets *lvl
+  int32_t build(int lo, int hi, int depth, int32_t *lvl) {
+    for (;;) {
+      if (lo == hi) {
+        *lvl = g_lvl[lo];
+        return g_slot[lo];
+      }
+      int s = -1;
+      for (int j = lo; j <= hi; ++j)
+        if (bit(j, depth)) {
+          s = j;
+          break;
+        }
+      if (s < 0 || s == lo) {  // unary trie vertex: suppressed
+        ++depth;
+        continue;
+      }
+      int32_t la, lb;
+      int32_t a = build(lo, s - 1, depth + 1, &la);
+      int32_t b = build(s, hi, depth + 1, &lb);
+      int32_t lv = 1 + std::max(la, lb);
+      int32_t out = new_contrib(lv);
+      raw.push_back(OpRec{OP_COMBINE, g_round, lv, a, b, out, g_parent, 0});
+      *lvl = lv;
+      return out;
+    }
+  }
+
+  int32_t reduce(int32_t *agg_lvl) {
+    const int k = (int)g_slot.size();
+    if (k == 1) {
+      *agg_lvl = g_lvl[0];
+      return g_slot[0];
+    }
+    // Relative weights w_j = 2^{l_j - l_min}; the code is invariant under a common
+    // scale.  Differences are capped so that W < 2^62 and all products fit 128 bits;
+    // the cap (>= 40 levels for k <= 2^21 siblings) is never reached by trees of
+    // practical size, and reaching it only changes the parenthesisation.
+    int32_t lmin = *std::min_element(g_lvl.begin(), g_lvl.end());
+    int lg = 0;
+    while ((1LL << lg) < k) ++lg;
+    int cap = 61 - lg;
+    codes.resize(k);
+    u128 W = 0;
+    std::vector<u128> w(k);
+    for (int j = 0; j < k; ++j) {
+      int e = std::min<int>(g_lvl[j] - lmin, cap);
+      w[j] = (u128)1 << e;
+      W += w[j];
+    }
+    u128 S = 0;
+    for (int j = 0; j < k; ++j) {
+      int d = 0;
+      while ((w[j] << d) < W) ++d;  // smallest d with 2^d >= W / w_j
+      d += 1;                        // d_j^0 = ceil(log2(W / w_j)) + 1
+      u128 num = (2 * S + w[j]) << d;
+      codes[j].r = num / (2 * W);    // leading d bits of the midpoint F_j + p_j / 2
+      codes[j].d = d;
+      S += w[j];
+    }
+    return build(0, k - 1, 0, agg_lvl);
+  }
+
+  int run(int selection) {
+    // ---- validation and static statistics
+    int64_t root = -1;
+    for (int64_t i = 0; i < N; ++i) {
+      int64_t p = parent[i];
+      if (p < 0) {
+        if (p != -1 || root >= 0) return RCR_INVALID_TREE;
+        root = i;
+      } else if (p >= N || p == i) {
+        return RCR_INVALID_TREE;
+      }
+    }
+    if (root < 0) return RCR_INVALID_TREE;
+    if (N > (int64_t)(INT32_MAX / 2 - 16)) return RCR_BAD_DIMS;
+    P.root = root;
+    P.parent32.resize(N);
+    std::vector<int32_t> deg(N, 0);
+    for (int64_t i = 0; i < N; ++i) {
+      P.parent32[i] = (int32_t)parent[i];
+      if (parent[i] >= 0) deg[parent[i]]++;
+    }
+    {  // BFS: reachability (rejects cycles) and height
+      std::vector<int64_t> start(N + 1, 0), kids(N > 0 ? N : 1);
+      for (int64_t i = 0; i < N; ++i)
+        if (parent[i] >= 0) start[parent[i] + 1]++;
+      for (int64_t i = 0; i < N; ++i) start[i + 1] += start[i];
+      std::vector<int64_t> fill(start.begin(), start.end() - 1);
+      for (int64_t i = 0; i < N; ++i)
+        if (parent[i] >= 0) kids[fill[parent[i]]++] = i;
+      std::vector<int64_t> order;
+      order.reserve(N);
+      std::vector<int32_t> depth(N, 0);
+      order.push_back(root);
+      for (size_t h = 0; h < order.size(); ++h) {
+        int64_t v = order[h];
+        for (int64_t c = start[v]; c < start[v + 1]; ++c) {
+          depth[kids[c]] = depth[v] + 1;
+          order.push_back(kids[c]);
+        }
+      }
+      if ((int64_t)order.size() != N) return RCR_INVALID_TREE;
+      int32_t h = 0;
+      for (int64_t i = 0; i < N; ++i) h = std::max(h, depth[i]);
+      P.height = h;
+    }
+    P.leaves = 0;
+    P.max_degree = 0;
+    for (int64_t i = 0; i < N; ++i) {
+      if (deg[i] == 0) P.leaves++;
+      P.max_degree = std::max<int64_t>(P.max_degree, deg[i]);
+    }
+
+    // ---- rounds
+    cur_par.assign(P.parent32.begin(), P.parent32.end());
+    lvlU.assign(N, 0);
+    lvlE.assign(N, 0);
+    edge_slot.resize(N);
+    sib_key.resize(N);
+    for (int64_t i = 0; i < N; ++i) edge_slot[i] = sib_key[i] = (int32_t)i;
+    cnt.assign(N, 0);
+    one_child.assign(N, -1);
+    alive.assign(N, 1);
+    sel.assign(N, 0);
+    rem_slot.assign(N, -1);
+    rem_par.assign(N, -1);
+    comp_r.assign(N, -1);
+    comp_k.assign(N, -1);
+    rem_kind.assign(N, 0);
+    next_slot = (int32_t)N;
+    std::vector<int32_t> live(N);
+    for (int64_t i = 0; i < N; ++i) live[i] = (int32_t)i;
+    std::vector<int32_t> leaves, elig;
+    std::vector<std::pair<int64_t, int32_t>> keyed;  // (parent * N + key, leaf)
+    int32_t rnd = 0;
+    while (live.size() > 1) {
+      ++rnd;
+      for (int32_t v : live) cnt[v] = 0;
+      for (int32_t v : live)
+        if (v != root) cnt[cur_par[v]]++;
+      leaves.clear();
+      for (int32_t v : live)
+        if (v != root && cnt[v] == 0) leaves.push_back(v);
+      // rakes (every non-root leaf of the tree at the start of the round)
+      keyed.clear();
+      for (int32_t j : leaves) {
+        int32_t lv = 1 + std::max(lvlU[j], lvlE[j]);
+        int32_t out = new_contrib(lv);
+        raw.push_back(OpRec{OP_RAKE, rnd, lv, j, edge_slot[j], out, cur_par[j], 0});
+        rem_kind[j] = 1;
+        rem_slot[j] = edge_slot[j];
+        rem_par[j] = cur_par[j];
+        removal_seq.push_back(j);
+        keyed.push_back({(int64_t)cur_par[j] * N + sib_key[j], out});
+        P.n_rake++;
+      }
+      std::sort(keyed.begin(), keyed.end());
+      for (size_t g0 = 0; g0 < keyed.size();) {
+        int32_t i = (int32_t)(keyed[g0].first / N);
+        size_t g1 = g0;
+        g_slot.clear();
+        g_lvl.clear();
+        while (g1 < keyed.size() && keyed[g1].first / N == i) {
+          g_slot.push_back(keyed[g1].second);
+          g_lvl.push_back(contrib_level[keyed[g1].second]);
+          ++g1;
+        }
+        g_parent = i;
+        g_round = rnd;
+        int32_t agg_lvl;
+        int32_t agg = reduce(&agg_lvl);
+        int32_t lv = 1 + std::max(lvlU[i], agg_lvl);
+        raw.push_back(OpRec{OP_ABSORB, rnd, lv, i, agg, 0, 0, 0});
+        lvlU[i] = lv;
+        g0 = g1;
+      }
+      for (int32_t j : leaves) {
+        alive[j] = 0;
+        cnt[cur_par[j]]--;
+      }
+      // unary non-root nodes of the post-rake tree and their single child
+      for (int32_t v : live)
+        if (alive[v] && v != root && cnt[cur_par[v]] == 1) one_child[cur_par[v]] = v;
+      elig.clear();
+      for (int32_t v : live)
+        if (alive[v] && v != root && cnt[v] == 1) elig.push_back(v);  // increasing id
+      if (selection == RCR_SELECT_GREEDY_INDEX) {
+        for (int32_t v : elig)
+          if (!sel[cur_par[v]] && !sel[one_child[v]]) sel[v] = 1;
+      } else {
+        // alternate positions along each maximal path of eligible nodes, from its top
+        for (int32_t v : elig) sel[v] = 2;  // mark eligible
+        for (int32_t v : elig) {
+          if (sel[cur_par[v]] == 2 || sel[cur_par[v]] == 1 || sel[cur_par[v]] == 3) continue;  // not a head
+          int64_t rank = 0;
+          for (int32_t u = v; u >= 0 && (sel[u] == 2); u = one_child[u], ++rank) sel[u] = (rank % 2 == 0) ? 1 : 3;
+        }
+        for (int32_t v : elig)
+          if (sel[v] != 1) sel[v] = 0;
+      }
+      for (int32_t j : elig) {
+        if (sel[j] != 1) continue;
+        int32_t i = cur_par[j], k = one_child[j];
+        int32_t lv = 1 + std::max(lvlE[j], std::max(lvlU[j], lvlE[k]));
+        int32_t s = next_slot++;
+        raw.push_back(OpRec{OP_COMPRESS, rnd, lv, j, edge_slot[j], edge_slot[k], s, k});
+        rem_kind[j] = 2;
+        rem_slot[j] = edge_slot[j];
+        rem_par[j] = i;
+        comp_r[j] = edge_slot[k];
+        comp_k[j] = k;
+        removal_seq.push_back(j);
+        edge_slot[k] = s;
+        lvlE[k] = lv;
+        cur_par[k] = i;
+        sib_key[k] = sib_key[j];
+        alive[j] = 0;
+        P.n_compress++;
+      }
+      for (int32_t j : elig) sel[j] = 0;
+      size_t w = 0;
+      for (int32_t v : live)
+        if (alive[v]) live[w++] = v;
+      live.resize(w);
+    }
+    P.rounds = rnd;
+    P.n_contrib = next_contrib;
+    P.n_edge_slots = next_slot;
+    for (const OpRec &o : raw) {
+      if (o.kind == OP_COMBINE) P.n_combine++;
+      if (o.kind == OP_ABSORB) P.n_absorb++;
+    }
+
+    // ---- contraction levels: sort by (level, kind), stable in creation order
+    int32_t L = 0;
+    for (const OpRec &o : raw) L = std::max(L, o.level);
+    {
+      std::vector<int64_t> count((size_t)L * 4 + 1, 0);
+      for (const OpRec &o : raw) count[(size_t)(o.level - 1) * 4 + o.kind + 1]++;
+      for (size_t t = 1; t < count.size(); ++t) count[t] += count[t - 1];
+      P.ops.resize(raw.size());
+      std::vector<int64_t> fill(count.begin(), count.end() - 1);
+      for (const OpRec &o : raw) P.ops[fill[(size_t)(o.level - 1) * 4 + o.kind]++] = o;
+      P.lvl_off.resize(L + 1);
+      for (int32_t t = 0; t <= L; ++t) P.lvl_off[t] = count[(size_t)t * 4];
+    }
+
+    // ---- expansion of compressions (reverse graph): level = 1 + level of the child's value
+    {
+      std::vector<int32_t> eP(N, 0);
+      int32_t LE = 0;
+      for (auto it = removal_seq.rbegin(); it != removal_seq.rend(); ++it) {
+        int32_t j = *it;
+        if (rem_kind[j] == 2) {
+          eP[j] = 1 + eP[comp_k[j]];
+          LE = std::max(LE, eP[j]);
+        }
+      }
+      std::vector<std::vector<Op4>> by(LE);
+      for (int32_t j : removal_seq)
+        if (rem_kind[j] == 2) by[eP[j] - 1].push_back(Op4{j, comp_r[j], comp_k[j], 0});
+      P.exp_off.assign(1, 0);
+      for (auto &v : by) {
+        P.exp_ops.insert(P.exp_ops.end(), v.begin(), v.end());
+        P.exp_off.push_back((int64_t)P.exp_ops.size());
+      }
+    }
+    // ---- composition of edge maps over compressions only
+    {
+      std::vector<int32_t> lT(next_slot, 0);
+      int32_t LT = 0;
+      std::vector<Op4> seq;
+      for (const OpRec &o : raw)
+        if (o.kind == OP_COMPRESS) {
+          lT[o.d] = 1 + std::max(lT[o.b], lT[o.c]);
+          LT = std::max(LT, lT[o.d]);
+          seq.push_back(Op4{o.b, o.c, o.d, o.a});
+        }
+      std::vector<std::vector<Op4>> by(LT);
+      for (const Op4 &q : seq) by[lT[q.c] - 1].push_back(q);
+      P.tc_off.assign(1, 0);
+      for (auto &v : by) {
+        P.tc_ops.insert(P.tc_ops.end(), v.begin(), v.end());
+        P.tc_off.push_back((int64_t)P.tc_ops.size());
+      }
+    }
+    // ---- state expansion: x_j from the state of its parent at removal time
+    {
+      std::vector<int32_t> eX(N, 0);
+      int32_t LX = 0;
+      for (auto it = removal_seq.rbegin(); it != removal_seq.rend(); ++it) {
+        int32_t j = *it;
+        eX[j] = 1 + eX[rem_par[j]];
+        LX = std::max(LX, eX[j]);
+      }
+      std::vector<std::vector<Op4>> by(LX);
+      for (int32_t j : removal_seq) by[eX[j] - 1].push_back(Op4{j, rem_slot[j], rem_par[j], 0});
+      P.sx_off.assign(1, 0);
+      for (auto &v : by) {
+        P.sx_ops.insert(P.sx_ops.end(), v.begin(), v.end());
+        P.sx_off.push_back((int64_t)P.sx_ops.size());
+      }
+    }
+    P.crew_ok = verify_crew();
+    return RCR_OK;
+  }
+
+  // Independent check of the level schedule: replay the levels in order and
+  // verify that every input was produced at an earlier level, that each datum
+  // has at most one writer per level, and that no datum written at a level is
+  // read by another op of that level.
+  bool verify_crew() const {
+    // datum ids: U_i -> i; edge slot s -> N + s; contribution c -> N + slots + c
+    const int64_t E0 = N, C0 = N + P.n_edge_slots, ND = C0 + P.n_contrib;
+    std::vector<int32_t> produced(ND, -1), wstamp(ND, -1), rstamp(ND, -1);
+    for (int64_t i = 0; i < N; ++i) produced[i] = 0;
+    for (int64_t s = 0; s < N; ++s) produced[E0 + s] = 0;
+    for (int64_t t = 1; t <= P.levels(); ++t) {
+      std::vector<int64_t> reads, writes;
+      for (int64_t k = P.lvl_off[t - 1]; k < P.lvl_off[t]; ++k) {
+        const OpRec &o = P.ops[k];
+        if (o.level != t) return false;
+        int64_t in[3];
+        int nin = 0;
+        int64_t outd = -1;
+        switch (o.kind) {
+          case OP_RAKE: in[0] = o.a; in[1] = E0 + o.b; nin = 2; outd = C0 + o.c; break;
+          case OP_COMBINE: in[0] = C0 + o.a; in[1] = C0 + o.b; nin = 2; outd = C0 + o.c; break;
+          case OP_ABSORB: in[0] = o.a; in[1] = C0 + o.b; nin = 2; outd = o.a; break;
+          case OP_COMPRESS: in[0] = E0 + o.b; in[1] = o.a; in[2] = E0 + o.c; nin = 3; outd = E0 + o.d; break;
+          default: return false;
+        }
+        for (int q = 0; q < nin; ++q) {
+          if (in[q] < 0 || in[q] >= ND) return false;
+          if (produced[in[q]] < 0 || produced[in[q]] >= t) return false;
+          if (!(o.kind == OP_ABSORB && in[q] == outd)) reads.push_back(in[q]);
+        }
+        if (outd < 0 || outd >= ND) return false;
+        if (wstamp[outd] == t) return false;  // two writers at one level
+        wstamp[outd] = (int32_t)t;
+        writes.push_back(outd);
+      }
+      for (int64_t r : reads) rstamp[r] = (int32_t)t;
+      for (int64_t w : writes) {
+        if (rstamp[w] == t) return false;  // read and written at the same level
+        produced[w] = (int32_t)t;
+      }
+    }
+    return true;
+  }
+};
+
+}  // namespace
+
+int build_plan(const int64_t *parent, int64_t N, int n, int m, int selection, PlanHost &out) {
+  if (!parent) return RCR_NULL_ARG;
+  if (N < 1 || n < 1 || m < 1 || n > RCR_MAX_DIM || m > RCR_MAX_DIM) return RCR_BAD_DIMS;
+  if (selection != RCR_SELECT_GREEDY_INDEX && selection != RCR_SELECT_LIST_RANK) return RCR_BAD_OPTION;
+  out = PlanHost();
+  out.N = N;
+  out.n = n;
+  out.m = m;
+  out.selection = selection;
+  Builder b(parent, N, out);
+  return b.run(selection);
+}
+
+int64_t depth_bound(int64_t N) {
+  if (N <= 1) return 0;
+  // floor(log2((2N - 1) * 36^R)), R = ceil(log_{3/2} N), via exact logs of integers:
+  // bits of (2N-1) plus R * log2(36), evaluated with a high-precision float and
+  // corrected by an integer comparison on 2^k <= (2N-1) * 36^R using long double.
+  int64_t R = 0;
+  long double p = 1.0L;
+  while (p < (long double)N) {
+    p *= 1.5L;
+    ++R;
+  }
+  long double v = log2l((long double)(2 * N - 1)) + (long double)R * log2l(36.0L);
+  return (int64_t)floorl(v + 1e-15L);
+}
+
+}  // namespace rcr

@@ -1,0 +1,74 @@
+// Host-side topology plan of the rake-compress contraction (Sec. VII).
+//
+// The plan is built once from the parent array and reused by every solve on
+// that topology (Algorithm 1, Step 1).  It records, for each primitive
+// operation, the static slot indices of its inputs and outputs and its
+// earliest-start dependency level (eq. (earliest-level)), so the executor can
+// launch all operations of one level together with no write conflicts
+// (unique writer per datum, reads only of data produced at earlier levels).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace rcr {
+
+enum OpKind : int32_t { OP_RAKE = 0, OP_COMBINE = 1, OP_ABSORB = 2, OP_COMPRESS = 3 };
+
+// One primitive operation; field meaning depends on kind (see rcr.h, rcr_plan_export).
+struct OpRec {
+  int32_t kind, round, level, a, b, c, d, e;
+};
+
+// Four int32 words: the records of the expansion and state passes.
+struct Op4 {
+  int32_t a, b, c, d;
+};
+
+struct PlanHost {
+  int64_t N = 0;
+  int n = 0, m = 0;
+  int64_t root = -1;
+  int selection = 0;
+  // statistics
+  int64_t height = 0, leaves = 0, max_degree = 0, rounds = 0;
+  int64_t n_rake = 0, n_compress = 0, n_combine = 0, n_absorb = 0;
+  int64_t n_contrib = 0;     // rake + combine output slots
+  int64_t n_edge_slots = 0;  // N original slots + one per compression
+  bool crew_ok = false;
+
+  // contraction (quadratic and affine passes): ops sorted by (level, kind);
+  // ops of level t (1-based) are [lvl_off[t-1], lvl_off[t]).
+  std::vector<OpRec> ops;
+  std::vector<int64_t> lvl_off;
+
+  // expansion of compressions: {j, r slot, child k, 0}; level-major like ops.
+  // Raked nodes and the root need no expansion op (their value is final when
+  // the node leaves the contraction).
+  std::vector<Op4> exp_ops;
+  std::vector<int64_t> exp_off;
+
+  // composition of edge maps along compressions only (composite transition
+  // matrices and state offsets): {l slot, r slot, new slot, j}.
+  std::vector<Op4> tc_ops;
+  std::vector<int64_t> tc_off;
+
+  // state expansion: {j, edge slot into j at removal, parent at removal, 0}.
+  std::vector<Op4> sx_ops;
+  std::vector<int64_t> sx_off;
+
+  std::vector<int32_t> parent32;  // original parent array (root: -1)
+
+  int64_t levels() const { return (int64_t)lvl_off.size() - 1; }
+  int64_t expand_levels() const { return (int64_t)exp_off.size() - 1; }
+  int64_t state_levels() const { return (int64_t)tc_off.size() - 1; }
+  int64_t sexp_levels() const { return (int64_t)sx_off.size() - 1; }
+};
+
+// Returns 0 or a negative RCR_* status.
+int build_plan(const int64_t *parent, int64_t N, int n, int m, int selection, PlanHost &out);
+
+// D_N of Lemma 4 (eq. (dependency-level-bound)).
+int64_t depth_bound(int64_t N);
+
+}  // namespace rcr

@@ -1,0 +1,220 @@
+"""Thin ctypes binding of librcr.so (include/rcr.h): argument marshalling only.
+
+Every step of the solve runs in the library's HIP kernels; this module only
+checks shapes, passes device pointers and the stream, and turns status codes
+into exceptions.  There is no CPU fallback: if the library is missing the
+import of `lib()` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librcr.so")
+
+FP64, MIXED32 = 0, 1
+EXEC_LEVELS, EXEC_GRAPH = 0, 1
+SELECT_GREEDY_INDEX, SELECT_LIST_RANK = 0, 1
+KERNEL_CLASSES = ("condense", "quad_contract", "quad_expand", "local_factor", "tcompose", "rhs_init",
+                  "aff_contract", "aff_expand", "local_affine", "state_contract", "state_expand",
+                  "recover", "residual")
+NUM_KERNEL_CLASSES = len(KERNEL_CLASSES)
+
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class PlanOptions(ctypes.Structure):
+    _fields_ = [("selection", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("n", ctypes.c_int32), ("m", ctypes.c_int32), ("root", ctypes.c_int64),
+                ("height", ctypes.c_int64), ("leaves", ctypes.c_int64), ("max_degree", ctypes.c_int64),
+                ("rounds", ctypes.c_int64), ("levels", ctypes.c_int64), ("expand_levels", ctypes.c_int64),
+                ("state_levels", ctypes.c_int64), ("sexp_levels", ctypes.c_int64),
+                ("n_rake", ctypes.c_int64), ("n_compress", ctypes.c_int64), ("n_combine", ctypes.c_int64),
+                ("n_absorb", ctypes.c_int64), ("depth_bound", ctypes.c_int64), ("crew_ok", ctypes.c_int64),
+                ("workspace_bytes_fp64", ctypes.c_int64), ("workspace_bytes_mixed", ctypes.c_int64)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("Q", "q", "c", "Delta", "R", "S", "r", "A", "B")]
+
+
+class Solution(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("K", "P", "x", "u", "lam")]
+
+
+class SolveOptions(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("refine_steps", ctypes.c_int32), ("executor", ctypes.c_int32),
+                ("check", ctypes.c_int32), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_int64),
+                ("kkt_residual", ctypes.POINTER(ctypes.c_double)), ("kernel_ms", ctypes.POINTER(ctypes.c_float)),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+EXPORTED = ("rcr_plan_create", "rcr_plan_info", "rcr_plan_export", "rcr_plan_destroy", "rcr_workspace_size",
+            "rcr_solve", "rcr_status_string")
+
+_lib = None
+_lock = threading.Lock()
+
+
+class RcrError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: status {status} ({status_string(status)})")
+
+
+def lib():
+    """Load librcr.so (fails loudly when it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+            L = ctypes.CDLL(LIB_PATH)
+            L.rcr_plan_create.restype = ctypes.c_int
+            L.rcr_plan_create.argtypes = [_i64p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(PlanOptions), ctypes.POINTER(ctypes.c_void_p)]
+            L.rcr_plan_info.restype = ctypes.c_int
+            L.rcr_plan_info.argtypes = [ctypes.c_void_p, ctypes.POINTER(PlanStats)]
+            L.rcr_plan_export.restype = ctypes.c_int
+            L.rcr_plan_export.argtypes = [ctypes.c_void_p, _i32p, ctypes.c_int64, _i64p]
+            L.rcr_plan_destroy.restype = None
+            L.rcr_plan_destroy.argtypes = [ctypes.c_void_p]
+            L.rcr_workspace_size.restype = ctypes.c_int64
+            L.rcr_workspace_size.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+            L.rcr_solve.restype = ctypes.c_int
+            L.rcr_solve.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.POINTER(Solution),
+                                    ctypes.POINTER(SolveOptions), ctypes.c_void_p]
+            L.rcr_status_string.restype = ctypes.c_char_p
+            L.rcr_status_string.argtypes = [ctypes.c_int]
+            _lib = L
+    return _lib
+
+
+def status_string(s: int) -> str:
+    return lib().rcr_status_string(int(s)).decode()
+
+
+class Plan:
+    """Reusable topology plan (rcr_plan_create).  Host-only; no GPU needed."""
+
+    def __init__(self, parent, n: int, m: int, selection: int = SELECT_GREEDY_INDEX):
+        L = lib()
+        self._parent = np.ascontiguousarray(parent, dtype=np.int64)
+        self.N = int(self._parent.shape[0])
+        self.n, self.m = int(n), int(m)
+        h = ctypes.c_void_p()
+        opt = PlanOptions(selection=selection)
+        rc = L.rcr_plan_create(self._parent.ctypes.data_as(_i64p), self.N, self.n, self.m, ctypes.byref(opt),
+                               ctypes.byref(h))
+        if rc != 0:
+            raise RcrError(rc, "rcr_plan_create")
+        self._h = h
+
+    def stats(self) -> dict:
+        s = PlanStats()
+        rc = lib().rcr_plan_info(self._h, ctypes.byref(s))
+        if rc != 0:
+            raise RcrError(rc, "rcr_plan_info")
+        return {k: int(getattr(s, k)) for k, _ in PlanStats._fields_}
+
+    def export_ops(self) -> np.ndarray:
+        cnt = ctypes.c_int64()
+        L = lib()
+        rc = L.rcr_plan_export(self._h, None, 0, ctypes.byref(cnt))
+        if rc != 0:
+            raise RcrError(rc, "rcr_plan_export")
+        ops = np.zeros((cnt.value, 8), dtype=np.int32)
+        rc = L.rcr_plan_export(self._h, ops.ctypes.data_as(_i32p), cnt.value, ctypes.byref(cnt))
+        if rc != 0:
+            raise RcrError(rc, "rcr_plan_export")
+        return ops
+
+    def workspace_size(self, precision: int = FP64) -> int:
+        return int(lib().rcr_workspace_size(self._h, precision))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().rcr_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+PROBLEM_FIELDS = ("Q", "q", "c", "Delta", "R", "S", "r", "A", "B")
+SOLUTION_FIELDS = ("K", "P", "x", "u", "lam")
+
+
+def _shapes(N, n, m):
+    return {"Q": (N, n, n), "q": (N, n), "c": (N, n), "Delta": (N, n, n), "R": (N, m, m), "S": (N, n, m),
+            "r": (N, m), "A": (N, n, n), "B": (N, n, m), "K": (N, m, n), "P": (N, n, n), "x": (N, n),
+            "u": (N, m), "lam": (N, n)}
+
+
+def _check(t, name, shape):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {shape}")
+
+
+def alloc_solution(plan: Plan, device="cuda"):
+    import torch
+    sh = _shapes(plan.N, plan.n, plan.m)
+    return {k: torch.empty(sh[k], dtype=torch.float64, device=device) for k in SOLUTION_FIELDS}
+
+
+def solve(plan: Plan, prob: dict, out: dict | None = None, precision: int = FP64, executor: int = EXEC_LEVELS,
+          check: bool = False, kkt_residual: bool = False, kernel_ms: bool = False, refine_steps: int = -1,
+          workspace=None, stream=None) -> dict:
+    """rcr_solve on device tensors.  Returns the solution dict, plus 'kkt_residual'
+    and 'kernel_ms' entries when requested."""
+    import torch
+    sh = _shapes(plan.N, plan.n, plan.m)
+    for k in PROBLEM_FIELDS:
+        _check(prob[k], k, sh[k])
+    if out is None:
+        out = alloc_solution(plan, prob["Q"].device)
+    for k in SOLUTION_FIELDS:
+        _check(out[k], k, sh[k])
+    p = Problem(**{k: prob[k].data_ptr() for k in PROBLEM_FIELDS})
+    s = Solution(**{k: out[k].data_ptr() for k in SOLUTION_FIELDS})
+    o = SolveOptions(precision=precision, refine_steps=refine_steps, executor=executor, check=int(check))
+    if workspace is not None:
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    res = ctypes.c_double(-1.0)
+    if kkt_residual:
+        o.kkt_residual = ctypes.pointer(res)
+    kms = (ctypes.c_float * NUM_KERNEL_CLASSES)()
+    if kernel_ms:
+        o.kernel_ms = ctypes.cast(kms, ctypes.POINTER(ctypes.c_float))
+    st = stream if stream is not None else torch.cuda.current_stream(prob["Q"].device)
+    rc = lib().rcr_solve(plan._h, ctypes.byref(p), ctypes.byref(s), ctypes.byref(o), ctypes.c_void_p(st.cuda_stream))
+    if rc != 0:
+        raise RcrError(rc, "rcr_solve")
+    result = dict(out)
+    if kkt_residual:
+        result["kkt_residual"] = res.value
+    if kernel_ms:
+        result["kernel_ms"] = {KERNEL_CLASSES[i]: float(kms[i]) for i in range(NUM_KERNEL_CLASSES)}
+    return result
+
+
+def to_device(data: dict, device="cuda") -> dict:
+    """Copy a host problem dict (numpy float64) to device tensors."""
+    import torch
+    return {k: torch.from_numpy(np.ascontiguousarray(data[k], dtype=np.float64)).to(device) for k in PROBLEM_FIELDS}

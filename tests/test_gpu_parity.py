@@ -1,0 +1,157 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle.
+
+Tolerance: every result array X in {K, P, x, u, lam} must satisfy
+max|X_gpu - X_oracle| / max|X_oracle| <= 1e-9 (the FP64 target).  Inputs are
+seeded synthetic instances; sizes span several tiles of the n x n blocks
+(n = 1 ... 16, m = 1 ... 16), ragged level widths, permuted labels, the
+degenerate trees (one node, two nodes, a star, a chain) and the full-size
+65,536-node n = 12 configuration.
+"""
+import sys
+import zlib
+
+import numpy as np
+import pytest
+
+from oracle import riccati as orc
+from paper_2608_01332_amd import rcr
+from paper_2608_01332_amd import workloads as w
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+TOL = 1e-9
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _gpu(parent, data, n, m, selection=rcr.SELECT_GREEDY_INDEX, **kw):
+    print(f"[gpu] N={len(parent)} n={n} m={m} sel={selection} {kw}", flush=True)
+    sys.stdout.flush()
+    plan = rcr.Plan(parent, n, m, selection=selection)
+    dev = rcr.to_device(data)
+    out = rcr.solve(plan, dev, check=True, **kw)
+    torch.cuda.synchronize()
+    res = {k: out[k].cpu().numpy() for k in rcr.SOLUTION_FIELDS}
+    for k in ("kkt_residual", "kernel_ms"):
+        if k in out:
+            res[k] = out[k]
+    return res
+
+
+def _assert_parity(g, ref, tol=TOL):
+    errs = {k: _rel(g[k], ref[k]) for k in rcr.SOLUTION_FIELDS}
+    assert max(errs.values()) <= tol, errs
+
+
+def _case(name, parent, n, m, delta_rank, cross, permute):
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    if permute:
+        parent, _ = w.permute_labels(parent, rng)
+    d = w.lqr_data(parent, w.DataSpec(n, m, delta_rank=delta_rank, delta_scale=0.05, cross=cross), rng)
+    return parent, d
+
+
+def test_config1_instance():
+    parent, d, spec = w.config_instance(1)
+    g = _gpu(parent, d, spec.n, spec.m, kkt_residual=True)
+    _assert_parity(g, orc.tree_riccati(parent, d))
+    assert g["kkt_residual"] < 1e-10
+
+
+DIMS = [(1, 1), (2, 1), (3, 2), (4, 2), (5, 3), (6, 2), (8, 3), (12, 4), (16, 4), (16, 16), (7, 16), (13, 9)]
+
+
+@pytest.mark.parametrize("n,m", DIMS)
+def test_random_trees_all_dims(n, m):
+    name = f"dims{n}x{m}"
+    rng = np.random.default_rng(n * 100 + m)
+    parent = w.tree_chainprob(int(rng.integers(150, 400)), 0.8, rng)
+    parent, d = _case(name, parent, n, m, delta_rank=max(1, n // 2), cross=True, permute=True)
+    g = _gpu(parent, d, n, m)
+    _assert_parity(g, orc.tree_riccati(parent, d))
+
+
+SHAPES = [("single", np.array([-1])), ("pair", np.array([-1, 0])), ("pair_rev", np.array([1, -1])),
+          ("star", w.tree_star(300)), ("chain", w.tree_chain(700)), ("balanced", w.tree_balanced(511)),
+          ("comb", w.tree_comb(301)), ("caterpillar", w.tree_caterpillar(200, 3)),
+          ("star_heavy", w.tree_star_heavy(20, np.full(20, 15))), ("tight", w.lemma2_tight_tree(64))]
+
+
+@pytest.mark.parametrize("name,parent", SHAPES, ids=[s[0] for s in SHAPES])
+def test_shapes(name, parent):
+    parent, d = _case(name, parent, 6, 2, delta_rank=3, cross=True, permute=len(parent) > 2)
+    g = _gpu(parent, d, 6, 2)
+    _assert_parity(g, orc.tree_riccati(parent, d))
+
+
+def test_list_rank_selection_matches_oracle():
+    rng = np.random.default_rng(8)
+    parent, d = _case("listrank", w.tree_chainprob(2000, 0.95, rng), 5, 2, 2, True, True)
+    g = _gpu(parent, d, 5, 2, selection=rcr.SELECT_LIST_RANK)
+    _assert_parity(g, orc.tree_riccati(parent, d))
+
+
+def test_config2_full_size_fp64():
+    """N = 65,536, n = 12, m = 4, rank-6 PSD Delta (singular C): every element checked."""
+    parent, d, spec = w.config_instance(2)
+    g = _gpu(parent, d, spec.n, spec.m, kkt_residual=True)
+    _assert_parity(g, orc.tree_riccati(parent, d))
+    assert g["kkt_residual"] < 1e-8
+
+
+def test_graph_executor_bitwise_equal_and_deterministic():
+    parent, d, spec = w.config_instance(1)
+    plan = rcr.Plan(parent, spec.n, spec.m)
+    dev = rcr.to_device(d)
+    outs = []
+    for ex in (rcr.EXEC_LEVELS, rcr.EXEC_LEVELS, rcr.EXEC_GRAPH, rcr.EXEC_GRAPH):
+        o = rcr.solve(plan, dev, executor=ex, check=True)
+        torch.cuda.synchronize()
+        outs.append({k: o[k].cpu().numpy().copy() for k in rcr.SOLUTION_FIELDS})
+    for o in outs[1:]:
+        for k in rcr.SOLUTION_FIELDS:
+            np.testing.assert_array_equal(o[k], outs[0][k])
+
+
+def test_graph_replays_with_new_data_in_same_buffers():
+    """Re-solve on the same plan and buffers with fresh data (plan and graph reused)."""
+    parent, d0, spec = w.config_instance(1)
+    plan = rcr.Plan(parent, spec.n, spec.m)
+    dev = rcr.to_device(d0)
+    out = rcr.alloc_solution(plan)
+    for s in range(3):
+        d = w.lqr_data(parent, spec, np.random.default_rng(100 + s))
+        for k in rcr.PROBLEM_FIELDS:
+            dev[k].copy_(torch.from_numpy(d[k]))
+        o = rcr.solve(plan, dev, out=out, executor=rcr.EXEC_GRAPH, check=True)
+        torch.cuda.synchronize()
+        _assert_parity({k: o[k].cpu().numpy() for k in rcr.SOLUTION_FIELDS}, orc.tree_riccati(parent, d))
+
+
+def test_error_not_pd():
+    parent, d, spec = w.config_instance(1)
+    d = dict(d)
+    d["R"] = d["R"].copy()
+    d["R"][5] = -np.eye(spec.m)
+    with pytest.raises(rcr.RcrError) as ei:
+        _gpu(parent, d, spec.n, spec.m)
+    assert ei.value.status == -4
+
+
+def test_error_nonfinite():
+    parent, d, spec = w.config_instance(1)
+    d = dict(d)
+    d["q"] = d["q"].copy()
+    d["q"][7, 0] = np.nan
+    with pytest.raises(rcr.RcrError) as ei:
+        _gpu(parent, d, spec.n, spec.m)
+    assert ei.value.status == -6
+
+
+def test_kernel_timing_option():
+    parent, d, spec = w.config_instance(1)
+    g = _gpu(parent, d, spec.n, spec.m, kernel_ms=True)
+    ms = g["kernel_ms"]
+    assert ms["quad_contract"] > 0 and ms["recover"] > 0

@@ -1,0 +1,170 @@
+"""The C++ planner behind the C-ABI (host only, no GPU): bit-exact agreement
+with the topology oracle for the paper's greedy index-order selection, and
+structural validity (Lemma 2 maximality, Lemma 4 depth, CREW) for the
+list-ranking selection, where several plans are correct."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import plan as pl
+from paper_2608_01332_amd import rcr
+from paper_2608_01332_amd import workloads as w
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+RAKE, COMBINE, ABSORB, COMPRESS = 0, 1, 2, 3
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "rcr.h")).read()
+    decl = set(re.findall(r"\b(rcr_[a-z_]+)\s*\(", hdr))
+    assert decl == set(rcr.EXPORTED)
+    L = rcr.lib()
+    for name in decl:
+        assert hasattr(L, name), name
+
+
+def _canon_cpp(ops):
+    removed, combines, absorbs = {}, set(), set()
+    cover = {}
+    for kind, rnd, lvl, a, b, c, d, e in ops.tolist():
+        if kind == RAKE:
+            removed[a] = ("R", rnd, lvl)
+            cover[c] = (a,)
+    for kind, rnd, lvl, a, b, c, d, e in ops.tolist():  # ops are level-sorted: inputs precede outputs
+        if kind == COMBINE:
+            cover[c] = tuple(sorted(cover[a] + cover[b]))
+            combines.add((d, rnd, lvl, cover[c]))
+        elif kind == ABSORB:
+            absorbs.add((a, rnd, lvl))
+        elif kind == COMPRESS:
+            removed[a] = ("C", rnd, lvl)
+    return removed, combines, absorbs
+
+
+def _trees():
+    rng = np.random.default_rng(77)
+    out = [("chain7", np.array([-1, 0, 1, 2, 3, 4, 5])), ("comb_fig2", np.array([-1, 0, 1, 1, 2, 4, 4, 5])),
+           ("chain300", w.tree_chain(300)), ("star200", w.tree_star(200)), ("balanced255", w.tree_balanced(255)),
+           ("comb101", w.tree_comb(101)), ("caterpillar", w.tree_caterpillar(40, 3)),
+           ("tight", w.lemma2_tight_tree(32)), ("single", np.array([-1])), ("pair", np.array([1, -1]))]
+    for t in range(10):
+        par = w.tree_chainprob(int(rng.integers(2, 2000)), float(rng.uniform(0.3, 0.99)), rng)
+        if t % 2:
+            par = w.permute_labels(par, rng)[0]
+        out.append((f"random{t}", par))
+    return out
+
+
+@pytest.mark.parametrize("name,parent", _trees(), ids=[t[0] for t in _trees()])
+def test_greedy_plan_matches_oracle_exactly(name, parent):
+    P = rcr.Plan(parent, 3, 2, selection=rcr.SELECT_GREEDY_INDEX)
+    st = P.stats()
+    ref = pl.make_plan(parent)
+    removed, combines, absorbs = _canon_cpp(P.export_ops())
+    assert removed == ref["removed"]
+    assert combines == set(ref["combines"])
+    assert absorbs == set(ref["absorbs"])
+    assert st["rounds"] == ref["rounds"]
+    assert st["levels"] == ref["levels"]
+    assert st["crew_ok"] == 1
+    assert st["n_rake"] + st["n_compress"] == len(parent) - 1
+    assert st["depth_bound"] == pl.depth_bound(len(parent))
+
+
+def _replay_valid(parent, ops):
+    """Replay the rounds and check: rakes = all non-root leaves at the round start;
+    compressions = a maximal set of pairwise non-adjacent non-root unary nodes of the
+    post-rake tree; every non-root node removed once."""
+    N = len(parent)
+    cur_par = list(map(int, parent))
+    alive = [True] * N
+    root = cur_par.index(-1)
+    by_round = {}
+    for kind, rnd, lvl, a, b, c, d, e in ops.tolist():
+        if kind in (RAKE, COMPRESS):
+            by_round.setdefault(rnd, {RAKE: [], COMPRESS: []})[kind].append((a, e))
+    for rnd in sorted(by_round):
+        kids = [[] for _ in range(N)]
+        for v in range(N):
+            if alive[v] and v != root:
+                kids[cur_par[v]].append(v)
+        leaves = {v for v in range(N) if alive[v] and v != root and not kids[v]}
+        assert {a for a, _ in by_round[rnd][RAKE]} == leaves
+        for v in leaves:
+            alive[v] = False
+        kids = [[] for _ in range(N)]
+        for v in range(N):
+            if alive[v] and v != root:
+                kids[cur_par[v]].append(v)
+        unary = {v for v in range(N) if alive[v] and v != root and len(kids[v]) == 1}
+        sel = {a for a, _ in by_round[rnd][COMPRESS]}
+        assert sel <= unary
+        for j in sel:
+            assert cur_par[j] not in sel and kids[j][0] not in sel
+        for v in unary - sel:  # maximal
+            assert cur_par[v] in sel or kids[v][0] in sel
+        for j, k in by_round[rnd][COMPRESS]:
+            assert kids[j] == [k]
+            cur_par[k] = cur_par[j]
+            alive[j] = False
+    assert sum(alive) == 1 and alive[root]
+
+
+@pytest.mark.parametrize("name,parent", _trees(), ids=[t[0] for t in _trees()])
+@pytest.mark.parametrize("selection", [rcr.SELECT_GREEDY_INDEX, rcr.SELECT_LIST_RANK])
+def test_plan_structurally_valid(name, parent, selection):
+    P = rcr.Plan(parent, 2, 1, selection=selection)
+    st = P.stats()
+    ops = P.export_ops()
+    _replay_valid(parent, ops)
+    N = len(parent)
+    assert st["crew_ok"] == 1
+    assert st["levels"] <= st["depth_bound"]
+    R = 0
+    while 1.5 ** R < N:
+        R += 1
+    assert st["rounds"] <= R
+    assert st["expand_levels"] <= st["depth_bound"] and st["sexp_levels"] <= st["depth_bound"]
+    # levels are sorted and every level is nonempty
+    lv = ops[:, 2]
+    assert np.all(np.diff(lv) >= 0)
+    if N > 1:
+        assert set(lv.tolist()) == set(range(1, st["levels"] + 1))
+
+
+def test_list_rank_compresses_half_of_each_unary_path():
+    """On a chain with permuted labels the list-ranking selection still takes alternate
+    positions along the path (ceil(L/2) of L eligible nodes), independent of the labels."""
+    rng = np.random.default_rng(5)
+    par, _ = w.permute_labels(w.tree_chain(1001), rng)
+    ops = rcr.Plan(par, 2, 1, selection=rcr.SELECT_LIST_RANK).export_ops()
+    first = ops[(ops[:, 0] == COMPRESS) & (ops[:, 1] == 1)]
+    assert len(first) == 499  # after the rake, depths 1..998 are eligible: alternate positions take 499
+    greedy = rcr.Plan(par, 2, 1).export_ops()
+    g1 = greedy[(greedy[:, 0] == COMPRESS) & (greedy[:, 1] == 1)]
+    assert len(g1) <= len(first)
+
+
+@pytest.mark.parametrize("parent", [[0, 0], [-1, -1], [-1, 2, 1], [-1, 5], [-2, 0], [1, 0, -1]])
+def test_invalid_trees(parent):
+    with pytest.raises(rcr.RcrError) as ei:
+        rcr.Plan(np.array(parent), 2, 1)
+    assert ei.value.status == -1
+
+
+@pytest.mark.parametrize("n,m", [(0, 1), (1, 0), (17, 2), (2, 17)])
+def test_bad_dims(n, m):
+    with pytest.raises(rcr.RcrError) as ei:
+        rcr.Plan(np.array([-1, 0]), n, m)
+    assert ei.value.status == -2
+
+
+def test_workspace_size_scales_linearly():
+    a = rcr.Plan(w.tree_chainprob(1000, 0.9, np.random.default_rng(0)), 8, 3)
+    b = rcr.Plan(w.tree_chainprob(4000, 0.9, np.random.default_rng(0)), 8, 3)
+    ra = a.workspace_size(rcr.FP64) / 1000
+    rb = b.workspace_size(rcr.FP64) / 4000
+    assert 0.7 < ra / rb < 1.4
+    assert a.workspace_size(rcr.MIXED32) < a.workspace_size(rcr.FP64) * 1.2
