@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Benchmark: tree-LQR factor + solve throughput on one MI355X.
+
+A step is one whole pass of the hot path, rcr_solve (Algorithm 1, Steps 2-6:
+condensation, quadratic contraction and expansion, local factors, affine
+contraction and expansion, local affine solve, state contraction and
+expansion, recovery), on one synthetic instance whose inputs are already
+resident in HBM.  The workload is the single-tree FP64 configuration:
+N = 65,536 nodes from the chain-probability generator (p = 0.95), n = 12,
+m = 4, rank-6 PSD dual regularisation with eigenvalues U(0, 1e-2).
+
+Output: one JSON line with nodes/s (whole job), p50/p99 per-step latency, the
+KKT residual reached, the roofline of the dominant kernel class (HIP events
+around each of its launches on the launch stream, algorithmic bytes per
+launch from the plan's operation counts), and the FP64 CPU oracle timed on a
+bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def algorithmic_words(st: dict, n: int, m: int) -> dict:
+    """Algorithmic FP words moved per solve, per kernel class: every primitive
+    reads each operand block once and writes each result block once (s = n^2,
+    t = n m, v = m^2)."""
+    s, t, v = n * n, n * m, m * m
+    N = st["N"]
+    E = N - 1
+    R, B, A, C = st["n_rake"], st["n_combine"], st["n_absorb"], st["n_compress"]
+    return {
+        "condense": N * 2 * s + E * (5 * s + 2 * t + v),
+        "quad_contract": R * 6 * s + B * 3 * s + A * 3 * s + C * 10 * s,
+        "quad_expand": C * 6 * s,
+        "local_factor": N * 4 * s + E * (3 * s + 3 * t + 2 * v),
+        "tcompose": C * 3 * s,
+        "rhs_init": N * 2 * n + E * (2 * s + t + 2 * n + m),
+        "aff_contract": R * (s + 4 * n) + (B + A) * 3 * n + C * (s + 4 * n),
+        "aff_expand": C * (s + 4 * n),
+        "local_affine": N * (3 * s + t + v + 3 * n + 2 * m),
+        "state_contract": C * (s + 3 * n),
+        "state_expand": E * (s + 3 * n),
+        "recover": N * (s + 4 * n) + E * (t + n + 2 * m),
+    }
+
+
+def read_traffic(kernel_class: str):
+    """HBM traffic per launch from the committed rocprofv3 PMC summary, if it was
+    taken on the current kernel source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_class}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2608_01332_amd", "csrc", "device.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if kv.get("source_sha") != sha:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(parent, data, seconds: float) -> dict:
+    from oracle import riccati as orc
+    N = len(parent)
+    runs, t0 = 0, time.perf_counter()
+    while True:
+        orc.tree_riccati(parent, data)
+        runs += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": N * runs / el, "unit": "nodes/s", "cores": 1, "kind": "oracle",
+            "sample": f"{runs} sequential FP64 solves of the N={N}, n=12, m=4 instance on 1 thread "
+                      f"({el:.1f} s)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--executor", choices=["graph", "levels"], default="graph")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU oracle sample length; 0 skips it")
+    ap.add_argument("--class-steps", type=int, default=5, help="steps of the per-launch event pass")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the solver shards by tree across GPUs with no communication, see DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_2608_01332_amd import rcr
+    from paper_2608_01332_amd import workloads as w
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    parent, data, spec = w.config_instance(2)
+    N, n, m = len(parent), spec.n, spec.m
+    t0 = time.perf_counter()
+    plan = rcr.Plan(parent, n, m)
+    plan_s = time.perf_counter() - t0
+    st = plan.stats()
+    prob = rcr.to_device(data, dev)
+    out = rcr.alloc_solution(plan, dev)
+    ex = rcr.EXEC_GRAPH if args.executor == "graph" else rcr.EXEC_LEVELS
+    stream = torch.cuda.current_stream(dev)
+
+    # accuracy at the measured configuration (outside the timed region)
+    chk = rcr.solve(plan, prob, out=out, executor=ex, check=True, kkt_residual=True)
+    kkt = chk["kkt_residual"]
+
+    for _ in range(args.warmup):
+        rcr.solve(plan, prob, out=out, executor=ex)
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    evs[0].record(stream)
+    for k in range(args.steps):
+        rcr.solve(plan, prob, out=out, executor=ex, stream=stream)
+        evs[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    step_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
+    total_ms = evs[0].elapsed_time(evs[-1])
+    ms_per_step = total_ms / args.steps
+    value = N * args.steps / (total_ms / 1e3)
+    p50 = float(np.percentile(step_ms, 50))
+    p99 = float(np.percentile(step_ms, 99))
+
+    # per-launch HIP-event pass: device time and launch count per kernel class
+    cls_ms, cls_n = {}, {}
+    for _ in range(max(1, args.class_steps)):
+        r = rcr.solve(plan, prob, out=out, executor=rcr.EXEC_LEVELS, kernel_ms=True, stream=stream)
+        for k, v in r["kernel_ms"].items():
+            cls_ms[k] = cls_ms.get(k, 0.0) + v
+            cls_n[k] = cls_n.get(k, 0) + r["kernel_launches"][k]
+    reps = max(1, args.class_steps)
+    words = algorithmic_words(st, n, m)
+    dom = max(words, key=lambda k: cls_ms.get(k, 0.0))
+    dom_ms = cls_ms[dom] / reps
+    dom_launches = cls_n[dom] / reps
+    bytes_per_solve = words[dom] * 8
+    achieved = bytes_per_solve / (dom_ms / 1e3) / 1e9
+    traffic = read_traffic(dom)
+    total_words = sum(words.values())
+    class_sum_ms = sum(cls_ms.values()) / reps
+
+    rec = {
+        "metric": "tree-LQR nodes/sec vs CPU Riccati at KKT res 1e-8; p50/p99 solve latency",
+        "value": value,
+        "unit": "nodes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "p50_ms": p50,
+        "p99_ms": p99,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "single tree-LQR factor+solve, N=65536 chain-prob p=0.95 tree, n=12, m=4, "
+                               "rank-6 PSD dual regularisation, FP64",
+                   "N": N, "n": n, "m": m, "height": st["height"], "levels": st["levels"],
+                   "rounds": st["rounds"], "executor": args.executor, "precision": "fp64"},
+        "kkt_residual": kkt,
+        "roofline": {"bound": "hbm", "kernel_class": dom, "achieved": achieved, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": traffic,
+                     "bytes_per_launch": bytes_per_solve / dom_launches,
+                     "avg_launch_us": dom_ms * 1e3 / dom_launches,
+                     "launches_per_step": dom_launches},
+        "solve_alg_bytes": total_words * 8,
+        "solve_alg_frac": total_words * 8 / (ms_per_step / 1e3) / 1e9 / PEAK_HBM_GBS,
+        "kernel_ms_per_step": {k: round(v / reps, 4) for k, v in cls_ms.items()},
+        "kernel_sum_ms_per_step": class_sum_ms,
+        "plan_ms": plan_s * 1e3,
+        "wall_ms_per_step": wall * 1e3 / args.steps,
+    }
+    if args.cpu_seconds > 0:
+        cb = cpu_baseline(parent, data, args.cpu_seconds)
+        rec["cpu_baseline"] = cb
+        rec["speedup_vs_cpu_oracle"] = value / cb["value"]
+    else:
+        rec["cpu_baseline"] = None
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -145,8 +145,11 @@ typedef struct {
   int64_t workspace_bytes;  /* its size                                                    */
   double *kkt_residual;     /* optional HOST out: max-abs KKT residual of eq. (kkt) over   */
                             /* all four blocks (forces a synchronisation)                  */
-  float *kernel_ms;         /* optional HOST out[RCR_NUM_KERNEL_CLASSES]: per kernel class */
-                            /* device time of this call from HIP events (synchronises)     */
+  float *kernel_ms;         /* optional HOST out[RCR_NUM_KERNEL_CLASSES]: per kernel class, */
+                            /* the summed device time of this call's launches, each launch */
+                            /* bracketed by a HIP event pair on `stream` (synchronises;    */
+                            /* the per-level executor is used)                             */
+  int32_t *kernel_launches; /* optional HOST out[RCR_NUM_KERNEL_CLASSES]: launch counts     */
   int32_t reserved[4];      /* zero */
 } rcr_solve_options;
 
@@ -164,7 +167,10 @@ typedef struct {
 #define RCR_K_STATE_EXPAND 10
 #define RCR_K_RECOVER 11
 #define RCR_K_RESIDUAL 12
-#define RCR_NUM_KERNEL_CLASSES 13
+#define RCR_K_QUAD_TAIL 13  /* narrow quadratic levels (contraction end + expansion start) */
+#define RCR_K_AFF_TAIL 14   /* narrow affine levels                                         */
+#define RCR_K_STATE_TAIL 15 /* narrow state levels                                          */
+#define RCR_NUM_KERNEL_CLASSES 16
 
 /* Device scratch one rcr_solve needs for this plan and precision. */
 int64_t rcr_workspace_size(const rcr_plan *plan, int32_t precision);

@@ -22,6 +22,7 @@ struct PlanDev {
   Op4 *exp_ops = nullptr, *tc_ops = nullptr, *sx_ops = nullptr;
   int32_t *parent = nullptr;
   int32_t *child_off = nullptr, *child_idx = nullptr;  // children in increasing id (residual)
+  int64_t *koff = nullptr, *exp_off = nullptr, *tc_off = nullptr, *sx_off = nullptr;  // level offsets
   size_t bytes = 0;
 };
 

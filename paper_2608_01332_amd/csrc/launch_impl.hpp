@@ -1,0 +1,252 @@
+// Launch sequence of one factor + solve for a padded block size NB.  Each
+// instantiation lives in its own translation unit (inst*.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <vector>
+
+#include "device.hpp"
+#include "kernels.hpp"
+#include "tail.hpp"
+#include "wide.hpp"
+
+namespace rcr {
+
+#ifndef HIPCK
+#define HIPCK(x)                                                                                      \
+  do {                                                                                                \
+    hipError_t e_ = (x);                                                                              \
+    if (e_ != hipSuccess) {                                                                           \
+      fprintf(stderr, "rcr: %s failed: %s (%s:%d)\n", #x, hipGetErrorString(e_), __FILE__, __LINE__); \
+      return RCR_HIP_ERROR;                                                                           \
+    }                                                                                                 \
+  } while (0)
+#endif
+
+inline unsigned blocks_for(int64_t cnt, int per) { return (unsigned)((cnt + per - 1) / per); }
+
+// Optional per-launch HIP event bracketing: every launch is enclosed by an
+// event pair on its own stream, so the summed durations per kernel class are
+// device execution times comparable with a kernel trace.
+struct Timer {
+  PlanObj *P = nullptr;
+  hipStream_t st = nullptr;
+  bool on = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> spans;
+  size_t used = 0;
+  int cls = 0;
+  hipEvent_t ev() {
+    if (used == P->events.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      P->events.push_back(e);
+    }
+    return P->events[used++];
+  }
+  void begin(int c) { cls = c; }
+  void end() {}
+  void pre() {
+    if (!on) return;
+    hipEvent_t a = ev(), b = ev();
+    if (!a || !b) return;
+    (void)hipEventRecord(a, st);
+    spans.push_back({cls, {a, b}});
+  }
+  void post() {
+    if (!on || spans.empty()) return;
+    (void)hipEventRecord(spans.back().second.second, st);
+  }
+};
+
+#define LAUNCH(tm, ...)          \
+  do {                           \
+    (tm).pre();                  \
+    hipLaunchKernelGGL(__VA_ARGS__); \
+    (tm).post();                 \
+  } while (0)
+
+// Narrow ranges run by the single-workgroup tail kernels: contraction levels
+// [c_begin, nc) whose widths are all <= cap, then expansion levels [0, e_end)
+// whose widths are all <= cap.  Empty when fewer than two levels qualify.
+struct TailRange {
+  int c_begin, c_end, e_begin, e_end;
+  int levels() const { return (c_end - c_begin) + (e_end - e_begin); }
+};
+inline TailRange tail_range(const std::vector<int64_t> &coff, int kstride, int kend,
+                            const std::vector<int64_t> *eoff, int64_t cap) {
+  const int nc = (int)((coff.size() - (kstride == 1 ? 1 : 0)) / kstride);
+  auto ccount = [&](int t) {
+    return kstride == 1 ? coff[t + 1] - coff[t] : coff[(size_t)t * kstride + kend] - coff[(size_t)t * kstride];
+  };
+  int cb = nc;
+  while (cb > 0 && ccount(cb - 1) <= cap) --cb;
+  int ee = 0;
+  if (eoff) {
+    const int ne = (int)eoff->size() - 1;
+    while (ee < ne && (*eoff)[ee + 1] - (*eoff)[ee] <= cap) ++ee;
+  }
+  TailRange tr{cb, nc, 0, ee};
+  if (tr.levels() < 2) tr = TailRange{nc, nc, 0, 0};
+  return tr;
+}
+
+template <typename K>
+inline void allow_lds(K kernel, size_t bytes) {
+  if (bytes > 65536) (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// Launch the whole factor + solve for working type T and padded sizes (NB, MB) on `st`.
+template <typename T, int NB, int MB>
+int launch_all_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st) {
+  const PlanHost &h = P.host;
+  constexpr int PW = TeamW<NB>::PW;
+  constexpr int NM = NB > MB ? NB : MB;
+  constexpr int PWm = TeamW<NM>::PW;
+  constexpr bool WIDE = MatLay<NB>::WIDE;  // one primitive per wavefront for the level kernels
+  const size_t lds_cond = (size_t)PW * (MB * MB + 2 * NB * MB) * sizeof(double);
+  const size_t lds_quad = (size_t)PW * lds_quad_words<T, NB>() * sizeof(T);
+  const size_t lds_lf = (size_t)PW * lds_lf_words<T, NB, MB>() * sizeof(T);
+  const size_t lds_wide = (size_t)wide_lds_words<(NB >= 12 ? NB : 12)>() * sizeof(T);
+  const size_t lds_lvl = WIDE ? lds_wide : lds_quad;  // per wavefront, level kernels
+  const unsigned NBk = blocks_for(h.N, PW);
+  // tail workgroup sizes
+  const size_t kMaxLds = 156 * 1024;
+  int mat_waves = (int)std::min<size_t>(MatLay<NB>::MAXW, kMaxLds / lds_lvl);
+  if (mat_waves < 1) mat_waves = 1;
+  const size_t lds_tail = (size_t)mat_waves * lds_lvl;
+  const int64_t mat_cap = 2 * (int64_t)mat_waves * MatLay<NB>::PW;
+  const int vec_waves = 16;
+  const int64_t vec_cap = 2 * (int64_t)vec_waves * (64 / TeamW<NB>::TW);
+  allow_lds(k_tail_quad<T, NB>, lds_tail);
+  allow_lds(k_tail_tc<T, NB>, lds_tail);
+  const TailRange tq = tail_range(h.kind_off, 5, 4, &h.exp_off, mat_cap);
+  const TailRange ttc = tail_range(h.tc_off, 1, 1, nullptr, mat_cap);
+  const TailRange ta = tail_range(h.kind_off, 5, 4, &h.exp_off, vec_cap);
+  const TailRange ts = tail_range(h.tc_off, 1, 1, &h.sx_off, vec_cap);
+
+  auto seg_of = [&](int64_t t, Seg &sg, int per) {
+    unsigned total = 0;
+    for (int s = 0; s <= 4; ++s) sg.off[s] = h.kind_off[(size_t)t * 5 + s];
+    sg.blk[0] = 0;
+    for (int s = 0; s < 4; ++s) {
+      total += blocks_for(sg.off[s + 1] - sg.off[s], per);
+      sg.blk[s + 1] = (int32_t)total;
+    }
+    return total;
+  };
+  tm.begin(RCR_K_CONDENSE);
+  LAUNCH(tm, (k_condense<T, NB, MB>), dim3(NBk), dim3(64), lds_cond, st, bf);
+
+  // ---- quadratic contraction and expansion
+  tm.begin(RCR_K_QUAD_CONTRACT);
+  for (int64_t t = 0; t < tq.c_begin; ++t) {
+    Seg sg;
+    if constexpr (WIDE) {
+      const unsigned nb = seg_of(t, sg, 1);
+      if (nb) LAUNCH(tm, (k_quad_level_wide<T, NB>), dim3(nb), dim3(64), lds_wide, st, bf, P.dev.ops, sg);
+    } else {
+      const unsigned nb = seg_of(t, sg, PW);
+      if (nb) LAUNCH(tm, (k_quad_level<T, NB>), dim3(nb), dim3(64), lds_quad, st, bf, P.dev.ops, sg);
+    }
+  }
+  if (tq.levels() > 0) {
+    tm.begin(RCR_K_QUAD_TAIL);
+    LAUNCH(tm, (k_tail_quad<T, NB>), dim3(1), dim3(64 * mat_waves), lds_tail, st, bf, P.dev.ops, P.dev.koff,
+           tq.c_begin, tq.c_end, P.dev.exp_ops, P.dev.exp_off, tq.e_begin, tq.e_end);
+  }
+  tm.begin(RCR_K_QUAD_EXPAND);
+  for (int64_t t = tq.e_end; t < h.expand_levels(); ++t) {
+    const int64_t cnt = h.exp_off[t + 1] - h.exp_off[t];
+    if (cnt <= 0) continue;
+    if constexpr (WIDE)
+      LAUNCH(tm, (k_quad_expand_wide<T, NB>), dim3((unsigned)cnt), dim3(64), lds_wide, st, bf, P.dev.exp_ops,
+             h.exp_off[t]);
+    else
+      LAUNCH(tm, (k_quad_expand<T, NB>), dim3(blocks_for(cnt, PW)), dim3(64), lds_quad, st, bf, P.dev.exp_ops,
+             h.exp_off[t], cnt);
+  }
+  tm.begin(RCR_K_LOCAL_FACTOR);
+  LAUNCH(tm, (k_local_factor<T, NB, MB>), dim3(NBk), dim3(64), lds_lf, st, bf);
+
+  // ---- composite transitions along compressions
+  tm.begin(RCR_K_TCOMPOSE);
+  for (int64_t t = 0; t < ttc.c_begin; ++t) {
+    const int64_t cnt = h.tc_off[t + 1] - h.tc_off[t];
+    if (cnt <= 0) continue;
+    if constexpr (WIDE)
+      LAUNCH(tm, (k_tcompose_wide<T, NB>), dim3((unsigned)cnt), dim3(64), lds_wide, st, bf, P.dev.tc_ops,
+             h.tc_off[t]);
+    else
+      LAUNCH(tm, (k_tcompose<T, NB>), dim3(blocks_for(cnt, PW)), dim3(64), lds_quad, st, bf, P.dev.tc_ops,
+             h.tc_off[t], cnt);
+  }
+  if (ttc.levels() > 0)
+    LAUNCH(tm, (k_tail_tc<T, NB>), dim3(1), dim3(64 * mat_waves), lds_tail, st, bf, P.dev.tc_ops, P.dev.tc_off,
+           ttc.c_begin, ttc.c_end);
+
+  // ---- solve: affine contraction and expansion
+  tm.begin(RCR_K_RHS_INIT);
+  LAUNCH(tm, (k_rhs_init<T, NB, MB>), dim3(NBk), dim3(64), 0, st, bf);
+  tm.begin(RCR_K_AFF_CONTRACT);
+  for (int64_t t = 0; t < ta.c_begin; ++t) {
+    Seg sg;
+    const unsigned nb = seg_of(t, sg, PW);
+    if (nb) LAUNCH(tm, (k_aff_level<T, NB>), dim3(nb), dim3(64), 0, st, bf, P.dev.ops, sg);
+  }
+  if (ta.levels() > 0) {
+    tm.begin(RCR_K_AFF_TAIL);
+    LAUNCH(tm, (k_tail_aff<T, NB>), dim3(1), dim3(64 * vec_waves), 0, st, bf, P.dev.ops, P.dev.koff, ta.c_begin,
+           ta.c_end, P.dev.exp_ops, P.dev.exp_off, ta.e_begin, ta.e_end);
+  }
+  tm.begin(RCR_K_AFF_EXPAND);
+  for (int64_t t = ta.e_end; t < h.expand_levels(); ++t) {
+    const int64_t cnt = h.exp_off[t + 1] - h.exp_off[t];
+    if (cnt > 0)
+      LAUNCH(tm, (k_aff_expand<T, NB>), dim3(blocks_for(cnt, PW)), dim3(64), 0, st, bf, P.dev.exp_ops,
+             h.exp_off[t], cnt);
+  }
+  tm.begin(RCR_K_LOCAL_AFFINE);
+  LAUNCH(tm, (k_local_affine<T, NB, MB>), dim3(blocks_for(h.N, PWm)), dim3(64), 0, st, bf);
+
+  // ---- state offsets and state expansion
+  tm.begin(RCR_K_STATE_CONTRACT);
+  for (int64_t t = 0; t < ts.c_begin; ++t) {
+    const int64_t cnt = h.tc_off[t + 1] - h.tc_off[t];
+    if (cnt > 0)
+      LAUNCH(tm, (k_state_level<T, NB>), dim3(blocks_for(cnt, PW)), dim3(64), 0, st, bf, P.dev.tc_ops,
+             h.tc_off[t], cnt);
+  }
+  if (ts.levels() > 0) {
+    tm.begin(RCR_K_STATE_TAIL);
+    LAUNCH(tm, (k_tail_state<T, NB>), dim3(1), dim3(64 * vec_waves), 0, st, bf, P.dev.tc_ops, P.dev.tc_off,
+           ts.c_begin, ts.c_end, P.dev.sx_ops, P.dev.sx_off, ts.e_begin, ts.e_end);
+  }
+  tm.begin(RCR_K_STATE_EXPAND);
+  for (int64_t t = ts.e_end; t < h.sexp_levels(); ++t) {
+    const int64_t cnt = h.sx_off[t + 1] - h.sx_off[t];
+    if (cnt > 0)
+      LAUNCH(tm, (k_state_expand<T, NB>), dim3(blocks_for(cnt, PW)), dim3(64), 0, st, bf, P.dev.sx_ops,
+             h.sx_off[t], cnt);
+  }
+  tm.begin(RCR_K_RECOVER);
+  LAUNCH(tm, (k_recover<T, NB, MB>), dim3(NBk), dim3(64), 0, st, bf);
+  HIPCK(hipGetLastError());
+  return RCR_OK;
+}
+
+inline int pad_n(int n) { return n <= 4 ? 4 : n <= 6 ? 6 : n <= 8 ? 8 : n <= 12 ? 12 : 16; }
+inline int pad_m(int m) { return m <= 4 ? 4 : m <= 8 ? 8 : 16; }
+
+template <typename T, int NB>
+int launch_all_m(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st) {
+  switch (pad_m(bf.m)) {
+    case 4: return launch_all_nb<T, NB, 4>(P, bf, tm, st);
+    case 8: return launch_all_nb<T, NB, 8>(P, bf, tm, st);
+    default: return launch_all_nb<T, NB, 16>(P, bf, tm, st);
+  }
+}
+
+
+}  // namespace rcr

@@ -307,6 +307,9 @@ struct Builder {
       for (const OpRec &o : raw) P.ops[fill[(size_t)(o.level - 1) * 4 + o.kind]++] = o;
       P.lvl_off.resize(L + 1);
       for (int32_t t = 0; t <= L; ++t) P.lvl_off[t] = count[(size_t)t * 4];
+      P.kind_off.resize((size_t)L * 5);
+      for (int32_t t = 0; t < L; ++t)
+        for (int s = 0; s <= 4; ++s) P.kind_off[(size_t)t * 5 + s] = count[(size_t)t * 4 + s];
     }
 
     // ---- expansion of compressions (reverse graph): level = 1 + level of the child's value

@@ -41,6 +41,8 @@ struct PlanHost {
   // ops of level t (1-based) are [lvl_off[t-1], lvl_off[t]).
   std::vector<OpRec> ops;
   std::vector<int64_t> lvl_off;
+  // kind_off[5 t + s]: first op of kind s in level t + 1 (s = 0..3), kind_off[5 t + 4] its end
+  std::vector<int64_t> kind_off;
 
   // expansion of compressions: {j, r slot, child k, 0}; level-major like ops.
   // Raked nodes and the root need no expansion op (their value is final when

@@ -1,0 +1,245 @@
+// Device building blocks shared by the solver kernels: the working-buffer
+// descriptor and the "team" primitives for small dense blocks.
+//
+// A team is TW consecutive lanes of one 64-lane wavefront (TW = 4, 8 or 16,
+// the smallest that covers the padded block size NB); 64 / TW teams share a
+// wavefront, and every workgroup is one wavefront, so a team never waits for
+// another wavefront and its LDS exchanges need no hardware barrier.  Lane r of a team owns row r of every NB x NB block in
+// registers; a block that other lanes must read is staged in the team's LDS
+// region, where whole rows are broadcast to the team.  Blocks of dimension
+// n < NB are padded with zeros (and the implicit identity of I + ...), which
+// leaves the leading n x n results unchanged: the padded coordinates decouple.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "plan.hpp"
+
+namespace rcr {
+
+enum { ST_SINGULAR = 1, ST_NOT_PD = 2, ST_NONFINITE = 4 };
+
+template <typename T>
+struct Bufs {
+  int n, m, root;
+  int64_t N;
+  // caller problem (float64, device)
+  const double *Q, *q, *c, *De, *R, *S, *r, *A, *B;
+  // right-hand side seen by the solve passes
+  const T *sq, *sr, *sc;
+  // working arrays
+  T *U, *EA, *EC, *EP, *CT, *PW, *Finv, *W, *Ginv, *Acl, *Tm, *Kw;
+  T *h, *cv, *z, *p, *kff, *b, *xw, *uw, *yw;
+  const int32_t *parent;
+  int *status;
+};
+
+template <int NB>
+struct TeamW {
+  static constexpr int TW = NB <= 4 ? 4 : (NB <= 8 ? 8 : 16);
+  static constexpr int PW = 64 / TW;  // teams per wavefront
+};
+
+// Ops of one dependency level, grouped by kind: kind s occupies ops
+// [off[s], off[s+1]) and workgroups [blk[s], blk[s+1]).  Every workgroup
+// therefore executes a single kind, so all its teams follow one code path.
+struct Seg {
+  int64_t off[5];
+  int32_t blk[5];
+};
+
+template <typename T>
+__device__ __forceinline__ T fmat(T a, T b, T c) {
+  return fma(a, b, c);
+}
+
+// Ordering point for a team's LDS traffic.  A workgroup is one wavefront and
+// a wavefront executes its LDS instructions in order, so only compiler
+// reordering has to be prevented (wavefront-scope fences emit no wait).
+__device__ __forceinline__ void team_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One step of a team-wide (value, index) max with a DPP lane permutation
+// (ties go to the smaller index, so every lane ends with the same pair).
+template <int CTRL>
+__device__ __forceinline__ void argmax_step(double &v, int &idx) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int olo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
+  const int ohi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
+  const int oi = __builtin_amdgcn_mov_dpp(idx, CTRL, 0xF, 0xF, false);
+  const double ov = __hiloint2double(ohi, olo);
+  if (ov > v || (ov == v && oi < idx)) {
+    v = ov;
+    idx = oi;
+  }
+}
+template <int CTRL>
+__device__ __forceinline__ void argmax_step(float &v, int &idx) {
+  const float ov = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+  const int oi = __builtin_amdgcn_mov_dpp(idx, CTRL, 0xF, 0xF, false);
+  if (ov > v || (ov == v && oi < idx)) {
+    v = ov;
+    idx = oi;
+  }
+}
+
+// Max over the TW lanes of a team: pairs (quad_perm [1,0,3,2]), quads
+// (quad_perm [2,3,0,1]), half rows (row_half_mirror), rows (row_mirror).
+template <int TW, typename T>
+__device__ __forceinline__ void team_argmax(T &v, int &idx) {
+  argmax_step<0xB1>(v, idx);
+  argmax_step<0x4E>(v, idx);
+  if (TW >= 8) argmax_step<0x141>(v, idx);
+  if (TW >= 16) argmax_step<0x140>(v, idx);
+}
+
+// row[j] = g[r][j] for r, j < n (row stride n), else 0
+template <typename T, int NB, typename S>
+__device__ __forceinline__ void ld_row(T (&row)[NB], const S *__restrict__ g, int n, int r) {
+#pragma unroll
+  for (int j = 0; j < NB; ++j) row[j] = (r < n && j < n) ? (T)g[(int64_t)r * n + j] : (T)0;
+}
+
+template <typename T, int NB>
+__device__ __forceinline__ void st_row(T *__restrict__ g, const T (&row)[NB], int n, int r, bool active) {
+  if (!active || r >= n) return;
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+    if (j < n) g[(int64_t)r * n + j] = row[j];
+}
+
+template <typename T, int NB>
+__device__ __forceinline__ void lds_put(T *L, const T (&row)[NB], int r) {
+  if (r >= NB) return;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) L[r * NB + j] = row[j];
+}
+
+template <typename T, int NB>
+__device__ __forceinline__ void lds_row(T (&row)[NB], const T *L, int k) {
+  const int kk = k < NB ? k : NB - 1;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) row[j] = L[kk * NB + j];
+}
+
+template <typename T, int NB>
+__device__ __forceinline__ void zero(T (&row)[NB]) {
+#pragma unroll
+  for (int j = 0; j < NB; ++j) row[j] = (T)0;
+}
+
+// The block products below stream LDS rows; every RCR_ROWS_IN_FLIGHT rows the
+// accumulators are pinned (an empty asm that reads and writes them) and memory
+// accesses are fenced for the compiler, so the loads of later rows are not
+// hoisted above the arithmetic of earlier ones (which would exhaust the
+// register file).  No instruction is emitted for the fence itself.
+#define RCR_ROWS_IN_FLIGHT 2
+template <typename T, int W>
+__device__ __forceinline__ void pin(T (&acc)[W], int off, int cnt) {
+#pragma unroll
+  for (int j = 0; j < cnt; ++j) asm volatile("" : "+v"(acc[off + j]));
+  asm volatile("" ::: "memory");
+}
+template <typename T>
+__device__ __forceinline__ void pin1(T &x) {
+  asm volatile("" : "+v"(x));
+}
+__device__ __forceinline__ void mem_fence_compiler() { asm volatile("" ::: "memory"); }
+#define RCR_ROW_FENCE(k, acc, off, cnt)                                 \
+  do {                                                                  \
+    if (((k) + 1) % RCR_ROWS_IN_FLIGHT == 0) pin(acc, off, cnt);        \
+  } while (0)
+
+// acc[j] += sum_k a[k] * L[k][j]        (a row of A times the block L)
+template <typename T, int NB, int W>
+__device__ __forceinline__ void mac_rowL(T (&acc)[W], int off, const T (&a)[NB], const T *L) {
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[off + j] = fmat(a[k], L[k * NB + j], acc[off + j]);
+    RCR_ROW_FENCE(k, acc, off, NB);
+  }
+}
+
+// acc[j] += sum_k a[k] * L[j][k]        (a row of A times L^T)
+template <typename T, int NB, int W>
+__device__ __forceinline__ void mac_rowLt(T (&acc)[W], int off, const T (&a)[NB], const T *L) {
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    T s = (T)0;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) s = fmat(a[k], L[j * NB + k], s);
+    acc[off + j] += s;
+    RCR_ROW_FENCE(j, acc, off, NB);
+  }
+}
+
+// acc[j] += sum_k L1[k][r] * L2[k][j]   (row r of L1^T L2)
+template <typename T, int NB>
+__device__ __forceinline__ void mac_colL(T (&acc)[NB], const T *L1, const T *L2, int r) {
+  const int rr = r < NB ? r : NB - 1;
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const T a = L1[k * NB + rr];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[j] = fmat(a, L2[k * NB + j], acc[j]);
+    RCR_ROW_FENCE(k, acc, 0, NB);
+  }
+}
+
+// Gauss-Jordan elimination with partial pivoting of the NB x W system whose
+// row r lives in lane r of the team (M[0:NB] the matrix, M[NB:W] the right-hand
+// sides).  On return M[NB:W] of lane r is row r of the solution.  The pivot
+// row travels through the team's LDS slot Lp (2 W words).  Pivots are chosen
+// by a width-TW butterfly argmax of |M[r][k]| over rows r >= k.
+template <typename T, int NB, int W, int TW>
+__device__ __forceinline__ void gj_team(T (&M)[W], T *Lp, int r, int *status) {
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    T cand = (r >= k && r < NB) ? (T)fabs(M[k]) : (T)-1;
+    int idx = r;
+    team_argmax<TW>(cand, idx);
+    if (r == idx) {
+#pragma unroll
+      for (int j = k; j < W; ++j) Lp[j] = M[j];
+    }
+    if (r == k && idx != k) {
+#pragma unroll
+      for (int j = k; j < W; ++j) Lp[W + j] = M[j];
+    }
+    team_sync();
+    if (r == idx && idx != k) {
+#pragma unroll
+      for (int j = k; j < W; ++j) M[j] = Lp[W + j];
+    }
+    if ((r & (TW - 1)) == 0 && !(cand > (T)0)) atomicOr(status, ST_SINGULAR);
+    const T inv = (T)1 / Lp[k];
+    const T g = (r == k) ? inv : -M[k] * inv;  // new row = h * row + g * pivot row
+    const T h = (r == k) ? (T)0 : (T)1;
+#pragma unroll
+    for (int j = k + 1; j < W; ++j) M[j] = fmat(g, Lp[j], h * M[j]);
+    team_sync();
+  }
+}
+
+// Store 0.5 (X + X^T) where lane r holds row r of X in `row`; Ls is an
+// NB x NB LDS scratch that the caller has synchronised for writing.
+template <typename T, int NB>
+__device__ __forceinline__ void sym_store(T *__restrict__ g, const T (&row)[NB], T *Ls, int n, int r,
+                                          bool active) {
+  lds_put(Ls, row, r);
+  team_sync();
+  const int rr = r < NB ? r : NB - 1;
+  T out[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) out[j] = (T)0.5 * (row[j] + Ls[j * NB + rr]);
+  st_row(g, out, n, r, active);
+  team_sync();
+}
+
+}  // namespace rcr

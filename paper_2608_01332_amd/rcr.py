@@ -21,7 +21,7 @@ EXEC_LEVELS, EXEC_GRAPH = 0, 1
 SELECT_GREEDY_INDEX, SELECT_LIST_RANK = 0, 1
 KERNEL_CLASSES = ("condense", "quad_contract", "quad_expand", "local_factor", "tcompose", "rhs_init",
                   "aff_contract", "aff_expand", "local_affine", "state_contract", "state_expand",
-                  "recover", "residual")
+                  "recover", "residual", "quad_tail", "aff_tail", "state_tail")
 NUM_KERNEL_CLASSES = len(KERNEL_CLASSES)
 
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -55,7 +55,7 @@ class SolveOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("refine_steps", ctypes.c_int32), ("executor", ctypes.c_int32),
                 ("check", ctypes.c_int32), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_int64),
                 ("kkt_residual", ctypes.POINTER(ctypes.c_double)), ("kernel_ms", ctypes.POINTER(ctypes.c_float)),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("kernel_launches", ctypes.POINTER(ctypes.c_int32)), ("reserved", ctypes.c_int32 * 4)]
 
 
 EXPORTED = ("rcr_plan_create", "rcr_plan_info", "rcr_plan_export", "rcr_plan_destroy", "rcr_workspace_size",
@@ -200,8 +200,10 @@ def solve(plan: Plan, prob: dict, out: dict | None = None, precision: int = FP64
     if kkt_residual:
         o.kkt_residual = ctypes.pointer(res)
     kms = (ctypes.c_float * NUM_KERNEL_CLASSES)()
+    kln = (ctypes.c_int32 * NUM_KERNEL_CLASSES)()
     if kernel_ms:
         o.kernel_ms = ctypes.cast(kms, ctypes.POINTER(ctypes.c_float))
+        o.kernel_launches = ctypes.cast(kln, ctypes.POINTER(ctypes.c_int32))
     st = stream if stream is not None else torch.cuda.current_stream(prob["Q"].device)
     rc = lib().rcr_solve(plan._h, ctypes.byref(p), ctypes.byref(s), ctypes.byref(o), ctypes.c_void_p(st.cuda_stream))
     if rc != 0:
@@ -211,6 +213,7 @@ def solve(plan: Plan, prob: dict, out: dict | None = None, precision: int = FP64
         result["kkt_residual"] = res.value
     if kernel_ms:
         result["kernel_ms"] = {KERNEL_CLASSES[i]: float(kms[i]) for i in range(NUM_KERNEL_CLASSES)}
+        result["kernel_launches"] = {KERNEL_CLASSES[i]: int(kln[i]) for i in range(NUM_KERNEL_CLASSES)}
     return result
 
 

@@ -154,4 +154,4 @@ def test_kernel_timing_option():
     parent, d, spec = w.config_instance(1)
     g = _gpu(parent, d, spec.n, spec.m, kernel_ms=True)
     ms = g["kernel_ms"]
-    assert ms["quad_contract"] > 0 and ms["recover"] > 0
+    assert ms["quad_contract"] + ms["quad_tail"] > 0 and ms["recover"] > 0 and ms["condense"] > 0
