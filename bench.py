@@ -99,6 +99,7 @@ def main() -> int:
     ap.add_argument("--executor", choices=["graph", "levels"], default="graph")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU oracle sample length; 0 skips it")
     ap.add_argument("--class-steps", type=int, default=5, help="steps of the per-launch event pass")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the MIXED32 + refinement leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
@@ -199,6 +200,31 @@ def main() -> int:
         "plan_ms": plan_s * 1e3,
         "wall_ms_per_step": wall * 1e3 / args.steps,
     }
+    if not args.no_mixed:
+        # the same workload in MIXED32: float32 factor/solves (float64 R/G Cholesky and
+        # compress solves), one refinement step on the float64 KKT residual
+        mout = rcr.alloc_solution(plan, dev)
+        chk = rcr.solve(plan, prob, out=mout, precision=rcr.MIXED32, refine_steps=1, executor=ex, check=True,
+                        kkt_residual=True)
+        for _ in range(args.warmup):
+            rcr.solve(plan, prob, out=mout, precision=rcr.MIXED32, refine_steps=1, executor=ex)
+        mev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        torch.cuda.synchronize()
+        mev[0].record(stream)
+        for k in range(args.steps):
+            rcr.solve(plan, prob, out=mout, precision=rcr.MIXED32, refine_steps=1, executor=ex, stream=stream)
+            mev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        mms = [mev[k].elapsed_time(mev[k + 1]) for k in range(args.steps)]
+        mtot = mev[0].elapsed_time(mev[-1])
+        rel = {}
+        for k in rcr.SOLUTION_FIELDS:
+            a, b = mout[k], out[k]
+            rel[k] = float((a - b).abs().max() / b.abs().max().clamp_min(1e-300))
+        rec["mixed32"] = {"value": N * args.steps / (mtot / 1e3), "unit": "nodes/s",
+                          "ms_per_step": mtot / args.steps, "p50_ms": float(np.percentile(mms, 50)),
+                          "p99_ms": float(np.percentile(mms, 99)), "refine_steps": 1,
+                          "kkt_residual": chk["kkt_residual"], "rel_err_vs_fp64": rel}
     if args.cpu_seconds > 0:
         cb = cpu_baseline(parent, data, args.cpu_seconds)
         rec["cpu_baseline"] = cb

@@ -42,57 +42,6 @@ __global__ void k_zero_status(int *st, double *resid) {
   if (threadIdx.x == 0) resid[0] = 0.0;
 }
 
-// Max-abs residual of the four KKT blocks of eq. (kkt), in float64, one 16-lane team per node v:
-//   node   Q x + q - y + sum_children (M u + A^T y_child)
-//   edge   M^T x_i + R u + r + B^T y_v;  A x_i + B u + c - x_v - Delta_v y_v   (v != root)
-//   root   c - x - Delta y
-__global__ __launch_bounds__(256) void k_kkt_residual(int64_t N, int n, int m, int root, const double *Q,
-                                                      const double *q, const double *c, const double *De,
-                                                      const double *R, const double *S, const double *rr,
-                                                      const double *A, const double *B, const double *x,
-                                                      const double *u, const double *y,
-                                                      const int32_t *parent, const int32_t *coff,
-                                                      const int32_t *cidx, double *out) {
-  const int64_t v = (int64_t)blockIdx.x * TEAMS_PER_BLOCK + threadIdx.x / TEAM;
-  const int r = threadIdx.x & (TEAM - 1);
-  if (v >= N) return;
-  const int nn = n * n, nm = n * m;
-  double worst = 0.0;
-  if (r < n) {
-    double s = q[v * n + r] - y[v * n + r];
-    for (int k = 0; k < n; ++k) s += Q[v * nn + r * n + k] * x[v * n + k];
-    for (int32_t t = coff[v]; t < coff[v + 1]; ++t) {
-      const int64_t j = cidx[t];
-      for (int k = 0; k < m; ++k) s += S[j * nm + r * m + k] * u[j * m + k];
-      for (int k = 0; k < n; ++k) s += A[j * nn + k * n + r] * y[j * n + k];
-    }
-    worst = fabs(s);
-    if (v == root) {
-      double t = c[v * n + r] - x[v * n + r];
-      for (int k = 0; k < n; ++k) t -= De[v * nn + r * n + k] * y[v * n + k];
-      worst = fmax(worst, fabs(t));
-    } else {
-      const int64_t i = parent[v];
-      double t = c[v * n + r] - x[v * n + r];
-      for (int k = 0; k < n; ++k) t += A[v * nn + r * n + k] * x[i * n + k] - De[v * nn + r * n + k] * y[v * n + k];
-      for (int k = 0; k < m; ++k) t += B[v * nm + r * m + k] * u[v * m + k];
-      worst = fmax(worst, fabs(t));
-    }
-  }
-  if (r < m && v != root) {
-    const int64_t i = parent[v];
-    double t = rr[v * m + r];
-    for (int k = 0; k < n; ++k) t += S[v * nm + k * m + r] * x[i * n + k] + B[v * nm + k * m + r] * y[v * n + k];
-    for (int k = 0; k < m; ++k) t += R[v * m * m + r * m + k] * u[v * m + k];
-    worst = fmax(worst, fabs(t));
-  }
-  if (!(worst == worst)) worst = INFINITY;
-  for (int off = 8; off > 0; off >>= 1) worst = fmax(worst, __shfl_xor(worst, off, TEAM));
-  if (r == 0 && worst > 0.0)
-    atomicMax(reinterpret_cast<unsigned long long *>(out), (unsigned long long)__double_as_longlong(worst));
-}
-
-// ------------------------------------------------------------ host side
 static inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 WsLayout workspace_layout(const PlanHost &ph, int precision) {
@@ -124,7 +73,7 @@ WsLayout workspace_layout(const PlanHost &ph, int precision) {
   L.b = take(S * n);
   if (precision == RCR_FP64) {
     L.PW = L.Kw = L.xw = L.uw = L.yw = (size_t)-1;  // the caller's outputs are used in place
-    L.rq = L.rr = L.rc = L.d_x = L.d_u = L.d_y = (size_t)-1;
+    L.rq = L.rr = L.rc = (size_t)-1;
   } else {
     L.PW = take(N * nn);
     L.Kw = take(N * m * n);
@@ -134,13 +83,6 @@ WsLayout workspace_layout(const PlanHost &ph, int precision) {
     L.rq = take(N * n);
     L.rr = take(N * m);
     L.rc = take(N * n);
-    size_t at = align_up(cur, 256);
-    L.d_x = at / 8;
-    cur = align_up(at + N * n * 8, 256);
-    L.d_u = cur / 8;
-    cur = align_up(cur + N * m * 8, 256);
-    L.d_y = cur / 8;
-    cur = align_up(cur + N * n * 8, 256);
   }
   L.total_bytes = cur;
   return L;
@@ -206,36 +148,111 @@ void plan_release_device(PlanObj &P) {
   P.ws_bytes[0] = P.ws_bytes[1] = 0;
 }
 
-#define RCR_DECL_NB(NBV)                                                                        \
-  extern template int launch_all_m<double, NBV>(PlanObj &, Bufs<double>, Timer &, hipStream_t);
+#define RCR_DECL_NB(NBV)                                                                                 \
+  extern template int launch_phase_m<double, NBV>(PlanObj &, Bufs<double>, Timer &, hipStream_t, int); \
+  extern template int launch_phase_m<float, NBV>(PlanObj &, Bufs<float>, Timer &, hipStream_t, int);
 RCR_DECL_NB(4)
 RCR_DECL_NB(6)
 RCR_DECL_NB(8)
 RCR_DECL_NB(12)
 RCR_DECL_NB(16)
+
+// phase 0: factor (Algorithm 1, Steps 2-3); phase 1: solve one right-hand side (Steps 4-6)
 template <typename T>
-static int launch_all(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st) {
+static int launch_phase(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase) {
   switch (pad_n(bf.n)) {
-    case 4: return launch_all_m<T, 4>(P, bf, tm, st);
-    case 6: return launch_all_m<T, 6>(P, bf, tm, st);
-    case 8: return launch_all_m<T, 8>(P, bf, tm, st);
-    case 12: return launch_all_m<T, 12>(P, bf, tm, st);
-    default: return launch_all_m<T, 16>(P, bf, tm, st);
+    case 4: return launch_phase_m<T, 4>(P, bf, tm, st, phase);
+    case 6: return launch_phase_m<T, 6>(P, bf, tm, st, phase);
+    case 8: return launch_phase_m<T, 8>(P, bf, tm, st, phase);
+    case 12: return launch_phase_m<T, 12>(P, bf, tm, st, phase);
+    default: return launch_phase_m<T, 16>(P, bf, tm, st, phase);
   }
 }
 
-static int launch_residual(PlanObj &P, const rcr_problem &in, const double *x, const double *u,
-                           const double *y, hipStream_t st) {
+// ---- element-wise helpers of the mixed-precision path
+template <typename A, typename B>
+__global__ __launch_bounds__(256) void k_cast(const A *__restrict__ a, B *__restrict__ b, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256) b[i] = (B)a[i];
+}
+
+// b += a (correction of the float64 iterate by a float32 step)
+__global__ __launch_bounds__(256) void k_accumulate(const float *__restrict__ a, double *__restrict__ b, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256)
+    b[i] += (double)a[i];
+}
+
+static unsigned grid_for(int64_t count) {
+  const int64_t b = (count + 255) / 256;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 4096));
+}
+
+// KKT residual blocks of eq. (kkt) in float64, one 16-lane team per node v, written
+// as the right-hand side of the correction solve (q' = r_x, r' = r_u, c'_root = r_root,
+// c'_v = r_dyn) when rq is non-null; the max-abs residual is accumulated into out.
+template <typename OT>
+__global__ __launch_bounds__(256) void k_residual_rhs(int64_t N, int n, int m, int root, const double *Q,
+                                                      const double *q, const double *c, const double *De,
+                                                      const double *R, const double *S, const double *rr,
+                                                      const double *A, const double *B, const double *x,
+                                                      const double *u, const double *y, const int32_t *parent,
+                                                      const int32_t *coff, const int32_t *cidx, OT *rq, OT *rr_out,
+                                                      OT *rc, double *out) {
+  const int64_t v = (int64_t)blockIdx.x * TEAMS_PER_BLOCK + threadIdx.x / TEAM;
+  const int r = threadIdx.x & (TEAM - 1);
+  if (v >= N) return;
+  const int nn = n * n, nm = n * m;
+  double worst = 0.0;
+  if (r < n) {
+    double s = q[v * n + r] - y[v * n + r];
+    for (int k = 0; k < n; ++k) s += Q[v * nn + r * n + k] * x[v * n + k];
+    for (int32_t t = coff[v]; t < coff[v + 1]; ++t) {
+      const int64_t j = cidx[t];
+      for (int k = 0; k < m; ++k) s += S[j * nm + r * m + k] * u[j * m + k];
+      for (int k = 0; k < n; ++k) s += A[j * nn + k * n + r] * y[j * n + k];
+    }
+    worst = fabs(s);
+    double t = c[v * n + r] - x[v * n + r];
+    if (v == root) {
+      for (int k = 0; k < n; ++k) t -= De[v * nn + r * n + k] * y[v * n + k];
+    } else {
+      const int64_t i = parent[v];
+      for (int k = 0; k < n; ++k) t += A[v * nn + r * n + k] * x[i * n + k] - De[v * nn + r * n + k] * y[v * n + k];
+      for (int k = 0; k < m; ++k) t += B[v * nm + r * m + k] * u[v * m + k];
+    }
+    worst = fmax(worst, fabs(t));
+    if (rq) {
+      rq[v * n + r] = (OT)s;
+      rc[v * n + r] = (OT)t;
+    }
+  }
+  for (int cc = r; cc < m; cc += TEAM) {
+    double t = 0.0;
+    if (v != root) {
+      const int64_t i = parent[v];
+      t = rr[v * m + cc];
+      for (int k = 0; k < n; ++k) t += S[v * nm + k * m + cc] * x[i * n + k] + B[v * nm + k * m + cc] * y[v * n + k];
+      for (int k = 0; k < m; ++k) t += R[v * m * m + cc * m + k] * u[v * m + k];
+    }
+    worst = fmax(worst, fabs(t));
+    if (rq) rr_out[v * m + cc] = (OT)t;
+  }
+  if (!(worst == worst)) worst = INFINITY;
+  for (int off = 8; off > 0; off >>= 1) worst = fmax(worst, __shfl_xor(worst, off, TEAM));
+  if (r == 0 && worst > 0.0)
+    atomicMax(reinterpret_cast<unsigned long long *>(out), (unsigned long long)__double_as_longlong(worst));
+}
+
+template <typename OT>
+static void launch_residual_rhs(PlanObj &P, const rcr_problem &in, const rcr_solution &out, OT *rq, OT *rr, OT *rc,
+                                hipStream_t st) {
   const PlanHost &h = P.host;
-  hipLaunchKernelGGL(k_kkt_residual, dim3(blocks_for(h.N, TEAMS_PER_BLOCK)), dim3(256), 0, st, h.N, h.n, h.m,
-                     (int)h.root, in.Q, in.q, in.c, in.Delta, in.R, in.S, in.r, in.A, in.B, x, u, y,
-                     P.dev.parent, P.dev.child_off, P.dev.child_idx, P.resid);
-  HIPCK(hipGetLastError());
-  return RCR_OK;
+  hipLaunchKernelGGL(k_residual_rhs<OT>, dim3(blocks_for(h.N, TEAMS_PER_BLOCK)), dim3(256), 0, st, h.N, h.n, h.m,
+                     (int)h.root, in.Q, in.q, in.c, in.Delta, in.R, in.S, in.r, in.A, in.B, out.x, out.u, out.lam,
+                     P.dev.parent, P.dev.child_off, P.dev.child_idx, rq, rr, rc, P.resid);
 }
 
 template <typename T>
-static Bufs<T> make_bufs(PlanObj &P, const WsLayout &L, void *ws, const rcr_problem &in, rcr_solution &out) {
+static Bufs<T> make_bufs(PlanObj &P, const WsLayout &L, void *ws, const rcr_problem &in) {
   const PlanHost &h = P.host;
   T *base = reinterpret_cast<T *>(ws);
   Bufs<T> bf;
@@ -253,12 +270,74 @@ static Bufs<T> make_bufs(PlanObj &P, const WsLayout &L, void *ws, const rcr_prob
   return bf;
 }
 
+// The whole launch sequence of one rcr_solve on `st` (directly, or while a graph is captured).
+static int launch_sequence(PlanObj &P, const rcr_problem &in, const rcr_solution &out, const rcr_solve_options &opt,
+                           const WsLayout &L, void *ws, Timer &tm, hipStream_t st) {
+  const PlanHost &h = P.host;
+  const int64_t Nn = h.N * h.n, Nm = h.N * h.m, Nnn = h.N * h.n * h.n, Nmn = h.N * h.m * h.n;
+  hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, st, P.status, P.resid);
+  if (opt.precision == RCR_FP64) {
+    Bufs<double> bf = make_bufs<double>(P, L, ws, in);
+    bf.sq = in.q;
+    bf.sr = in.r;
+    bf.sc = in.c;
+    bf.PW = out.P;
+    bf.Kw = out.K;
+    bf.xw = out.x;
+    bf.uw = out.u;
+    bf.yw = out.lam;
+    int rc = launch_phase<double>(P, bf, tm, st, 0);
+    if (!rc) rc = launch_phase<double>(P, bf, tm, st, 1);
+    return rc;
+  }
+  // MIXED32: float32 factor and solves; float64 R/G Cholesky and compress (I + C P) solve
+  // inside the kernels; float64 residual, correction right-hand side and update.
+  float *base = reinterpret_cast<float *>(ws);
+  Bufs<float> bf = make_bufs<float>(P, L, ws, in);
+  float *rq = base + L.rq, *rr = base + L.rr, *rc_ = base + L.rc;
+  bf.sq = rq;
+  bf.sr = rr;
+  bf.sc = rc_;
+  bf.PW = base + L.PW;
+  bf.Kw = base + L.Kw;
+  bf.xw = base + L.xw;
+  bf.uw = base + L.uw;
+  bf.yw = base + L.yw;
+  tm.begin(RCR_K_RESIDUAL);
+  LAUNCH(tm, (k_cast<double, float>), dim3(grid_for(Nn)), dim3(256), 0, st, in.q, rq, Nn);
+  LAUNCH(tm, (k_cast<double, float>), dim3(grid_for(Nm)), dim3(256), 0, st, in.r, rr, Nm);
+  LAUNCH(tm, (k_cast<double, float>), dim3(grid_for(Nn)), dim3(256), 0, st, in.c, rc_, Nn);
+  int rc = launch_phase<float>(P, bf, tm, st, 0);
+  if (!rc) rc = launch_phase<float>(P, bf, tm, st, 1);
+  if (rc) return rc;
+  tm.begin(RCR_K_RESIDUAL);
+  LAUNCH(tm, (k_cast<float, double>), dim3(grid_for(Nn)), dim3(256), 0, st, bf.xw, out.x, Nn);
+  LAUNCH(tm, (k_cast<float, double>), dim3(grid_for(Nm)), dim3(256), 0, st, bf.uw, out.u, Nm);
+  LAUNCH(tm, (k_cast<float, double>), dim3(grid_for(Nn)), dim3(256), 0, st, bf.yw, out.lam, Nn);
+  for (int it = 0; it < opt.refine_steps; ++it) {
+    tm.begin(RCR_K_RESIDUAL);
+    tm.pre();
+    launch_residual_rhs<float>(P, in, out, rq, rr, rc_, st);
+    tm.post();
+    rc = launch_phase<float>(P, bf, tm, st, 1);
+    if (rc) return rc;
+    tm.begin(RCR_K_RESIDUAL);
+    LAUNCH(tm, k_accumulate, dim3(grid_for(Nn)), dim3(256), 0, st, bf.xw, out.x, Nn);
+    LAUNCH(tm, k_accumulate, dim3(grid_for(Nm)), dim3(256), 0, st, bf.uw, out.u, Nm);
+    LAUNCH(tm, k_accumulate, dim3(grid_for(Nn)), dim3(256), 0, st, bf.yw, out.lam, Nn);
+  }
+  tm.begin(RCR_K_RESIDUAL);
+  LAUNCH(tm, (k_cast<float, double>), dim3(grid_for(Nmn)), dim3(256), 0, st, bf.Kw, out.K, Nmn);
+  LAUNCH(tm, (k_cast<float, double>), dim3(grid_for(Nnn)), dim3(256), 0, st, bf.PW, out.P, Nnn);
+  HIPCK(hipGetLastError());
+  return RCR_OK;
+}
+
 int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_options &opt, hipStream_t st) {
   std::lock_guard<std::mutex> lock(P.mu);
   int rc = plan_upload(P);
   if (rc) return rc;
   const int prec = opt.precision;
-  if (prec != RCR_FP64) return RCR_BAD_OPTION;  // MIXED32 is dispatched by solve_mixed
   const WsLayout L = workspace_layout(P.host, prec);
   void *ws = opt.workspace;
   if (ws) {
@@ -273,16 +352,6 @@ int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_
     }
     ws = P.ws[prec];
   }
-  Bufs<double> bf = make_bufs<double>(P, L, ws, in, out);
-  bf.sq = in.q;
-  bf.sr = in.r;
-  bf.sc = in.c;
-  bf.PW = out.P;
-  bf.Kw = out.K;
-  bf.xw = out.x;
-  bf.uw = out.u;
-  bf.yw = out.lam;
-
   Timer tm;
   tm.P = &P;
   tm.st = st;
@@ -292,7 +361,8 @@ int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_
     GraphKey key;
     memset(&key, 0, sizeof(key));
     const void *ptrs[16] = {in.Q, in.q, in.c, in.Delta, in.R, in.S, in.r, in.A, in.B,
-                            out.K, out.P, out.x, out.u, out.lam, ws, (const void *)(intptr_t)prec};
+                            out.K, out.P, out.x, out.u, out.lam, ws,
+                            (const void *)(intptr_t)(prec + 4 * opt.refine_steps)};
     memcpy(key.p, ptrs, sizeof(ptrs));
     auto it = P.graphs.find(key);
     if (it == P.graphs.end()) {
@@ -300,9 +370,8 @@ int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_
       HIPCK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
       hipGraph_t g;
       HIPCK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-      hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, cs, P.status, P.resid);
       Timer off;
-      int lrc = launch_all<double>(P, bf, off, cs);
+      int lrc = launch_sequence(P, in, out, opt, L, ws, off, cs);
       hipError_t ce = hipStreamEndCapture(cs, &g);
       (void)hipStreamDestroy(cs);
       if (lrc) return lrc;
@@ -315,13 +384,15 @@ int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_
     }
     HIPCK(hipGraphLaunch(it->second, st));
   } else {
-    hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, st, P.status, P.resid);
-    rc = launch_all<double>(P, bf, tm, st);
+    rc = launch_sequence(P, in, out, opt, L, ws, tm, st);
     if (rc) return rc;
   }
   if (opt.kkt_residual) {
-    rc = launch_residual(P, in, out.x, out.u, out.lam, st);
-    if (rc) return rc;
+    tm.begin(RCR_K_RESIDUAL);
+    // the residual of the returned iterate (the refinement's accumulator is reset first)
+    hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, st, P.status + 8, P.resid);
+    launch_residual_rhs<double>(P, in, out, nullptr, nullptr, nullptr, st);
+    HIPCK(hipGetLastError());
   }
   if (opt.check || opt.kkt_residual || tm.on) {
     HIPCK(hipStreamSynchronize(st));

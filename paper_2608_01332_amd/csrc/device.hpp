@@ -31,7 +31,6 @@ struct WsLayout {
   size_t U, EA, EC, EP, CT, PW, Finv, W, Ginv, Acl, Tm, Kw;  // matrices
   size_t h, cv, z, p, kff, b, xw, uw, yw;                     // vectors
   size_t rq, rr, rc;                                          // right-hand side copies (mixed)
-  size_t d_x, d_u, d_y;                                       // FP64 iterate (mixed), in doubles
   size_t total_bytes;
 };
 

@@ -84,8 +84,9 @@ __device__ __forceinline__ void tau_team(T *__restrict__ out, const T (&a)[NB], 
 
 template <typename T, int NB>
 __host__ __device__ constexpr int lds_quad_words() {
-  // compress: Pt, Ar, Al, X, Y (5 NB^2) + pivot slots (2 * 3 NB); rake: 4 NB^2 + 4 NB
-  return 5 * NB * NB + 6 * NB;
+  // compress: Pt, Ar, Al, X, Y (5 NB^2) + float64 pivot slots (2 * 3 NB doubles);
+  // rake: 4 NB^2 + 4 NB.  Counted in words of T.
+  return 5 * NB * NB + 6 * NB * (int)(sizeof(double) / sizeof(T));
 }
 
 // ---------------------------------------------------------------- factor kernels
@@ -216,7 +217,8 @@ __device__ __forceinline__ void quad_op_team(const Bufs<T> &bf, const OpRec &o, 
     const int64_t j = o.a, l = o.b, rs = o.c, sn = o.d;
     T *LPt = L, *LAr = L + NB * NB, *LAl = L + 2 * NB * NB, *LX = L + 3 * NB * NB, *LY = L + 4 * NB * NB;
     T *Lp = L + 5 * NB * NB;
-    T M[W];
+    typedef double ST;  // the compress composition's (I + C_l Pt) solve is always float64
+    ST M[W];
     {
       T pt[NB], uj[NB], al[NB], cl[NB];
       ld_row(pt, bf.EP + rs * nn, n, r);
@@ -235,20 +237,20 @@ __device__ __forceinline__ void quad_op_team(const Bufs<T> &bf, const OpRec &o, 
       team_sync();
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
-        M[q] = (q == r) ? (T)1 : (T)0;
-        M[NB + q] = al[q];
-        M[2 * NB + q] = (T)0;
+        M[q] = (q == r) ? (ST)1 : (ST)0;
+        M[NB + q] = (ST)al[q];
+        M[2 * NB + q] = (ST)0;
       }
-      mac_rowL<T, NB, W>(M, 0, cl, LPt);        // S = I + C_l Pt
-      mac_rowLt<T, NB, W>(M, 2 * NB, cl, LAr);  // C_l A_r^T
+      mac_rowL<ST, NB, W>(M, 0, cl, LPt);        // S = I + C_l Pt
+      mac_rowLt<ST, NB, W>(M, 2 * NB, cl, LAr);  // C_l A_r^T
     }
-    gj_team<T, NB, W, TW>(M, Lp, r, bf.status);
+    gj_team<ST, NB, W, TW>(M, reinterpret_cast<ST *>(Lp), r, bf.status);
     {
       T x[NB], y[NB];
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
-        x[q] = M[NB + q];
-        y[q] = M[2 * NB + q];
+        x[q] = (T)M[NB + q];
+        y[q] = (T)M[2 * NB + q];
       }
       lds_put(LX, x, r);
       lds_put(LY, y, r);

@@ -97,9 +97,10 @@ inline void allow_lds(K kernel, size_t bytes) {
   if (bytes > 65536) (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-// Launch the whole factor + solve for working type T and padded sizes (NB, MB) on `st`.
+// Launch one phase for working type T and padded sizes (NB, MB) on `st`:
+// phase 0 = factor (Algorithm 1, Steps 2-3), phase 1 = solve (Steps 4-6).
 template <typename T, int NB, int MB>
-int launch_all_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st) {
+int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase) {
   const PlanHost &h = P.host;
   constexpr int PW = TeamW<NB>::PW;
   constexpr int NM = NB > MB ? NB : MB;
@@ -108,7 +109,7 @@ int launch_all_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st) {
   const size_t lds_cond = (size_t)PW * (MB * MB + 2 * NB * MB) * sizeof(double);
   const size_t lds_quad = (size_t)PW * lds_quad_words<T, NB>() * sizeof(T);
   const size_t lds_lf = (size_t)PW * lds_lf_words<T, NB, MB>() * sizeof(T);
-  const size_t lds_wide = (size_t)wide_lds_words<(NB >= 12 ? NB : 12)>() * sizeof(T);
+  const size_t lds_wide = (size_t)wide_lds_words<T, (NB >= 12 ? NB : 12)>() * sizeof(T);
   const size_t lds_lvl = WIDE ? lds_wide : lds_quad;  // per wavefront, level kernels
   const unsigned NBk = blocks_for(h.N, PW);
   // tail workgroup sizes
@@ -136,6 +137,7 @@ int launch_all_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st) {
     }
     return total;
   };
+  if (phase == 0) {
   tm.begin(RCR_K_CONDENSE);
   LAUNCH(tm, (k_condense<T, NB, MB>), dim3(NBk), dim3(64), lds_cond, st, bf);
 
@@ -186,6 +188,7 @@ int launch_all_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st) {
     LAUNCH(tm, (k_tail_tc<T, NB>), dim3(1), dim3(64 * mat_waves), lds_tail, st, bf, P.dev.tc_ops, P.dev.tc_off,
            ttc.c_begin, ttc.c_end);
 
+  } else {
   // ---- solve: affine contraction and expansion
   tm.begin(RCR_K_RHS_INIT);
   LAUNCH(tm, (k_rhs_init<T, NB, MB>), dim3(NBk), dim3(64), 0, st, bf);
@@ -232,6 +235,7 @@ int launch_all_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st) {
   }
   tm.begin(RCR_K_RECOVER);
   LAUNCH(tm, (k_recover<T, NB, MB>), dim3(NBk), dim3(64), 0, st, bf);
+  }
   HIPCK(hipGetLastError());
   return RCR_OK;
 }
@@ -240,11 +244,11 @@ inline int pad_n(int n) { return n <= 4 ? 4 : n <= 6 ? 6 : n <= 8 ? 8 : n <= 12 
 inline int pad_m(int m) { return m <= 4 ? 4 : m <= 8 ? 8 : 16; }
 
 template <typename T, int NB>
-int launch_all_m(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st) {
+int launch_phase_m(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase) {
   switch (pad_m(bf.m)) {
-    case 4: return launch_all_nb<T, NB, 4>(P, bf, tm, st);
-    case 8: return launch_all_nb<T, NB, 8>(P, bf, tm, st);
-    default: return launch_all_nb<T, NB, 16>(P, bf, tm, st);
+    case 4: return launch_phase_nb<T, NB, 4>(P, bf, tm, st, phase);
+    case 8: return launch_phase_nb<T, NB, 8>(P, bf, tm, st, phase);
+    default: return launch_phase_nb<T, NB, 16>(P, bf, tm, st, phase);
   }
 }
 

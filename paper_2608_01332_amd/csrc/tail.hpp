@@ -25,7 +25,7 @@ struct MatLay {
   template <typename T>
   static constexpr int lw() {
     if constexpr (WIDE)
-      return wide_lds_words<NB>();
+      return wide_lds_words<T, NB>();
     else
       return lds_quad_words<T, NB>();
   }

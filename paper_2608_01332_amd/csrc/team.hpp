@@ -156,24 +156,25 @@ __device__ __forceinline__ void mem_fence_compiler() { asm volatile("" ::: "memo
   } while (0)
 
 // acc[j] += sum_k a[k] * L[k][j]        (a row of A times the block L)
-template <typename T, int NB, int W>
-__device__ __forceinline__ void mac_rowL(T (&acc)[W], int off, const T (&a)[NB], const T *L) {
+// Products are formed in the accumulator type Acc.
+template <typename Acc, int NB, int W, typename TR, typename TL>
+__device__ __forceinline__ void mac_rowL(Acc (&acc)[W], int off, const TR (&a)[NB], const TL *L) {
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
 #pragma unroll
-    for (int j = 0; j < NB; ++j) acc[off + j] = fmat(a[k], L[k * NB + j], acc[off + j]);
+    for (int j = 0; j < NB; ++j) acc[off + j] = fmat((Acc)a[k], (Acc)L[k * NB + j], acc[off + j]);
     RCR_ROW_FENCE(k, acc, off, NB);
   }
 }
 
 // acc[j] += sum_k a[k] * L[j][k]        (a row of A times L^T)
-template <typename T, int NB, int W>
-__device__ __forceinline__ void mac_rowLt(T (&acc)[W], int off, const T (&a)[NB], const T *L) {
+template <typename Acc, int NB, int W, typename TR, typename TL>
+__device__ __forceinline__ void mac_rowLt(Acc (&acc)[W], int off, const TR (&a)[NB], const TL *L) {
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    T s = (T)0;
+    Acc s = (Acc)0;
 #pragma unroll
-    for (int k = 0; k < NB; ++k) s = fmat(a[k], L[j * NB + k], s);
+    for (int k = 0; k < NB; ++k) s = fmat((Acc)a[k], (Acc)L[j * NB + k], s);
     acc[off + j] += s;
     RCR_ROW_FENCE(j, acc, off, NB);
   }

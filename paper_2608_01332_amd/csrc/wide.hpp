@@ -93,43 +93,43 @@ __device__ __forceinline__ void wput_piece(T *L, int ld, const T (&p)[WideCfg<NB
 }
 
 // out[c] += sum_k A[r][k] B[k][q CQ + c]
-template <typename T, int NB>
-__device__ __forceinline__ void wmm_AB(T (&out)[WideCfg<NB>::CQ], const T *A, int lda, const T *B, int ldb) {
+template <typename Acc, int NB, typename TA, typename TB>
+__device__ __forceinline__ void wmm_AB(Acc (&out)[WideCfg<NB>::CQ], const TA *A, int lda, const TB *B, int ldb) {
   constexpr int CQ = WideCfg<NB>::CQ;
   const int q = wq_of(), r = wr_of() < NB ? wr_of() : NB - 1;
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
-    const T a = A[r * lda + k];
+    const Acc a = (Acc)A[r * lda + k];
 #pragma unroll
-    for (int c = 0; c < CQ; ++c) out[c] = fmat(a, B[k * ldb + q * CQ + c], out[c]);
+    for (int c = 0; c < CQ; ++c) out[c] = fmat(a, (Acc)B[k * ldb + q * CQ + c], out[c]);
     if (k % 4 == 3) pin(out, 0, CQ);
   }
 }
 
 // out[c] += sum_k A[k][r] B[k][q CQ + c]      (A^T B)
-template <typename T, int NB>
-__device__ __forceinline__ void wmm_AtB(T (&out)[WideCfg<NB>::CQ], const T *A, int lda, const T *B, int ldb) {
+template <typename Acc, int NB, typename TA, typename TB>
+__device__ __forceinline__ void wmm_AtB(Acc (&out)[WideCfg<NB>::CQ], const TA *A, int lda, const TB *B, int ldb) {
   constexpr int CQ = WideCfg<NB>::CQ;
   const int q = wq_of(), r = wr_of() < NB ? wr_of() : NB - 1;
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
-    const T a = A[k * lda + r];
+    const Acc a = (Acc)A[k * lda + r];
 #pragma unroll
-    for (int c = 0; c < CQ; ++c) out[c] = fmat(a, B[k * ldb + q * CQ + c], out[c]);
+    for (int c = 0; c < CQ; ++c) out[c] = fmat(a, (Acc)B[k * ldb + q * CQ + c], out[c]);
     if (k % 4 == 3) pin(out, 0, CQ);
   }
 }
 
 // out[c] += sum_k A[r][k] B[q CQ + c][k]      (A B^T)
-template <typename T, int NB>
-__device__ __forceinline__ void wmm_ABt(T (&out)[WideCfg<NB>::CQ], const T *A, int lda, const T *B, int ldb) {
+template <typename Acc, int NB, typename TA, typename TB>
+__device__ __forceinline__ void wmm_ABt(Acc (&out)[WideCfg<NB>::CQ], const TA *A, int lda, const TB *B, int ldb) {
   constexpr int CQ = WideCfg<NB>::CQ;
   const int q = wq_of(), r = wr_of() < NB ? wr_of() : NB - 1;
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
-    const T a = A[r * lda + k];
+    const Acc a = (Acc)A[r * lda + k];
 #pragma unroll
-    for (int c = 0; c < CQ; ++c) out[c] = fmat(a, B[(q * CQ + c) * ldb + k], out[c]);
+    for (int c = 0; c < CQ; ++c) out[c] = fmat(a, (Acc)B[(q * CQ + c) * ldb + k], out[c]);
     if (k % 4 == 3) pin(out, 0, CQ);
   }
 }
@@ -207,10 +207,11 @@ __device__ __forceinline__ void gj_wide(T *LM, T *Lp, T *LF, int *status, bool r
   team_sync();
 }
 
-template <int NB>
+template <typename T, int NB>
 __host__ __device__ constexpr int wide_lds_words() {
-  // compress: Pt, Ar, Al, Cl, Z, S (6 NB^2) + M (3 NB^2) + pivot (2 * 3 NB) + LF (16)
-  return 9 * NB * NB + 6 * NB + 16;
+  // compress: Pt, Ar, Al, Cl, Z, S (6 NB^2 words of T) + the float64 system M
+  // (3 NB^2), pivot row slots (2 * 3 NB) and multipliers (16); in words of T
+  return 6 * NB * NB + (3 * NB * NB + 6 * NB + 16) * (int)(sizeof(double) / sizeof(T));
 }
 
 // tau(alpha, Ux) = Pm + A^T Ux (I + C Ux)^{-1} A  (eq. (terminal-fold)), symmetrised.
@@ -297,9 +298,11 @@ __device__ __forceinline__ void quad_op_wide(const Bufs<T> &bf, const OpRec &o, 
   } else {
     // alpha_{lr} = alpha_r o_{U_j} alpha_l  (eqs. (compress-intermediates), (composition))
     constexpr int W = 3 * NB;
+    typedef double ST;  // the (I + C_l Pt) solve is always float64
     const int64_t j = o.a, l = o.b, rs = o.c, sn = o.d;
     T *LPt = L, *LAr = L + NB * NB, *LAl = L + 2 * NB * NB, *LCl = L + 3 * NB * NB, *LZ = L + 4 * NB * NB;
-    T *LS = L + 5 * NB * NB, *LM = L + 6 * NB * NB, *Lp = LM + NB * W, *LF = Lp + 2 * W;
+    T *LS = L + 5 * NB * NB;
+    ST *LM = reinterpret_cast<ST *>(L + 6 * NB * NB), *Lp = LM + NB * W, *LF = Lp + 2 * W;
     const int q = wq_of(), r = wr_of();
     T cr[CQ], pl[CQ];
     {
@@ -320,25 +323,25 @@ __device__ __forceinline__ void quad_op_wide(const Bufs<T> &bf, const OpRec &o, 
     }
     team_sync();
     {
-      T sb[CQ], ct[CQ];
+      ST sb[CQ], ct[CQ];
 #pragma unroll
       for (int c = 0; c < CQ; ++c) {
-        sb[c] = (q * CQ + c == r) ? (T)1 : (T)0;
-        ct[c] = (T)0;
+        sb[c] = (q * CQ + c == r) ? (ST)1 : (ST)0;
+        ct[c] = (ST)0;
       }
-      wmm_AB<T, NB>(sb, LCl, NB, LPt, NB);   // S = I + C_l Pt
-      wmm_ABt<T, NB>(ct, LCl, NB, LAr, NB);  // C_l A_r^T
+      wmm_AB<ST, NB>(sb, LCl, NB, LPt, NB);   // S = I + C_l Pt
+      wmm_ABt<ST, NB>(ct, LCl, NB, LAr, NB);  // C_l A_r^T
       if (r < NB) {
 #pragma unroll
         for (int c = 0; c < CQ; ++c) {
           LM[r * W + q * CQ + c] = sb[c];
-          LM[r * W + NB + q * CQ + c] = LAl[r * NB + q * CQ + c];
+          LM[r * W + NB + q * CQ + c] = (ST)LAl[r * NB + q * CQ + c];
           LM[r * W + 2 * NB + q * CQ + c] = ct[c];
         }
       }
     }
     team_sync();
-    gj_wide<T, NB, W>(LM, Lp, LF, bf.status, active);  // [X | Y] = S^{-1} [A_l | C_l A_r^T]
+    gj_wide<ST, NB, W>(LM, Lp, LF, bf.status, active);  // [X | Y] = S^{-1} [A_l | C_l A_r^T]
     {
       T an[CQ], z[CQ];
 #pragma unroll

@@ -1,0 +1,88 @@
+"""GPU mixed-precision path (RCR_MIXED32): float32 factor and solves with the
+R/G Cholesky factorisations and the compress (I + C P) solve in float64, then
+iterative refinement on the float64 KKT residual of eq. (kkt), reusing the
+factor (Sec. IV: the KKT matrix, hence the factor, does not depend on
+(q, r, c)).
+
+Targets: KKT residual (max-abs over the four blocks) <= 1e-8 after one
+refinement step; the per-result error against the FP64 oracle is reported
+and bounded: after refinement the solution (x, u, lam) is within 1e-7
+relative, while K and P come from the float32 factor and are within 1e-4
+relative (they are not refined).
+"""
+import numpy as np
+import pytest
+
+from oracle import riccati as orc
+from paper_2608_01332_amd import rcr
+from paper_2608_01332_amd import workloads as w
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _run(parent, d, n, m, refine=1, executor=rcr.EXEC_LEVELS):
+    print(f"[gpu-mixed] N={len(parent)} n={n} m={m} refine={refine}", flush=True)
+    plan = rcr.Plan(parent, n, m)
+    dev = rcr.to_device(d)
+    out = rcr.solve(plan, dev, precision=rcr.MIXED32, refine_steps=refine, check=True, kkt_residual=True,
+                    executor=executor)
+    torch.cuda.synchronize()
+    res = {k: out[k].cpu().numpy() for k in rcr.SOLUTION_FIELDS}
+    ref = orc.tree_riccati(parent, d)
+    errs = {k: _rel(res[k], ref[k]) for k in rcr.SOLUTION_FIELDS}
+    print(f"[gpu-mixed]   kkt={out['kkt_residual']:.3e} errs={ {k: f'{v:.2e}' for k, v in errs.items()} }", flush=True)
+    return out["kkt_residual"], errs
+
+
+def _check(kkt, errs):
+    assert kkt <= 1e-8, kkt
+    for k in ("x", "u", "lam"):
+        assert errs[k] <= 1e-7, (k, errs)
+    for k in ("K", "P"):
+        assert errs[k] <= 1e-4, (k, errs)
+
+
+def test_mixed_config1():
+    parent, d, spec = w.config_instance(1)
+    _check(*_run(parent, d, spec.n, spec.m))
+
+
+def test_mixed_config2_full_size():
+    parent, d, spec = w.config_instance(2)
+    _check(*_run(parent, d, spec.n, spec.m))
+
+
+@pytest.mark.parametrize("n,m", [(3, 2), (6, 2), (8, 3), (12, 4), (16, 4)])
+def test_mixed_random(n, m):
+    rng = np.random.default_rng(n * 31 + m)
+    parent = w.tree_chainprob(3000, 0.9, rng)
+    parent, _ = w.permute_labels(parent, rng)
+    d = w.lqr_data(parent, w.DataSpec(n, m, delta_rank=n // 2, delta_scale=0.01, cross=True), rng)
+    _check(*_run(parent, d, n, m))
+
+
+def test_mixed_refinement_reduces_residual():
+    parent, d, spec = w.config_instance(1)
+    k0, _ = _run(parent, d, spec.n, spec.m, refine=0)
+    k1, _ = _run(parent, d, spec.n, spec.m, refine=1)
+    k2, _ = _run(parent, d, spec.n, spec.m, refine=2)
+    assert k1 < k0 and k2 <= k1 * 1.5
+
+
+def test_mixed_graph_matches_levels_bitwise():
+    parent, d, spec = w.config_instance(1)
+    plan = rcr.Plan(parent, spec.n, spec.m)
+    dev = rcr.to_device(d)
+    outs = []
+    for ex in (rcr.EXEC_LEVELS, rcr.EXEC_GRAPH, rcr.EXEC_GRAPH):
+        o = rcr.solve(plan, dev, precision=rcr.MIXED32, executor=ex, check=True)
+        torch.cuda.synchronize()
+        outs.append({k: o[k].cpu().numpy().copy() for k in rcr.SOLUTION_FIELDS})
+    for o in outs[1:]:
+        for k in rcr.SOLUTION_FIELDS:
+            np.testing.assert_array_equal(o[k], outs[0][k])
