@@ -91,6 +91,93 @@ def cpu_baseline(parent, data, seconds: float) -> dict:
                       f"({el:.1f} s)"}
 
 
+def bench_batch(args) -> dict:
+    """512 independent trees (N log-uniform in [256, 16384], p ~ U(0.8, 0.98), n = 8,
+    m = 3), MIXED32 with one refinement step: one merged launch sequence for the whole
+    batch against one solve per tree, both checked at KKT residual <= 1e-8."""
+    import numpy as np
+    import torch
+    from paper_2608_01332_amd import rcr
+    from paper_2608_01332_amd import workloads as w
+    dev = torch.device("cuda:0")
+    T = args.trees
+    pars, datas = [], []
+    for t in range(T):
+        p_, d_, spec = w.config_instance(3, tree=t)
+        pars.append(p_)
+        datas.append(d_)
+    n, m = spec.n, spec.m
+    plans = [rcr.Plan(p_, n, m) for p_ in pars]
+    t0 = time.perf_counter()
+    B = rcr.Plan.batch(plans)
+    merge_ms = (time.perf_counter() - t0) * 1e3
+    Ntot = B.N
+    big = rcr.to_device(rcr.concat_problems(datas), dev)
+    out = rcr.alloc_solution(B, dev)
+    stream = torch.cuda.current_stream(dev)
+    kw = dict(precision=rcr.MIXED32, refine_steps=1, executor=rcr.EXEC_GRAPH)
+    chk = rcr.solve(B, big, out=out, check=True, kkt_residual=True, **kw)
+    for _ in range(args.warmup):
+        rcr.solve(B, big, out=out, **kw)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        rcr.solve(B, big, out=out, stream=stream, **kw)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    batched_ms = e0.elapsed_time(e1) / args.steps
+    # one solve per tree, on views of the same device arrays
+    offs = B.offsets
+    views = []
+    worst = 0.0
+    for t, p_ in enumerate(plans):
+        lo, hi = int(offs[t]), int(offs[t + 1])
+        pv = {k: big[k][lo:hi] for k in rcr.PROBLEM_FIELDS}
+        ov = {k: out[k][lo:hi] for k in rcr.SOLUTION_FIELDS}
+        views.append((p_, pv, ov))
+        r = rcr.solve(p_, pv, out=ov, check=True, kkt_residual=True, **kw)
+        worst = max(worst, r["kkt_residual"])
+    for p_, pv, ov in views:
+        rcr.solve(p_, pv, out=ov, **kw)
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // 4)
+    e0.record(stream)
+    for _ in range(reps):
+        for p_, pv, ov in views:
+            rcr.solve(p_, pv, out=ov, stream=stream, **kw)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    separate_ms = e0.elapsed_time(e1) / reps
+    st = B.stats()
+    rec = {
+        "metric": "tree-LQR nodes/sec vs CPU Riccati at KKT res 1e-8; p50/p99 solve latency",
+        "value": Ntot / (batched_ms / 1e3), "unit": "nodes/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": batched_ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64-refine", "data": "synthetic",
+        "config": {"workload": f"{T} trees, N log-uniform [256,16384], p~U(0.8,0.98), n=8, m=3, MIXED32 + 1 "
+                               "refinement, one merged launch sequence", "trees": T, "nodes": int(Ntot),
+                   "levels": st["levels"], "height_max": st["height"]},
+        "kkt_residual_batched": chk["kkt_residual"], "kkt_residual_separate_max": worst,
+        "separate_ms_per_step": separate_ms, "separate_nodes_per_s": Ntot / (separate_ms / 1e3),
+        "batched_speedup": separate_ms / batched_ms, "merge_plan_ms": merge_ms,
+    }
+    if args.cpu_seconds > 0:
+        from oracle import riccati as orc
+        nth = min(16, os.cpu_count() or 1)
+        tt0 = time.perf_counter()
+        done, nodes = 0, 0
+        while time.perf_counter() - tt0 < args.cpu_seconds and done < T:
+            chunk = list(zip(pars[done:done + 32], datas[done:done + 32]))
+            orc.tree_riccati_batch(chunk, nth)
+            nodes += sum(len(p_) for p_, _ in chunk)
+            done += len(chunk)
+        el = time.perf_counter() - tt0
+        rec["cpu_baseline"] = {"value": nodes / el, "unit": "nodes/s", "cores": nth, "kind": "oracle",
+                               "sample": f"first {done} of the {T} trees ({nodes} nodes), FP64, {nth} threads, {el:.1f} s"}
+    return rec
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +187,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU oracle sample length; 0 skips it")
     ap.add_argument("--class-steps", type=int, default=5, help="steps of the per-launch event pass")
     ap.add_argument("--no-mixed", action="store_true", help="skip the MIXED32 + refinement leg")
+    ap.add_argument("--workload", choices=["single", "batch"], default="single",
+                    help="single: the 65,536-node tree (default); batch: the 512-tree batched workload")
+    ap.add_argument("--trees", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
@@ -114,6 +204,9 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
+    if args.workload == "batch":
+        print(json.dumps(bench_batch(args)), flush=True)
+        return 0
     dev = torch.device("cuda:0")
     parent, data, spec = w.config_instance(2)
     N, n, m = len(parent), spec.n, spec.m
@@ -158,10 +251,20 @@ def main() -> int:
             cls_n[k] = cls_n.get(k, 0) + r["kernel_launches"][k]
     reps = max(1, args.class_steps)
     words = algorithmic_words(st, n, m)
-    dom = max(words, key=lambda k: cls_ms.get(k, 0.0))
+    # The per-level quadratic contraction launches cover levels 1..k (k = their launch
+    # count); the narrow levels after them run in the tail kernel.  Its algorithmic
+    # bytes are those of the ops in its own levels.
+    ops = plan.export_ops()
+    k_q = cls_n.get("quad_contract", 0) // reps
+    sel = ops[ops[:, 2] <= k_q]
+    s_, per_kind = n * n, {0: 6, 1: 3, 2: 3, 3: 10}
+    words_q = sum(int((sel[:, 0] == kind).sum()) * mult * s_ for kind, mult in per_kind.items())
+    measured = dict(words)
+    measured["quad_contract"] = words_q
+    dom = max(measured, key=lambda k: cls_ms.get(k, 0.0))
     dom_ms = cls_ms[dom] / reps
     dom_launches = cls_n[dom] / reps
-    bytes_per_solve = words[dom] * 8
+    bytes_per_solve = measured[dom] * 8
     achieved = bytes_per_solve / (dom_ms / 1e3) / 1e9
     traffic = read_traffic(dom)
     total_words = sum(words.values())

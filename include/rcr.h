@@ -89,6 +89,7 @@ typedef struct {
   int64_t crew_ok;       /* 1 if every datum has one writer and is read only at a later level */
   int64_t workspace_bytes_fp64;  /* device scratch of one FP64 solve                    */
   int64_t workspace_bytes_mixed; /* device scratch of one MIXED32 solve                 */
+  int64_t n_trees;               /* 1, or the number of trees of a batched plan         */
 } rcr_plan_stats;
 
 /* Build the topology plan of Sec. VII from a HOST parent array (int64, N
@@ -118,6 +119,18 @@ int rcr_plan_info(const rcr_plan *plan, rcr_plan_stats *out);
 int rcr_plan_export(const rcr_plan *plan, int32_t *ops, int64_t capacity, int64_t *count);
 
 void rcr_plan_destroy(rcr_plan *plan);
+
+/* Batched plan of k independent trees (their forest), for solving many trees
+ * with one merged launch sequence.  The parts must share n and m; they are
+ * only read.  Tree t occupies nodes [off_t, off_t + N_t) of the batched
+ * problem, in part order (off_0 = 0), and edge slots likewise; per-node and
+ * per-edge arrays of rcr_solve are the concatenation of the trees' arrays.
+ * Dependency level t of the batch is the union of every tree's level t (the
+ * trees share no data, so each datum keeps a unique writer); the launch count
+ * is that of the deepest tree, not the sum over trees.  The batched plan is
+ * independent of the parts afterwards.  Errors: RCR_NULL_ARG, RCR_BAD_DIMS
+ * (different n or m, or too many slots), RCR_OOM. */
+int rcr_batch_plan_create(const rcr_plan *const *plans, int32_t k, rcr_plan **out);
 
 /* ------------------------------------------------------------------ solving */
 typedef struct {

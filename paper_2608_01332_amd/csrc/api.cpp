@@ -3,6 +3,7 @@
 
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "../../include/rcr.h"
 #include "device.hpp"
@@ -24,6 +25,30 @@ int rcr_plan_create(const int64_t *parent, int64_t N, int32_t n, int32_t m, cons
   int rc;
   try {
     rc = rcr::build_plan(parent, N, n, m, selection, p->obj.host);
+  } catch (const std::bad_alloc &) {
+    rc = RCR_OOM;
+  }
+  if (rc) {
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return RCR_OK;
+}
+
+int rcr_batch_plan_create(const rcr_plan *const *plans, int32_t k, rcr_plan **out) {
+  if (!plans || !out || k < 1) return RCR_NULL_ARG;
+  *out = nullptr;
+  std::vector<const rcr::PlanHost *> parts;
+  for (int32_t t = 0; t < k; ++t) {
+    if (!plans[t]) return RCR_NULL_ARG;
+    parts.push_back(&plans[t]->obj.host);
+  }
+  rcr_plan *p = new (std::nothrow) rcr_plan();
+  if (!p) return RCR_OOM;
+  int rc;
+  try {
+    rc = rcr::merge_plans(parts, p->obj.host);
   } catch (const std::bad_alloc &) {
     rc = RCR_OOM;
   }
@@ -59,6 +84,7 @@ int rcr_plan_info(const rcr_plan *plan, rcr_plan_stats *out) {
   out->crew_ok = h.crew_ok ? 1 : 0;
   out->workspace_bytes_fp64 = (int64_t)rcr::workspace_layout(h, RCR_FP64).total_bytes;
   out->workspace_bytes_mixed = (int64_t)rcr::workspace_layout(h, RCR_MIXED32).total_bytes;
+  out->n_trees = h.tree_off.empty() ? 1 : (int64_t)h.tree_off.size() - 1;
   return RCR_OK;
 }
 

@@ -212,7 +212,7 @@ __global__ __launch_bounds__(256) void k_residual_rhs(int64_t N, int n, int m, i
     }
     worst = fabs(s);
     double t = c[v * n + r] - x[v * n + r];
-    if (v == root) {
+    if (parent[v] < 0) {
       for (int k = 0; k < n; ++k) t -= De[v * nn + r * n + k] * y[v * n + k];
     } else {
       const int64_t i = parent[v];
@@ -227,8 +227,8 @@ __global__ __launch_bounds__(256) void k_residual_rhs(int64_t N, int n, int m, i
   }
   for (int cc = r; cc < m; cc += TEAM) {
     double t = 0.0;
-    if (v != root) {
-      const int64_t i = parent[v];
+    const int64_t i = parent[v];
+    if (i >= 0) {
       t = rr[v * m + cc];
       for (int k = 0; k < n; ++k) t += S[v * nm + k * m + cc] * x[i * n + k] + B[v * nm + k * m + cc] * y[v * n + k];
       for (int k = 0; k < m; ++k) t += R[v * m * m + cc * m + k] * u[v * m + k];

@@ -110,7 +110,7 @@ RCR_MAT_KERNEL(NB) void k_condense(Bufs<T> bf) {
     ld_row(q, bf.Q + v * nn, n, r);
     st_row(bf.U + v * nn, q, n, r, active);
   }
-  const bool edge = (v != bf.root);
+  const bool edge = (bf.parent[v] >= 0);
   // Cholesky of R (lane 0, sequential; R padded with the identity)
   if (r == 0) {
     for (int i = 0; i < MB; ++i)
@@ -368,7 +368,7 @@ RCR_MAT_KERNEL(NB) void k_local_factor(Bufs<T> bf) {
   const int64_t v = active ? v0 : bf.N - 1;
   const int n = bf.n, m = bf.m;
   const int64_t nn = (int64_t)n * n, nm = (int64_t)n * m;
-  const bool isroot = (v == bf.root);
+  const bool isroot = (bf.parent[v] < 0);
   const bool edge = active && !isroot;
   const int rr = r < NB ? r : NB - 1;
   T pv[NB], dv[NB];
@@ -568,7 +568,7 @@ __global__ __launch_bounds__(64) void k_rhs_init(Bufs<T> bf) {
   const int n = bf.n, m = bf.m;
   const int64_t nn = (int64_t)n * n;
   if (r < n) bf.h[v * n + r] = bf.sq[v * n + r];
-  if (v == bf.root) {
+  if (bf.parent[v] < 0) {
     if (r < n) bf.z[v * n + r] = (T)0;
     return;
   }
@@ -662,7 +662,7 @@ __global__ __launch_bounds__(64) void k_local_affine(Bufs<T> bf) {
   if (v >= bf.N) return;
   const int n = bf.n, m = bf.m;
   const int64_t nn = (int64_t)n * n, nm = (int64_t)n * m;
-  const bool isroot = (v == bf.root);
+  const bool isroot = (bf.parent[v] < 0);
   const T *pv = isroot ? bf.h + v * n : bf.p + v * n;
   T f = (T)0;
   if (r < n) {
@@ -784,8 +784,8 @@ __global__ __launch_bounds__(64) void k_recover(Bufs<T> bf) {
   }
   for (int c = r; c < m; c += TW) {
     T u = (T)0;
-    if (v != bf.root) {
-      const int64_t i = bf.parent[v];
+    const int64_t i = bf.parent[v];
+    if (i >= 0) {
       u = bf.kff[v * m + c];
 #pragma unroll
       for (int k = 0; k < NB; ++k)

@@ -432,6 +432,121 @@ int build_plan(const int64_t *parent, int64_t N, int n, int m, int selection, Pl
   return b.run(selection);
 }
 
+int merge_plans(const std::vector<const PlanHost *> &parts, PlanHost &out) {
+  if (parts.empty()) return RCR_NULL_ARG;
+  const int n = parts[0]->n, m = parts[0]->m;
+  out = PlanHost();
+  out.n = n;
+  out.m = m;
+  int64_t N = 0, C = 0, NC = 0;
+  int64_t L = 0, LE = 0, LT = 0, LX = 0;
+  for (const PlanHost *p : parts) {
+    if (!p) return RCR_NULL_ARG;
+    if (p->n != n || p->m != m) return RCR_BAD_DIMS;
+    N += p->N;
+    C += p->n_edge_slots - p->N;
+    NC += p->n_contrib;
+    L = std::max(L, p->levels());
+    LE = std::max(LE, p->expand_levels());
+    LT = std::max(LT, p->state_levels());
+    LX = std::max(LX, p->sexp_levels());
+  }
+  if (N + C > (int64_t)(INT32_MAX / 2 - 16) || NC > (int64_t)(INT32_MAX / 2 - 16)) return RCR_BAD_DIMS;
+  const size_t k = parts.size();
+  std::vector<int64_t> vb(k), ecb(k), cb(k);
+  {
+    int64_t a = 0, e = N, c = 0;
+    for (size_t t = 0; t < k; ++t) {
+      vb[t] = a;
+      ecb[t] = e;
+      cb[t] = c;
+      a += parts[t]->N;
+      e += parts[t]->n_edge_slots - parts[t]->N;
+      c += parts[t]->n_contrib;
+    }
+  }
+  out.N = N;
+  out.n_edge_slots = N + C;
+  out.n_contrib = NC;
+  out.root = parts[0]->root;
+  out.selection = parts[0]->selection;
+  out.crew_ok = true;
+  out.tree_off.resize(k + 1);
+  out.parent32.resize(N);
+  for (size_t t = 0; t < k; ++t) {
+    const PlanHost &p = *parts[t];
+    out.tree_off[t] = vb[t];
+    for (int64_t v = 0; v < p.N; ++v)
+      out.parent32[vb[t] + v] = p.parent32[v] < 0 ? -1 : (int32_t)(vb[t] + p.parent32[v]);
+    out.height = std::max(out.height, p.height);
+    out.leaves += p.leaves;
+    out.max_degree = std::max(out.max_degree, p.max_degree);
+    out.rounds = std::max(out.rounds, p.rounds);
+    out.n_rake += p.n_rake;
+    out.n_compress += p.n_compress;
+    out.n_combine += p.n_combine;
+    out.n_absorb += p.n_absorb;
+    out.crew_ok = out.crew_ok && p.crew_ok;
+  }
+  out.tree_off[k] = N;
+  auto node = [&](size_t t, int32_t v) { return (int32_t)(vb[t] + v); };
+  auto slot = [&](size_t t, int32_t s2) {
+    return (int32_t)(s2 < parts[t]->N ? vb[t] + s2 : ecb[t] + (s2 - parts[t]->N));
+  };
+  auto contrib = [&](size_t t, int32_t c) { return (int32_t)(cb[t] + c); };
+  // contraction: level-major, kind-minor, tree order within a (level, kind) group
+  out.lvl_off.assign(1, 0);
+  out.kind_off.resize((size_t)L * 5);
+  for (int64_t lv = 0; lv < L; ++lv) {
+    for (int kind = 0; kind < 4; ++kind) {
+      out.kind_off[(size_t)lv * 5 + kind] = (int64_t)out.ops.size();
+      for (size_t t = 0; t < k; ++t) {
+        const PlanHost &p = *parts[t];
+        if (lv >= p.levels()) continue;
+        for (int64_t i = p.kind_off[(size_t)lv * 5 + kind]; i < p.kind_off[(size_t)lv * 5 + kind + 1]; ++i) {
+          OpRec o = p.ops[i];
+          switch (o.kind) {
+            case OP_RAKE: o.a = node(t, o.a); o.b = slot(t, o.b); o.c = contrib(t, o.c); o.d = node(t, o.d); break;
+            case OP_COMBINE: o.a = contrib(t, o.a); o.b = contrib(t, o.b); o.c = contrib(t, o.c); o.d = node(t, o.d); break;
+            case OP_ABSORB: o.a = node(t, o.a); o.b = contrib(t, o.b); break;
+            default: o.a = node(t, o.a); o.b = slot(t, o.b); o.c = slot(t, o.c); o.d = slot(t, o.d); o.e = node(t, o.e);
+          }
+          out.ops.push_back(o);
+        }
+      }
+    }
+    out.kind_off[(size_t)lv * 5 + 4] = (int64_t)out.ops.size();
+    out.lvl_off.push_back((int64_t)out.ops.size());
+  }
+  auto merge4 = [&](int64_t levels, const std::vector<Op4> PlanHost::*ops, const std::vector<int64_t> PlanHost::*off,
+                    std::vector<Op4> &dst, std::vector<int64_t> &doff, int kind) {
+    doff.assign(1, 0);
+    for (int64_t lv = 0; lv < levels; ++lv) {
+      for (size_t t = 0; t < k; ++t) {
+        const PlanHost &p = *parts[t];
+        const std::vector<int64_t> &po = p.*off;
+        if (lv + 1 >= (int64_t)po.size()) continue;
+        for (int64_t i = po[lv]; i < po[lv + 1]; ++i) {
+          Op4 q = (p.*ops)[i];
+          if (kind == 0) {         // expansion {j, r slot, k}
+            q.a = node(t, q.a); q.b = slot(t, q.b); q.c = node(t, q.c);
+          } else if (kind == 1) {  // composition {l slot, r slot, new slot, j}
+            q.a = slot(t, q.a); q.b = slot(t, q.b); q.c = slot(t, q.c); q.d = node(t, q.d);
+          } else {                 // state expansion {j, slot, parent}
+            q.a = node(t, q.a); q.b = slot(t, q.b); q.c = node(t, q.c);
+          }
+          dst.push_back(q);
+        }
+      }
+      doff.push_back((int64_t)dst.size());
+    }
+  };
+  merge4(LE, &PlanHost::exp_ops, &PlanHost::exp_off, out.exp_ops, out.exp_off, 0);
+  merge4(LT, &PlanHost::tc_ops, &PlanHost::tc_off, out.tc_ops, out.tc_off, 1);
+  merge4(LX, &PlanHost::sx_ops, &PlanHost::sx_off, out.sx_ops, out.sx_off, 2);
+  return RCR_OK;
+}
+
 int64_t depth_bound(int64_t N) {
   if (N <= 1) return 0;
   // floor(log2((2N - 1) * 36^R)), R = ceil(log_{3/2} N), via exact logs of integers:

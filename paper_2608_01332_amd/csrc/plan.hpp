@@ -61,6 +61,10 @@ struct PlanHost {
 
   std::vector<int32_t> parent32;  // original parent array (root: -1)
 
+  // batched plans: a forest of independent trees; tree t owns nodes
+  // [tree_off[t], tree_off[t + 1])
+  std::vector<int64_t> tree_off;
+
   int64_t levels() const { return (int64_t)lvl_off.size() - 1; }
   int64_t expand_levels() const { return (int64_t)exp_off.size() - 1; }
   int64_t state_levels() const { return (int64_t)tc_off.size() - 1; }
@@ -69,6 +73,12 @@ struct PlanHost {
 
 // Returns 0 or a negative RCR_* status.
 int build_plan(const int64_t *parent, int64_t N, int n, int m, int selection, PlanHost &out);
+
+// Merge the plans of independent trees into one plan of their forest: node,
+// edge and contribution slots are offset per tree, and dependency level t of
+// the merged plan is the union of every tree's level t (trees are disjoint, so
+// the union keeps a unique writer per datum).  Returns 0 or a negative RCR_* status.
+int merge_plans(const std::vector<const PlanHost *> &parts, PlanHost &out);
 
 // D_N of Lemma 4 (eq. (dependency-level-bound)).
 int64_t depth_bound(int64_t N);

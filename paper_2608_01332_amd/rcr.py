@@ -40,7 +40,8 @@ class PlanStats(ctypes.Structure):
                 ("state_levels", ctypes.c_int64), ("sexp_levels", ctypes.c_int64),
                 ("n_rake", ctypes.c_int64), ("n_compress", ctypes.c_int64), ("n_combine", ctypes.c_int64),
                 ("n_absorb", ctypes.c_int64), ("depth_bound", ctypes.c_int64), ("crew_ok", ctypes.c_int64),
-                ("workspace_bytes_fp64", ctypes.c_int64), ("workspace_bytes_mixed", ctypes.c_int64)]
+                ("workspace_bytes_fp64", ctypes.c_int64), ("workspace_bytes_mixed", ctypes.c_int64),
+                ("n_trees", ctypes.c_int64)]
 
 
 class Problem(ctypes.Structure):
@@ -58,8 +59,8 @@ class SolveOptions(ctypes.Structure):
                 ("kernel_launches", ctypes.POINTER(ctypes.c_int32)), ("reserved", ctypes.c_int32 * 4)]
 
 
-EXPORTED = ("rcr_plan_create", "rcr_plan_info", "rcr_plan_export", "rcr_plan_destroy", "rcr_workspace_size",
-            "rcr_solve", "rcr_status_string")
+EXPORTED = ("rcr_plan_create", "rcr_plan_info", "rcr_plan_export", "rcr_plan_destroy", "rcr_batch_plan_create",
+            "rcr_workspace_size", "rcr_solve", "rcr_status_string")
 
 _lib = None
 _lock = threading.Lock()
@@ -88,6 +89,9 @@ def lib():
             L.rcr_plan_export.argtypes = [ctypes.c_void_p, _i32p, ctypes.c_int64, _i64p]
             L.rcr_plan_destroy.restype = None
             L.rcr_plan_destroy.argtypes = [ctypes.c_void_p]
+            L.rcr_batch_plan_create.restype = ctypes.c_int
+            L.rcr_batch_plan_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                                ctypes.POINTER(ctypes.c_void_p)]
             L.rcr_workspace_size.restype = ctypes.c_int64
             L.rcr_workspace_size.argtypes = [ctypes.c_void_p, ctypes.c_int32]
             L.rcr_solve.restype = ctypes.c_int
@@ -105,6 +109,26 @@ def status_string(s: int) -> str:
 
 class Plan:
     """Reusable topology plan (rcr_plan_create).  Host-only; no GPU needed."""
+
+    @classmethod
+    def batch(cls, plans) -> "Plan":
+        """Batched plan of independent trees (rcr_batch_plan_create); tree t owns the
+        nodes [offsets[t], offsets[t + 1]) of the concatenated problem."""
+        L = lib()
+        k = len(plans)
+        arr = (ctypes.c_void_p * k)(*[p._h.value for p in plans])
+        h = ctypes.c_void_p()
+        rc = L.rcr_batch_plan_create(arr, k, ctypes.byref(h))
+        if rc != 0:
+            raise RcrError(rc, "rcr_batch_plan_create")
+        self = cls.__new__(cls)
+        self._h = h
+        self.N = int(sum(p.N for p in plans))
+        self.n, self.m = plans[0].n, plans[0].m
+        self.offsets = np.cumsum([0] + [p.N for p in plans]).astype(np.int64)
+        self._parent = np.concatenate([np.where(p._parent >= 0, p._parent + o, -1)
+                                       for p, o in zip(plans, self.offsets[:-1])])
+        return self
 
     def __init__(self, parent, n: int, m: int, selection: int = SELECT_GREEDY_INDEX):
         L = lib()
@@ -215,6 +239,12 @@ def solve(plan: Plan, prob: dict, out: dict | None = None, precision: int = FP64
         result["kernel_ms"] = {KERNEL_CLASSES[i]: float(kms[i]) for i in range(NUM_KERNEL_CLASSES)}
         result["kernel_launches"] = {KERNEL_CLASSES[i]: int(kln[i]) for i in range(NUM_KERNEL_CLASSES)}
     return result
+
+
+def concat_problems(datas) -> dict:
+    """Concatenate host problems of independent trees in the node order of a
+    batched plan (Plan.batch)."""
+    return {k: np.concatenate([np.ascontiguousarray(d[k]) for d in datas], axis=0) for k in PROBLEM_FIELDS}
 
 
 def to_device(data: dict, device="cuda") -> dict:

@@ -168,3 +168,46 @@ def test_workspace_size_scales_linearly():
     rb = b.workspace_size(rcr.FP64) / 4000
     assert 0.7 < ra / rb < 1.4
     assert a.workspace_size(rcr.MIXED32) < a.workspace_size(rcr.FP64) * 1.2
+
+
+def test_batched_plan_is_union_of_remapped_trees():
+    """rcr_batch_plan_create: level t of the forest plan is the union of every tree's
+    level t with node/edge/contribution slots offset per tree."""
+    rng = np.random.default_rng(31)
+    pars = [w.tree_chainprob(int(rng.integers(1, 300)), float(rng.uniform(0.5, 0.98)), rng) for _ in range(7)]
+    plans = [rcr.Plan(p, 4, 2) for p in pars]
+    B = rcr.Plan.batch(plans)
+    st = B.stats()
+    sts = [p.stats() for p in plans]
+    assert st["n_trees"] == 7 and st["N"] == sum(len(p) for p in pars)
+    assert st["levels"] == max(s["levels"] for s in sts)
+    for k in ("n_rake", "n_compress", "n_combine", "n_absorb"):
+        assert st[k] == sum(s[k] for s in sts)
+    N = st["N"]
+    vb = B.offsets
+    extra = np.cumsum([0] + [s["n_compress"] for s in sts])
+    cb = np.cumsum([0] + [s["n_rake"] + s["n_combine"] for s in sts])
+    want = set()
+    for t, p in enumerate(plans):
+        Nt = len(pars[t])
+        node = lambda v: int(vb[t] + v)
+        slot = lambda s_: int(vb[t] + s_) if s_ < Nt else int(N + extra[t] + s_ - Nt)
+        con = lambda c: int(cb[t] + c)
+        for kind, rnd, lvl, a, b, c, d, e in p.export_ops().tolist():
+            if kind == RAKE:
+                want.add((kind, lvl, node(a), slot(b), con(c), node(d), 0))
+            elif kind == COMBINE:
+                want.add((kind, lvl, con(a), con(b), con(c), node(d), 0))
+            elif kind == ABSORB:
+                want.add((kind, lvl, node(a), con(b), 0, 0, 0))
+            else:
+                want.add((kind, lvl, node(a), slot(b), slot(c), slot(d), node(e)))
+    got = set()
+    for kind, rnd, lvl, a, b, c, d, e in B.export_ops().tolist():
+        if kind == ABSORB:
+            got.add((kind, lvl, a, b, 0, 0, 0))
+        elif kind in (RAKE, COMBINE):
+            got.add((kind, lvl, a, b, c, d, 0))
+        else:
+            got.add((kind, lvl, a, b, c, d, e))
+    assert got == want
