@@ -178,6 +178,57 @@ def bench_batch(args) -> dict:
     return rec
 
 
+def bench_extreme(args) -> dict:
+    """Shape-extreme trees at N = 1,048,576 (n = 6, m = 2, FP64): one plan per tree
+    reused across 8 re-solves with fresh cost/dynamics data (copied to the device
+    outside the timed region)."""
+    import numpy as np
+    import torch
+    from paper_2608_01332_amd import rcr
+    from paper_2608_01332_amd import workloads as w
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    res = {}
+    for ti, kind in enumerate(["caterpillar", "star_heavy", "chainprob"]):
+        par = w.shape_extreme(kind)
+        t0 = time.perf_counter()
+        plan = rcr.Plan(par, 6, 2)
+        plan_ms = (time.perf_counter() - t0) * 1e3
+        prob, out, times, kkt = None, None, [], 0.0
+        for s_ in range(args.resolves):
+            d = w.lqr_data(par, w.DataSpec(6, 2), np.random.default_rng(w.config_seed(4, s_, ti)))
+            if prob is None:
+                prob = rcr.to_device(d, dev)
+                out = rcr.alloc_solution(plan, dev)
+                rcr.solve(plan, prob, out=out, executor=rcr.EXEC_GRAPH)  # graph capture (untimed)
+            else:
+                for k in rcr.PROBLEM_FIELDS:
+                    prob[k].copy_(torch.from_numpy(d[k]))
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            rcr.solve(plan, prob, out=out, executor=rcr.EXEC_GRAPH, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+            r = rcr.solve(plan, prob, out=out, executor=rcr.EXEC_GRAPH, kkt_residual=True)
+            kkt = max(kkt, r["kkt_residual"])
+        st = plan.stats()
+        res[kind] = {"nodes_per_s": len(par) / (float(np.median(times)) / 1e3), "median_ms": float(np.median(times)),
+                     "max_ms": float(np.max(times)), "resolves": args.resolves, "kkt_residual_max": kkt,
+                     "plan_ms": plan_ms, "height": st["height"], "levels": st["levels"], "rounds": st["rounds"]}
+        del prob, out
+        torch.cuda.empty_cache()
+    tot_ms = sum(v["median_ms"] for v in res.values())
+    return {"metric": "tree-LQR nodes/sec vs CPU Riccati at KKT res 1e-8; p50/p99 solve latency",
+            "value": 3 * 1048576 / (tot_ms / 1e3), "unit": "nodes/s", "n_gpus": 1, "steps": args.resolves,
+            "warmup": 1, "ms_per_step": tot_ms / 3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "shape-extreme trees N=1,048,576 (caterpillar, star-heavy, chain-prob 0.9), "
+                                   "n=6, m=2, FP64, plan reused across re-solves"},
+            "trees": res}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,8 +238,10 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU oracle sample length; 0 skips it")
     ap.add_argument("--class-steps", type=int, default=5, help="steps of the per-launch event pass")
     ap.add_argument("--no-mixed", action="store_true", help="skip the MIXED32 + refinement leg")
-    ap.add_argument("--workload", choices=["single", "batch"], default="single",
-                    help="single: the 65,536-node tree (default); batch: the 512-tree batched workload")
+    ap.add_argument("--workload", choices=["single", "batch", "extreme"], default="single",
+                    help="single: the 65,536-node tree (default); batch: the 512-tree batched workload; "
+                         "extreme: the 1M-node shape-extreme trees")
+    ap.add_argument("--resolves", type=int, default=8)
     ap.add_argument("--trees", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -206,6 +259,9 @@ def main() -> int:
         return 1
     if args.workload == "batch":
         print(json.dumps(bench_batch(args)), flush=True)
+        return 0
+    if args.workload == "extreme":
+        print(json.dumps(bench_extreme(args)), flush=True)
         return 0
     dev = torch.device("cuda:0")
     parent, data, spec = w.config_instance(2)
