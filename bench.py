@@ -54,10 +54,44 @@ def algorithmic_words(st: dict, n: int, m: int) -> dict:
     }
 
 
+def kernel_source_sha() -> str:
+    """Digest of every HIP/C++ source of the solver library (a traffic figure is
+    only reported for the kernels it was measured on)."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2608_01332_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def bench_copy(args) -> dict:
+    """Plain device-to-device copy of a known size: the calibration kernel for
+    the FETCH_SIZE / WRITE_SIZE counters, and the achievable HBM copy rate."""
+    import torch
+    nbytes = args.copy_mib << 20
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").normal_()
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"workload": "copy", "bytes_read_per_launch": nbytes, "bytes_written_per_launch": nbytes,
+            "launches": reps + 3, "ms_per_copy": ms, "copy_GBps": 2 * nbytes / (ms / 1e3) / 1e9}
+
+
 def read_traffic(kernel_class: str):
     """HBM traffic per launch from the committed rocprofv3 PMC summary, if it was
     taken on the current kernel source (else None)."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel_class}.txt")
     if not os.path.exists(path):
         return None
@@ -66,9 +100,7 @@ def read_traffic(kernel_class: str):
         if "=" in line and not line.lstrip().startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_2608_01332_amd", "csrc", "device.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if kv.get("source_sha") != sha:
+    if kv.get("source_sha") != kernel_source_sha():
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -238,9 +270,10 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU oracle sample length; 0 skips it")
     ap.add_argument("--class-steps", type=int, default=5, help="steps of the per-launch event pass")
     ap.add_argument("--no-mixed", action="store_true", help="skip the MIXED32 + refinement leg")
-    ap.add_argument("--workload", choices=["single", "batch", "extreme"], default="single",
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--workload", choices=["single", "batch", "extreme", "copy"], default="single",
                     help="single: the 65,536-node tree (default); batch: the 512-tree batched workload; "
-                         "extreme: the 1M-node shape-extreme trees")
+                         "extreme: the 1M-node shape-extreme trees; copy: plain HBM copy (counter calibration)")
     ap.add_argument("--resolves", type=int, default=8)
     ap.add_argument("--trees", type=int, default=512)
     args = ap.parse_args()
@@ -262,6 +295,9 @@ def main() -> int:
         return 0
     if args.workload == "extreme":
         print(json.dumps(bench_extreme(args)), flush=True)
+        return 0
+    if args.workload == "copy":
+        print(json.dumps(bench_copy(args)), flush=True)
         return 0
     dev = torch.device("cuda:0")
     parent, data, spec = w.config_instance(2)
