@@ -261,6 +261,135 @@ def bench_extreme(args) -> dict:
             "trees": res}
 
 
+def _serve_pool(specs, dev):
+    """Device data blocks of every (n, m, variant) class a request stream uses."""
+    import torch
+    from paper_2608_01332_amd import rcr
+    from paper_2608_01332_amd import workloads as w
+    need = {}
+    for e in specs:
+        key = (e["n"], e["m"], e["variant"])
+        need[key] = max(need.get(key, 0), e["N"])
+    pool = {}
+    for (n, m, var), Nmax in sorted(need.items()):
+        d = w.serve_data_block(Nmax, n, m, var, seed=w.config_seed(5))
+        pool[(n, m, var)] = {k: torch.from_numpy(d[k]).to(dev) for k in rcr.PROBLEM_FIELDS}
+    return pool
+
+
+def run_serving(specs, pars, pool, dev, slots: int, batching: bool, budget: int, planner_threads: int,
+                sample_every: int = 0):
+    """Drive a Server with the stream's arrival times in real time; returns the
+    completed requests (outputs kept only for every sample_every-th) and the
+    wall time from the first arrival to the last completion."""
+    import torch
+    from paper_2608_01332_amd import serve
+    srv = serve.Server(dev, slots=slots, batching=batching, hbm_budget=budget, planner_threads=planner_threads)
+    # the planner and preparation threads run C code between short Python steps:
+    # hand them the interpreter lock promptly
+    old_switch = sys.getswitchinterval()
+    sys.setswitchinterval(2e-4)
+    reqs = [serve.Request(rid=e["rid"], parent=pars[e["topo"]], n=e["n"], m=e["m"],
+                          prob={k: v[:e["N"]] for k, v in pool[(e["n"], e["m"], e["variant"])].items()},
+                          topo=e["topo"]) for e in specs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    i, done, seen = 0, 0, 0
+    while done < len(reqs):
+        now = time.perf_counter() - t0
+        while i < len(reqs) and specs[i]["arrival"] <= now:
+            reqs[i].arrival = t0 + specs[i]["arrival"]
+            srv.submit(reqs[i])
+            i += 1
+        done += srv.poll()
+        time.sleep(0)
+        while seen < len(srv.done):
+            r = srv.done[seen]
+            if not sample_every or r.rid % sample_every:
+                r.out = {}
+            seen += 1
+    wall = max(r.t_done for r in reqs) - t0
+    groups = srv.groups
+    stats = dict(srv.stats)
+    srv.close()
+    sys.setswitchinterval(old_switch)
+    return reqs, wall, groups, stats
+
+
+def bench_serve(args) -> dict:
+    """Serving stream: Poisson arrivals (rates swept) of tree-LQR solves with N
+    log-uniform in [1k, 128k], n in {4, 8, 12, 16}, m in {2, 4}, p ~ U(0.85, 0.97),
+    MIXED32 + one refinement step, 30% of requests resending an earlier topology
+    with new data; admitted by HBM footprint into 4 stream slots with continuous
+    batching.  Latency from arrival to completion, planning of cache misses
+    included; the request data is resident in HBM when it arrives."""
+    import numpy as np
+    import torch
+    from paper_2608_01332_amd import rcr
+    from paper_2608_01332_amd import workloads as w
+    dev = torch.device("cuda:0")
+    rates = [float(x) for x in args.rates.split(",")]
+    streams = []
+    for ri, rate in enumerate(rates):
+        count = args.requests if args.requests else (10000 if rate >= 500 else int(rate * 20))
+        specs = w.serve_requests(count, rate, seed=w.config_seed(5, 0, ri))
+        streams.append((rate, specs))
+    t_gen = time.perf_counter()
+    pool = _serve_pool([e for _, sp in streams for e in sp], dev)
+    print(f"[serve] data pool {len(pool)} blocks in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    budget = args.hbm_budget_gib << 30
+    rows = []
+    for ri, (rate, specs) in enumerate(streams):
+        pars = {}
+        for e in specs:
+            if e["topo"] not in pars:
+                pars[e["topo"]] = w.serve_tree(e)
+        modes = [("continuous", 4, True)] + ([("fifo", 1, False)] if rate in args.fifo_rates else [])
+        for mode, slots, batching in modes:
+            sample = 97 if mode == "continuous" else 0
+            reqs, wall, groups, hstats = run_serving(specs, pars, pool, dev, slots, batching, budget,
+                                                     args.planner_threads, sample_every=sample)
+            lat = np.array([(r.t_done - r.arrival) * 1e3 for r in reqs])
+            nodes = sum(r.N for r in reqs)
+            row = {"rate_per_s": rate, "mode": mode, "slots": slots, "requests": len(reqs),
+                   "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                   "mean_ms": float(lat.mean()), "nodes_per_s": nodes / wall, "solves_per_s": len(reqs) / wall,
+                   "groups": groups, "mean_group": len(reqs) / max(groups, 1),
+                   "plan_cache_hits": float(np.mean([r.cache_hit for r in reqs])),
+                   "host_s": {k: round(v, 3) for k, v in hstats.items()}, "wall_s": wall}
+            if sample:
+                # each sampled result against the same request solved alone
+                worst_diff, worst_kkt = 0.0, 0.0
+                for r in reqs:
+                    if not r.out:
+                        continue
+                    plan = rcr.Plan(r.parent, r.n, r.m)
+                    alone = rcr.solve(plan, r.prob, precision=rcr.MIXED32, refine_steps=1, kkt_residual=True)
+                    for k in rcr.SOLUTION_FIELDS:
+                        worst_diff = max(worst_diff, float((alone[k] - r.out[k]).abs().max()))
+                    worst_kkt = max(worst_kkt, alone["kkt_residual"])
+                    r.out = {}
+                row["sampled"] = sum(1 for r in reqs if r.rid % sample == 0)
+                row["max_abs_diff_alone_vs_mix"] = worst_diff
+                row["max_kkt_residual"] = worst_kkt
+            rows.append(row)
+            print(f"[serve] {json.dumps(row)}", file=sys.stderr, flush=True)
+            del reqs
+            torch.cuda.empty_cache()
+    cont = [r for r in rows if r["mode"] == "continuous"]
+    best = max(cont, key=lambda r: r["nodes_per_s"])
+    return {"metric": "tree-LQR nodes/sec vs CPU Riccati at KKT res 1e-8; p50/p99 solve latency",
+            "value": best["nodes_per_s"], "unit": "nodes/s", "n_gpus": 1, "steps": sum(r["requests"] for r in cont),
+            "warmup": 0, "ms_per_step": best["mean_ms"], "p50_ms": best["p50_ms"], "p99_ms": best["p99_ms"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64-refine",
+            "data": "synthetic",
+            "config": {"workload": "serving: Poisson arrivals, N log-uniform [1k,128k], n in {4,8,12,16}, m in {2,4}, "
+                                   "p ~ U(0.85,0.97), MIXED32 + 1 refinement, 30% plan reuse, 4 slots, "
+                                   "continuous batching, HBM-footprint admission",
+                       "hbm_budget_gib": args.hbm_budget_gib},
+            "rates": rows}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,9 +400,16 @@ def main() -> int:
     ap.add_argument("--class-steps", type=int, default=5, help="steps of the per-launch event pass")
     ap.add_argument("--no-mixed", action="store_true", help="skip the MIXED32 + refinement leg")
     ap.add_argument("--copy-mib", type=int, default=1024)
-    ap.add_argument("--workload", choices=["single", "batch", "extreme", "copy"], default="single",
+    ap.add_argument("--rates", default="100,200,500,1000,2000,5000")
+    ap.add_argument("--requests", type=int, default=0, help="requests per rate (0: 10k, or 20 s of arrivals below 500/s)")
+    ap.add_argument("--fifo-rates", type=lambda s: [float(x) for x in s.split(",") if x], default=[100.0, 500.0, 2000.0],
+                    help="rates at which the one-slot FIFO queue (no batching) is also measured")
+    ap.add_argument("--hbm-budget-gib", type=int, default=96)
+    ap.add_argument("--planner-threads", type=int, default=12)
+    ap.add_argument("--workload", choices=["single", "batch", "extreme", "copy", "serve"], default="single",
                     help="single: the 65,536-node tree (default); batch: the 512-tree batched workload; "
-                         "extreme: the 1M-node shape-extreme trees; copy: plain HBM copy (counter calibration)")
+                         "extreme: the 1M-node shape-extreme trees; copy: plain HBM copy (counter calibration); "
+                         "serve: the request stream at swept arrival rates")
     ap.add_argument("--resolves", type=int, default=8)
     ap.add_argument("--trees", type=int, default=512)
     args = ap.parse_args()
@@ -298,6 +434,9 @@ def main() -> int:
         return 0
     if args.workload == "copy":
         print(json.dumps(bench_copy(args)), flush=True)
+        return 0
+    if args.workload == "serve":
+        print(json.dumps(bench_serve(args)), flush=True)
         return 0
     dev = torch.device("cuda:0")
     parent, data, spec = w.config_instance(2)

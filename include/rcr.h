@@ -32,9 +32,11 @@
  *    Definition 1 (R_e > 0, Delta_i >= 0, Q_i - sum_out M R^-1 M^T >= 0); the
  *    solver only reports pivot breakdowns it meets (RCR_SINGULAR, RCR_NOT_PD).
  *  - Return value: 0 on success, a negative RCR_* status otherwise.
- *    rcr_status_string() names it.  Calls are thread-safe for distinct plans;
- *    concurrent rcr_solve calls that share a plan and its cached workspace
- *    race unless each passes its own workspace.
+ *    rcr_status_string() names it.  Calls are thread-safe.  One plan may
+ *    serve concurrent solves on different streams when each passes its own
+ *    workspace (the workspace also holds that solve's status words and
+ *    residual accumulator); solves that share the plan-owned workspace must
+ *    be ordered by the caller.
  */
 #ifndef RCR_H
 #define RCR_H
@@ -118,6 +120,10 @@ int rcr_plan_info(const rcr_plan *plan, rcr_plan_stats *out);
  * Errors: RCR_NULL_ARG, RCR_SMALL_WORKSPACE (capacity < count). */
 int rcr_plan_export(const rcr_plan *plan, int32_t *ops, int64_t capacity, int64_t *count);
 
+/* Release a plan.  Its device memory is returned in stream order after the
+ * latest rcr_solve that used it has completed; the host is not blocked.  The
+ * caller must not destroy a plan while a solve issued before that latest one,
+ * on another stream, is still running.  NULL is ignored. */
 void rcr_plan_destroy(rcr_plan *plan);
 
 /* Batched plan of k independent trees (their forest), for solving many trees
@@ -131,6 +137,14 @@ void rcr_plan_destroy(rcr_plan *plan);
  * independent of the parts afterwards.  Errors: RCR_NULL_ARG, RCR_BAD_DIMS
  * (different n or m, or too many slots), RCR_OOM. */
 int rcr_batch_plan_create(const rcr_plan *const *plans, int32_t k, rcr_plan **out);
+
+/* Make the plan's device copy now (on the current device, in the order of
+ * `stream`, a hipStream_t or NULL), instead of at its first rcr_solve; waits
+ * for the copy.  A no-op when the copy exists.  Lets a caller move the
+ * host-to-device transfer of a fresh plan off its critical path (e.g. into a
+ * worker thread).  Errors: RCR_NULL_ARG, RCR_OOM, RCR_HIP_ERROR,
+ * RCR_NO_DEVICE. */
+int rcr_plan_upload(const rcr_plan *plan, void *stream);
 
 /* ------------------------------------------------------------------ solving */
 typedef struct {
@@ -185,13 +199,17 @@ typedef struct {
 #define RCR_K_STATE_TAIL 15 /* narrow state levels                                          */
 #define RCR_NUM_KERNEL_CLASSES 16
 
-/* Device scratch one rcr_solve needs for this plan and precision. */
+/* Device scratch one rcr_solve needs for this plan and precision (including
+ * a 512-byte header for the solve's status words and residual).  This is the
+ * request's HBM footprint beyond its inputs and outputs. */
 int64_t rcr_workspace_size(const rcr_plan *plan, int32_t precision);
 
 /* Factor and solve one tree-LQR instance (Algorithm 1, Steps 2-6) on
  * `stream` (a hipStream_t; NULL = the default stream).  Asynchronous and
  * stream-ordered unless options request a synchronisation.  opt may be NULL
- * (FP64, per-level executor, no check).  Errors: RCR_NULL_ARG, RCR_BAD_OPTION,
+ * (FP64, per-level executor, no check).  The first solve of a plan copies its
+ * integer arrays to the device in the order of `stream` and waits for that
+ * copy, so it must not be issued while `stream` is being captured.  Errors: RCR_NULL_ARG, RCR_BAD_OPTION,
  * RCR_SMALL_WORKSPACE, RCR_OOM, RCR_HIP_ERROR, RCR_NO_DEVICE and, when
  * opt->check is set, RCR_SINGULAR, RCR_NOT_PD, RCR_NONFINITE. */
 int rcr_solve(const rcr_plan *plan, const rcr_problem *in, rcr_solution *out,

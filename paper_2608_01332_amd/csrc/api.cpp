@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -58,6 +59,15 @@ int rcr_batch_plan_create(const rcr_plan *const *plans, int32_t k, rcr_plan **ou
   }
   *out = p;
   return RCR_OK;
+}
+
+int rcr_plan_upload(const rcr_plan *plan, void *stream) {
+  if (!plan) return RCR_NULL_ARG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return RCR_NO_DEVICE;
+  rcr_plan *pl = const_cast<rcr_plan *>(plan);
+  std::lock_guard<std::mutex> lock(pl->obj.mu);
+  return rcr::plan_upload(pl->obj, (hipStream_t)stream);
 }
 
 int rcr_plan_info(const rcr_plan *plan, rcr_plan_stats *out) {

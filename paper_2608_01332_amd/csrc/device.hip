@@ -49,7 +49,7 @@ WsLayout workspace_layout(const PlanHost &ph, int precision) {
   const size_t S = (size_t)ph.n_edge_slots, NC = (size_t)std::max<int64_t>(ph.n_contrib, 1);
   const size_t es = precision == RCR_FP64 ? 8 : 4;
   WsLayout L;
-  size_t cur = 0;
+  size_t cur = WS_HEADER_BYTES;  // per-solve status words and residual accumulator
   auto take = [&](size_t elems) {
     size_t at = cur;
     cur = align_up(cur + elems * es, 256);
@@ -88,27 +88,18 @@ WsLayout workspace_layout(const PlanHost &ph, int precision) {
   return L;
 }
 
+static inline int *ws_status(void *ws) { return reinterpret_cast<int *>(ws); }
+static inline double *ws_resid(void *ws) { return reinterpret_cast<double *>(static_cast<char *>(ws) + 256); }
 
-
-int plan_upload(PlanObj &P) {
-  if (P.dev.ops) return RCR_OK;
+// The plan's integer arrays live in one device allocation, made and filled in
+// the order of `st` and released in stream order after the last solve that
+// used them (no device-wide synchronisation on destroy).
+int plan_upload(PlanObj &P, hipStream_t st) {
+  if (P.dev.base) return RCR_OK;
   const PlanHost &h = P.host;
   int dev = 0;
   HIPCK(hipGetDevice(&dev));
   P.dev.device = dev;
-  auto up = [&](void **dst, const void *src, size_t bytes) -> int {
-    size_t b = std::max<size_t>(bytes, 16);
-    if (hipMalloc(dst, b) != hipSuccess) return RCR_OOM;
-    P.dev.bytes += b;
-    if (bytes && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return RCR_HIP_ERROR;
-    return RCR_OK;
-  };
-  int rc;
-  if ((rc = up((void **)&P.dev.ops, h.ops.data(), h.ops.size() * sizeof(OpRec)))) return rc;
-  if ((rc = up((void **)&P.dev.exp_ops, h.exp_ops.data(), h.exp_ops.size() * sizeof(Op4)))) return rc;
-  if ((rc = up((void **)&P.dev.tc_ops, h.tc_ops.data(), h.tc_ops.size() * sizeof(Op4)))) return rc;
-  if ((rc = up((void **)&P.dev.sx_ops, h.sx_ops.data(), h.sx_ops.size() * sizeof(Op4)))) return rc;
-  if ((rc = up((void **)&P.dev.parent, h.parent32.data(), h.parent32.size() * sizeof(int32_t)))) return rc;
   std::vector<int32_t> coff(h.N + 1, 0), cidx(std::max<int64_t>(h.N, 1), 0);
   for (int64_t j = 0; j < h.N; ++j)
     if (h.parent32[j] >= 0) coff[h.parent32[j] + 1]++;
@@ -118,16 +109,44 @@ int plan_upload(PlanObj &P) {
     for (int64_t j = 0; j < h.N; ++j)
       if (h.parent32[j] >= 0) cidx[fill[h.parent32[j]]++] = (int32_t)j;
   }
-  if ((rc = up((void **)&P.dev.child_off, coff.data(), coff.size() * sizeof(int32_t)))) return rc;
-  if ((rc = up((void **)&P.dev.koff, h.kind_off.data(), h.kind_off.size() * sizeof(int64_t)))) return rc;
-  if ((rc = up((void **)&P.dev.exp_off, h.exp_off.data(), h.exp_off.size() * sizeof(int64_t)))) return rc;
-  if ((rc = up((void **)&P.dev.tc_off, h.tc_off.data(), h.tc_off.size() * sizeof(int64_t)))) return rc;
-  if ((rc = up((void **)&P.dev.sx_off, h.sx_off.data(), h.sx_off.size() * sizeof(int64_t)))) return rc;
-  if ((rc = up((void **)&P.dev.child_idx, cidx.data(), cidx.size() * sizeof(int32_t)))) return rc;
-  if (hipMalloc((void **)&P.status, 256) != hipSuccess) return RCR_OOM;
-  if (hipMalloc((void **)&P.resid, 256) != hipSuccess) return RCR_OOM;
-  HIPCK(hipMemset(P.status, 0, 256));
-  HIPCK(hipMemset(P.resid, 0, 256));
+  struct Piece {
+    void **dst;
+    const void *src;
+    size_t bytes;
+  };
+  const Piece pieces[] = {
+      {(void **)&P.dev.ops, h.ops.data(), h.ops.size() * sizeof(OpRec)},
+      {(void **)&P.dev.exp_ops, h.exp_ops.data(), h.exp_ops.size() * sizeof(Op4)},
+      {(void **)&P.dev.tc_ops, h.tc_ops.data(), h.tc_ops.size() * sizeof(Op4)},
+      {(void **)&P.dev.sx_ops, h.sx_ops.data(), h.sx_ops.size() * sizeof(Op4)},
+      {(void **)&P.dev.parent, h.parent32.data(), h.parent32.size() * sizeof(int32_t)},
+      {(void **)&P.dev.child_off, coff.data(), coff.size() * sizeof(int32_t)},
+      {(void **)&P.dev.child_idx, cidx.data(), cidx.size() * sizeof(int32_t)},
+      {(void **)&P.dev.koff, h.kind_off.data(), h.kind_off.size() * sizeof(int64_t)},
+      {(void **)&P.dev.exp_off, h.exp_off.data(), h.exp_off.size() * sizeof(int64_t)},
+      {(void **)&P.dev.tc_off, h.tc_off.data(), h.tc_off.size() * sizeof(int64_t)},
+      {(void **)&P.dev.sx_off, h.sx_off.data(), h.sx_off.size() * sizeof(int64_t)},
+  };
+  size_t total = 0;
+  for (const Piece &pc : pieces) total = align_up(total + std::max<size_t>(pc.bytes, 16), 256);
+  std::vector<char> stage(total, 0);
+  size_t at = 0;
+  for (const Piece &pc : pieces) {
+    if (pc.bytes) memcpy(stage.data() + at, pc.src, pc.bytes);
+    at = align_up(at + std::max<size_t>(pc.bytes, 16), 256);
+  }
+  char *base = nullptr;
+  if (hipMallocAsync((void **)&base, total, st) != hipSuccess) return RCR_OOM;
+  P.dev.base = base;
+  P.dev.bytes = total;
+  at = 0;
+  for (const Piece &pc : pieces) {
+    *pc.dst = base + at;
+    at = align_up(at + std::max<size_t>(pc.bytes, 16), 256);
+  }
+  HIPCK(hipMemcpyAsync(base, stage.data(), total, hipMemcpyHostToDevice, st));
+  // the staging buffer is released on return, and solves on other streams may use the arrays
+  HIPCK(hipStreamSynchronize(st));
   return RCR_OK;
 }
 
@@ -136,14 +155,15 @@ void plan_release_device(PlanObj &P) {
   P.graphs.clear();
   for (hipEvent_t e : P.events) (void)hipEventDestroy(e);
   P.events.clear();
-  void *ptrs[] = {P.dev.ops,    P.dev.exp_ops, P.dev.tc_ops, P.dev.sx_ops, P.dev.parent, P.dev.child_off,
-                  P.dev.child_idx, P.dev.koff,  P.dev.exp_off, P.dev.tc_off, P.dev.sx_off, P.status,
-                  P.resid,        P.ws[0],       P.ws[1]};
+  // release after the last solve that used the plan (its completion event), in
+  // the order of the default stream, without blocking the host
+  void *ptrs[] = {P.dev.base, P.ws[0], P.ws[1]};
+  if (P.last_done) (void)hipStreamWaitEvent(nullptr, P.last_done, 0);
   for (void *p : ptrs)
-    if (p) (void)hipFree(p);
+    if (p) (void)hipFreeAsync(p, nullptr);
+  if (P.last_done) (void)hipEventDestroy(P.last_done);
+  P.last_done = nullptr;
   P.dev = PlanDev();
-  P.status = nullptr;
-  P.resid = nullptr;
   P.ws[0] = P.ws[1] = nullptr;
   P.ws_bytes[0] = P.ws_bytes[1] = 0;
 }
@@ -244,11 +264,12 @@ __global__ __launch_bounds__(256) void k_residual_rhs(int64_t N, int n, int m, i
 
 template <typename OT>
 static void launch_residual_rhs(PlanObj &P, const rcr_problem &in, const rcr_solution &out, OT *rq, OT *rr, OT *rc,
+                                double *resid,
                                 hipStream_t st) {
   const PlanHost &h = P.host;
   hipLaunchKernelGGL(k_residual_rhs<OT>, dim3(blocks_for(h.N, TEAMS_PER_BLOCK)), dim3(256), 0, st, h.N, h.n, h.m,
                      (int)h.root, in.Q, in.q, in.c, in.Delta, in.R, in.S, in.r, in.A, in.B, out.x, out.u, out.lam,
-                     P.dev.parent, P.dev.child_off, P.dev.child_idx, rq, rr, rc, P.resid);
+                     P.dev.parent, P.dev.child_off, P.dev.child_idx, rq, rr, rc, resid);
 }
 
 template <typename T>
@@ -266,7 +287,7 @@ static Bufs<T> make_bufs(PlanObj &P, const WsLayout &L, void *ws, const rcr_prob
   bf.Finv = base + L.Finv; bf.W = base + L.W; bf.Ginv = base + L.Ginv; bf.Acl = base + L.Acl; bf.Tm = base + L.Tm;
   bf.h = base + L.h; bf.cv = base + L.cv; bf.z = base + L.z; bf.p = base + L.p; bf.kff = base + L.kff; bf.b = base + L.b;
   bf.parent = P.dev.parent;
-  bf.status = P.status;
+  bf.status = ws_status(ws);
   return bf;
 }
 
@@ -275,7 +296,7 @@ static int launch_sequence(PlanObj &P, const rcr_problem &in, const rcr_solution
                            const WsLayout &L, void *ws, Timer &tm, hipStream_t st) {
   const PlanHost &h = P.host;
   const int64_t Nn = h.N * h.n, Nm = h.N * h.m, Nnn = h.N * h.n * h.n, Nmn = h.N * h.m * h.n;
-  hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, st, P.status, P.resid);
+  hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, st, ws_status(ws), ws_resid(ws));
   if (opt.precision == RCR_FP64) {
     Bufs<double> bf = make_bufs<double>(P, L, ws, in);
     bf.sq = in.q;
@@ -317,7 +338,7 @@ static int launch_sequence(PlanObj &P, const rcr_problem &in, const rcr_solution
   for (int it = 0; it < opt.refine_steps; ++it) {
     tm.begin(RCR_K_RESIDUAL);
     tm.pre();
-    launch_residual_rhs<float>(P, in, out, rq, rr, rc_, st);
+    launch_residual_rhs<float>(P, in, out, rq, rr, rc_, ws_resid(ws), st);
     tm.post();
     rc = launch_phase<float>(P, bf, tm, st, 1);
     if (rc) return rc;
@@ -335,7 +356,7 @@ static int launch_sequence(PlanObj &P, const rcr_problem &in, const rcr_solution
 
 int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_options &opt, hipStream_t st) {
   std::lock_guard<std::mutex> lock(P.mu);
-  int rc = plan_upload(P);
+  int rc = plan_upload(P, st);
   if (rc) return rc;
   const int prec = opt.precision;
   const WsLayout L = workspace_layout(P.host, prec);
@@ -343,15 +364,13 @@ int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_
   if (ws) {
     if ((size_t)opt.workspace_bytes < L.total_bytes) return RCR_SMALL_WORKSPACE;
   } else {
-    if (P.ws_bytes[prec] < L.total_bytes) {
-      if (P.ws[prec]) (void)hipFree(P.ws[prec]);
-      P.ws[prec] = nullptr;
-      P.ws_bytes[prec] = 0;
-      if (hipMalloc(&P.ws[prec], L.total_bytes) != hipSuccess) return RCR_OOM;
+    if (!P.ws[prec]) {
+      if (hipMallocAsync(&P.ws[prec], L.total_bytes, st) != hipSuccess) return RCR_OOM;
       P.ws_bytes[prec] = L.total_bytes;
     }
     ws = P.ws[prec];
   }
+  if (!P.last_done) HIPCK(hipEventCreateWithFlags(&P.last_done, hipEventDisableTiming));
   Timer tm;
   tm.P = &P;
   tm.st = st;
@@ -390,10 +409,11 @@ int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_
   if (opt.kkt_residual) {
     tm.begin(RCR_K_RESIDUAL);
     // the residual of the returned iterate (the refinement's accumulator is reset first)
-    hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, st, P.status + 8, P.resid);
-    launch_residual_rhs<double>(P, in, out, nullptr, nullptr, nullptr, st);
+    hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, st, ws_status(ws) + 8, ws_resid(ws));
+    launch_residual_rhs<double>(P, in, out, nullptr, nullptr, nullptr, ws_resid(ws), st);
     HIPCK(hipGetLastError());
   }
+  HIPCK(hipEventRecord(P.last_done, st));
   if (opt.check || opt.kkt_residual || tm.on) {
     HIPCK(hipStreamSynchronize(st));
     if (tm.on) {
@@ -408,10 +428,13 @@ int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_
         if (opt.kernel_launches) opt.kernel_launches[sp.first] += 1;
       }
     }
-    if (opt.kkt_residual) HIPCK(hipMemcpy(opt.kkt_residual, P.resid, sizeof(double), hipMemcpyDeviceToHost));
+    double resid = 0.0;
+    int stw = 0;
+    HIPCK(hipMemcpyAsync(&resid, ws_resid(ws), sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCK(hipMemcpyAsync(&stw, ws_status(ws), sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    if (opt.kkt_residual) *opt.kkt_residual = resid;
     if (opt.check) {
-      int stw = 0;
-      HIPCK(hipMemcpy(&stw, P.status, sizeof(int), hipMemcpyDeviceToHost));
       if (stw & ST_NOT_PD) return RCR_NOT_PD;
       if (stw & ST_SINGULAR) return RCR_SINGULAR;
       if (stw & ST_NONFINITE) return RCR_NONFINITE;

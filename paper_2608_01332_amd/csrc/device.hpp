@@ -18,6 +18,7 @@ namespace rcr {
 // Device copy of a plan's integer arrays.
 struct PlanDev {
   int device = -1;
+  char *base = nullptr;  // one allocation holding every array below
   OpRec *ops = nullptr;
   Op4 *exp_ops = nullptr, *tc_ops = nullptr, *sx_ops = nullptr;
   int32_t *parent = nullptr;
@@ -33,6 +34,11 @@ struct WsLayout {
   size_t rq, rr, rc;                                          // right-hand side copies (mixed)
   size_t total_bytes;
 };
+
+// The first WS_HEADER_BYTES of a workspace hold the solve's status words
+// (bytes 0..255) and its residual accumulator (bytes 256..263), so that one
+// plan can serve concurrent solves on different streams with distinct workspaces.
+constexpr size_t WS_HEADER_BYTES = 512;
 
 WsLayout workspace_layout(const PlanHost &ph, int precision);
 
@@ -51,13 +57,12 @@ struct PlanObj {
   std::mutex mu;
   void *ws[2] = {nullptr, nullptr};  // plan-owned workspace per precision
   size_t ws_bytes[2] = {0, 0};
-  int *status = nullptr;             // device status words
-  double *resid = nullptr;           // device residual accumulator
+  hipEvent_t last_done = nullptr;    // completion of the latest solve (stream-ordered release)
   std::map<GraphKey, hipGraphExec_t> graphs;
   std::vector<hipEvent_t> events;
 };
 
-int plan_upload(PlanObj &P);
+int plan_upload(PlanObj &P, hipStream_t st);
 void plan_release_device(PlanObj &P);
 
 int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_options &opt,

@@ -494,6 +494,19 @@ int merge_plans(const std::vector<const PlanHost *> &parts, PlanHost &out) {
     return (int32_t)(s2 < parts[t]->N ? vb[t] + s2 : ecb[t] + (s2 - parts[t]->N));
   };
   auto contrib = [&](size_t t, int32_t c) { return (int32_t)(cb[t] + c); };
+  {
+    size_t n_ops = 0, n_exp = 0, n_tc = 0, n_sx = 0;
+    for (const PlanHost *p : parts) {
+      n_ops += p->ops.size();
+      n_exp += p->exp_ops.size();
+      n_tc += p->tc_ops.size();
+      n_sx += p->sx_ops.size();
+    }
+    out.ops.reserve(n_ops);
+    out.exp_ops.reserve(n_exp);
+    out.tc_ops.reserve(n_tc);
+    out.sx_ops.reserve(n_sx);
+  }
   // contraction: level-major, kind-minor, tree order within a (level, kind) group
   out.lvl_off.assign(1, 0);
   out.kind_off.resize((size_t)L * 5);

@@ -60,6 +60,7 @@ class SolveOptions(ctypes.Structure):
 
 
 EXPORTED = ("rcr_plan_create", "rcr_plan_info", "rcr_plan_export", "rcr_plan_destroy", "rcr_batch_plan_create",
+            "rcr_plan_upload",
             "rcr_workspace_size", "rcr_solve", "rcr_status_string")
 
 _lib = None
@@ -92,6 +93,8 @@ def lib():
             L.rcr_batch_plan_create.restype = ctypes.c_int
             L.rcr_batch_plan_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
                                                 ctypes.POINTER(ctypes.c_void_p)]
+            L.rcr_plan_upload.restype = ctypes.c_int
+            L.rcr_plan_upload.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
             L.rcr_workspace_size.restype = ctypes.c_int64
             L.rcr_workspace_size.argtypes = [ctypes.c_void_p, ctypes.c_int32]
             L.rcr_solve.restype = ctypes.c_int
@@ -161,6 +164,14 @@ class Plan:
         if rc != 0:
             raise RcrError(rc, "rcr_plan_export")
         return ops
+
+    def upload(self, stream=None):
+        """rcr_plan_upload: make the device copy now, in the order of `stream`."""
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream()
+        rc = lib().rcr_plan_upload(self._h, ctypes.c_void_p(st.cuda_stream))
+        if rc != 0:
+            raise RcrError(rc, "rcr_plan_upload")
 
     def workspace_size(self, precision: int = FP64) -> int:
         return int(lib().rcr_workspace_size(self._h, precision))

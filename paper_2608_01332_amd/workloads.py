@@ -301,3 +301,49 @@ def native_node_control_data(parent: np.ndarray, spec: DataSpec, rng: np.random.
         M = np.einsum("nij,njk,nlk->nil", LQ, Xi, LR) / 2.0
     return {"Q": d["Q"], "q": d["q"], "c": d["c"], "Delta": d["Delta"],
             "M": M, "R": d["R"], "r": d["r"], "A": d["A"], "B": d["B"]}
+
+
+# --------------------------------------------------------------------------- serving stream
+def serve_requests(count: int, rate: float, seed: int, n_choices=(4, 8, 12, 16), m_choices=(2, 4),
+                   N_range=(1024, 131072), p_range=(0.85, 0.97), reuse: float = 0.3) -> list:
+    """A stream of tree-LQR solve requests with Poisson arrivals at `rate` per
+    second.  A fresh request draws N log-uniform in N_range, n and m uniformly
+    from their choices and a chain probability p ~ U(p_range); with
+    probability `reuse` a request instead resends the topology (and n, m) of an
+    earlier request, uniformly chosen, with new data.  Each entry: rid,
+    arrival (s), topo (topology id), N, n, m, p, tree_seed, variant (which data
+    variant of its (n, m) class it uses; a resend takes the other variant than
+    the request it resends), resend_of (that request's rid, or -1)."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=count)
+    t = np.cumsum(gaps) - gaps[0]
+    out = []
+    for k in range(count):
+        if out and rng.random() < reuse:
+            prev = out[int(rng.integers(0, len(out)))]
+            e = dict(prev)
+            e.update(rid=k, arrival=float(t[k]), variant=1 - prev["variant"], resend_of=prev["rid"])
+        else:
+            N = int(round(math.exp(rng.uniform(math.log(N_range[0]), math.log(N_range[1])))))
+            e = {"rid": k, "arrival": float(t[k]), "topo": k, "N": N,
+                 "n": int(rng.choice(n_choices)), "m": int(rng.choice(m_choices)),
+                 "p": float(rng.uniform(*p_range)), "tree_seed": seed * 1000003 + k, "variant": 0,
+                 "resend_of": -1}
+        out.append(e)
+    return out
+
+
+def serve_tree(e: dict) -> np.ndarray:
+    """The parent array of a serving request (root 0)."""
+    return tree_chainprob(e["N"], e["p"], np.random.default_rng(e["tree_seed"]))
+
+
+def serve_data_block(N: int, n: int, m: int, variant: int, seed: int) -> dict:
+    """Data of the (n, m) class, variant `variant`, for N nodes with root 0: a
+    request of N' <= N nodes whose root is node 0 uses rows [0, N').  Rank n/2
+    PSD dual regularisation with eigenvalues U(0, 1e-2), S = 0; the root's edge
+    slot is inert.  Rows of an edge slot do not depend on the topology, so one
+    block serves every tree of the class."""
+    par = np.arange(-1, N - 1, dtype=np.int64)  # any tree with root 0: only the root row is special
+    return lqr_data(par, DataSpec(n, m, delta_rank=max(1, n // 2)),
+                    np.random.default_rng(seed * 97 + 13 * n + m + 1000 * variant))
