@@ -390,6 +390,52 @@ def bench_serve(args) -> dict:
             "rates": rows}
 
 
+def bench_lift(args) -> dict:
+    """The node-control variant of the 65,536-node instance (n = 12, m = 4, one
+    control per non-leaf node) solved through the exact lifting: device lift,
+    rake-compress solve of the 127,970-node lifted tree (state 16), device
+    projection."""
+    import numpy as np
+    import torch
+    from paper_2608_01332_amd import rcr
+    from paper_2608_01332_amd import workloads as w
+    dev = torch.device("cuda:0")
+    par, nd = w.config2_lift_instance()
+    t0 = time.perf_counter()
+    plan = rcr.Plan.lift(par, 12, 4)
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    prob = rcr.to_device(nd, dev, fields=rcr.NATIVE_FIELDS)
+    stream = torch.cuda.current_stream(dev)
+    res = {}
+    for name, prec in (("fp64", rcr.FP64), ("mixed32", rcr.MIXED32)):
+        chk = rcr.lift_solve(plan, prob, precision=prec, refine_steps=1, executor=rcr.EXEC_GRAPH, check=True,
+                             kkt_residual=True)
+        out = {k: chk[k] for k in rcr.NATIVE_SOLUTION_FIELDS}
+        for _ in range(args.warmup):
+            rcr.lift_solve(plan, prob, out=out, precision=prec, refine_steps=1, executor=rcr.EXEC_GRAPH)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        torch.cuda.synchronize()
+        evs[0].record(stream)
+        for k in range(args.steps):
+            rcr.lift_solve(plan, prob, out=out, precision=prec, refine_steps=1, executor=rcr.EXEC_GRAPH,
+                           stream=stream)
+            evs[k + 1].record(stream)
+        torch.cuda.synchronize()
+        ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
+        res[name] = {"native_nodes_per_s": len(par) / (float(np.mean(ms)) / 1e3),
+                     "lifted_nodes_per_s": plan.N / (float(np.mean(ms)) / 1e3),
+                     "ms_per_step": float(np.mean(ms)), "p50_ms": float(np.percentile(ms, 50)),
+                     "p99_ms": float(np.percentile(ms, 99)), "kkt_residual_lifted": chk["kkt_residual"]}
+    return {"metric": "tree-LQR nodes/sec vs CPU Riccati at KKT res 1e-8; p50/p99 solve latency",
+            "value": res["fp64"]["native_nodes_per_s"], "unit": "nodes/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": res["fp64"]["ms_per_step"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "node-control variant of the N=65536 p=0.95 tree, n=12, m=4, one control per "
+                                   "non-leaf node, exact lifting to 127,970 nodes of state 16",
+                       "lifted_N": plan.N, "plan_ms": plan_ms},
+            "precisions": res}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -406,10 +452,10 @@ def main() -> int:
                     help="rates at which the one-slot FIFO queue (no batching) is also measured")
     ap.add_argument("--hbm-budget-gib", type=int, default=96)
     ap.add_argument("--planner-threads", type=int, default=12)
-    ap.add_argument("--workload", choices=["single", "batch", "extreme", "copy", "serve"], default="single",
+    ap.add_argument("--workload", choices=["single", "batch", "extreme", "copy", "serve", "lift"], default="single",
                     help="single: the 65,536-node tree (default); batch: the 512-tree batched workload; "
                          "extreme: the 1M-node shape-extreme trees; copy: plain HBM copy (counter calibration); "
-                         "serve: the request stream at swept arrival rates")
+                         "serve: the request stream at swept arrival rates; lift: the node-control variant through the lifting")
     ap.add_argument("--resolves", type=int, default=8)
     ap.add_argument("--trees", type=int, default=512)
     args = ap.parse_args()
@@ -437,6 +483,9 @@ def main() -> int:
         return 0
     if args.workload == "serve":
         print(json.dumps(bench_serve(args)), flush=True)
+        return 0
+    if args.workload == "lift":
+        print(json.dumps(bench_lift(args)), flush=True)
         return 0
     dev = torch.device("cuda:0")
     parent, data, spec = w.config_instance(2)

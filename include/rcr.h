@@ -215,6 +215,54 @@ int64_t rcr_workspace_size(const rcr_plan *plan, int32_t precision);
 int rcr_solve(const rcr_plan *plan, const rcr_problem *in, rcr_solution *out,
               const rcr_solve_options *opt, void *stream);
 
+/* ------------------------------------------------- node-control problems */
+/* Scenario MPC with one control v_i per non-leaf node, shared by all its
+ * outgoing transitions x_j = A_j x_i + B_j v_i + c_j (Sec. II-B, eq.
+ * (node-control), saddle function eq. (node-lagrangian)).  Device pointers,
+ * float64, row-major, one block per node (native tree of N nodes, state n,
+ * control m):
+ *   per node    Q[N][n][n]  q[N][n]  c[N][n]  Delta[N][n][n]
+ *               M[N][n][m]  R[N][m][m]  r[N][m]   (cost of v_i; rows of leaves
+ *                                                  are not read)
+ *   per edge    A[N][n][n]  B[N][n][m]            (slot j: edge parent[j] -> j;
+ *                                                  root slot not read)
+ *   outputs     x[N][n]  v[N][m] (zero rows at leaves)  lam[N][n]
+ * The solve runs through the exact lifting of Prop. 2: an edge-control tree
+ * with a predecision node i^- (id i) for every node and a decision node i^+
+ * (id N + rank of i among the non-leaves) for every non-leaf, lifted state
+ * (x, v) of dimension n + m, decision edges per eq. (decision-edge) and
+ * uncertainty edges per eq. (uncertainty-edge) (dummy control cost I). */
+typedef struct {
+  const double *Q, *q, *c, *Delta; /* per node                  */
+  const double *M, *R, *r;         /* per node (non-leaf rows)  */
+  const double *A, *B;             /* per edge slot             */
+} rcr_native_problem;
+
+typedef struct {
+  double *x, *v, *lam;
+} rcr_native_solution;
+
+/* Plan of the lifted tree of the HOST native parent array (N entries) for
+ * state n and control m (n + m <= RCR_MAX_DIM).  The plan's rcr_plan_info
+ * describes the lifted tree (N + #non-leaves nodes, state n + m); its
+ * rcr_workspace_size includes the lifted problem and solution buffers.
+ * Errors: RCR_NULL_ARG, RCR_BAD_DIMS, RCR_INVALID_TREE, RCR_BAD_OPTION,
+ * RCR_OOM. */
+int rcr_lift_plan_create(const int64_t *parent, int64_t N, int32_t n, int32_t m,
+                         const rcr_plan_options *opt, rcr_plan **out);
+
+/* Solve a node-control problem with a plan from rcr_lift_plan_create: device
+ * kernels write the lifted data (eqs. (decision-edge), (uncertainty-edge)),
+ * rcr_solve runs on the lifted tree, and device kernels project the lifted
+ * solution back (x_i and lam_i = the first n entries of the lifted state and
+ * multiplier of i^-, v_i = the control of i's decision edge).  Options as for
+ * rcr_solve; a caller workspace must hold rcr_workspace_size(plan,
+ * precision) bytes; opt->kkt_residual reports the residual of the lifted
+ * system.  Errors: those of rcr_solve, and RCR_BAD_OPTION when the plan is not
+ * a lifted plan. */
+int rcr_lift_solve(const rcr_plan *plan, const rcr_native_problem *in, rcr_native_solution *out,
+                   const rcr_solve_options *opt, void *stream);
+
 /* Static name of a status code. */
 const char *rcr_status_string(int status);
 

@@ -37,6 +37,47 @@ int rcr_plan_create(const int64_t *parent, int64_t N, int32_t n, int32_t m, cons
   return RCR_OK;
 }
 
+int rcr_lift_plan_create(const int64_t *parent, int64_t N, int32_t n, int32_t m, const rcr_plan_options *opt,
+                         rcr_plan **out) {
+  if (!parent || !out) return RCR_NULL_ARG;
+  *out = nullptr;
+  int selection = opt ? opt->selection : RCR_SELECT_GREEDY_INDEX;
+  rcr_plan *p = new (std::nothrow) rcr_plan();
+  if (!p) return RCR_OOM;
+  int rc;
+  try {
+    rc = rcr::build_lift_plan(parent, N, n, m, selection, p->obj.host);
+  } catch (const std::bad_alloc &) {
+    rc = RCR_OOM;
+  }
+  if (rc) {
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return RCR_OK;
+}
+
+int rcr_lift_solve(const rcr_plan *plan, const rcr_native_problem *in, rcr_native_solution *out,
+                   const rcr_solve_options *opt, void *stream) {
+  if (!plan || !in || !out) return RCR_NULL_ARG;
+  const double *need[] = {in->Q, in->q, in->c, in->Delta, in->M, in->R, in->r, in->A, in->B,
+                          out->x, out->v, out->lam};
+  for (const double *p : need)
+    if (!p) return RCR_NULL_ARG;
+  rcr_solve_options o;
+  memset(&o, 0, sizeof(o));
+  if (opt) o = *opt;
+  if (o.precision != RCR_FP64 && o.precision != RCR_MIXED32) return RCR_BAD_OPTION;
+  if (o.executor != RCR_EXEC_LEVELS && o.executor != RCR_EXEC_GRAPH) return RCR_BAD_OPTION;
+  if (o.refine_steps < 0) o.refine_steps = 1;
+  if (!plan->obj.host.lift_N) return RCR_BAD_OPTION;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return RCR_NO_DEVICE;
+  rcr_plan *pl = const_cast<rcr_plan *>(plan);
+  return rcr::lift_solve(pl->obj, *in, *out, o, (hipStream_t)stream);
+}
+
 int rcr_batch_plan_create(const rcr_plan *const *plans, int32_t k, rcr_plan **out) {
   if (!plans || !out || k < 1) return RCR_NULL_ARG;
   *out = nullptr;
@@ -92,8 +133,8 @@ int rcr_plan_info(const rcr_plan *plan, rcr_plan_stats *out) {
   out->n_absorb = h.n_absorb;
   out->depth_bound = rcr::depth_bound(h.N);
   out->crew_ok = h.crew_ok ? 1 : 0;
-  out->workspace_bytes_fp64 = (int64_t)rcr::workspace_layout(h, RCR_FP64).total_bytes;
-  out->workspace_bytes_mixed = (int64_t)rcr::workspace_layout(h, RCR_MIXED32).total_bytes;
+  out->workspace_bytes_fp64 = (int64_t)rcr::total_workspace_bytes(h, RCR_FP64);
+  out->workspace_bytes_mixed = (int64_t)rcr::total_workspace_bytes(h, RCR_MIXED32);
   out->n_trees = h.tree_off.empty() ? 1 : (int64_t)h.tree_off.size() - 1;
   return RCR_OK;
 }
@@ -116,7 +157,7 @@ void rcr_plan_destroy(rcr_plan *plan) {
 
 int64_t rcr_workspace_size(const rcr_plan *plan, int32_t precision) {
   if (!plan || (precision != RCR_FP64 && precision != RCR_MIXED32)) return 0;
-  return (int64_t)rcr::workspace_layout(plan->obj.host, precision).total_bytes;
+  return (int64_t)rcr::total_workspace_bytes(plan->obj.host, precision);
 }
 
 int rcr_solve(const rcr_plan *plan, const rcr_problem *in, rcr_solution *out, const rcr_solve_options *opt,

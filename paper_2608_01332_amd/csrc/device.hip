@@ -88,6 +88,25 @@ WsLayout workspace_layout(const PlanHost &ph, int precision) {
   return L;
 }
 
+// Float64 word counts of the lifted problem and solution per lifted node (d = n + m).
+static void lift_words(int d, int m, size_t in_w[9], size_t out_w[5]) {
+  const size_t dd = (size_t)d * d, dm = (size_t)d * m, mm = (size_t)m * m;
+  const size_t iw[9] = {dd, (size_t)d, (size_t)d, dd, mm, dm, (size_t)m, dd, dm};  // Q q c Delta R S r A B
+  const size_t ow[5] = {dm, dd, (size_t)d, (size_t)m, (size_t)d};                  // K P x u lam
+  for (int k = 0; k < 9; ++k) in_w[k] = iw[k];
+  for (int k = 0; k < 5; ++k) out_w[k] = ow[k];
+}
+
+size_t total_workspace_bytes(const PlanHost &ph, int precision) {
+  size_t cur = workspace_layout(ph, precision).total_bytes;
+  if (!ph.lift_N) return cur;
+  size_t iw[9], ow[5];
+  lift_words(ph.n, ph.m, iw, ow);
+  for (int k = 0; k < 9; ++k) cur = align_up(cur + iw[k] * 8 * (size_t)ph.N, 256);
+  for (int k = 0; k < 5; ++k) cur = align_up(cur + ow[k] * 8 * (size_t)ph.N, 256);
+  return cur;
+}
+
 static inline int *ws_status(void *ws) { return reinterpret_cast<int *>(ws); }
 static inline double *ws_resid(void *ws) { return reinterpret_cast<double *>(static_cast<char *>(ws) + 256); }
 
@@ -126,6 +145,7 @@ int plan_upload(PlanObj &P, hipStream_t st) {
       {(void **)&P.dev.exp_off, h.exp_off.data(), h.exp_off.size() * sizeof(int64_t)},
       {(void **)&P.dev.tc_off, h.tc_off.data(), h.tc_off.size() * sizeof(int64_t)},
       {(void **)&P.dev.sx_off, h.sx_off.data(), h.sx_off.size() * sizeof(int64_t)},
+      {(void **)&P.dev.lift_plus, h.lift_plus.data(), h.lift_plus.size() * sizeof(int32_t)},
   };
   size_t total = 0;
   for (const Piece &pc : pieces) total = align_up(total + std::max<size_t>(pc.bytes, 16), 256);
@@ -365,8 +385,9 @@ int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_
     if ((size_t)opt.workspace_bytes < L.total_bytes) return RCR_SMALL_WORKSPACE;
   } else {
     if (!P.ws[prec]) {
-      if (hipMallocAsync(&P.ws[prec], L.total_bytes, st) != hipSuccess) return RCR_OOM;
-      P.ws_bytes[prec] = L.total_bytes;
+      const size_t nb = total_workspace_bytes(P.host, prec);
+      if (hipMallocAsync(&P.ws[prec], nb, st) != hipSuccess) return RCR_OOM;
+      P.ws_bytes[prec] = nb;
     }
     ws = P.ws[prec];
   }
@@ -440,6 +461,127 @@ int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_
       if (stw & ST_NONFINITE) return RCR_NONFINITE;
     }
   }
+  return RCR_OK;
+}
+
+// ------------------------------------------------------------ exact lifting
+struct LiftedPtrs {
+  double *Q, *q, *c, *De, *R, *S, *r, *A, *B;
+};
+
+// Lifted data of a node-control problem (Prop. 2), one wavefront per lifted
+// node v: v < N is the predecision node of native node v, v >= N the decision
+// node of native node parent'(v).
+//   predecision node i^-:  Q' = diag(Q_i, 0), q' = (q_i, 0), c' = (c_i, 0),
+//     Delta' = diag(Delta_i, 0); its edge from pa(i)^+ is the uncertainty
+//     edge of eq. (uncertainty-edge): A' = [[A_i, B_i], [0, 0]], B' = 0,
+//     dummy control cost R' = I, S' = 0, r' = 0 (inert at the root: A' = 0)
+//   decision node i^+:  zero costs and offsets; its edge from i^- is the
+//     decision edge of eq. (decision-edge): A' = [[I, 0], [0, 0]], B' = [0; I],
+//     R' = R_i, S' = [M_i; 0], r' = r_i
+__global__ __launch_bounds__(256) void k_lift(int64_t N, int64_t NL, int n, int m, const int32_t *__restrict__ lparent,
+                                              rcr_native_problem in, LiftedPtrs o) {
+  const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (v >= NL) return;
+  const int d = n + m;
+  const bool pre = v < N;
+  const int64_t i = pre ? v : (int64_t)lparent[v];
+  const bool unc = pre && lparent[v] >= 0;
+  const int64_t nn = (int64_t)n * n, nm = (int64_t)n * m, mm = (int64_t)m * m;
+  const int64_t dd = (int64_t)d * d, dm = (int64_t)d * m;
+  for (int e = lane; e < d * d; e += 64) {
+    const int a = e / d, b = e % d;
+    const bool xx = pre && a < n && b < n;
+    o.Q[v * dd + e] = xx ? in.Q[i * nn + a * n + b] : 0.0;
+    o.De[v * dd + e] = xx ? in.Delta[i * nn + a * n + b] : 0.0;
+    double av = 0.0;
+    if (unc && a < n) av = b < n ? in.A[i * nn + a * n + b] : in.B[i * nm + a * m + (b - n)];
+    if (!pre && a == b && a < n) av = 1.0;
+    o.A[v * dd + e] = av;
+  }
+  for (int e = lane; e < d; e += 64) {
+    o.q[v * d + e] = (pre && e < n) ? in.q[i * n + e] : 0.0;
+    o.c[v * d + e] = (pre && e < n) ? in.c[i * n + e] : 0.0;
+  }
+  for (int e = lane; e < m * m; e += 64) o.R[v * mm + e] = pre ? ((e / m == e % m) ? 1.0 : 0.0) : in.R[i * mm + e];
+  for (int e = lane; e < d * m; e += 64) {
+    const int a = e / m, b = e % m;
+    o.S[v * dm + e] = (!pre && a < n) ? in.M[i * nm + a * m + b] : 0.0;
+    o.B[v * dm + e] = (!pre && a >= n && a - n == b) ? 1.0 : 0.0;
+  }
+  for (int e = lane; e < m; e += 64) o.r[v * m + e] = pre ? 0.0 : in.r[i * m + e];
+}
+
+// Native solution from the lifted one: x_i, lam_i = the first n entries of the
+// lifted state and multiplier of i^-, v_i = the control of the decision edge
+// into i^+ (zero at leaves).
+__global__ __launch_bounds__(256) void k_project(int64_t N, int n, int m, const int32_t *__restrict__ plus,
+                                                 const double *__restrict__ xl, const double *__restrict__ ul,
+                                                 const double *__restrict__ yl, double *x, double *vv, double *lam) {
+  const int d = n + m;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < N * n; t += stride) {
+    const int64_t i = t / n;
+    const int a = (int)(t % n);
+    x[t] = xl[i * d + a];
+    lam[t] = yl[i * d + a];
+  }
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < N * m; t += stride) {
+    const int64_t i = t / m;
+    const int b = (int)(t % m);
+    const int32_t k = plus[i];
+    vv[t] = k >= 0 ? ul[(int64_t)k * m + b] : 0.0;
+  }
+}
+
+int lift_solve(PlanObj &P, const rcr_native_problem &in, rcr_native_solution &out, const rcr_solve_options &opt,
+               hipStream_t st) {
+  const PlanHost &h = P.host;
+  if (!h.lift_N) return RCR_BAD_OPTION;
+  const int prec = opt.precision;
+  void *ws = opt.workspace;
+  const size_t need = total_workspace_bytes(h, prec);
+  {
+    std::lock_guard<std::mutex> lock(P.mu);
+    int rc = plan_upload(P, st);
+    if (rc) return rc;
+    if (ws) {
+      if ((size_t)opt.workspace_bytes < need) return RCR_SMALL_WORKSPACE;
+    } else {
+      if (!P.ws[prec]) {
+        if (hipMallocAsync(&P.ws[prec], need, st) != hipSuccess) return RCR_OOM;
+        P.ws_bytes[prec] = need;
+      }
+      ws = P.ws[prec];
+    }
+  }
+  const size_t solver_bytes = workspace_layout(h, prec).total_bytes;
+  size_t iw[9], ow[5];
+  lift_words(h.n, h.m, iw, ow);
+  double *ptr[14];
+  size_t cur = solver_bytes;
+  for (int k = 0; k < 14; ++k) {
+    ptr[k] = reinterpret_cast<double *>(static_cast<char *>(ws) + cur);
+    cur = align_up(cur + (k < 9 ? iw[k] : ow[k - 9]) * 8 * (size_t)h.N, 256);
+  }
+  const LiftedPtrs lp{ptr[0], ptr[1], ptr[2], ptr[3], ptr[4], ptr[5], ptr[6], ptr[7], ptr[8]};
+  const int64_t NL = h.N, N = h.lift_N;
+  const int n = h.lift_n, m = h.m;
+  hipLaunchKernelGGL(k_lift, dim3((unsigned)((NL + 3) / 4)), dim3(256), 0, st, N, NL, n, m, P.dev.parent, in, lp);
+  HIPCK(hipGetLastError());
+  rcr_problem lin{ptr[0], ptr[1], ptr[2], ptr[3], ptr[4], ptr[5], ptr[6], ptr[7], ptr[8]};
+  rcr_solution lout{ptr[9], ptr[10], ptr[11], ptr[12], ptr[13]};
+  rcr_solve_options o2 = opt;
+  o2.workspace = ws;
+  o2.workspace_bytes = (int64_t)solver_bytes;
+  int rc = solve(P, lin, lout, o2, st);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_project, dim3(grid_for(N * std::max(n, m))), dim3(256), 0, st, N, n, m, P.dev.lift_plus,
+                     lout.x, lout.u, lout.lam, out.x, out.v, out.lam);
+  HIPCK(hipGetLastError());
+  std::lock_guard<std::mutex> lock(P.mu);
+  HIPCK(hipEventRecord(P.last_done, st));
   return RCR_OK;
 }
 

@@ -24,6 +24,7 @@ struct PlanDev {
   int32_t *parent = nullptr;
   int32_t *child_off = nullptr, *child_idx = nullptr;  // children in increasing id (residual)
   int64_t *koff = nullptr, *exp_off = nullptr, *tc_off = nullptr, *sx_off = nullptr;  // level offsets
+  int32_t *lift_plus = nullptr;  // lifted plans: decision node of each native non-leaf
   size_t bytes = 0;
 };
 
@@ -41,6 +42,10 @@ struct WsLayout {
 constexpr size_t WS_HEADER_BYTES = 512;
 
 WsLayout workspace_layout(const PlanHost &ph, int precision);
+
+// Whole device scratch of a solve with this plan: the solver's workspace and,
+// for a lifted plan, the float64 lifted problem and solution that follow it.
+size_t total_workspace_bytes(const PlanHost &ph, int precision);
 
 struct GraphKey {
   const void *p[16];
@@ -67,5 +72,8 @@ void plan_release_device(PlanObj &P);
 
 int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_options &opt,
           hipStream_t stream);
+
+int lift_solve(PlanObj &P, const rcr_native_problem &in, rcr_native_solution &out, const rcr_solve_options &opt,
+               hipStream_t stream);
 
 }  // namespace rcr

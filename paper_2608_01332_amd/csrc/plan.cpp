@@ -432,8 +432,40 @@ int build_plan(const int64_t *parent, int64_t N, int n, int m, int selection, Pl
   return b.run(selection);
 }
 
+// Lifted tree (Prop. 2): native node i keeps id i as its predecision node i^-;
+// every non-leaf i gains a decision node i^+ with id N + (rank of i among the
+// non-leaves in increasing id), the child of i^- through the decision edge;
+// each native child j of i hangs below i^+ through its uncertainty edge.
+int build_lift_plan(const int64_t *parent, int64_t N, int n, int m, int selection, PlanHost &out) {
+  if (!parent) return RCR_NULL_ARG;
+  if (N < 1 || n < 1 || m < 1 || n + m > RCR_MAX_DIM) return RCR_BAD_DIMS;
+  if (N > (int64_t)(INT32_MAX / 4)) return RCR_BAD_DIMS;
+  std::vector<char> nonleaf(N, 0);
+  for (int64_t j = 0; j < N; ++j) {
+    if (parent[j] < -1 || parent[j] >= N) return RCR_INVALID_TREE;
+    if (parent[j] >= 0) nonleaf[parent[j]] = 1;
+  }
+  std::vector<int32_t> plus(N, -1);
+  int64_t NL = N;
+  for (int64_t i = 0; i < N; ++i)
+    if (nonleaf[i]) plus[i] = (int32_t)NL++;
+  std::vector<int64_t> lp(NL);
+  for (int64_t i = 0; i < N; ++i) lp[i] = parent[i] < 0 ? -1 : plus[parent[i]];
+  for (int64_t i = 0; i < N; ++i)
+    if (plus[i] >= 0) lp[plus[i]] = i;
+  // a cycle of the native tree is a cycle of the lifted one: build_plan rejects it
+  int rc = build_plan(lp.data(), NL, n + m, m, selection, out);
+  if (rc) return rc;
+  out.lift_N = N;
+  out.lift_n = n;
+  out.lift_plus = std::move(plus);
+  return RCR_OK;
+}
+
 int merge_plans(const std::vector<const PlanHost *> &parts, PlanHost &out) {
   if (parts.empty()) return RCR_NULL_ARG;
+  for (const PlanHost *p : parts)
+    if (p && p->lift_N) return RCR_BAD_OPTION;  // lifted plans are solved through rcr_lift_solve
   const int n = parts[0]->n, m = parts[0]->m;
   out = PlanHost();
   out.n = n;

@@ -65,6 +65,13 @@ struct PlanHost {
   // [tree_off[t], tree_off[t + 1])
   std::vector<int64_t> tree_off;
 
+  // lifted plans of node-control problems (Sec. II-B): the native tree has
+  // lift_N nodes of state dimension lift_n; native non-leaf i has the decision
+  // node lift_plus[i] (-1 for leaves).  lift_N == 0 for ordinary plans.
+  int64_t lift_N = 0;
+  int lift_n = 0;
+  std::vector<int32_t> lift_plus;
+
   int64_t levels() const { return (int64_t)lvl_off.size() - 1; }
   int64_t expand_levels() const { return (int64_t)exp_off.size() - 1; }
   int64_t state_levels() const { return (int64_t)tc_off.size() - 1; }
@@ -73,6 +80,12 @@ struct PlanHost {
 
 // Returns 0 or a negative RCR_* status.
 int build_plan(const int64_t *parent, int64_t N, int n, int m, int selection, PlanHost &out);
+
+// Plan of the lifted edge-control tree of a node-control problem (Sec. II-B,
+// Prop. 2) on the native tree `parent` with state dimension n and control
+// dimension m: the lifted state has dimension n + m.  Returns 0 or a negative
+// RCR_* status.
+int build_lift_plan(const int64_t *parent, int64_t N, int n, int m, int selection, PlanHost &out);
 
 // Merge the plans of independent trees into one plan of their forest: node,
 // edge and contribution slots are offset per tree, and dependency level t of

@@ -16,6 +16,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librcr.so")
 
+ERR_INVALID_TREE, ERR_BAD_DIMS, ERR_NULL_ARG, ERR_NOT_PD, ERR_SINGULAR, ERR_NONFINITE = -1, -2, -3, -4, -5, -6
+ERR_OOM, ERR_HIP_ERROR, ERR_BAD_OPTION, ERR_SMALL_WORKSPACE, ERR_NO_DEVICE = -7, -8, -9, -10, -11
 FP64, MIXED32 = 0, 1
 EXEC_LEVELS, EXEC_GRAPH = 0, 1
 SELECT_GREEDY_INDEX, SELECT_LIST_RANK = 0, 1
@@ -52,6 +54,14 @@ class Solution(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in ("K", "P", "x", "u", "lam")]
 
 
+class NativeProblem(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("Q", "q", "c", "Delta", "M", "R", "r", "A", "B")]
+
+
+class NativeSolution(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("x", "v", "lam")]
+
+
 class SolveOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("refine_steps", ctypes.c_int32), ("executor", ctypes.c_int32),
                 ("check", ctypes.c_int32), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_int64),
@@ -60,7 +70,7 @@ class SolveOptions(ctypes.Structure):
 
 
 EXPORTED = ("rcr_plan_create", "rcr_plan_info", "rcr_plan_export", "rcr_plan_destroy", "rcr_batch_plan_create",
-            "rcr_plan_upload",
+            "rcr_plan_upload", "rcr_lift_plan_create", "rcr_lift_solve",
             "rcr_workspace_size", "rcr_solve", "rcr_status_string")
 
 _lib = None
@@ -93,6 +103,12 @@ def lib():
             L.rcr_batch_plan_create.restype = ctypes.c_int
             L.rcr_batch_plan_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
                                                 ctypes.POINTER(ctypes.c_void_p)]
+            L.rcr_lift_plan_create.restype = ctypes.c_int
+            L.rcr_lift_plan_create.argtypes = [_i64p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                               ctypes.POINTER(PlanOptions), ctypes.POINTER(ctypes.c_void_p)]
+            L.rcr_lift_solve.restype = ctypes.c_int
+            L.rcr_lift_solve.argtypes = [ctypes.c_void_p, ctypes.POINTER(NativeProblem),
+                                         ctypes.POINTER(NativeSolution), ctypes.POINTER(SolveOptions), ctypes.c_void_p]
             L.rcr_plan_upload.restype = ctypes.c_int
             L.rcr_plan_upload.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
             L.rcr_workspace_size.restype = ctypes.c_int64
@@ -131,6 +147,25 @@ class Plan:
         self.offsets = np.cumsum([0] + [p.N for p in plans]).astype(np.int64)
         self._parent = np.concatenate([np.where(p._parent >= 0, p._parent + o, -1)
                                        for p, o in zip(plans, self.offsets[:-1])])
+        return self
+
+    @classmethod
+    def lift(cls, parent, n: int, m: int, selection: int = SELECT_GREEDY_INDEX) -> "Plan":
+        """Plan of the lifted tree of a node-control problem (rcr_lift_plan_create)
+        on the native parent array, state n and control m; solve it with lift_solve."""
+        L = lib()
+        self = cls.__new__(cls)
+        self._parent = np.ascontiguousarray(parent, dtype=np.int64)
+        h = ctypes.c_void_p()
+        opt = PlanOptions(selection=selection)
+        rc = L.rcr_lift_plan_create(self._parent.ctypes.data_as(_i64p), int(self._parent.shape[0]), int(n), int(m),
+                                    ctypes.byref(opt), ctypes.byref(h))
+        if rc != 0:
+            raise RcrError(rc, "rcr_lift_plan_create")
+        self._h = h
+        st = self.stats()
+        self.N, self.n, self.m = st["N"], st["n"], st["m"]
+        self.native_N, self.native_n = int(self._parent.shape[0]), int(n)
         return self
 
     def __init__(self, parent, n: int, m: int, selection: int = SELECT_GREEDY_INDEX):
@@ -252,13 +287,57 @@ def solve(plan: Plan, prob: dict, out: dict | None = None, precision: int = FP64
     return result
 
 
+NATIVE_FIELDS = ("Q", "q", "c", "Delta", "M", "R", "r", "A", "B")
+NATIVE_SOLUTION_FIELDS = ("x", "v", "lam")
+
+
+def _native_shapes(N, n, m):
+    return {"Q": (N, n, n), "q": (N, n), "c": (N, n), "Delta": (N, n, n), "M": (N, n, m), "R": (N, m, m),
+            "r": (N, m), "A": (N, n, n), "B": (N, n, m), "x": (N, n), "v": (N, m), "lam": (N, n)}
+
+
+def lift_solve(plan: Plan, prob: dict, out: dict | None = None, precision: int = FP64, executor: int = EXEC_LEVELS,
+               check: bool = False, kkt_residual: bool = False, refine_steps: int = -1, workspace=None,
+               stream=None) -> dict:
+    """rcr_lift_solve: a node-control problem (device tensors, NATIVE_FIELDS) through
+    the exact lifting.  Returns x, v, lam (and 'kkt_residual' of the lifted system)."""
+    import torch
+    if getattr(plan, "native_N", None) is None:
+        raise ValueError("lift_solve needs a plan from Plan.lift")
+    sh = _native_shapes(plan.native_N, plan.native_n, plan.m)
+    for k in NATIVE_FIELDS:
+        _check(prob[k], k, sh[k])
+    if out is None:
+        out = {k: torch.empty(sh[k], dtype=torch.float64, device=prob["Q"].device) for k in NATIVE_SOLUTION_FIELDS}
+    for k in NATIVE_SOLUTION_FIELDS:
+        _check(out[k], k, sh[k])
+    p = NativeProblem(**{k: prob[k].data_ptr() for k in NATIVE_FIELDS})
+    s = NativeSolution(**{k: out[k].data_ptr() for k in NATIVE_SOLUTION_FIELDS})
+    o = SolveOptions(precision=precision, refine_steps=refine_steps, executor=executor, check=int(check))
+    if workspace is not None:
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    res = ctypes.c_double(-1.0)
+    if kkt_residual:
+        o.kkt_residual = ctypes.pointer(res)
+    st = stream if stream is not None else torch.cuda.current_stream(prob["Q"].device)
+    rc = lib().rcr_lift_solve(plan._h, ctypes.byref(p), ctypes.byref(s), ctypes.byref(o),
+                              ctypes.c_void_p(st.cuda_stream))
+    if rc != 0:
+        raise RcrError(rc, "rcr_lift_solve")
+    result = dict(out)
+    if kkt_residual:
+        result["kkt_residual"] = res.value
+    return result
+
+
 def concat_problems(datas) -> dict:
     """Concatenate host problems of independent trees in the node order of a
     batched plan (Plan.batch)."""
     return {k: np.concatenate([np.ascontiguousarray(d[k]) for d in datas], axis=0) for k in PROBLEM_FIELDS}
 
 
-def to_device(data: dict, device="cuda") -> dict:
+def to_device(data: dict, device="cuda", fields=PROBLEM_FIELDS) -> dict:
     """Copy a host problem dict (numpy float64) to device tensors."""
     import torch
-    return {k: torch.from_numpy(np.ascontiguousarray(data[k], dtype=np.float64)).to(device) for k in PROBLEM_FIELDS}
+    return {k: torch.from_numpy(np.ascontiguousarray(data[k], dtype=np.float64)).to(device) for k in fields}

@@ -347,3 +347,14 @@ def serve_data_block(N: int, n: int, m: int, variant: int, seed: int) -> dict:
     par = np.arange(-1, N - 1, dtype=np.int64)  # any tree with root 0: only the root row is special
     return lqr_data(par, DataSpec(n, m, delta_rank=max(1, n // 2)),
                     np.random.default_rng(seed * 97 + 13 * n + m + 1000 * variant))
+
+
+def config2_lift_instance(resolve: int = 0):
+    """The one-control-per-information-node variant of the 65,536-node instance:
+    the same tree (p = 0.95) and distributions (n = 12, m = 4, rank-6 PSD
+    Delta), as a native node-control problem with M_i = 0, lifted to state 16."""
+    seed = config_seed(2, resolve, 0)
+    parent = tree_chainprob(65536, 0.95, np.random.default_rng(seed))
+    data = native_node_control_data(parent, DataSpec(12, 4, delta_rank=6, delta_scale=1e-2),
+                                    np.random.default_rng(seed + 104729))
+    return parent, data
