@@ -90,62 +90,90 @@ __host__ __device__ constexpr int lds_quad_words() {
 }
 
 // ---------------------------------------------------------------- factor kernels
+// The single-pass kernels (condense, local factor, right-hand-side init, local
+// affine solve, recovery) give each wavefront PW consecutive nodes, one per
+// team.  Their per-node blocks are contiguous ranges, moved between HBM and
+// per-team LDS tiles with coalesced accesses (team.hpp, stage_*), so the row
+// layout of the team arithmetic never reaches global memory.
+
+// Per-team LDS of k_condense (doubles): A, Delta and the output Pbar (NB x NB;
+// A and Delta are overwritten by Abar and Cbar), B, S, Bt, St (NB x MB), R (MB x MB).
+template <int NB, int MB>
+struct CondLay {
+  static constexpr int A = 0, D = NB * NB, P = 2 * NB * NB, B = 3 * NB * NB, S = B + NB * MB, Bt = S + NB * MB,
+                       St = Bt + NB * MB, R = St + NB * MB, words = R + MB * MB;
+};
+
 template <typename T, int NB, int MB>
 RCR_MAT_KERNEL(NB) void k_condense(Bufs<T> bf) {
   // One team per node v: U_v = Q_v; for v != root, in float64 with the
   // Cholesky factor L of R_v:  Bt = B L^{-T},  St = M L^{-T}  (rows, n x m)
   //   Abar = A - Bt St^T,  Cbar = Delta_v + Bt Bt^T,  Pbar = -St St^T.
-  constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW;
-  constexpr int LW = MB * MB + 2 * NB * MB;  // doubles per team
+  using Ly = CondLay<NB, MB>;
+  constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW, TS = Ly::words;
   extern __shared__ double smd[];
-  const int team = threadIdx.x / TW, r = threadIdx.x % TW;
-  const int64_t v0 = (int64_t)blockIdx.x * PW + team;
-  const bool active = v0 < bf.N;
-  const int64_t v = active ? v0 : bf.N - 1;
+  const int lane = threadIdx.x & 63, team = lane / TW, r = lane % TW;
+  const int64_t v0 = (int64_t)blockIdx.x * PW;
+  const int cnt = (int)((bf.N - v0) < PW ? (bf.N - v0) : PW);
   const int n = bf.n, m = bf.m;
-  const int64_t nn = (int64_t)n * n, nm = (int64_t)n * m;
-  double *L = smd + team * LW, *LBt = L + MB * MB, *LSt = LBt + NB * MB;
+  const int64_t nn = (int64_t)n * n;
+  range_copy<PW * NB * NB>(bf.U + v0 * nn, bf.Q + v0 * nn, cnt * (int)nn, lane);  // U = Q
   {
-    T q[NB];
-    ld_row(q, bf.Q + v * nn, n, r);
-    st_row(bf.U + v * nn, q, n, r, active);
+    double ra[Tile<PW, NB, NB>::IT], rd[Tile<PW, NB, NB>::IT];
+    stage_load<PW, NB, NB>(ra, bf.A, v0, cnt, n, n, lane);
+    stage_load<PW, NB, NB>(rd, bf.De, v0, cnt, n, n, lane);
+    double rb[Tile<PW, NB, MB>::IT], rs[Tile<PW, NB, MB>::IT], rq[Tile<PW, MB, MB>::IT];
+    stage_load<PW, NB, MB>(rb, bf.B, v0, cnt, n, m, lane);
+    stage_load<PW, NB, MB>(rs, bf.S, v0, cnt, n, m, lane);
+    stage_load<PW, MB, MB>(rq, bf.R, v0, cnt, m, m, lane);
+    stage_put<PW, NB, NB>(smd + Ly::A, TS, ra, lane);
+    stage_put<PW, NB, NB>(smd + Ly::D, TS, rd, lane);
+    stage_put<PW, NB, MB>(smd + Ly::B, TS, rb, lane);
+    stage_put<PW, NB, MB>(smd + Ly::S, TS, rs, lane);
+    stage_put<PW, MB, MB>(smd + Ly::R, TS, rq, lane);
   }
-  const bool edge = (bf.parent[v] >= 0);
-  // Cholesky of R (lane 0, sequential; R padded with the identity)
+  team_sync();
+  const bool active = team < cnt;
+  const int64_t v = v0 + (active ? team : 0);
+  const bool edge = active && bf.parent[v] >= 0;
+  const uint64_t noedge = __ballot(r == 0 && !edge);
+  double *L = smd + team * TS, *LR = L + Ly::R, *LBt = L + Ly::Bt, *LSt = L + Ly::St;
+  // Cholesky of R (lane 0, sequential; padded with the identity)
   if (r == 0) {
     for (int i = 0; i < MB; ++i)
       for (int j = 0; j < MB; ++j)
-        L[i * MB + j] = (i < m && j < m) ? bf.R[v * m * m + i * m + j] : (i == j ? 1.0 : 0.0);
+        if (i >= m || j >= m) LR[i * MB + j] = (i == j) ? 1.0 : 0.0;
     for (int j = 0; j < MB; ++j) {
-      double s = L[j * MB + j];
-      for (int k = 0; k < j; ++k) s -= L[j * MB + k] * L[j * MB + k];
-      if (edge && active && !(s > 0.0)) atomicOr(bf.status, ST_NOT_PD);
+      double s = LR[j * MB + j];
+      for (int k = 0; k < j; ++k) s -= LR[j * MB + k] * LR[j * MB + k];
+      if (edge && !(s > 0.0)) atomicOr(bf.status, ST_NOT_PD);
       const double d = sqrt(s);
-      L[j * MB + j] = d;
+      LR[j * MB + j] = d;
       for (int i = j + 1; i < MB; ++i) {
-        double t = L[i * MB + j];
-        for (int k = 0; k < j; ++k) t -= L[i * MB + k] * L[j * MB + k];
-        L[i * MB + j] = t / d;
+        double t = LR[i * MB + j];
+        for (int k = 0; k < j; ++k) t -= LR[i * MB + k] * LR[j * MB + k];
+        LR[i * MB + j] = t / d;
       }
     }
   }
   team_sync();
+  const int rr = r < NB ? r : NB - 1;
   double bt[MB], st[MB];
 #pragma unroll
   for (int c = 0; c < MB; ++c) {
-    bt[c] = (r < n && c < m) ? bf.B[v * nm + (int64_t)r * m + c] : 0.0;
-    st[c] = (r < n && c < m) ? bf.S[v * nm + (int64_t)r * m + c] : 0.0;
+    bt[c] = L[Ly::B + rr * MB + c];
+    st[c] = L[Ly::S + rr * MB + c];
   }
 #pragma unroll
   for (int c = 0; c < MB; ++c) {  // forward substitution L y = row^T
     double sb = bt[c], ss = st[c];
 #pragma unroll
     for (int k = 0; k < c; ++k) {
-      sb -= L[c * MB + k] * bt[k];
-      ss -= L[c * MB + k] * st[k];
+      sb -= LR[c * MB + k] * bt[k];
+      ss -= LR[c * MB + k] * st[k];
     }
-    bt[c] = sb / L[c * MB + c];
-    st[c] = ss / L[c * MB + c];
+    bt[c] = sb / LR[c * MB + c];
+    st[c] = ss / LR[c * MB + c];
   }
   if (r < NB) {
 #pragma unroll
@@ -155,8 +183,7 @@ RCR_MAT_KERNEL(NB) void k_condense(Bufs<T> bf) {
     }
   }
   team_sync();
-  T oa[NB], oc[NB], op[NB];
-  const int rr = r < NB ? r : NB - 1;
+  double oa[NB], oc[NB], op[NB];
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     double sbb = 0.0, sbs = 0.0, sss = 0.0;
@@ -167,18 +194,27 @@ RCR_MAT_KERNEL(NB) void k_condense(Bufs<T> bf) {
       sbs = fma(bt[c], sj, sbs);
       sss = fma(st[c], sj, sss);
     }
-    const bool in = (rr < n && j < n);
-    oa[j] = (T)((in ? bf.A[v * nn + (int64_t)rr * n + j] : 0.0) - sbs);
-    oc[j] = (T)((in ? bf.De[v * nn + (int64_t)rr * n + j] : 0.0) + sbb);
-    op[j] = (T)(-sss);
+    oa[j] = L[Ly::A + rr * NB + j] - sbs;
+    oc[j] = L[Ly::D + rr * NB + j] + sbb;
+    op[j] = -sss;
     pin1(oa[j]);
     pin1(oc[j]);
     pin1(op[j]);
     mem_fence_compiler();
   }
-  st_row(bf.EA + v * nn, oa, n, r, active && edge);
-  st_row(bf.EC + v * nn, oc, n, r, active && edge);
-  st_row(bf.EP + v * nn, op, n, r, active && edge);
+  if (r < NB) {  // each lane overwrites only its own rows of A and Delta
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      L[Ly::A + r * NB + j] = oa[j];
+      L[Ly::D + r * NB + j] = oc[j];
+      L[Ly::P + r * NB + j] = op[j];
+    }
+  }
+  team_sync();
+  // the edge records of every team but the edge-less ones (the root, idle teams)
+  stage_store<PW, NB, NB>(bf.EA, smd + Ly::A, TS, v0, cnt, n, n, lane, noedge, TW);
+  stage_store<PW, NB, NB>(bf.EC, smd + Ly::D, TS, v0, cnt, n, n, lane, noedge, TW);
+  stage_store<PW, NB, NB>(bf.EP, smd + Ly::P, TS, v0, cnt, n, n, lane, noedge, TW);
 }
 
 // One quadratic-contraction primitive of kind s on a team (lane r, LDS L).
@@ -343,50 +379,73 @@ RCR_MAT_KERNEL(NB) void k_quad_expand(Bufs<T> bf, const Op4 *__restrict__ ops, i
   qexp_op_team<T, NB>(bf, o, L, r, active);
 }
 
+// Per-team LDS of k_local_factor.  Words of T: P (later A^cl), Finv, A
+// (later T = F^-1 A^cl), Delta (later W), B, WB (later K^T), pivot slots;
+// then doubles: S (NB x MB), R and G (MB x MB).
 template <typename T, int NB, int MB>
-__host__ __device__ constexpr int lds_lf_words() {
-  // P, Finv, A, B, WB (later K^T rows), pivot slots (2 * 2 NB), G (MB^2 float64)
-  return 3 * NB * NB + 2 * NB * MB + 4 * NB + 2 * MB * MB;
-}
+struct LfLay {
+  static constexpr int P = 0, Fi = NB * NB, A = 2 * NB * NB, D = 3 * NB * NB, B = 4 * NB * NB, WB = B + NB * MB,
+                       Lp = WB + NB * MB, tend = Lp + 4 * NB;
+  static constexpr int dbeg = (tend * (int)sizeof(T) + 7) / 8;  // in doubles
+  static constexpr int S = dbeg, R = S + NB * MB, G = R + MB * MB, words = G + MB * MB;  // doubles per team
+};
 
 template <typename T, int NB, int MB>
 RCR_MAT_KERNEL(NB) void k_local_factor(Bufs<T> bf) {
   // One team per node v:  F = I + Delta P, Finv, W = P F^-1; for v != root and
   // e = (parent, v):  WB = W B,  H^T = A^T WB + M,  G = R + B^T WB (float64
   // Cholesky),  K^T = -H^T G^-1,  G^-1,  A^cl = A + B K,  T = F^-1 A^cl.
-  constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW;
-  constexpr int LW = lds_lf_words<T, NB, MB>();
+  using Ly = LfLay<T, NB, MB>;
+  constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW, TS = Ly::words;
+  constexpr int TST = TS * (int)(sizeof(double) / sizeof(T));  // team stride in words of T
   constexpr int W2 = 2 * NB;
   extern __shared__ double smd[];
-  const int team = threadIdx.x / TW, r = threadIdx.x % TW;
-  T *L = reinterpret_cast<T *>(smd) + team * LW;
-  T *LP = L, *LFi = L + NB * NB, *LA = L + 2 * NB * NB, *LB = L + 3 * NB * NB, *LWB = LB + NB * MB;
-  T *LKt = LWB, *Lp = LWB + NB * MB;  // K^T rows reuse the WB rows once G and H are formed
-  double *LG = reinterpret_cast<double *>(Lp + 4 * NB);  // NB even: 8-byte aligned
-  const int64_t v0 = (int64_t)blockIdx.x * PW + team;
-  const bool active = v0 < bf.N;
-  const int64_t v = active ? v0 : bf.N - 1;
+  T *smt = reinterpret_cast<T *>(smd);
+  const int lane = threadIdx.x & 63, team = lane / TW, r = lane % TW;
+  const int64_t v0 = (int64_t)blockIdx.x * PW;
+  const int cnt = (int)((bf.N - v0) < PW ? (bf.N - v0) : PW);
   const int n = bf.n, m = bf.m;
   const int64_t nn = (int64_t)n * n, nm = (int64_t)n * m;
-  const bool isroot = (bf.parent[v] < 0);
-  const bool edge = active && !isroot;
-  const int rr = r < NB ? r : NB - 1;
-  T pv[NB], dv[NB];
-  ld_row(pv, (isroot ? bf.U : bf.PW) + v * nn, n, r);
-  ld_row(dv, bf.De + v * nn, n, r);
-  if (isroot) st_row(bf.PW + v * nn, pv, n, r, active);
-  lds_put(LP, pv, r);
-  T av[NB];
-  ld_row(av, bf.A + v * nn, n, r);
-  lds_put(LA, av, r);
-  T bv[MB];
-#pragma unroll
-  for (int c = 0; c < MB; ++c) bv[c] = (r < n && c < m) ? (T)bf.B[v * nm + (int64_t)r * m + c] : (T)0;
-  if (r < NB) {
-#pragma unroll
-    for (int c = 0; c < MB; ++c) LB[r * MB + c] = bv[c];
+  {
+    T rp[Tile<PW, NB, NB>::IT];
+    double rd[Tile<PW, NB, NB>::IT], ra[Tile<PW, NB, NB>::IT];
+    stage_load<PW, NB, NB>(rp, bf.PW, v0, cnt, n, n, lane);
+    stage_load<PW, NB, NB>(rd, bf.De, v0, cnt, n, n, lane);
+    stage_load<PW, NB, NB>(ra, bf.A, v0, cnt, n, n, lane);
+    double rb[Tile<PW, NB, MB>::IT], rs[Tile<PW, NB, MB>::IT], rq[Tile<PW, MB, MB>::IT];
+    stage_load<PW, NB, MB>(rb, bf.B, v0, cnt, n, m, lane);
+    stage_load<PW, NB, MB>(rs, bf.S, v0, cnt, n, m, lane);
+    stage_load<PW, MB, MB>(rq, bf.R, v0, cnt, m, m, lane);
+    stage_put<PW, NB, NB>(smt + Ly::P, TST, rp, lane);
+    stage_put<PW, NB, NB>(smt + Ly::D, TST, rd, lane);
+    stage_put<PW, NB, NB>(smt + Ly::A, TST, ra, lane);
+    stage_put<PW, NB, MB>(smt + Ly::B, TST, rb, lane);
+    stage_put<PW, NB, MB>(smd + Ly::S, TS, rs, lane);
+    stage_put<PW, MB, MB>(smd + Ly::R, TS, rq, lane);
   }
   team_sync();
+  const bool active = team < cnt;
+  const int64_t v = v0 + (active ? team : 0);
+  const bool isroot = active && bf.parent[v] < 0;
+  const bool edge = active && !isroot;
+  const uint64_t noedge = __ballot(r == 0 && !edge);
+  T *L = smt + team * TST;
+  T *LP = L + Ly::P, *LFi = L + Ly::Fi, *LA = L + Ly::A, *LDe = L + Ly::D, *LB = L + Ly::B, *LWB = L + Ly::WB;
+  T *LKt = LWB, *Lp = L + Ly::Lp;
+  double *LS = smd + team * TS + Ly::S, *LR = smd + team * TS + Ly::R, *LG = smd + team * TS + Ly::G;
+  if (isroot) {  // P_root = U_root (eq. (value-reconstruction) at the root), also its output
+    T u[NB];
+    ld_row(u, bf.U + v * nn, n, r);
+    st_row(bf.PW + v * nn, u, n, r, true);
+    lds_put(LP, u, r);
+  }
+  team_sync();
+  const int rr = r < NB ? r : NB - 1;
+  T pv[NB], dv[NB], av[NB], bv[MB];
+  stage_row<NB, NB>(pv, LP, r);
+  stage_row<NB, NB>(dv, LDe, r);
+  stage_row<NB, NB>(av, LA, r);
+  stage_row<NB, MB>(bv, LB, r);
   T M[W2];
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
@@ -398,13 +457,12 @@ RCR_MAT_KERNEL(NB) void k_local_factor(Bufs<T> bf) {
   T fi[NB];
 #pragma unroll
   for (int q = 0; q < NB; ++q) fi[q] = M[NB + q];
-  st_row(bf.Finv + v * nn, fi, n, r, active);
   lds_put(LFi, fi, r);
   team_sync();
   T wv[NB];
   zero(wv);
   mac_rowL<T, NB, NB>(wv, 0, pv, LFi);  // W = P F^-1
-  st_row(bf.W + v * nn, wv, n, r, active);
+  lds_put(LDe, wv, r);                  // Delta is dead: its tile keeps W
   // WB row r
   T wb[MB];
 #pragma unroll
@@ -423,7 +481,7 @@ RCR_MAT_KERNEL(NB) void k_local_factor(Bufs<T> bf) {
   // H^T row r = (A^T WB)[r] + M[r];  G = R + B^T WB by lanes c < m (float64)
   double ht[MB];
 #pragma unroll
-  for (int c = 0; c < MB; ++c) ht[c] = (r < n && c < m) ? bf.S[v * nm + (int64_t)r * m + c] : 0.0;
+  for (int c = 0; c < MB; ++c) ht[c] = LS[rr * MB + c];
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
     const double akr = (double)LA[k * NB + rr];
@@ -433,7 +491,7 @@ RCR_MAT_KERNEL(NB) void k_local_factor(Bufs<T> bf) {
   }
   for (int c = r; c < MB; c += TW) {
     for (int d = 0; d < MB; ++d) {
-      double g = (c < m && d < m) ? bf.R[v * m * m + c * m + d] : (c == d ? 1.0 : 0.0);
+      double g = (c < m && d < m) ? LR[c * MB + d] : (c == d ? 1.0 : 0.0);
       for (int k = 0; k < NB; ++k) g = fma((double)LB[k * MB + c], (double)LWB[k * MB + d], g);
       LG[c * MB + d] = g;
     }
@@ -454,7 +512,7 @@ RCR_MAT_KERNEL(NB) void k_local_factor(Bufs<T> bf) {
     }
   }
   team_sync();
-  // K^T row r = -G^{-1} H^T[r]  (two triangular solves)
+  // K^T row r = -G^{-1} H^T[r]  (two triangular solves); zero at the root
 #pragma unroll
   for (int c = 0; c < MB; ++c) {
     double t = ht[c];
@@ -471,17 +529,12 @@ RCR_MAT_KERNEL(NB) void k_local_factor(Bufs<T> bf) {
   }
   T kt[MB];
 #pragma unroll
-  for (int c = 0; c < MB; ++c) kt[c] = (T)(-ht[c]);
-  if (active && r < n) {
-#pragma unroll
-    for (int c = 0; c < MB; ++c)
-      if (c < m) bf.Kw[v * nm + (int64_t)c * n + r] = isroot ? (T)0 : kt[c];
-  }
-  if (r < NB) {
+  for (int c = 0; c < MB; ++c) kt[c] = isroot ? (T)0 : (T)(-ht[c]);
+  if (r < NB) {  // WB was last read before the Cholesky
 #pragma unroll
     for (int c = 0; c < MB; ++c) LKt[r * MB + c] = kt[c];
   }
-  // G^{-1} rows c (lanes c < m)
+  // G^{-1} rows c (lanes c < m), m x m per edge
   for (int c = r; c < m; c += TW) {
     double e[MB];
 #pragma unroll
@@ -518,13 +571,19 @@ RCR_MAT_KERNEL(NB) void k_local_factor(Bufs<T> bf) {
     pin1(acl[q]);
     mem_fence_compiler();
   }
-  st_row(bf.Acl + v * nn, acl, n, r, edge);
-  lds_put(LP, acl, r);  // A^cl replaces P in LDS
+  lds_put(LP, acl, r);  // A^cl replaces P
   team_sync();
   T tv[NB];
   zero(tv);
   mac_rowL<T, NB, NB>(tv, 0, fi, LP);  // T = F^-1 A^cl
-  st_row(bf.Tm + v * nn, tv, n, r, edge);
+  lds_put(LA, tv, r);                  // A was last read for H^T
+  team_sync();
+  stage_store<PW, NB, NB>(bf.Finv, smt + Ly::Fi, TST, v0, cnt, n, n, lane);
+  stage_store<PW, NB, NB>(bf.W, smt + Ly::D, TST, v0, cnt, n, n, lane);
+  stage_store<PW, NB, NB>(bf.Acl, smt + Ly::P, TST, v0, cnt, n, n, lane, noedge, TW);
+  stage_store<PW, NB, NB>(bf.Tm, smt + Ly::A, TST, v0, cnt, n, n, lane, noedge, TW);
+  stage_store<PW, MB, NB, true>(bf.Kw, smt + Ly::WB, TST, v0, cnt, m, n, lane);  // K = (K^T)^T, m x n
+  (void)nm;
 }
 
 // Composite transition of one compression on a team: T_new = T_r T_l.
@@ -558,34 +617,59 @@ RCR_MAT_KERNEL(NB) void k_tcompose(Bufs<T> bf, const Op4 *__restrict__ ops, int6
 // Vector primitives: one team per op, lane r computes entry r.  Inputs that
 // every lane needs are read from global memory (broadcast within a team).
 
+// Per-team LDS of k_rhs_init (words of T): W, A^cl (NB x NB), K (MB x NB),
+// c, W c, z (NB), r (MB).
+template <int NB, int MB>
+struct RhsLay {
+  static constexpr int W = 0, Acl = NB * NB, K = 2 * NB * NB, c = K + MB * NB, wc = c + NB, z = wc + NB,
+                       r = z + NB, words = r + MB;
+};
+
 template <typename T, int NB, int MB>
 __global__ __launch_bounds__(64) void k_rhs_init(Bufs<T> bf) {
   // h_i = q_i;  z_e = K_e^T r_e + (A^cl_e)^T W_j c_j  (eq. (affine-edge))
-  constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW;
-  const int team = threadIdx.x / TW, r = threadIdx.x % TW;
-  const int64_t v = (int64_t)blockIdx.x * PW + team;
-  if (v >= bf.N) return;
+  using Ly = RhsLay<NB, MB>;
+  constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW, TS = Ly::words;
+  extern __shared__ double smd[];
+  T *smt = reinterpret_cast<T *>(smd);
+  const int lane = threadIdx.x & 63, team = lane / TW, r = lane % TW;
+  const int64_t v0 = (int64_t)blockIdx.x * PW;
+  const int cnt = (int)((bf.N - v0) < PW ? (bf.N - v0) : PW);
   const int n = bf.n, m = bf.m;
-  const int64_t nn = (int64_t)n * n;
-  if (r < n) bf.h[v * n + r] = bf.sq[v * n + r];
-  if (bf.parent[v] < 0) {
-    if (r < n) bf.z[v * n + r] = (T)0;
-    return;
+  range_copy<PW * NB>(bf.h + v0 * n, bf.sq + v0 * n, cnt * n, lane);  // h = q
+  {
+    T rw[Tile<PW, NB, NB>::IT], ra[Tile<PW, NB, NB>::IT], rk[Tile<PW, MB, NB>::IT];
+    T rc[Tile<PW, 1, NB>::IT], rr_[Tile<PW, 1, MB>::IT];
+    stage_load<PW, NB, NB>(rw, bf.W, v0, cnt, n, n, lane);
+    stage_load<PW, NB, NB>(ra, bf.Acl, v0, cnt, n, n, lane);
+    stage_load<PW, MB, NB>(rk, bf.Kw, v0, cnt, m, n, lane);
+    stage_load<PW, 1, NB>(rc, bf.sc, v0, cnt, 1, n, lane);
+    stage_load<PW, 1, MB>(rr_, bf.sr, v0, cnt, 1, m, lane);
+    stage_put<PW, NB, NB>(smt + Ly::W, TS, rw, lane);
+    stage_put<PW, NB, NB>(smt + Ly::Acl, TS, ra, lane);
+    stage_put<PW, MB, NB>(smt + Ly::K, TS, rk, lane);
+    stage_put<PW, 1, NB>(smt + Ly::c, TS, rc, lane);
+    stage_put<PW, 1, MB>(smt + Ly::r, TS, rr_, lane);
   }
+  team_sync();
+  const bool active = team < cnt;
+  const int64_t v = v0 + (active ? team : 0);
+  const bool edge = active && bf.parent[v] >= 0;
+  T *L = smt + team * TS;
+  const int rr = r < NB ? r : NB - 1;
   T wc = (T)0;
 #pragma unroll
-  for (int k = 0; k < NB; ++k)
-    if (r < n && k < n) wc = fmat(bf.W[v * nn + r * n + k], bf.sc[v * n + k], wc);
+  for (int k = 0; k < NB; ++k) wc = fmat(L[Ly::W + rr * NB + k], L[Ly::c + k], wc);
+  if (r < NB) L[Ly::wc + r] = wc;
+  team_sync();
   T s = (T)0;
 #pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    const T wk = __shfl(wc, k, TW);
-    if (r < n && k < n) s = fmat(bf.Acl[v * nn + k * n + r], wk, s);
-  }
+  for (int k = 0; k < NB; ++k) s = fmat(L[Ly::Acl + k * NB + rr], L[Ly::wc + k], s);
 #pragma unroll
-  for (int k = 0; k < MB; ++k)
-    if (r < n && k < m) s = fmat(bf.Kw[v * n * m + k * n + r], bf.sr[v * m + k], s);
-  if (r < n) bf.z[v * n + r] = s;
+  for (int k = 0; k < MB; ++k) s = fmat(L[Ly::K + k * NB + rr], L[Ly::r + k], s);
+  if (r < NB) L[Ly::z + r] = edge ? s : (T)0;  // no edge at the root: z = 0
+  team_sync();
+  stage_store<PW, 1, NB>(bf.z, smt + Ly::z, TS, v0, cnt, 1, n, lane);
 }
 
 // One affine-contraction primitive of kind s (lane r of its team).
@@ -651,69 +735,102 @@ __global__ __launch_bounds__(64) void k_aff_expand(Bufs<T> bf, const Op4 *__rest
   affexp_op<T, NB>(bf, ops[off + q0], r);
 }
 
+// Per-team LDS of k_local_affine (words of T): Delta, W, Finv (NB x NB),
+// B (NB x MB), G^-1 (MB x MB), p, c, f, g, B k - f, b (NB), r, t, k (MB).
+template <int NB, int MB>
+struct LaLay {
+  static constexpr int D = 0, W = NB * NB, Fi = 2 * NB * NB, B = 3 * NB * NB, Gi = B + NB * MB, p = Gi + MB * MB,
+                       c = p + NB, f = c + NB, g = f + NB, wv = g + NB, b = wv + NB, r = b + NB, t = r + MB,
+                       k = t + MB, words = k + MB;
+};
+
 template <typename T, int NB, int MB>
 __global__ __launch_bounds__(64) void k_local_affine(Bufs<T> bf) {
   // f = Delta p - c, g = p - W f; e = (parent, v): k = -G^-1 (r + B^T g),
   // b = F^-1 (B k - f); root: x = -F^-1 f.  Teams cover max(NB, MB) lanes.
+  using Ly = LaLay<NB, MB>;
   constexpr int NM = NB > MB ? NB : MB;
-  constexpr int TW = TeamW<NM>::TW, PW = TeamW<NM>::PW;
-  const int team = threadIdx.x / TW, r = threadIdx.x % TW;
-  const int64_t v = (int64_t)blockIdx.x * PW + team;
-  if (v >= bf.N) return;
+  constexpr int TW = TeamW<NM>::TW, PW = TeamW<NM>::PW, TS = Ly::words;
+  extern __shared__ double smd[];
+  T *smt = reinterpret_cast<T *>(smd);
+  const int lane = threadIdx.x & 63, team = lane / TW, r = lane % TW;
+  const int64_t v0 = (int64_t)blockIdx.x * PW;
+  const int cnt = (int)((bf.N - v0) < PW ? (bf.N - v0) : PW);
   const int n = bf.n, m = bf.m;
-  const int64_t nn = (int64_t)n * n, nm = (int64_t)n * m;
-  const bool isroot = (bf.parent[v] < 0);
-  const T *pv = isroot ? bf.h + v * n : bf.p + v * n;
-  T f = (T)0;
-  if (r < n) {
-    f = -bf.sc[v * n + r];
-#pragma unroll
-    for (int k = 0; k < NB; ++k)
-      if (k < n) f = fmat((T)bf.De[v * nn + r * n + k], pv[k], f);
+  {
+    double rd[Tile<PW, NB, NB>::IT], rb[Tile<PW, NB, MB>::IT];
+    T rw[Tile<PW, NB, NB>::IT], rf[Tile<PW, NB, NB>::IT], rg[Tile<PW, MB, MB>::IT];
+    T rp[Tile<PW, 1, NB>::IT], rc[Tile<PW, 1, NB>::IT], rr_[Tile<PW, 1, MB>::IT];
+    stage_load<PW, NB, NB>(rd, bf.De, v0, cnt, n, n, lane);
+    stage_load<PW, NB, NB>(rw, bf.W, v0, cnt, n, n, lane);
+    stage_load<PW, NB, NB>(rf, bf.Finv, v0, cnt, n, n, lane);
+    stage_load<PW, NB, MB>(rb, bf.B, v0, cnt, n, m, lane);
+    stage_load<PW, MB, MB>(rg, bf.Ginv, v0, cnt, m, m, lane);
+    stage_load<PW, 1, NB>(rp, bf.p, v0, cnt, 1, n, lane);
+    stage_load<PW, 1, NB>(rc, bf.sc, v0, cnt, 1, n, lane);
+    stage_load<PW, 1, MB>(rr_, bf.sr, v0, cnt, 1, m, lane);
+    stage_put<PW, NB, NB>(smt + Ly::D, TS, rd, lane);
+    stage_put<PW, NB, NB>(smt + Ly::W, TS, rw, lane);
+    stage_put<PW, NB, NB>(smt + Ly::Fi, TS, rf, lane);
+    stage_put<PW, NB, MB>(smt + Ly::B, TS, rb, lane);
+    stage_put<PW, MB, MB>(smt + Ly::Gi, TS, rg, lane);
+    stage_put<PW, 1, NB>(smt + Ly::p, TS, rp, lane);
+    stage_put<PW, 1, NB>(smt + Ly::c, TS, rc, lane);
+    stage_put<PW, 1, MB>(smt + Ly::r, TS, rr_, lane);
   }
-  if (isroot) {
-    if (r < n) bf.p[v * n + r] = pv[r];
+  team_sync();
+  const bool active = team < cnt;
+  const int64_t v = v0 + (active ? team : 0);
+  const bool isroot = active && bf.parent[v] < 0;
+  const bool edge = active && !isroot;
+  const uint64_t noedge = __ballot(r == 0 && !edge);
+  T *L = smt + team * TS;
+  if (isroot && r < n) {  // the root's value vector is h_root; it is also p_root
+    const T hv = bf.h[v * n + r];
+    L[Ly::p + r] = hv;
+    bf.p[v * n + r] = hv;
+  }
+  team_sync();
+  const int rr = r < NB ? r : NB - 1;
+  const int rm = r < MB ? r : MB - 1;
+  T f = -L[Ly::c + rr];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) f = fmat(L[Ly::D + rr * NB + k], L[Ly::p + k], f);
+  if (r < NB) L[Ly::f + r] = f;
+  team_sync();
+  if (isroot) {  // x_root = -F^-1 f  (eq. (xroot))
     T x = (T)0;
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      const T fk = __shfl(f, k, TW);
-      if (r < n && k < n) x = fmat(-bf.Finv[v * nn + r * n + k], fk, x);
-    }
+    for (int k = 0; k < NB; ++k) x = fmat(-L[Ly::Fi + rr * NB + k], L[Ly::f + k], x);
     if (r < n) bf.xw[v * n + r] = x;
-    return;
   }
-  T g = (r < n) ? pv[r] : (T)0;
+  T g = L[Ly::p + rr];
 #pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    const T fk = __shfl(f, k, TW);
-    if (r < n && k < n) g = fmat(-bf.W[v * nn + r * n + k], fk, g);
-  }
-  T t = (r < m) ? bf.sr[v * m + r] : (T)0;  // lane c < m: r_c + (B^T g)_c
+  for (int k = 0; k < NB; ++k) g = fmat(-L[Ly::W + rr * NB + k], L[Ly::f + k], g);
+  if (r < NB) L[Ly::g + r] = g;
+  team_sync();
+  T t = L[Ly::r + rm];  // lane c < m: r_c + (B^T g)_c
 #pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    const T gk = __shfl(g, k, TW);
-    if (r < m && k < n) t = fmat((T)bf.B[v * nm + k * m + r], gk, t);
-  }
+  for (int k = 0; k < NB; ++k) t = fmat(L[Ly::B + k * MB + rm], L[Ly::g + k], t);
+  if (r < MB) L[Ly::t + r] = t;
+  team_sync();
   T kk = (T)0;
 #pragma unroll
-  for (int d = 0; d < MB; ++d) {
-    const T td = __shfl(t, d < TW ? d : 0, TW);
-    if (r < m && d < m) kk = fmat(-bf.Ginv[v * m * m + r * m + d], td, kk);
-  }
-  if (r < m) bf.kff[v * m + r] = kk;
+  for (int d = 0; d < MB; ++d) kk = fmat(-L[Ly::Gi + rm * MB + d], L[Ly::t + d], kk);
+  if (r < MB) L[Ly::k + r] = kk;
+  team_sync();
   T wv = -f;  // lane r < n: (B k - f)_r
 #pragma unroll
-  for (int d = 0; d < MB; ++d) {
-    const T kd = __shfl(kk, d < TW ? d : 0, TW);
-    if (r < n && d < m) wv = fmat((T)bf.B[v * nm + r * m + d], kd, wv);
-  }
+  for (int d = 0; d < MB; ++d) wv = fmat(L[Ly::B + rr * MB + d], L[Ly::k + d], wv);
+  if (r < NB) L[Ly::wv + r] = wv;
+  team_sync();
   T bb = (T)0;
 #pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    const T wk = __shfl(wv, k, TW);
-    if (r < n && k < n) bb = fmat(bf.Finv[v * nn + r * n + k], wk, bb);
-  }
-  if (r < n) bf.b[v * n + r] = bb;
+  for (int k = 0; k < NB; ++k) bb = fmat(L[Ly::Fi + rr * NB + k], L[Ly::wv + k], bb);
+  if (r < NB) L[Ly::b + r] = bb;
+  team_sync();
+  stage_store<PW, 1, MB>(bf.kff, smt + Ly::k, TS, v0, cnt, 1, m, lane, noedge, TW);
+  stage_store<PW, 1, NB>(bf.b, smt + Ly::b, TS, v0, cnt, 1, n, lane, noedge, TW);
 }
 
 // State-offset composition of one compression: b_new = T_r b_l + b_r.
@@ -764,37 +881,65 @@ __global__ __launch_bounds__(64) void k_state_expand(Bufs<T> bf, const Op4 *__re
   sexp_op<T, NB>(bf, ops[off + q0], r);
 }
 
+// Per-team LDS of k_recover (words of T): P (NB x NB), K (MB x NB), x, p,
+// x of the parent, y (NB), k, u (MB).
+template <int NB, int MB>
+struct RecLay {
+  static constexpr int P = 0, K = NB * NB, x = K + MB * NB, p = x + NB, xp = p + NB, y = xp + NB, k = y + NB,
+                       u = k + MB, words = u + MB;
+};
+
 template <typename T, int NB, int MB>
 __global__ __launch_bounds__(64) void k_recover(Bufs<T> bf) {
   // y_v = P_v x_v + p_v;  u_e = K_e x_parent + k_e;  non-finite check
-  constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW;
-  const int team = threadIdx.x / TW, r = threadIdx.x % TW;
-  const int64_t v = (int64_t)blockIdx.x * PW + team;
-  if (v >= bf.N) return;
+  using Ly = RecLay<NB, MB>;
+  constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW, TS = Ly::words;
+  extern __shared__ double smd[];
+  T *smt = reinterpret_cast<T *>(smd);
+  const int lane = threadIdx.x & 63, team = lane / TW, r = lane % TW;
+  const int64_t v0 = (int64_t)blockIdx.x * PW;
+  const int cnt = (int)((bf.N - v0) < PW ? (bf.N - v0) : PW);
   const int n = bf.n, m = bf.m;
-  const int64_t nn = (int64_t)n * n, nm = (int64_t)n * m;
-  bool bad = false;
-  if (r < n) {
-    T y = bf.p[v * n + r];
-#pragma unroll
-    for (int k = 0; k < NB; ++k)
-      if (k < n) y = fmat(bf.PW[v * nn + r * n + k], bf.xw[v * n + k], y);
-    bf.yw[v * n + r] = y;
-    bad = !isfinite((double)y) || !isfinite((double)bf.xw[v * n + r]);
+  {
+    T rp[Tile<PW, NB, NB>::IT], rk[Tile<PW, MB, NB>::IT], rx[Tile<PW, 1, NB>::IT], rv[Tile<PW, 1, NB>::IT];
+    T rf[Tile<PW, 1, MB>::IT];
+    stage_load<PW, NB, NB>(rp, bf.PW, v0, cnt, n, n, lane);
+    stage_load<PW, MB, NB>(rk, bf.Kw, v0, cnt, m, n, lane);
+    stage_load<PW, 1, NB>(rx, bf.xw, v0, cnt, 1, n, lane);
+    stage_load<PW, 1, NB>(rv, bf.p, v0, cnt, 1, n, lane);
+    stage_load<PW, 1, MB>(rf, bf.kff, v0, cnt, 1, m, lane);
+    stage_put<PW, NB, NB>(smt + Ly::P, TS, rp, lane);
+    stage_put<PW, MB, NB>(smt + Ly::K, TS, rk, lane);
+    stage_put<PW, 1, NB>(smt + Ly::x, TS, rx, lane);
+    stage_put<PW, 1, NB>(smt + Ly::p, TS, rv, lane);
+    stage_put<PW, 1, MB>(smt + Ly::k, TS, rf, lane);
   }
-  for (int c = r; c < m; c += TW) {
-    T u = (T)0;
-    const int64_t i = bf.parent[v];
-    if (i >= 0) {
-      u = bf.kff[v * m + c];
+  const bool active = team < cnt;
+  const int64_t v = v0 + (active ? team : 0);
+  const int64_t i = active ? (int64_t)bf.parent[v] : -1;
+  T *L = smt + team * TS;
+  if (r < NB) L[Ly::xp + r] = (i >= 0 && r < n) ? bf.xw[i * n + r] : (T)0;  // x of the parent (a gather)
+  team_sync();
+  const int rr = r < NB ? r : NB - 1;
+  T y = L[Ly::p + rr];
 #pragma unroll
-      for (int k = 0; k < NB; ++k)
-        if (k < n) u = fmat(bf.Kw[v * nm + c * n + k], bf.xw[i * n + k], u);
+  for (int k = 0; k < NB; ++k) y = fmat(L[Ly::P + rr * NB + k], L[Ly::x + k], y);
+  if (r < NB) L[Ly::y + r] = y;
+  bool bad = active && r < n && (!isfinite((double)y) || !isfinite((double)L[Ly::x + r]));
+  for (int c = r; c < MB; c += TW) {
+    T u = (T)0;
+    if (i >= 0) {
+      u = L[Ly::k + c];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) u = fmat(L[Ly::K + c * NB + k], L[Ly::xp + k], u);
     }
-    bf.uw[v * m + c] = u;
-    bad = bad || !isfinite((double)u);
+    L[Ly::u + c] = u;
+    bad = bad || (active && c < m && !isfinite((double)u));
   }
   if (bad) atomicOr(bf.status, ST_NONFINITE);
+  team_sync();
+  stage_store<PW, 1, NB>(bf.yw, smt + Ly::y, TS, v0, cnt, 1, n, lane);
+  stage_store<PW, 1, MB>(bf.uw, smt + Ly::u, TS, v0, cnt, 1, m, lane);
 }
 
 }  // namespace rcr

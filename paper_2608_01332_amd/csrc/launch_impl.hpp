@@ -106,9 +106,17 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
   constexpr int NM = NB > MB ? NB : MB;
   constexpr int PWm = TeamW<NM>::PW;
   constexpr bool WIDE = MatLay<NB>::WIDE;  // one primitive per wavefront for the level kernels
-  const size_t lds_cond = (size_t)PW * (MB * MB + 2 * NB * MB) * sizeof(double);
+  const size_t lds_cond = (size_t)PW * CondLay<NB, MB>::words * sizeof(double);
   const size_t lds_quad = (size_t)PW * lds_quad_words<T, NB>() * sizeof(T);
-  const size_t lds_lf = (size_t)PW * lds_lf_words<T, NB, MB>() * sizeof(T);
+  const size_t lds_lf = (size_t)PW * LfLay<T, NB, MB>::words * sizeof(double);
+  const size_t lds_rhs = (size_t)PW * RhsLay<NB, MB>::words * sizeof(T);
+  const size_t lds_la = (size_t)PWm * LaLay<NB, MB>::words * sizeof(T);
+  const size_t lds_rec = (size_t)PW * RecLay<NB, MB>::words * sizeof(T);
+  allow_lds(k_condense<T, NB, MB>, lds_cond);
+  allow_lds(k_local_factor<T, NB, MB>, lds_lf);
+  allow_lds(k_rhs_init<T, NB, MB>, lds_rhs);
+  allow_lds(k_local_affine<T, NB, MB>, lds_la);
+  allow_lds(k_recover<T, NB, MB>, lds_rec);
   const size_t lds_wide = (size_t)wide_lds_words<T, (NB >= 12 ? NB : 12)>() * sizeof(T);
   const size_t lds_lvl = WIDE ? lds_wide : lds_quad;  // per wavefront, level kernels
   const unsigned NBk = blocks_for(h.N, PW);
@@ -191,7 +199,7 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
   } else {
   // ---- solve: affine contraction and expansion
   tm.begin(RCR_K_RHS_INIT);
-  LAUNCH(tm, (k_rhs_init<T, NB, MB>), dim3(NBk), dim3(64), 0, st, bf);
+  LAUNCH(tm, (k_rhs_init<T, NB, MB>), dim3(NBk), dim3(64), lds_rhs, st, bf);
   tm.begin(RCR_K_AFF_CONTRACT);
   for (int64_t t = 0; t < ta.c_begin; ++t) {
     Seg sg;
@@ -211,7 +219,7 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
              h.exp_off[t], cnt);
   }
   tm.begin(RCR_K_LOCAL_AFFINE);
-  LAUNCH(tm, (k_local_affine<T, NB, MB>), dim3(blocks_for(h.N, PWm)), dim3(64), 0, st, bf);
+  LAUNCH(tm, (k_local_affine<T, NB, MB>), dim3(blocks_for(h.N, PWm)), dim3(64), lds_la, st, bf);
 
   // ---- state offsets and state expansion
   tm.begin(RCR_K_STATE_CONTRACT);
@@ -234,7 +242,7 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
              h.sx_off[t], cnt);
   }
   tm.begin(RCR_K_RECOVER);
-  LAUNCH(tm, (k_recover<T, NB, MB>), dim3(NBk), dim3(64), 0, st, bf);
+  LAUNCH(tm, (k_recover<T, NB, MB>), dim3(NBk), dim3(64), lds_rec, st, bf);
   }
   HIPCK(hipGetLastError());
   return RCR_OK;

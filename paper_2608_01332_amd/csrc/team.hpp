@@ -243,4 +243,89 @@ __device__ __forceinline__ void sym_store(T *__restrict__ g, const T (&row)[NB],
   team_sync();
 }
 
+// ---------------------------------------------------------------- staging
+// The PW consecutive nodes [v0, v0 + cnt) of one wavefront own a contiguous
+// range of every per-node array.  A tile copies such a range between global
+// memory (rn x cn words per node, row-major) and per-team LDS tiles padded to
+// RB x CB (team t's tile at lds + t * ts).  Consecutive lanes take consecutive
+// padded positions, so the active lanes of one access cover one contiguous
+// global range; every load of a tile is issued before any LDS write.
+// Padded positions of the LDS tile are written as zero.
+template <int PW, int RB, int CB>
+struct Tile {
+  static constexpr int TOT = PW * RB * CB;
+  static constexpr int IT = (TOT + 63) / 64;
+};
+
+template <int PW, int RB, int CB, typename S>
+__device__ __forceinline__ void stage_load(S (&reg)[(PW * RB * CB + 63) / 64], const S *__restrict__ g, int64_t v0,
+                                          int cnt, int rn, int cn, int lane) {
+  constexpr int TOT = Tile<PW, RB, CB>::TOT;
+  const int64_t w = (int64_t)rn * cn;
+#pragma unroll
+  for (int k = 0; k < Tile<PW, RB, CB>::IT; ++k) {
+    const int p = lane + 64 * k;
+    const int t = p / (RB * CB), r = (p / CB) % RB, j = p % CB;
+    const bool ok = p < TOT && t < cnt && r < rn && j < cn;
+    reg[k] = ok ? g[(v0 + t) * w + r * cn + j] : (S)0;
+  }
+}
+
+template <int PW, int RB, int CB, typename S, typename T>
+__device__ __forceinline__ void stage_put(T *lds, int ts, const S (&reg)[(PW * RB * CB + 63) / 64], int lane) {
+  constexpr int TOT = Tile<PW, RB, CB>::TOT;
+#pragma unroll
+  for (int k = 0; k < Tile<PW, RB, CB>::IT; ++k) {
+    const int p = lane + 64 * k;
+    if (p < TOT) {
+      const int t = p / (RB * CB), r = (p / CB) % RB, j = p % CB;
+      lds[t * ts + r * CB + j] = (T)reg[k];
+    }
+  }
+}
+
+// LDS tiles -> global rows of nodes t < cnt.  Bit t * tw of `skip` (a ballot
+// over lanes, tw = team width) marks a team whose node is not written.  With
+// TRANS, the LDS tile holds the transpose of the global block (LDS row j,
+// column r -> global row r, column j; the LDS tile is CB x RB).
+template <int PW, int RB, int CB, bool TRANS = false, typename T, typename D>
+__device__ __forceinline__ void stage_store(D *__restrict__ g, const T *lds, int ts, int64_t v0, int cnt, int rn,
+                                           int cn, int lane, uint64_t skip = 0, int tw = 64) {
+  constexpr int TOT = Tile<PW, RB, CB>::TOT;
+  const int64_t w = (int64_t)rn * cn;
+#pragma unroll
+  for (int k = 0; k < Tile<PW, RB, CB>::IT; ++k) {
+    const int p = lane + 64 * k;
+    const int t = p / (RB * CB), r = (p / CB) % RB, j = p % CB;
+    const bool skipped = (skip >> ((t * tw) & 63)) & 1;
+    if (p < TOT && t < cnt && !skipped && r < rn && j < cn)
+      g[(v0 + t) * w + r * cn + j] = (D)(TRANS ? lds[t * ts + j * RB + r] : lds[t * ts + r * CB + j]);
+  }
+}
+
+// Contiguous copy of `count` words (at most PW * MAXW), converted to D.
+template <int MAXC, typename S, typename D>
+__device__ __forceinline__ void range_copy(D *__restrict__ dst, const S *__restrict__ src, int count, int lane) {
+  S reg[(MAXC + 63) / 64];
+#pragma unroll
+  for (int k = 0; k < (MAXC + 63) / 64; ++k) {
+    const int e = lane + 64 * k;
+    reg[k] = e < count ? src[e] : (S)0;
+  }
+#pragma unroll
+  for (int k = 0; k < (MAXC + 63) / 64; ++k) {
+    const int e = lane + 64 * k;
+    if (e < count) dst[e] = (D)reg[k];
+  }
+}
+
+// Row r of a team's padded LDS tile (RB rows of CB words) into registers
+// (lanes r >= RB read the last row; their values are not used).
+template <int RB, int CB, typename T, typename S>
+__device__ __forceinline__ void stage_row(T (&row)[CB], const S *tile, int r) {
+  const int rr = r < RB ? r : RB - 1;
+#pragma unroll
+  for (int j = 0; j < CB; ++j) row[j] = (T)tile[rr * CB + j];
+}
+
 }  // namespace rcr
