@@ -54,11 +54,11 @@ __device__ __forceinline__ void tau_team(T *__restrict__ out, const T (&a)[NB], 
     M[NB + q] = a[q];
   }
   mac_rowL<T, NB, W>(M, 0, c, LU);  // I + C Ux  |  A
-  gj_team<T, NB, W, TW>(M, Lp, r, status);
+  const int row = gj_team<T, NB, W, TW>(M, Lp, r, status);
   T x[NB];
 #pragma unroll
   for (int q = 0; q < NB; ++q) x[q] = M[NB + q];
-  lds_put(LX, x, r);
+  lds_put_at(LX, x, row, r);
   team_sync();
   T y[NB];
   zero(y);
@@ -280,7 +280,7 @@ __device__ __forceinline__ void quad_op_team(const Bufs<T> &bf, const OpRec &o, 
       mac_rowL<ST, NB, W>(M, 0, cl, LPt);        // S = I + C_l Pt
       mac_rowLt<ST, NB, W>(M, 2 * NB, cl, LAr);  // C_l A_r^T
     }
-    gj_team<ST, NB, W, TW>(M, reinterpret_cast<ST *>(Lp), r, bf.status);
+    const int row = gj_team<ST, NB, W, TW>(M, reinterpret_cast<ST *>(Lp), r, bf.status);
     {
       T x[NB], y[NB];
 #pragma unroll
@@ -288,8 +288,8 @@ __device__ __forceinline__ void quad_op_team(const Bufs<T> &bf, const OpRec &o, 
         x[q] = (T)M[NB + q];
         y[q] = (T)M[2 * NB + q];
       }
-      lds_put(LX, x, r);
-      lds_put(LY, y, r);
+      lds_put_at(LX, x, row, r);
+      lds_put_at(LY, y, row, r);
     }
     team_sync();
     T cn[NB];
@@ -379,15 +379,17 @@ RCR_MAT_KERNEL(NB) void k_quad_expand(Bufs<T> bf, const Op4 *__restrict__ ops, i
   qexp_op_team<T, NB>(bf, o, L, r, active);
 }
 
-// Per-team LDS of k_local_factor.  Words of T: P (later A^cl), Finv, A
-// (later T = F^-1 A^cl), Delta (later W), B, WB (later K^T), pivot slots;
-// then doubles: S (NB x MB), R and G (MB x MB).
+// Per-team LDS of k_local_factor.  Words of T: P (then W, then A^cl), Finv,
+// A (later T = F^-1 A^cl), B, WB (later K^T), pivot slots; then doubles: G
+// (MB x MB).  Delta, S and R are read by their rows' own lanes straight from
+// global memory, which keeps the footprint (and so the occupancy) of this
+// latency-bound kernel at eight wavefronts per compute unit for NB = 12.
 template <typename T, int NB, int MB>
 struct LfLay {
-  static constexpr int P = 0, Fi = NB * NB, A = 2 * NB * NB, D = 3 * NB * NB, B = 4 * NB * NB, WB = B + NB * MB,
-                       Lp = WB + NB * MB, tend = Lp + 4 * NB;
+  static constexpr int P = 0, Fi = NB * NB, A = 2 * NB * NB, B = 3 * NB * NB, WB = B + NB * MB, Lp = WB + NB * MB,
+                       tend = Lp + 4 * NB;
   static constexpr int dbeg = (tend * (int)sizeof(T) + 7) / 8;  // in doubles
-  static constexpr int S = dbeg, R = S + NB * MB, G = R + MB * MB, words = G + MB * MB;  // doubles per team
+  static constexpr int G = dbeg, words = G + MB * MB;            // doubles per team
 };
 
 template <typename T, int NB, int MB>
@@ -408,20 +410,13 @@ RCR_MAT_KERNEL(NB) void k_local_factor(Bufs<T> bf) {
   const int64_t nn = (int64_t)n * n, nm = (int64_t)n * m;
   {
     T rp[Tile<PW, NB, NB>::IT];
-    double rd[Tile<PW, NB, NB>::IT], ra[Tile<PW, NB, NB>::IT];
+    double ra[Tile<PW, NB, NB>::IT], rb[Tile<PW, NB, MB>::IT];
     stage_load<PW, NB, NB>(rp, bf.PW, v0, cnt, n, n, lane);
-    stage_load<PW, NB, NB>(rd, bf.De, v0, cnt, n, n, lane);
     stage_load<PW, NB, NB>(ra, bf.A, v0, cnt, n, n, lane);
-    double rb[Tile<PW, NB, MB>::IT], rs[Tile<PW, NB, MB>::IT], rq[Tile<PW, MB, MB>::IT];
     stage_load<PW, NB, MB>(rb, bf.B, v0, cnt, n, m, lane);
-    stage_load<PW, NB, MB>(rs, bf.S, v0, cnt, n, m, lane);
-    stage_load<PW, MB, MB>(rq, bf.R, v0, cnt, m, m, lane);
     stage_put<PW, NB, NB>(smt + Ly::P, TST, rp, lane);
-    stage_put<PW, NB, NB>(smt + Ly::D, TST, rd, lane);
     stage_put<PW, NB, NB>(smt + Ly::A, TST, ra, lane);
     stage_put<PW, NB, MB>(smt + Ly::B, TST, rb, lane);
-    stage_put<PW, NB, MB>(smd + Ly::S, TS, rs, lane);
-    stage_put<PW, MB, MB>(smd + Ly::R, TS, rq, lane);
   }
   team_sync();
   const bool active = team < cnt;
@@ -430,9 +425,9 @@ RCR_MAT_KERNEL(NB) void k_local_factor(Bufs<T> bf) {
   const bool edge = active && !isroot;
   const uint64_t noedge = __ballot(r == 0 && !edge);
   T *L = smt + team * TST;
-  T *LP = L + Ly::P, *LFi = L + Ly::Fi, *LA = L + Ly::A, *LDe = L + Ly::D, *LB = L + Ly::B, *LWB = L + Ly::WB;
+  T *LP = L + Ly::P, *LFi = L + Ly::Fi, *LA = L + Ly::A, *LB = L + Ly::B, *LWB = L + Ly::WB;
   T *LKt = LWB, *Lp = L + Ly::Lp;
-  double *LS = smd + team * TS + Ly::S, *LR = smd + team * TS + Ly::R, *LG = smd + team * TS + Ly::G;
+  double *LG = smd + team * TS + Ly::G;
   if (isroot) {  // P_root = U_root (eq. (value-reconstruction) at the root), also its output
     T u[NB];
     ld_row(u, bf.U + v * nn, n, r);
@@ -443,7 +438,7 @@ RCR_MAT_KERNEL(NB) void k_local_factor(Bufs<T> bf) {
   const int rr = r < NB ? r : NB - 1;
   T pv[NB], dv[NB], av[NB], bv[MB];
   stage_row<NB, NB>(pv, LP, r);
-  stage_row<NB, NB>(dv, LDe, r);
+  ld_row(dv, bf.De + v * nn, n, r);
   stage_row<NB, NB>(av, LA, r);
   stage_row<NB, MB>(bv, LB, r);
   T M[W2];
@@ -453,16 +448,19 @@ RCR_MAT_KERNEL(NB) void k_local_factor(Bufs<T> bf) {
     M[NB + q] = (q == r) ? (T)1 : (T)0;
   }
   mac_rowL<T, NB, W2>(M, 0, dv, LP);  // F = I + Delta P  |  I
-  gj_team<T, NB, W2, TW>(M, Lp, r, bf.status);
+  const int row = gj_team<T, NB, W2, TW>(M, Lp, r, bf.status);
   T fi[NB];
 #pragma unroll
   for (int q = 0; q < NB; ++q) fi[q] = M[NB + q];
-  lds_put(LFi, fi, r);
+  lds_put_at(LFi, fi, row, r);
   team_sync();
+  lds_row(fi, LFi, r);  // row r of F^-1
   T wv[NB];
   zero(wv);
   mac_rowL<T, NB, NB>(wv, 0, pv, LFi);  // W = P F^-1
-  lds_put(LDe, wv, r);                  // Delta is dead: its tile keeps W
+  lds_put(LP, wv, r);                   // P was last read for F: its tile passes W out
+  team_sync();
+  stage_store<PW, NB, NB>(bf.W, smt + Ly::P, TST, v0, cnt, n, n, lane);
   // WB row r
   T wb[MB];
 #pragma unroll
@@ -481,7 +479,7 @@ RCR_MAT_KERNEL(NB) void k_local_factor(Bufs<T> bf) {
   // H^T row r = (A^T WB)[r] + M[r];  G = R + B^T WB by lanes c < m (float64)
   double ht[MB];
 #pragma unroll
-  for (int c = 0; c < MB; ++c) ht[c] = LS[rr * MB + c];
+  for (int c = 0; c < MB; ++c) ht[c] = (r < n && c < m) ? bf.S[v * nm + (int64_t)r * m + c] : 0.0;
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
     const double akr = (double)LA[k * NB + rr];
@@ -491,7 +489,7 @@ RCR_MAT_KERNEL(NB) void k_local_factor(Bufs<T> bf) {
   }
   for (int c = r; c < MB; c += TW) {
     for (int d = 0; d < MB; ++d) {
-      double g = (c < m && d < m) ? LR[c * MB + d] : (c == d ? 1.0 : 0.0);
+      double g = (c < m && d < m) ? bf.R[v * m * m + c * m + d] : (c == d ? 1.0 : 0.0);
       for (int k = 0; k < NB; ++k) g = fma((double)LB[k * MB + c], (double)LWB[k * MB + d], g);
       LG[c * MB + d] = g;
     }
@@ -571,7 +569,7 @@ RCR_MAT_KERNEL(NB) void k_local_factor(Bufs<T> bf) {
     pin1(acl[q]);
     mem_fence_compiler();
   }
-  lds_put(LP, acl, r);  // A^cl replaces P
+  lds_put(LP, acl, r);  // A^cl replaces W (already stored)
   team_sync();
   T tv[NB];
   zero(tv);
@@ -579,11 +577,9 @@ RCR_MAT_KERNEL(NB) void k_local_factor(Bufs<T> bf) {
   lds_put(LA, tv, r);                  // A was last read for H^T
   team_sync();
   stage_store<PW, NB, NB>(bf.Finv, smt + Ly::Fi, TST, v0, cnt, n, n, lane);
-  stage_store<PW, NB, NB>(bf.W, smt + Ly::D, TST, v0, cnt, n, n, lane);
   stage_store<PW, NB, NB>(bf.Acl, smt + Ly::P, TST, v0, cnt, n, n, lane, noedge, TW);
   stage_store<PW, NB, NB>(bf.Tm, smt + Ly::A, TST, v0, cnt, n, n, lane, noedge, TW);
   stage_store<PW, MB, NB, true>(bf.Kw, smt + Ly::WB, TST, v0, cnt, m, n, lane);  // K = (K^T)^T, m x n
-  (void)nm;
 }
 
 // Composite transition of one compression on a team: T_new = T_r T_l.

@@ -92,6 +92,31 @@ inline TailRange tail_range(const std::vector<int64_t> &coff, int kstride, int k
   return tr;
 }
 
+// LDS image of a vector tail (vec_tail_bytes) and the shrinking of its range
+// to an LDS budget: the wider boundary level leaves the tail first.
+inline size_t vec_tail_lds(const TailRange &tr, const std::vector<int64_t> &coff, int cstride, int cend, size_t rc,
+                           const std::vector<int64_t> &eoff) {
+  const int nc = tr.c_end - tr.c_begin, ne = tr.e_end - tr.e_begin;
+  const int64_t ncops = nc ? coff[(size_t)(tr.c_end - 1) * cstride + cend] - coff[(size_t)tr.c_begin * cstride] : 0;
+  const int64_t neops = eoff[tr.e_end] - eoff[tr.e_begin];
+  return (size_t)16 * (nc + ne) + rc * (size_t)ncops + 16 * (size_t)neops;
+}
+inline TailRange fit_vec_tail(TailRange tr, const std::vector<int64_t> &coff, int cstride, int cend, size_t rc,
+                              const std::vector<int64_t> &eoff, size_t budget) {
+  while (tr.levels() >= 2 && vec_tail_lds(tr, coff, cstride, cend, rc, eoff) > budget) {
+    const int64_t cw = tr.c_end > tr.c_begin ? coff[(size_t)tr.c_begin * cstride + cend] -
+                                                    coff[(size_t)tr.c_begin * cstride]
+                                              : -1;
+    const int64_t ew = tr.e_end > tr.e_begin ? eoff[tr.e_end] - eoff[tr.e_end - 1] : -1;
+    if (cw >= ew)
+      ++tr.c_begin;
+    else
+      --tr.e_end;
+  }
+  if (tr.levels() < 2) tr = TailRange{tr.c_end, tr.c_end, 0, 0};
+  return tr;
+}
+
 template <typename K>
 inline void allow_lds(K kernel, size_t bytes) {
   if (bytes > 65536) (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -118,6 +143,8 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
   allow_lds(k_local_affine<T, NB, MB>, lds_la);
   allow_lds(k_recover<T, NB, MB>, lds_rec);
   const size_t lds_wide = (size_t)wide_lds_words<T, (NB >= 12 ? NB : 12)>() * sizeof(T);
+  const size_t lds_wexp = (size_t)tau_lds_words<T, (NB >= 12 ? NB : 12)>() * sizeof(T);
+  const size_t lds_wtc = (size_t)2 * (NB >= 12 ? NB : 12) * (NB >= 12 ? NB : 12) * sizeof(T);
   const size_t lds_lvl = WIDE ? lds_wide : lds_quad;  // per wavefront, level kernels
   const unsigned NBk = blocks_for(h.N, PW);
   // tail workgroup sizes
@@ -127,13 +154,20 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
   const size_t lds_tail = (size_t)mat_waves * lds_lvl;
   const int64_t mat_cap = 2 * (int64_t)mat_waves * MatLay<NB>::PW;
   const int vec_waves = 16;
-  const int64_t vec_cap = 2 * (int64_t)vec_waves * (64 / TeamW<NB>::TW);
+  const int64_t vec_cap = 4 * (int64_t)vec_waves * (64 / TeamW<NB>::TW);
+  const size_t kVecTailLds = 144 * 1024;
   allow_lds(k_tail_quad<T, NB>, lds_tail);
   allow_lds(k_tail_tc<T, NB>, lds_tail);
   const TailRange tq = tail_range(h.kind_off, 5, 4, &h.exp_off, mat_cap);
   const TailRange ttc = tail_range(h.tc_off, 1, 1, nullptr, mat_cap);
-  const TailRange ta = tail_range(h.kind_off, 5, 4, &h.exp_off, vec_cap);
-  const TailRange ts = tail_range(h.tc_off, 1, 1, &h.sx_off, vec_cap);
+  const TailRange ta = fit_vec_tail(tail_range(h.kind_off, 5, 4, &h.exp_off, vec_cap), h.kind_off, 5, 4,
+                                    sizeof(OpRec), h.exp_off, kVecTailLds);
+  const TailRange ts = fit_vec_tail(tail_range(h.tc_off, 1, 1, &h.sx_off, vec_cap), h.tc_off, 1, 1, sizeof(Op4),
+                                    h.sx_off, kVecTailLds);
+  const size_t lds_ta = vec_tail_lds(ta, h.kind_off, 5, 4, sizeof(OpRec), h.exp_off);
+  const size_t lds_ts = vec_tail_lds(ts, h.tc_off, 1, 1, sizeof(Op4), h.sx_off);
+  allow_lds(k_tail_aff<T, NB>, lds_ta);
+  allow_lds(k_tail_state<T, NB>, lds_ts);
 
   auto seg_of = [&](int64_t t, Seg &sg, int per) {
     unsigned total = 0;
@@ -171,7 +205,7 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
     const int64_t cnt = h.exp_off[t + 1] - h.exp_off[t];
     if (cnt <= 0) continue;
     if constexpr (WIDE)
-      LAUNCH(tm, (k_quad_expand_wide<T, NB>), dim3((unsigned)cnt), dim3(64), lds_wide, st, bf, P.dev.exp_ops,
+      LAUNCH(tm, (k_quad_expand_wide<T, NB>), dim3((unsigned)cnt), dim3(64), lds_wexp, st, bf, P.dev.exp_ops,
              h.exp_off[t]);
     else
       LAUNCH(tm, (k_quad_expand<T, NB>), dim3(blocks_for(cnt, PW)), dim3(64), lds_quad, st, bf, P.dev.exp_ops,
@@ -186,7 +220,7 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
     const int64_t cnt = h.tc_off[t + 1] - h.tc_off[t];
     if (cnt <= 0) continue;
     if constexpr (WIDE)
-      LAUNCH(tm, (k_tcompose_wide<T, NB>), dim3((unsigned)cnt), dim3(64), lds_wide, st, bf, P.dev.tc_ops,
+      LAUNCH(tm, (k_tcompose_wide<T, NB>), dim3((unsigned)cnt), dim3(64), lds_wtc, st, bf, P.dev.tc_ops,
              h.tc_off[t]);
     else
       LAUNCH(tm, (k_tcompose<T, NB>), dim3(blocks_for(cnt, PW)), dim3(64), lds_quad, st, bf, P.dev.tc_ops,
@@ -208,7 +242,7 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
   }
   if (ta.levels() > 0) {
     tm.begin(RCR_K_AFF_TAIL);
-    LAUNCH(tm, (k_tail_aff<T, NB>), dim3(1), dim3(64 * vec_waves), 0, st, bf, P.dev.ops, P.dev.koff, ta.c_begin,
+    LAUNCH(tm, (k_tail_aff<T, NB>), dim3(1), dim3(64 * vec_waves), lds_ta, st, bf, P.dev.ops, P.dev.koff, ta.c_begin,
            ta.c_end, P.dev.exp_ops, P.dev.exp_off, ta.e_begin, ta.e_end);
   }
   tm.begin(RCR_K_AFF_EXPAND);
@@ -231,7 +265,7 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
   }
   if (ts.levels() > 0) {
     tm.begin(RCR_K_STATE_TAIL);
-    LAUNCH(tm, (k_tail_state<T, NB>), dim3(1), dim3(64 * vec_waves), 0, st, bf, P.dev.tc_ops, P.dev.tc_off,
+    LAUNCH(tm, (k_tail_state<T, NB>), dim3(1), dim3(64 * vec_waves), lds_ts, st, bf, P.dev.tc_ops, P.dev.tc_off,
            ts.c_begin, ts.c_end, P.dev.sx_ops, P.dev.sx_off, ts.e_begin, ts.e_end);
   }
   tm.begin(RCR_K_STATE_EXPAND);

@@ -98,6 +98,116 @@ RCR_TAIL_MAT_KERNEL(NB) void k_tail_tc(Bufs<T> bf, const Op4 *__restrict__ ops, 
   }
 }
 
+// ---------------------------------------------------------------- vector tails
+// The affine and state passes run matrix-vector primitives whose matrices
+// (the transitions T and their composites) are outputs of the factor, known
+// before the pass starts.  Their tail kernels therefore (1) copy the level
+// bounds and every op record of their levels into LDS once, and (2) prefetch,
+// one level ahead, the matrix column (affine: Z = T^T) or row (state) that
+// each team needs for its first primitive of the next level.  A level then
+// costs one round trip for the vectors the previous level wrote, the
+// arithmetic, and the workgroup barrier.
+struct VecTailLds {
+  int nl, nc;            // levels (contraction first), contraction levels
+  int64_t cbase, ebase;  // first contraction / expansion op of the tail
+  int64_t ncops, neops;
+  size_t bytes;
+};
+
+// LDS image: int64 level bounds (2 per level, relative to the op arrays in
+// LDS), then the contraction records (RC bytes each), then the expansion
+// records (Op4).
+template <int RC>
+__host__ __device__ inline size_t vec_tail_bytes(int nl, int64_t ncops, int64_t neops) {
+  return (size_t)16 * nl + (size_t)RC * ncops + sizeof(Op4) * neops;
+}
+
+// Copy the bounds and records into LDS (all threads), then barrier.
+template <typename RecC>
+__device__ __forceinline__ void vec_tail_stage(char *lds, const RecC *__restrict__ cops, const int64_t *__restrict__ coff,
+                                               int cstride, int cend, int t0, int t1, const Op4 *__restrict__ eops,
+                                               const int64_t *__restrict__ eoff, int e0, int e1, int64_t &cbase,
+                                               int64_t &ebase, RecC *&lc, Op4 *&le, int64_t *&lb) {
+  const int nc = t1 - t0, nl = nc + (e1 - e0);
+  cbase = nc ? coff[(size_t)t0 * cstride] : 0;
+  const int64_t cstop = nc ? coff[(size_t)(t1 - 1) * cstride + cend] : 0;
+  ebase = eoff[e0];
+  const int64_t estop = eoff[e1];
+  lb = reinterpret_cast<int64_t *>(lds);
+  lc = reinterpret_cast<RecC *>(lds + 16 * (size_t)nl);
+  le = reinterpret_cast<Op4 *>(lds + 16 * (size_t)nl + sizeof(RecC) * (size_t)(cstop - cbase));
+  for (int l = threadIdx.x; l < nl; l += blockDim.x) {
+    if (l < nc) {
+      lb[2 * l] = coff[(size_t)(t0 + l) * cstride] - cbase;
+      lb[2 * l + 1] = coff[(size_t)(t0 + l) * cstride + cend] - cbase;
+    } else {
+      lb[2 * l] = eoff[e0 + l - nc] - ebase;
+      lb[2 * l + 1] = eoff[e0 + l - nc + 1] - ebase;
+    }
+  }
+  // records as 16-byte words
+  const int4 *gc = reinterpret_cast<const int4 *>(cops + cbase);
+  int4 *dc = reinterpret_cast<int4 *>(lc);
+  const int64_t wc = (cstop - cbase) * (int64_t)(sizeof(RecC) / 16);
+  for (int64_t k = threadIdx.x; k < wc; k += blockDim.x) dc[k] = gc[k];
+  const int4 *ge = reinterpret_cast<const int4 *>(eops + ebase);
+  int4 *de = reinterpret_cast<int4 *>(le);
+  for (int64_t k = threadIdx.x; k < estop - ebase; k += blockDim.x) de[k] = ge[k];
+  __syncthreads();
+}
+
+// Column r (COL) or row r of the n x n block at g into registers (zero padded).
+template <typename T, int NB, bool COL>
+__device__ __forceinline__ void vec_mat_line(T (&v)[NB], const T *__restrict__ g, int n, int r) {
+#pragma unroll
+  for (int k = 0; k < NB; ++k) v[k] = (r < n && k < n) ? (COL ? g[k * n + r] : g[r * n + k]) : (T)0;
+}
+
+// Matrix block of an affine-pass primitive (-1: none): rake -> edge slot,
+// compress -> left slot; expansion -> right slot.
+__device__ __forceinline__ int64_t aff_block(const OpRec &o) {
+  return (o.kind == OP_RAKE || o.kind == OP_COMPRESS) ? (int64_t)o.b : -1;
+}
+
+// aff_op / affexp_op with the lane's column of Z = T^T already in registers.
+template <typename T, int NB>
+__device__ __forceinline__ void aff_op_col(const Bufs<T> &bf, const OpRec &o, int r, const T (&col)[NB]) {
+  const int n = bf.n;
+  if (r >= n) return;
+  if (o.kind == OP_RAKE) {  // m = Z h_j + z,  p_j = h_j
+    const int64_t j = o.a, e = o.b, out = o.c;
+    T acc = bf.z[e * n + r];
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+      if (k < n) acc = fmat(col[k], bf.h[j * n + k], acc);
+    bf.cv[out * n + r] = acc;
+    bf.p[j * n + r] = bf.h[j * n + r];
+  } else if (o.kind == OP_COMBINE) {
+    bf.cv[(int64_t)o.c * n + r] = bf.cv[(int64_t)o.a * n + r] + bf.cv[(int64_t)o.b * n + r];
+  } else if (o.kind == OP_ABSORB) {
+    bf.h[(int64_t)o.a * n + r] += bf.cv[(int64_t)o.b * n + r];
+  } else {  // z_new = z_l + Z_l (h_j + z_r)
+    const int64_t j = o.a, l = o.b, rs = o.c, sn = o.d;
+    T acc = bf.z[l * n + r];
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+      if (k < n) acc = fmat(col[k], bf.h[j * n + k] + bf.z[rs * n + k], acc);
+    bf.z[sn * n + r] = acc;
+  }
+}
+
+template <typename T, int NB>
+__device__ __forceinline__ void affexp_op_col(const Bufs<T> &bf, const Op4 &o, int r, const T (&col)[NB]) {
+  const int n = bf.n;
+  if (r >= n) return;
+  const int64_t j = o.a, rs = o.b, k = o.c;
+  T acc = bf.h[j * n + r] + bf.z[rs * n + r];
+#pragma unroll
+  for (int q = 0; q < NB; ++q)
+    if (q < n) acc = fmat(col[q], bf.p[k * n + q], acc);
+  bf.p[j * n + r] = acc;
+}
+
 // Affine contraction levels [t0, t1) then affine expansion levels [e0, e1).
 template <typename T, int NB>
 __global__ __launch_bounds__(1024) void k_tail_aff(Bufs<T> bf, const OpRec *__restrict__ ops,
@@ -105,36 +215,111 @@ __global__ __launch_bounds__(1024) void k_tail_aff(Bufs<T> bf, const OpRec *__re
                                                    const Op4 *__restrict__ eops, const int64_t *__restrict__ eoff,
                                                    int e0, int e1) {
   constexpr int TW = TeamW<NB>::TW;
+  extern __shared__ double smd[];
+  int64_t cbase, ebase, *lb;
+  OpRec *lc;
+  Op4 *le;
+  vec_tail_stage<OpRec>(reinterpret_cast<char *>(smd), ops, koff, 5, 4, t0, t1, eops, eoff, e0, e1, cbase, ebase,
+                        lc, le, lb);
+  const int nc = t1 - t0, nl = nc + (e1 - e0);
   const int slot = threadIdx.x / TW, nslot = blockDim.x / TW, r = threadIdx.x % TW;
-  for (int t = t0; t < t1; ++t) {
-    const int64_t beg = koff[(size_t)t * 5], end = koff[(size_t)t * 5 + 4];
-    for (int64_t i = beg + slot; i < end; i += nslot) {
-      const OpRec o = ops[i];
-      aff_op<T, NB>(bf, o, o.kind, r);
+  const int n = bf.n;
+  const int64_t nn = (int64_t)n * n;
+  auto block_of = [&](int l, int64_t i) -> int64_t { return l < nc ? aff_block(lc[i]) : (int64_t)le[i].b; };
+  T pf[NB];
+  {
+    const int64_t i = lb[0] + slot;
+    const int64_t blk = (nl > 0 && i < lb[1]) ? block_of(0, i) : -1;
+    if (blk >= 0) vec_mat_line<T, NB, true>(pf, bf.Tm + blk * nn, n, r);
+  }
+  for (int l = 0; l < nl; ++l) {
+    T nx[NB];
+    if (l + 1 < nl) {
+      const int64_t i = lb[2 * (l + 1)] + slot;
+      const int64_t blk = (i < lb[2 * (l + 1) + 1]) ? block_of(l + 1, i) : -1;
+      if (blk >= 0) vec_mat_line<T, NB, true>(nx, bf.Tm + blk * nn, n, r);
+    }
+    const int64_t b0 = lb[2 * l], b1 = lb[2 * l + 1];
+    for (int64_t i = b0 + slot; i < b1; i += nslot) {
+      T col[NB];
+      if (i == b0 + slot) {
+#pragma unroll
+        for (int k = 0; k < NB; ++k) col[k] = pf[k];
+      } else {
+        const int64_t blk = block_of(l, i);
+        if (blk >= 0) vec_mat_line<T, NB, true>(col, bf.Tm + blk * nn, n, r);
+      }
+      if (l < nc)
+        aff_op_col<T, NB>(bf, lc[i], r, col);
+      else
+        affexp_op_col<T, NB>(bf, le[i], r, col);
     }
     __syncthreads();
-  }
-  for (int e = e0; e < e1; ++e) {
-    for (int64_t i = eoff[e] + slot; i < eoff[e + 1]; i += nslot) affexp_op<T, NB>(bf, eops[i], r);
-    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NB; ++k) pf[k] = nx[k];
   }
 }
 
-// State-offset composition levels [t0, t1) then state expansion levels [e0, e1).
+// State-offset composition levels [t0, t1) then state expansion levels [e0, e1):
+// b_new = T_r b_l + b_r and x_j = T_s x_i + b_s with the lane's row of T.
 template <typename T, int NB>
 __global__ __launch_bounds__(1024) void k_tail_state(Bufs<T> bf, const Op4 *__restrict__ ops,
                                                      const int64_t *__restrict__ off, int t0, int t1,
                                                      const Op4 *__restrict__ xops, const int64_t *__restrict__ xoff,
                                                      int e0, int e1) {
   constexpr int TW = TeamW<NB>::TW;
+  extern __shared__ double smd[];
+  int64_t cbase, ebase, *lb;
+  Op4 *lc, *le;
+  vec_tail_stage<Op4>(reinterpret_cast<char *>(smd), ops, off, 1, 1, t0, t1, xops, xoff, e0, e1, cbase, ebase, lc,
+                      le, lb);
+  const int nc = t1 - t0, nl = nc + (e1 - e0);
   const int slot = threadIdx.x / TW, nslot = blockDim.x / TW, r = threadIdx.x % TW;
-  for (int t = t0; t < t1; ++t) {
-    for (int64_t i = off[t] + slot; i < off[t + 1]; i += nslot) state_op<T, NB>(bf, ops[i], r);
-    __syncthreads();
+  const int n = bf.n;
+  const int64_t nn = (int64_t)n * n;
+  // composition {l slot, r slot, new slot, j}: T_r;  expansion {j, slot, parent}: T_slot
+  auto block_of = [&](int l, int64_t i) -> int64_t { return (int64_t)(l < nc ? lc[i].b : le[i].b); };
+  T pf[NB];
+  {
+    const int64_t i = lb[0] + slot;
+    if (nl > 0 && i < lb[1]) vec_mat_line<T, NB, false>(pf, bf.Tm + block_of(0, i) * nn, n, r);
   }
-  for (int e = e0; e < e1; ++e) {
-    for (int64_t i = xoff[e] + slot; i < xoff[e + 1]; i += nslot) sexp_op<T, NB>(bf, xops[i], r);
+  for (int l = 0; l < nl; ++l) {
+    T nx[NB];
+    if (l + 1 < nl) {
+      const int64_t i = lb[2 * (l + 1)] + slot;
+      if (i < lb[2 * (l + 1) + 1]) vec_mat_line<T, NB, false>(nx, bf.Tm + block_of(l + 1, i) * nn, n, r);
+    }
+    const int64_t b0 = lb[2 * l], b1 = lb[2 * l + 1];
+    for (int64_t i = b0 + slot; i < b1; i += nslot) {
+      T row[NB];
+      if (i == b0 + slot) {
+#pragma unroll
+        for (int k = 0; k < NB; ++k) row[k] = pf[k];
+      } else {
+        vec_mat_line<T, NB, false>(row, bf.Tm + block_of(l, i) * nn, n, r);
+      }
+      if (r < n) {
+        if (l < nc) {
+          const Op4 o = lc[i];
+          T acc = bf.b[(int64_t)o.b * n + r];
+#pragma unroll
+          for (int k = 0; k < NB; ++k)
+            if (k < n) acc = fmat(row[k], bf.b[(int64_t)o.a * n + k], acc);
+          bf.b[(int64_t)o.c * n + r] = acc;
+        } else {
+          const Op4 o = le[i];
+          T acc = bf.b[(int64_t)o.b * n + r];
+#pragma unroll
+          for (int k = 0; k < NB; ++k)
+            if (k < n) acc = fmat(row[k], bf.xw[(int64_t)o.c * n + k], acc);
+          bf.xw[(int64_t)o.a * n + r] = acc;
+        }
+      }
+    }
     __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NB; ++k) pf[k] = nx[k];
   }
 }
 

@@ -64,39 +64,6 @@ __device__ __forceinline__ void team_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One step of a team-wide (value, index) max with a DPP lane permutation
-// (ties go to the smaller index, so every lane ends with the same pair).
-template <int CTRL>
-__device__ __forceinline__ void argmax_step(double &v, int &idx) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  const int olo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
-  const int ohi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
-  const int oi = __builtin_amdgcn_mov_dpp(idx, CTRL, 0xF, 0xF, false);
-  const double ov = __hiloint2double(ohi, olo);
-  if (ov > v || (ov == v && oi < idx)) {
-    v = ov;
-    idx = oi;
-  }
-}
-template <int CTRL>
-__device__ __forceinline__ void argmax_step(float &v, int &idx) {
-  const float ov = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
-  const int oi = __builtin_amdgcn_mov_dpp(idx, CTRL, 0xF, 0xF, false);
-  if (ov > v || (ov == v && oi < idx)) {
-    v = ov;
-    idx = oi;
-  }
-}
-
-// Max over the TW lanes of a team: pairs (quad_perm [1,0,3,2]), quads
-// (quad_perm [2,3,0,1]), half rows (row_half_mirror), rows (row_mirror).
-template <int TW, typename T>
-__device__ __forceinline__ void team_argmax(T &v, int &idx) {
-  argmax_step<0xB1>(v, idx);
-  argmax_step<0x4E>(v, idx);
-  if (TW >= 8) argmax_step<0x141>(v, idx);
-  if (TW >= 16) argmax_step<0x140>(v, idx);
-}
 
 // row[j] = g[r][j] for r, j < n (row stride n), else 0
 template <typename T, int NB, typename S>
@@ -198,34 +165,98 @@ __device__ __forceinline__ void mac_colL(T (&acc)[NB], const T *L1, const T *L2,
 // sides).  On return M[NB:W] of lane r is row r of the solution.  The pivot
 // row travels through the team's LDS slot Lp (2 W words).  Pivots are chosen
 // by a width-TW butterfly argmax of |M[r][k]| over rows r >= k.
+// ---------------------------------------------------------------- pivoting
+// Pivot key of a candidate row, 32 bits: the float32 magnitude of the entry
+// (whose bit pattern orders like an unsigned integer) with its lowest four
+// bits replaced by 15 - row, so that one unsigned max over the candidates
+// yields a largest magnitude (up to a relative 2^-19, irrelevant to the
+// stability of partial pivoting) and its row, an exact tie going to the
+// smaller row.  0 marks a lane without a candidate; rows 0..15 only.
+__device__ __forceinline__ unsigned piv_key(double v, int row, bool cand) {
+  const unsigned b = __float_as_uint((float)fabs(v));
+  return cand ? ((b & ~15u) | (unsigned)(15 - row)) : 0u;
+}
+__device__ __forceinline__ unsigned piv_key(float v, int row, bool cand) {
+  const unsigned b = __float_as_uint(fabsf(v));
+  return cand ? ((b & ~15u) | (unsigned)(15 - row)) : 0u;
+}
+__device__ __forceinline__ int piv_row(unsigned key) { return 15 - (int)(key & 15u); }
+// no candidate, or a zero (or float32-underflowing) magnitude
+__device__ __forceinline__ bool piv_zero(unsigned key) { return (key >> 4) == 0u; }
+
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_umax(unsigned v) {
+  const unsigned o = (unsigned)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+  return v > o ? v : o;
+}
+// Max over the TW lanes of a team, left in every lane: pairs (quad_perm
+// [1,0,3,2]), quads (quad_perm [2,3,0,1]), half rows (row_half_mirror), rows
+// (row_mirror).
+template <int TW>
+__device__ __forceinline__ unsigned team_umax(unsigned v) {
+  v = dpp_umax<0xB1>(v);
+  v = dpp_umax<0x4E>(v);
+  if (TW >= 8) v = dpp_umax<0x141>(v);
+  if (TW >= 16) v = dpp_umax<0x140>(v);
+  return v;
+}
+
+// 1 / d from the hardware reciprocal refined by Newton steps x <- x (2 - d x)
+// (two in float64, one in float32); d is a nonzero pivot.
+__device__ __forceinline__ double rcp_nr(double d) {
+  double x = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, x, 1.0);
+  x = fma(x, e, x);
+  e = fma(-d, x, 1.0);
+  return fma(x, e, x);
+}
+__device__ __forceinline__ float rcp_nr(float d) {
+  float x = __builtin_amdgcn_rcpf(d);
+  const float e = fmaf(-d, x, 1.0f);
+  return fmaf(x, e, x);
+}
+
+// Gauss-Jordan elimination with partial pivoting of the NB x W system whose
+// row r lane r holds in M (rows r >= NB are ghosts).  Rows are never swapped:
+// at step k the unused row p of largest |M[k]| becomes the pivot row, is
+// scaled by 1 / M_p[k] and eliminated from every other row (Lp: W words).
+// Returns the solution row the lane holds on exit: the leading NB x NB block
+// is reduced to a permutation, and the lane whose row pivoted at step k holds
+// row k of the solution in M[NB..W).  Ghost lanes return their own index.
 template <typename T, int NB, int W, int TW>
-__device__ __forceinline__ void gj_team(T (&M)[W], T *Lp, int r, int *status) {
+__device__ __forceinline__ int gj_team(T (&M)[W], T *Lp, int r, int *status) {
+  bool used = r >= NB, sing = false;
+  int step = r;
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
-    T cand = (r >= k && r < NB) ? (T)fabs(M[k]) : (T)-1;
-    int idx = r;
-    team_argmax<TW>(cand, idx);
-    if (r == idx) {
+    const unsigned key = team_umax<TW>(piv_key(M[k], r, !used));
+    const int p = piv_row(key);
+    sing = sing || piv_zero(key);
+    if (r == p) {
 #pragma unroll
       for (int j = k; j < W; ++j) Lp[j] = M[j];
     }
-    if (r == k && idx != k) {
-#pragma unroll
-      for (int j = k; j < W; ++j) Lp[W + j] = M[j];
-    }
     team_sync();
-    if (r == idx && idx != k) {
+    const T inv = rcp_nr(Lp[k]);
+    const T g = (r == p) ? inv - (T)1 : -M[k] * inv;  // the pivot row becomes inv * row
 #pragma unroll
-      for (int j = k; j < W; ++j) M[j] = Lp[W + j];
+    for (int j = k; j < W; ++j) M[j] = fmat(g, Lp[j], M[j]);
+    if (r == p) {
+      used = true;
+      step = k;
     }
-    if ((r & (TW - 1)) == 0 && !(cand > (T)0)) atomicOr(status, ST_SINGULAR);
-    const T inv = (T)1 / Lp[k];
-    const T g = (r == k) ? inv : -M[k] * inv;  // new row = h * row + g * pivot row
-    const T h = (r == k) ? (T)0 : (T)1;
-#pragma unroll
-    for (int j = k + 1; j < W; ++j) M[j] = fmat(g, Lp[j], h * M[j]);
     team_sync();
   }
+  if ((r & (TW - 1)) == 0 && sing) atomicOr(status, ST_SINGULAR);
+  return step;
+}
+
+// Row `at` of an NB-wide LDS matrix := row (lanes r >= NB write nothing).
+template <typename T, int NB>
+__device__ __forceinline__ void lds_put_at(T *L, const T (&row)[NB], int at, int r) {
+  if (r >= NB) return;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) L[at * NB + j] = row[j];
 }
 
 // Store 0.5 (X + X^T) where lane r holds row r of X in `row`; Ls is an

@@ -158,60 +158,69 @@ __device__ __forceinline__ float readlane_t<float>(float v, int lane) {
 
 // Gauss-Jordan elimination with partial pivoting of the NB x W system staged
 // in LDS (LM, row stride W): lane (q, r) works on the piece
-// [q WQ, q WQ + WQ) of row r.  The pivot of column k is found by a DPP argmax
-// among the 16 lanes holding column k and broadcast with readlane; the pivot
-// row and the multipliers travel through LDS (Lp: 2 W words, LF: 16 words).
-// On return LM holds the eliminated system: columns [NB, W) are the solution.
+// [q WQ, q WQ + WQ) of row r.  Rows are never swapped.  At step k the pivot
+// key (piv_key) of column k is reduced over the 16 lanes holding that column
+// and made wave-uniform with readlane, which also fetches the exact pivot
+// value from its lane; each lane's multiplier (its row's entry in column k)
+// comes from the lane holding it by a cross-lane permute; only the pivot row
+// travels through LDS (Lp: W words).  The pivot row is scaled by 1 / pivot
+// and eliminated from every other row.  On return LM holds the eliminated
+// system in pivot order: row k is the row that pivoted at step k, so columns
+// [NB, W) are the solution.  (LF is unused scratch kept for the layout.)
 template <typename T, int NB, int W>
 __device__ __forceinline__ void gj_wide(T *LM, T *Lp, T *LF, int *status, bool report) {
   constexpr int WQ = W / 4;
   const int q = wq_of(), r = wr_of();
+  (void)LF;
   T m[WQ];
 #pragma unroll
   for (int c = 0; c < WQ; ++c) m[c] = (r < NB) ? LM[r * W + q * WQ + c] : (T)0;
+  bool used = r >= NB, sing = false;
+  int step = 0;
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
     const int qk = k / WQ, ck = k % WQ;
-    T cand = (q == qk && r >= k && r < NB) ? (T)fabs(m[ck]) : (T)-1;
-    int idx = r;
-    team_argmax<16>(cand, idx);
-    const int p = __builtin_amdgcn_readlane(idx, qk * 16);
-    const T pmag = readlane_t<T>(cand, qk * 16);
-    if (report && (threadIdx.x & 63) == 0 && !(pmag > (T)0)) atomicOr(status, ST_SINGULAR);
-    if (q == qk) LF[r] = m[ck];
+    const unsigned key = (unsigned)__builtin_amdgcn_readlane(
+        (int)team_umax<16>(piv_key(m[ck], r, !used && q == qk)), qk * 16);
+    const int p = piv_row(key);
+    sing = sing || piv_zero(key);
+    const T piv = readlane_t<T>(m[ck], qk * 16 + p);
+    const T f = __shfl(m[ck], qk * 16 + r, 64);  // entry (r, k), held by lane (qk, r)
     if (r == p) {
 #pragma unroll
       for (int c = 0; c < WQ; ++c) Lp[q * WQ + c] = m[c];
     }
-    if (r == k && p != k) {
-#pragma unroll
-      for (int c = 0; c < WQ; ++c) Lp[W + q * WQ + c] = m[c];
-    }
+    const T inv = rcp_nr(piv);
     team_sync();
-    if (r == p && p != k) {
+    const T g = (r == p) ? inv - (T)1 : -f * inv;  // the pivot row becomes inv * row
 #pragma unroll
-      for (int c = 0; c < WQ; ++c) m[c] = Lp[W + q * WQ + c];
+    for (int c = 0; c < WQ; ++c) m[c] = fmat(g, Lp[q * WQ + c], m[c]);
+    if (r == p) {
+      used = true;
+      step = k;
     }
-    const T inv = (T)1 / Lp[k];
-    const T fsrc = (r == p) ? LF[k] : LF[r];
-    const T g = (r == k) ? inv : -fsrc * inv;
-    const T h = (r == k) ? (T)0 : (T)1;
-#pragma unroll
-    for (int c = 0; c < WQ; ++c) m[c] = fmat(g, Lp[q * WQ + c], h * m[c]);
     team_sync();
   }
+  if (report && (threadIdx.x & 63) == 0 && sing) atomicOr(status, ST_SINGULAR);
   if (r < NB) {
 #pragma unroll
-    for (int c = 0; c < WQ; ++c) LM[r * W + q * WQ + c] = m[c];
+    for (int c = 0; c < WQ; ++c) LM[step * W + q * WQ + c] = m[c];
   }
   team_sync();
 }
 
 template <typename T, int NB>
 __host__ __device__ constexpr int wide_lds_words() {
-  // compress: Pt, Ar, Al, Cl, Z, S (6 NB^2 words of T) + the float64 system M
-  // (3 NB^2), pivot row slots (2 * 3 NB) and multipliers (16); in words of T
-  return 6 * NB * NB + (3 * NB * NB + 6 * NB + 16) * (int)(sizeof(double) / sizeof(T));
+  // compress: Pt, Ar, Al, Cl (4 NB^2 words of T; C_l's block later holds the
+  // symmetrisation scratch) + the float64 system M (3 NB^2, later Z), the
+  // pivot row (3 NB) and 16 spare words; in words of T
+  return 4 * NB * NB + (3 * NB * NB + 3 * NB + 16) * (int)(sizeof(double) / sizeof(T));
+}
+
+template <typename T, int NB>
+__host__ __device__ constexpr int tau_lds_words() {
+  // tau_wide: A, C, Ux, Y (4 NB^2) + the system NB x 2 NB + pivot row (2 NB) + 16 spare
+  return 6 * NB * NB + 2 * NB + 16;
 }
 
 // tau(alpha, Ux) = Pm + A^T Ux (I + C Ux)^{-1} A  (eq. (terminal-fold)), symmetrised.
@@ -222,7 +231,7 @@ __device__ __forceinline__ void tau_wide(T *__restrict__ out, const T (&tA)[Wide
                                          const T (&pm)[WideCfg<NB>::CQ], T *L, int n, bool active, int *status) {
   constexpr int CQ = WideCfg<NB>::CQ, W = 2 * NB;
   T *LA = L, *LC = L + NB * NB, *LU = L + 2 * NB * NB, *LY = L + 3 * NB * NB, *LM = L + 4 * NB * NB;
-  T *Lp = LM + NB * W, *LF = Lp + 2 * W;
+  T *Lp = LM + NB * W, *LF = Lp + W;
   const int q = wq_of(), r = wr_of();
   wput<T, NB>(LA, NB, tA);
   wput<T, NB>(LC, NB, tC);
@@ -300,9 +309,10 @@ __device__ __forceinline__ void quad_op_wide(const Bufs<T> &bf, const OpRec &o, 
     constexpr int W = 3 * NB;
     typedef double ST;  // the (I + C_l Pt) solve is always float64
     const int64_t j = o.a, l = o.b, rs = o.c, sn = o.d;
-    T *LPt = L, *LAr = L + NB * NB, *LAl = L + 2 * NB * NB, *LCl = L + 3 * NB * NB, *LZ = L + 4 * NB * NB;
-    T *LS = L + 5 * NB * NB;
-    ST *LM = reinterpret_cast<ST *>(L + 6 * NB * NB), *Lp = LM + NB * W, *LF = Lp + 2 * W;
+    T *LPt = L, *LAr = L + NB * NB, *LAl = L + 2 * NB * NB, *LCl = L + 3 * NB * NB;
+    ST *LM = reinterpret_cast<ST *>(L + 4 * NB * NB), *Lp = LM + NB * W, *LF = Lp + W;
+    T *LS = LCl;                          // C_l is dead once S and C_l A_r^T are formed
+    T *LZ = reinterpret_cast<T *>(LM);    // the system is dead once X and Y are consumed
     const int q = wq_of(), r = wr_of();
     T cr[CQ], pl[CQ];
     {
@@ -353,6 +363,7 @@ __device__ __forceinline__ void quad_op_wide(const Bufs<T> &bf, const OpRec &o, 
       wmm_AB<T, NB>(cr, LAr, NB, LM + 2 * NB, W);  // C_r + A_r Y
       wmm_AB<T, NB>(z, LPt, NB, LM + NB, W);       // Pt X
       wstore_piece<T, NB>(bf.EA + sn * nn, an, n, active);
+      team_sync();  // every read of the system precedes the writes that reuse it
       wput_piece<T, NB>(LS, NB, cr);
       wput_piece<T, NB>(LZ, NB, z);
     }
