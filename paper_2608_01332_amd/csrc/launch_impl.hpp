@@ -144,7 +144,7 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
   allow_lds(k_recover<T, NB, MB>, lds_rec);
   const size_t lds_wide = (size_t)wide_lds_words<T, (NB >= 12 ? NB : 12)>() * sizeof(T);
   const size_t lds_wexp = (size_t)tau_lds_words<T, (NB >= 12 ? NB : 12)>() * sizeof(T);
-  const size_t lds_wtc = (size_t)2 * (NB >= 12 ? NB : 12) * (NB >= 12 ? NB : 12) * sizeof(T);
+  const size_t lds_wtc = (size_t)2 * WideCfg<(NB >= 12 ? NB : 12)>::BS * sizeof(T);
   const size_t lds_lvl = WIDE ? lds_wide : lds_quad;  // per wavefront, level kernels
   const unsigned NBk = blocks_for(h.N, PW);
   // tail workgroup sizes

@@ -18,6 +18,10 @@ struct WideCfg {
   static_assert(NB % 4 == 0 && NB <= 16, "wide layout needs NB in {12, 16}");
   static constexpr int CQ = NB / 4;
   static constexpr int TILE = (NB * NB + 63) / 64;  // block elements per lane when copying
+  // LDS row stride of an NB x NB block: one padding word makes the 16 rows a
+  // column access touches fall in distinct bank pairs (no 4-way conflicts)
+  static constexpr int LD = NB + 1;
+  static constexpr int BS = NB * LD;  // LDS words of one block
 };
 
 __device__ __forceinline__ int wq_of() { return (int)((threadIdx.x & 63) >> 4); }
@@ -137,10 +141,10 @@ __device__ __forceinline__ void wmm_ABt(Acc (&out)[WideCfg<NB>::CQ], const TA *A
 // 0.5 (X + X^T) for the lane's piece, X staged in LDS (row stride NB).
 template <typename T, int NB>
 __device__ __forceinline__ void wsym(T (&p)[WideCfg<NB>::CQ], const T *LX) {
-  constexpr int CQ = WideCfg<NB>::CQ;
+  constexpr int CQ = WideCfg<NB>::CQ, LD = WideCfg<NB>::LD;
   const int q = wq_of(), r = wr_of() < NB ? wr_of() : NB - 1;
 #pragma unroll
-  for (int c = 0; c < CQ; ++c) p[c] = (T)0.5 * (LX[r * NB + q * CQ + c] + LX[(q * CQ + c) * NB + r]);
+  for (int c = 0; c < CQ; ++c) p[c] = (T)0.5 * (LX[r * LD + q * CQ + c] + LX[(q * CQ + c) * LD + r]);
 }
 
 template <typename T>
@@ -157,7 +161,7 @@ __device__ __forceinline__ float readlane_t<float>(float v, int lane) {
 }
 
 // Gauss-Jordan elimination with partial pivoting of the NB x W system staged
-// in LDS (LM, row stride W): lane (q, r) works on the piece
+// in LDS (LM, row stride W + 1): lane (q, r) works on the piece
 // [q WQ, q WQ + WQ) of row r.  Rows are never swapped.  At step k the pivot
 // key (piv_key) of column k is reduced over the 16 lanes holding that column
 // and made wave-uniform with readlane, which also fetches the exact pivot
@@ -169,12 +173,12 @@ __device__ __forceinline__ float readlane_t<float>(float v, int lane) {
 // [NB, W) are the solution.  (LF is unused scratch kept for the layout.)
 template <typename T, int NB, int W>
 __device__ __forceinline__ void gj_wide(T *LM, T *Lp, T *LF, int *status, bool report) {
-  constexpr int WQ = W / 4;
+  constexpr int WQ = W / 4, LW = W + 1;
   const int q = wq_of(), r = wr_of();
   (void)LF;
   T m[WQ];
 #pragma unroll
-  for (int c = 0; c < WQ; ++c) m[c] = (r < NB) ? LM[r * W + q * WQ + c] : (T)0;
+  for (int c = 0; c < WQ; ++c) m[c] = (r < NB) ? LM[r * LW + q * WQ + c] : (T)0;
   bool used = r >= NB, sing = false;
   int step = 0;
 #pragma unroll
@@ -204,7 +208,7 @@ __device__ __forceinline__ void gj_wide(T *LM, T *Lp, T *LF, int *status, bool r
   if (report && (threadIdx.x & 63) == 0 && sing) atomicOr(status, ST_SINGULAR);
   if (r < NB) {
 #pragma unroll
-    for (int c = 0; c < WQ; ++c) LM[step * W + q * WQ + c] = m[c];
+    for (int c = 0; c < WQ; ++c) LM[step * LW + q * WQ + c] = m[c];
   }
   team_sync();
 }
@@ -214,13 +218,13 @@ __host__ __device__ constexpr int wide_lds_words() {
   // compress: Pt, Ar, Al, Cl (4 NB^2 words of T; C_l's block later holds the
   // symmetrisation scratch) + the float64 system M (3 NB^2, later Z), the
   // pivot row (3 NB) and 16 spare words; in words of T
-  return 4 * NB * NB + (3 * NB * NB + 3 * NB + 16) * (int)(sizeof(double) / sizeof(T));
+  return 4 * WideCfg<NB>::BS + (NB * (3 * NB + 1) + 3 * NB + 16) * (int)(sizeof(double) / sizeof(T));
 }
 
 template <typename T, int NB>
 __host__ __device__ constexpr int tau_lds_words() {
   // tau_wide: A, C, Ux, Y (4 NB^2) + the system NB x 2 NB + pivot row (2 NB) + 16 spare
-  return 6 * NB * NB + 2 * NB + 16;
+  return 4 * WideCfg<NB>::BS + NB * (2 * NB + 1) + 2 * NB + 16;
 }
 
 // tau(alpha, Ux) = Pm + A^T Ux (I + C Ux)^{-1} A  (eq. (terminal-fold)), symmetrised.
@@ -229,24 +233,24 @@ template <typename T, int NB>
 __device__ __forceinline__ void tau_wide(T *__restrict__ out, const T (&tA)[WideCfg<NB>::TILE],
                                          const T (&tC)[WideCfg<NB>::TILE], const T (&tU)[WideCfg<NB>::TILE],
                                          const T (&pm)[WideCfg<NB>::CQ], T *L, int n, bool active, int *status) {
-  constexpr int CQ = WideCfg<NB>::CQ, W = 2 * NB;
-  T *LA = L, *LC = L + NB * NB, *LU = L + 2 * NB * NB, *LY = L + 3 * NB * NB, *LM = L + 4 * NB * NB;
-  T *Lp = LM + NB * W, *LF = Lp + W;
+  constexpr int CQ = WideCfg<NB>::CQ, W = 2 * NB, LW = W + 1, LD = WideCfg<NB>::LD, BS = WideCfg<NB>::BS;
+  T *LA = L, *LC = L + BS, *LU = L + 2 * BS, *LY = L + 3 * BS, *LM = L + 4 * BS;
+  T *Lp = LM + NB * LW, *LF = Lp + W;
   const int q = wq_of(), r = wr_of();
-  wput<T, NB>(LA, NB, tA);
-  wput<T, NB>(LC, NB, tC);
-  wput<T, NB>(LU, NB, tU);
+  wput<T, NB>(LA, LD, tA);
+  wput<T, NB>(LC, LD, tC);
+  wput<T, NB>(LU, LD, tU);
   team_sync();
   {
     T s[CQ];
 #pragma unroll
     for (int c = 0; c < CQ; ++c) s[c] = (q * CQ + c == r) ? (T)1 : (T)0;
-    wmm_AB<T, NB>(s, LC, NB, LU, NB);  // I + C Ux
+    wmm_AB<T, NB>(s, LC, LD, LU, LD);  // I + C Ux
     if (r < NB) {
 #pragma unroll
       for (int c = 0; c < CQ; ++c) {
-        LM[r * W + q * CQ + c] = s[c];
-        LM[r * W + NB + q * CQ + c] = LA[r * NB + q * CQ + c];
+        LM[r * LW + q * CQ + c] = s[c];
+        LM[r * LW + NB + q * CQ + c] = LA[r * LD + q * CQ + c];
       }
     }
   }
@@ -256,15 +260,15 @@ __device__ __forceinline__ void tau_wide(T *__restrict__ out, const T (&tA)[Wide
     T y[CQ];
 #pragma unroll
     for (int c = 0; c < CQ; ++c) y[c] = (T)0;
-    wmm_AB<T, NB>(y, LU, NB, LM + NB, W);  // Y = Ux X
-    wput_piece<T, NB>(LY, NB, y);
+    wmm_AB<T, NB>(y, LU, LD, LM + NB, LW);  // Y = Ux X
+    wput_piece<T, NB>(LY, LD, y);
   }
   team_sync();
   T o[CQ];
 #pragma unroll
   for (int c = 0; c < CQ; ++c) o[c] = (T)0;
-  wmm_AtB<T, NB>(o, LA, NB, LY, NB);  // A^T Y
-  wput_piece<T, NB>(LC, NB, o);       // C is dead: reuse for the symmetrisation
+  wmm_AtB<T, NB>(o, LA, LD, LY, LD);  // A^T Y
+  wput_piece<T, NB>(LC, LD, o);       // C is dead: reuse for the symmetrisation
   team_sync();
   wsym<T, NB>(o, LC);
 #pragma unroll
@@ -306,11 +310,11 @@ __device__ __forceinline__ void quad_op_wide(const Bufs<T> &bf, const OpRec &o, 
     }
   } else {
     // alpha_{lr} = alpha_r o_{U_j} alpha_l  (eqs. (compress-intermediates), (composition))
-    constexpr int W = 3 * NB;
+    constexpr int W = 3 * NB, LW = W + 1, LD = WideCfg<NB>::LD, BS = WideCfg<NB>::BS;
     typedef double ST;  // the (I + C_l Pt) solve is always float64
     const int64_t j = o.a, l = o.b, rs = o.c, sn = o.d;
-    T *LPt = L, *LAr = L + NB * NB, *LAl = L + 2 * NB * NB, *LCl = L + 3 * NB * NB;
-    ST *LM = reinterpret_cast<ST *>(L + 4 * NB * NB), *Lp = LM + NB * W, *LF = Lp + W;
+    T *LPt = L, *LAr = L + BS, *LAl = L + 2 * BS, *LCl = L + 3 * BS;
+    ST *LM = reinterpret_cast<ST *>(L + 4 * BS), *Lp = LM + NB * LW, *LF = Lp + W;
     T *LS = LCl;                          // C_l is dead once S and C_l A_r^T are formed
     T *LZ = reinterpret_cast<T *>(LM);    // the system is dead once X and Y are consumed
     const int q = wq_of(), r = wr_of();
@@ -326,10 +330,10 @@ __device__ __forceinline__ void quad_op_wide(const Bufs<T> &bf, const OpRec &o, 
       wfetch_piece<T, NB>(pl, bf.EP + l * nn, n);
 #pragma unroll
       for (int u = 0; u < TL; ++u) tP[u] += tU[u];
-      wput<T, NB>(LPt, NB, tP);
-      wput<T, NB>(LAr, NB, tAr);
-      wput<T, NB>(LAl, NB, tAl);
-      wput<T, NB>(LCl, NB, tCl);
+      wput<T, NB>(LPt, LD, tP);
+      wput<T, NB>(LAr, LD, tAr);
+      wput<T, NB>(LAl, LD, tAl);
+      wput<T, NB>(LCl, LD, tCl);
     }
     team_sync();
     {
@@ -339,14 +343,14 @@ __device__ __forceinline__ void quad_op_wide(const Bufs<T> &bf, const OpRec &o, 
         sb[c] = (q * CQ + c == r) ? (ST)1 : (ST)0;
         ct[c] = (ST)0;
       }
-      wmm_AB<ST, NB>(sb, LCl, NB, LPt, NB);   // S = I + C_l Pt
-      wmm_ABt<ST, NB>(ct, LCl, NB, LAr, NB);  // C_l A_r^T
+      wmm_AB<ST, NB>(sb, LCl, LD, LPt, LD);   // S = I + C_l Pt
+      wmm_ABt<ST, NB>(ct, LCl, LD, LAr, LD);  // C_l A_r^T
       if (r < NB) {
 #pragma unroll
         for (int c = 0; c < CQ; ++c) {
-          LM[r * W + q * CQ + c] = sb[c];
-          LM[r * W + NB + q * CQ + c] = (ST)LAl[r * NB + q * CQ + c];
-          LM[r * W + 2 * NB + q * CQ + c] = ct[c];
+          LM[r * LW + q * CQ + c] = sb[c];
+          LM[r * LW + NB + q * CQ + c] = (ST)LAl[r * LD + q * CQ + c];
+          LM[r * LW + 2 * NB + q * CQ + c] = ct[c];
         }
       }
     }
@@ -359,13 +363,13 @@ __device__ __forceinline__ void quad_op_wide(const Bufs<T> &bf, const OpRec &o, 
         an[c] = (T)0;
         z[c] = (T)0;
       }
-      wmm_AB<T, NB>(an, LAr, NB, LM + NB, W);      // A_r X
-      wmm_AB<T, NB>(cr, LAr, NB, LM + 2 * NB, W);  // C_r + A_r Y
-      wmm_AB<T, NB>(z, LPt, NB, LM + NB, W);       // Pt X
+      wmm_AB<T, NB>(an, LAr, LD, LM + NB, LW);      // A_r X
+      wmm_AB<T, NB>(cr, LAr, LD, LM + 2 * NB, LW);  // C_r + A_r Y
+      wmm_AB<T, NB>(z, LPt, LD, LM + NB, LW);       // Pt X
       wstore_piece<T, NB>(bf.EA + sn * nn, an, n, active);
       team_sync();  // every read of the system precedes the writes that reuse it
-      wput_piece<T, NB>(LS, NB, cr);
-      wput_piece<T, NB>(LZ, NB, z);
+      wput_piece<T, NB>(LS, LD, cr);
+      wput_piece<T, NB>(LZ, LD, z);
     }
     team_sync();
     wsym<T, NB>(cr, LS);
@@ -373,8 +377,8 @@ __device__ __forceinline__ void quad_op_wide(const Bufs<T> &bf, const OpRec &o, 
     T pn[CQ];
 #pragma unroll
     for (int c = 0; c < CQ; ++c) pn[c] = (T)0;
-    wmm_AtB<T, NB>(pn, LAl, NB, LZ, NB);  // A_l^T Z
-    wput_piece<T, NB>(LPt, NB, pn);       // Pt is dead: reuse for the symmetrisation
+    wmm_AtB<T, NB>(pn, LAl, LD, LZ, LD);  // A_l^T Z
+    wput_piece<T, NB>(LPt, LD, pn);       // Pt is dead: reuse for the symmetrisation
     team_sync();
     wsym<T, NB>(pn, LPt);
 #pragma unroll
@@ -408,13 +412,14 @@ __device__ __forceinline__ void tcomp_op_wide(const Bufs<T> &bf, const Op4 &o, T
   T tl[TL], tr[TL];
   wfetch<T, NB>(tl, bf.Tm + (int64_t)o.a * nn, n);
   wfetch<T, NB>(tr, bf.Tm + (int64_t)o.b * nn, n);
-  wput<T, NB>(L, NB, tl);
-  wput<T, NB>(L + NB * NB, NB, tr);
+  constexpr int LD = WideCfg<NB>::LD, BS = WideCfg<NB>::BS;
+  wput<T, NB>(L, LD, tl);
+  wput<T, NB>(L + BS, LD, tr);
   team_sync();
   T out[CQ];
 #pragma unroll
   for (int c = 0; c < CQ; ++c) out[c] = (T)0;
-  wmm_AB<T, NB>(out, L + NB * NB, NB, L, NB);  // T_r T_l
+  wmm_AB<T, NB>(out, L + BS, LD, L, LD);  // T_r T_l
   wstore_piece<T, NB>(bf.Tm + (int64_t)o.c * nn, out, n, true);
 }
 
