@@ -86,7 +86,7 @@ template <typename T, int NB>
 __host__ __device__ constexpr int lds_quad_words() {
   // compress: Pt, Ar, Al, X, Y (5 NB^2) + float64 pivot slots (2 * 3 NB doubles);
   // rake: 4 NB^2 + 4 NB.  Counted in words of T.
-  return 5 * NB * NB + 6 * NB * (int)(sizeof(double) / sizeof(T));
+  return team_stride<T>(5 * NB * NB + 6 * NB * (int)(sizeof(double) / sizeof(T)));
 }
 
 // ---------------------------------------------------------------- factor kernels
@@ -101,7 +101,7 @@ __host__ __device__ constexpr int lds_quad_words() {
 template <int NB, int MB>
 struct CondLay {
   static constexpr int A = 0, D = NB * NB, P = 2 * NB * NB, B = 3 * NB * NB, S = B + NB * MB, Bt = S + NB * MB,
-                       St = Bt + NB * MB, R = St + NB * MB, words = R + MB * MB;
+                       St = Bt + NB * MB, R = St + NB * MB, words = team_stride<double>(R + MB * MB);
 };
 
 template <typename T, int NB, int MB>
@@ -389,7 +389,7 @@ struct LfLay {
   static constexpr int P = 0, Fi = NB * NB, A = 2 * NB * NB, B = 3 * NB * NB, WB = B + NB * MB, Lp = WB + NB * MB,
                        tend = Lp + 4 * NB;
   static constexpr int dbeg = (tend * (int)sizeof(T) + 7) / 8;  // in doubles
-  static constexpr int G = dbeg, words = G + MB * MB;            // doubles per team
+  static constexpr int G = dbeg, words = team_stride<double>(G + MB * MB);  // doubles per team
 };
 
 template <typename T, int NB, int MB>
@@ -625,7 +625,7 @@ template <typename T, int NB, int MB>
 __global__ __launch_bounds__(64) void k_rhs_init(Bufs<T> bf) {
   // h_i = q_i;  z_e = K_e^T r_e + (A^cl_e)^T W_j c_j  (eq. (affine-edge))
   using Ly = RhsLay<NB, MB>;
-  constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW, TS = Ly::words;
+  constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW, TS = team_stride<T>(Ly::words);
   extern __shared__ double smd[];
   T *smt = reinterpret_cast<T *>(smd);
   const int lane = threadIdx.x & 63, team = lane / TW, r = lane % TW;
@@ -746,7 +746,7 @@ __global__ __launch_bounds__(64) void k_local_affine(Bufs<T> bf) {
   // b = F^-1 (B k - f); root: x = -F^-1 f.  Teams cover max(NB, MB) lanes.
   using Ly = LaLay<NB, MB>;
   constexpr int NM = NB > MB ? NB : MB;
-  constexpr int TW = TeamW<NM>::TW, PW = TeamW<NM>::PW, TS = Ly::words;
+  constexpr int TW = TeamW<NM>::TW, PW = TeamW<NM>::PW, TS = team_stride<T>(Ly::words);
   extern __shared__ double smd[];
   T *smt = reinterpret_cast<T *>(smd);
   const int lane = threadIdx.x & 63, team = lane / TW, r = lane % TW;
@@ -889,7 +889,7 @@ template <typename T, int NB, int MB>
 __global__ __launch_bounds__(64) void k_recover(Bufs<T> bf) {
   // y_v = P_v x_v + p_v;  u_e = K_e x_parent + k_e;  non-finite check
   using Ly = RecLay<NB, MB>;
-  constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW, TS = Ly::words;
+  constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW, TS = team_stride<T>(Ly::words);
   extern __shared__ double smd[];
   T *smt = reinterpret_cast<T *>(smd);
   const int lane = threadIdx.x & 63, team = lane / TW, r = lane % TW;

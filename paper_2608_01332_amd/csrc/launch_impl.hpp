@@ -9,6 +9,7 @@
 
 #include "device.hpp"
 #include "kernels.hpp"
+#include "lfwide.hpp"
 #include "tail.hpp"
 #include "wide.hpp"
 
@@ -134,9 +135,10 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
   const size_t lds_cond = (size_t)PW * CondLay<NB, MB>::words * sizeof(double);
   const size_t lds_quad = (size_t)PW * lds_quad_words<T, NB>() * sizeof(T);
   const size_t lds_lf = (size_t)PW * LfLay<T, NB, MB>::words * sizeof(double);
-  const size_t lds_rhs = (size_t)PW * RhsLay<NB, MB>::words * sizeof(T);
-  const size_t lds_la = (size_t)PWm * LaLay<NB, MB>::words * sizeof(T);
-  const size_t lds_rec = (size_t)PW * RecLay<NB, MB>::words * sizeof(T);
+  const size_t lds_lfw = (size_t)LfwLay<T, (NB >= 12 ? NB : 12), MB>::words * sizeof(double);
+  const size_t lds_rhs = (size_t)PW * team_stride<T>(RhsLay<NB, MB>::words) * sizeof(T);
+  const size_t lds_la = (size_t)PWm * team_stride<T>(LaLay<NB, MB>::words) * sizeof(T);
+  const size_t lds_rec = (size_t)PW * team_stride<T>(RecLay<NB, MB>::words) * sizeof(T);
   allow_lds(k_condense<T, NB, MB>, lds_cond);
   allow_lds(k_local_factor<T, NB, MB>, lds_lf);
   allow_lds(k_rhs_init<T, NB, MB>, lds_rhs);
@@ -212,7 +214,12 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
              h.exp_off[t], cnt);
   }
   tm.begin(RCR_K_LOCAL_FACTOR);
-  LAUNCH(tm, (k_local_factor<T, NB, MB>), dim3(NBk), dim3(64), lds_lf, st, bf);
+  if constexpr (WIDE) {
+    allow_lds(k_local_factor_wide<T, NB, MB>, lds_lfw);
+    LAUNCH(tm, (k_local_factor_wide<T, NB, MB>), dim3((unsigned)h.N), dim3(64), lds_lfw, st, bf);
+  } else {
+    LAUNCH(tm, (k_local_factor<T, NB, MB>), dim3(NBk), dim3(64), lds_lf, st, bf);
+  }
 
   // ---- composite transitions along compressions
   tm.begin(RCR_K_TCOMPOSE);

@@ -1,0 +1,264 @@
+// Local factor (eqs. (FW), (factor-local)) in the wide layout for NB in
+// {12, 16}: one node per 64-lane wavefront, lane (q, r) owning row r and
+// column quarter q of every NB x NB block (wide.hpp).  Per node v:
+//   F = I + Delta P,  Finv by Gauss-Jordan on [F | I],  W = P Finv;
+//   for the edge e = (parent, v):  WB = W B,  H^T = A^T WB + M,
+//   G = R + B^T WB (float64 Cholesky),  K = -G^-1 H,  G^-1,
+//   A^cl = A + B K,  T = Finv A^cl;
+//   at the root P = U is also the output P.
+// One wavefront per node shortens the dependent chain of the elimination
+// four-fold against a 16-lane team and keeps enough wavefronts resident to
+// hide it; the control-sized float64 work (G, its factor and inverse) is
+// replicated in registers when m is at most 4.
+#pragma once
+
+#include "wide.hpp"
+
+namespace rcr {
+
+template <typename T, int NB, int MB>
+struct LfwLay {
+  static constexpr int LD = WideCfg<NB>::LD, BS = WideCfg<NB>::BS, W = 2 * NB, LW = W + 1, MBP = MB + 1;
+  // words of T: P (later W), Delta (later A^cl), A, the system [F | I], pivot row,
+  // B, WB, K^T (NB x MB each, row stride MB + 1)
+  static constexpr int P = 0, D = BS, A = 2 * BS, M = 3 * BS, Lp = M + NB * LW, B = Lp + W, WB = B + NB * MBP,
+                       Kt = WB + NB * MBP, tend = Kt + NB * MBP;
+  // doubles: H^T (NB x MB), G and G^-1 (MB x MB)
+  static constexpr int dbeg = (tend * (int)sizeof(T) + 7) / 8;
+  static constexpr int Ht = dbeg, G = Ht + NB * MBP, Gi = G + MB * MB, words = Gi + MB * MB;
+};
+
+// Cholesky factor and inverse of the MB x MB SPD matrix G (row-major in LDS)
+// in registers; reports a non-positive pivot through `bad`.
+template <int MB>
+__device__ __forceinline__ void chol_inv_regs(const double *LG, double (&Gi)[MB][MB], bool &bad) {
+  double L[MB][MB];
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < MB; ++j) L[i][j] = (j <= i) ? LG[i * MB + j] : 0.0;
+  double dinv[MB];
+#pragma unroll
+  for (int j = 0; j < MB; ++j) {
+    double s = L[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
+    bad = bad || !(s > 0.0);
+    const double d = sqrt(s);
+    L[j][j] = d;
+    dinv[j] = 1.0 / d;
+#pragma unroll
+    for (int i = j + 1; i < MB; ++i) {
+      double t = L[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
+      L[i][j] = t * dinv[j];
+    }
+  }
+  // Li = L^-1 (lower triangular), G^-1 = Li^T Li
+  double Li[MB][MB];
+#pragma unroll
+  for (int c = 0; c < MB; ++c) {
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+      double t = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < i; ++k) t -= L[i][k] * Li[k][c];
+      Li[i][c] = (i >= c) ? t * dinv[i] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < MB; ++c)
+#pragma unroll
+    for (int d = 0; d < MB; ++d) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < MB; ++k) s += Li[k][c] * Li[k][d];
+      Gi[c][d] = s;
+    }
+}
+
+template <typename T, int NB, int MB>
+RCR_MAT_KERNEL(NB) void k_local_factor_wide(Bufs<T> bf) {
+  using Ly = LfwLay<T, NB, MB>;
+  constexpr int CQ = WideCfg<NB>::CQ, TL = WideCfg<NB>::TILE, LD = Ly::LD, LW = Ly::LW, MBP = Ly::MBP;
+  constexpr int TB = (NB * MB + 63) / 64;
+  extern __shared__ double smd[];
+  T *L = reinterpret_cast<T *>(smd);
+  T *LP = L + Ly::P, *LDe = L + Ly::D, *LA = L + Ly::A, *LM = L + Ly::M, *Lp = L + Ly::Lp;
+  T *LB = L + Ly::B, *LWB = L + Ly::WB, *LKt = L + Ly::Kt;
+  double *LH = smd + Ly::Ht, *LG = smd + Ly::G, *LGi = smd + Ly::Gi;
+  const int64_t v = blockIdx.x;
+  const int n = bf.n, m = bf.m;
+  const int64_t nn = (int64_t)n * n, nm = (int64_t)n * m;
+  const int q = wq_of(), r = wr_of(), lane = (int)(threadIdx.x & 63);
+  const int rr = r < NB ? r : NB - 1;
+  const bool isroot = bf.parent[v] < 0;
+  const bool edge = !isroot;
+  {
+    T tP[TL], tD[TL], tA[TL], tB[TB];
+    wfetch<T, NB>(tP, (isroot ? bf.U : bf.PW) + v * nn, n);
+    wfetch<T, NB>(tD, bf.De + v * nn, n);
+    wfetch<T, NB>(tA, bf.A + v * nn, n);
+#pragma unroll
+    for (int u = 0; u < TB; ++u) {
+      const int e = lane + 64 * u, i = e / MB, c = e % MB;
+      tB[u] = (e < NB * MB && i < n && c < m) ? (T)bf.B[v * nm + (int64_t)i * m + c] : (T)0;
+    }
+    if (isroot) wstore_tile<T, NB>(bf.PW + v * nn, tP, n, true);  // P_root = U_root
+    wput<T, NB>(LP, LD, tP);
+    wput<T, NB>(LDe, LD, tD);
+    wput<T, NB>(LA, LD, tA);
+#pragma unroll
+    for (int u = 0; u < TB; ++u) {
+      const int e = lane + 64 * u, i = e / MB, c = e % MB;
+      if (e < NB * MB) LB[i * MBP + c] = tB[u];
+    }
+  }
+  team_sync();
+  {  // the system [F | I], F = I + Delta P
+    T f[CQ];
+#pragma unroll
+    for (int c = 0; c < CQ; ++c) f[c] = (q * CQ + c == r) ? (T)1 : (T)0;
+    wmm_AB<T, NB>(f, LDe, LD, LP, LD);
+    if (r < NB) {
+#pragma unroll
+      for (int c = 0; c < CQ; ++c) {
+        LM[r * LW + q * CQ + c] = f[c];
+        LM[r * LW + NB + q * CQ + c] = (q * CQ + c == r) ? (T)1 : (T)0;
+      }
+    }
+  }
+  team_sync();
+  gj_wide<T, NB, 2 * NB>(LM, Lp, Lp, bf.status, true);
+  const T *LFi = LM + NB;  // Finv, row stride LW
+  {
+    T fi[CQ], w[CQ];
+#pragma unroll
+    for (int c = 0; c < CQ; ++c) {
+      fi[c] = LFi[rr * LW + q * CQ + c];
+      w[c] = (T)0;
+    }
+    wstore_piece<T, NB>(bf.Finv + v * nn, fi, n, true);
+    wmm_AB<T, NB>(w, LP, LD, LFi, LW);  // W = P Finv
+    wstore_piece<T, NB>(bf.W + v * nn, w, n, true);
+    team_sync();  // the reads of P precede its replacement by W
+    wput_piece<T, NB>(LP, LD, w);
+  }
+  team_sync();
+  for (int c = q; c < MB; c += 4) {  // WB = W B
+    T s = (T)0;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) s = fmat(LP[rr * LD + k], LB[k * MBP + c], s);
+    if (r < NB) LWB[r * MBP + c] = s;
+  }
+  team_sync();
+  for (int c = q; c < MB; c += 4) {  // H^T = A^T WB + M (float64)
+    double h = (r < n && c < m) ? bf.S[v * nm + (int64_t)r * m + c] : 0.0;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) h = fma((double)LA[k * LD + rr], (double)LWB[k * MBP + c], h);
+    if (r < NB) LH[r * MBP + c] = h;
+  }
+  if (r < MB) {
+    for (int c = q; c < MB; c += 4) {  // G = R + B^T WB (float64; padded with the identity)
+      double g = (r < m && c < m) ? bf.R[v * m * m + r * m + c] : (r == c ? 1.0 : 0.0);
+#pragma unroll
+      for (int k = 0; k < NB; ++k) g = fma((double)LB[k * MBP + r], (double)LWB[k * MBP + c], g);
+      LG[r * MB + c] = g;
+    }
+  }
+  team_sync();
+  if constexpr (MB <= 4) {
+    double Gi[MB][MB];
+    bool bad = false;
+    chol_inv_regs<MB>(LG, Gi, bad);
+    if (edge && lane == 0 && bad) atomicOr(bf.status, ST_NOT_PD);
+    // row q of G^-1 and the entry (r, q), selected with compile-time indices
+    double gq[MB], grq = 0.0;
+#pragma unroll
+    for (int d = 0; d < MB; ++d) gq[d] = 0.0;
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+      for (int d = 0; d < MB; ++d) {
+        gq[d] = (i == q) ? Gi[i][d] : gq[d];
+        grq = (i == r && d == q) ? Gi[i][d] : grq;
+      }
+    if (q < MB) {  // K^T row r, column q = -(G^-1 H^T[r])_q
+      double kt = 0.0;
+#pragma unroll
+      for (int d = 0; d < MB; ++d) kt = fma(-gq[d], LH[rr * MBP + d], kt);
+      if (isroot) kt = 0.0;
+      if (r < NB) LKt[r * MBP + q] = (T)kt;
+      if (r < n && q < m) bf.Kw[v * nm + (int64_t)q * n + r] = (T)kt;
+    }
+    if (edge && r < m && q < m) bf.Ginv[v * m * m + r * m + q] = (T)grq;
+  } else {
+    if (lane == 0) {  // Cholesky of G in float64 (lane 0)
+      for (int j = 0; j < MB; ++j) {
+        double s2 = LG[j * MB + j];
+        for (int k = 0; k < j; ++k) s2 -= LG[j * MB + k] * LG[j * MB + k];
+        if (edge && !(s2 > 0.0)) atomicOr(bf.status, ST_NOT_PD);
+        const double d = sqrt(s2);
+        LG[j * MB + j] = d;
+        for (int i = j + 1; i < MB; ++i) {
+          double t = LG[i * MB + j];
+          for (int k = 0; k < j; ++k) t -= LG[i * MB + k] * LG[j * MB + k];
+          LG[i * MB + j] = t / d;
+        }
+      }
+    }
+    team_sync();
+    if (lane < MB) {  // row `lane` of G^-1 by two triangular solves
+      const int c = lane;
+      double e[MB];
+      for (int d = 0; d < MB; ++d) e[d] = (d == c) ? 1.0 : 0.0;
+      for (int d = 0; d < MB; ++d) {
+        double t = e[d];
+        for (int k = 0; k < d; ++k) t -= LG[d * MB + k] * e[k];
+        e[d] = t / LG[d * MB + d];
+      }
+      for (int d = MB - 1; d >= 0; --d) {
+        double t = e[d];
+        for (int k = d + 1; k < MB; ++k) t -= LG[k * MB + d] * e[k];
+        e[d] = t / LG[d * MB + d];
+      }
+      for (int d = 0; d < MB; ++d) LGi[c * MB + d] = e[d];
+    }
+    team_sync();
+    for (int c = q; c < MB; c += 4) {
+      double kt = 0.0;
+      for (int d = 0; d < MB; ++d) kt = fma(-LGi[c * MB + d], LH[rr * MBP + d], kt);
+      if (isroot) kt = 0.0;
+      if (r < NB) LKt[r * MBP + c] = (T)kt;
+      if (r < n && c < m) bf.Kw[v * nm + (int64_t)c * n + r] = (T)kt;
+    }
+    if (edge && r < m) {
+      for (int c = q; c < m; c += 4) bf.Ginv[v * m * m + r * m + c] = (T)LGi[r * MB + c];
+    }
+  }
+  team_sync();
+  {  // A^cl = A + B K  (K[c][j] = K^T[j][c]); Delta's block (dead since F) keeps it
+    T acl[CQ];
+#pragma unroll
+    for (int cc = 0; cc < CQ; ++cc) {
+      const int j = q * CQ + cc;
+      T s = LA[rr * LD + j];
+#pragma unroll
+      for (int c = 0; c < MB; ++c) s = fmat(LB[rr * MBP + c], LKt[j * MBP + c], s);
+      acl[cc] = s;
+    }
+    if (edge) wstore_piece<T, NB>(bf.Acl + v * nn, acl, n, true);
+    wput_piece<T, NB>(LDe, LD, acl);
+  }
+  team_sync();
+  {
+    T t[CQ];
+#pragma unroll
+    for (int c = 0; c < CQ; ++c) t[c] = (T)0;
+    wmm_AB<T, NB>(t, LFi, LW, LDe, LD);  // T = Finv A^cl
+    if (edge) wstore_piece<T, NB>(bf.Tm + v * nn, t, n, true);
+  }
+}
+
+}  // namespace rcr

@@ -50,6 +50,16 @@ struct Seg {
   int32_t blk[5];
 };
 
+// Stride (in words of T) between the LDS regions of the teams of a
+// wavefront: the smallest value >= words that is 1 more than a multiple of
+// 128 bytes, so the teams' regions start in different banks and the team-wide
+// broadcast reads of one instruction never collide.
+template <typename T>
+__host__ __device__ constexpr int team_stride(int words) {
+  constexpr int K = 128 / (int)sizeof(T);
+  return words + ((1 - words) % K + K) % K;
+}
+
 template <typename T>
 __device__ __forceinline__ T fmat(T a, T b, T c) {
   return fma(a, b, c);

@@ -13,6 +13,11 @@
 
 namespace rcr {
 
+// Operand rows a block product keeps in flight between scheduling pins.
+#ifndef RCR_WMM_PIN
+#define RCR_WMM_PIN 4
+#endif
+
 template <int NB>
 struct WideCfg {
   static_assert(NB % 4 == 0 && NB <= 16, "wide layout needs NB in {12, 16}");
@@ -106,7 +111,7 @@ __device__ __forceinline__ void wmm_AB(Acc (&out)[WideCfg<NB>::CQ], const TA *A,
     const Acc a = (Acc)A[r * lda + k];
 #pragma unroll
     for (int c = 0; c < CQ; ++c) out[c] = fmat(a, (Acc)B[k * ldb + q * CQ + c], out[c]);
-    if (k % 4 == 3) pin(out, 0, CQ);
+    if (k % RCR_WMM_PIN == RCR_WMM_PIN - 1) pin(out, 0, CQ);
   }
 }
 
@@ -120,7 +125,7 @@ __device__ __forceinline__ void wmm_AtB(Acc (&out)[WideCfg<NB>::CQ], const TA *A
     const Acc a = (Acc)A[k * lda + r];
 #pragma unroll
     for (int c = 0; c < CQ; ++c) out[c] = fmat(a, (Acc)B[k * ldb + q * CQ + c], out[c]);
-    if (k % 4 == 3) pin(out, 0, CQ);
+    if (k % RCR_WMM_PIN == RCR_WMM_PIN - 1) pin(out, 0, CQ);
   }
 }
 
@@ -134,7 +139,7 @@ __device__ __forceinline__ void wmm_ABt(Acc (&out)[WideCfg<NB>::CQ], const TA *A
     const Acc a = (Acc)A[r * lda + k];
 #pragma unroll
     for (int c = 0; c < CQ; ++c) out[c] = fmat(a, (Acc)B[(q * CQ + c) * ldb + k], out[c]);
-    if (k % 4 == 3) pin(out, 0, CQ);
+    if (k % RCR_WMM_PIN == RCR_WMM_PIN - 1) pin(out, 0, CQ);
   }
 }
 
