@@ -358,6 +358,8 @@ def bench_serve(args) -> dict:
                    "plan_cache_hits": float(np.mean([r.cache_hit for r in reqs])),
                    "host_s": {k: round(v, 3) for k, v in hstats.items()}, "wall_s": wall}
             if sample:
+                torch.cuda.synchronize()
+                torch.cuda.empty_cache()  # the run's cached group buffers
                 # each sampled result against the same request solved alone
                 worst_diff, worst_kkt = 0.0, 0.0
                 for r in reqs:
@@ -450,7 +452,7 @@ def main() -> int:
     ap.add_argument("--requests", type=int, default=0, help="requests per rate (0: 10k, or 20 s of arrivals below 500/s)")
     ap.add_argument("--fifo-rates", type=lambda s: [float(x) for x in s.split(",") if x], default=[100.0, 500.0, 2000.0],
                     help="rates at which the one-slot FIFO queue (no batching) is also measured")
-    ap.add_argument("--hbm-budget-gib", type=int, default=96)
+    ap.add_argument("--hbm-budget-gib", type=int, default=64)
     ap.add_argument("--planner-threads", type=int, default=12)
     ap.add_argument("--workload", choices=["single", "batch", "extreme", "copy", "serve", "lift"], default="single",
                     help="single: the 65,536-node tree (default); batch: the 512-tree batched workload; "
