@@ -263,6 +263,39 @@ int rcr_lift_plan_create(const int64_t *parent, int64_t N, int32_t n, int32_t m,
 int rcr_lift_solve(const rcr_plan *plan, const rcr_native_problem *in, rcr_native_solution *out,
                    const rcr_solve_options *opt, void *stream);
 
+/* ------------------------------------------------------- launch mapping */
+/* How a plan maps its narrow dependency levels onto single-workgroup tail
+ * kernels (the levels near the root hold few primitives; running them inside
+ * one workgroup separated by barriers avoids a launch and a device-wide
+ * round trip per level).  A level runs in a tail kernel when its primitives
+ * fit in the given number of rounds of the tail workgroup.  0 selects the
+ * default of a field; quad_tail_rounds < 0 or vec_tail_rounds < 0 disables
+ * that tail.  Results do not depend on the mapping (every primitive runs the
+ * same arithmetic wherever it is launched); only the time does. */
+typedef struct {
+  int32_t quad_tail_rounds; /* quadratic contraction/expansion tail (default 2)            */
+  int32_t vec_tail_rounds;  /* affine and state tails (default 4)                           */
+  int32_t vec_tail_waves;   /* wavefronts of the vector tail workgroup, 1..16 (default 16) */
+  int32_t reserved[5];
+} rcr_launch_config;
+
+/* Set (NULL: reset to defaults) or read a plan's launch mapping.  Host only;
+ * a change drops the plan's captured graphs.  Errors: RCR_NULL_ARG,
+ * RCR_BAD_OPTION (vec_tail_waves outside 0..16). */
+int rcr_plan_set_launch(rcr_plan *plan, const rcr_launch_config *cfg);
+int rcr_plan_get_launch(const rcr_plan *plan, rcr_launch_config *cfg);
+
+/* Autotune the launch mapping of a plan on a representative problem: every
+ * candidate of a small grid (quad_tail_rounds in {1, 2, 4, 8},
+ * vec_tail_rounds in {2, 4, 8}, vec_tail_waves in {8, 16}) is timed with HIP
+ * events on `stream` (one warm-up and three timed solves each, with the
+ * options in opt; the per-level executor is used for the timing), the fastest
+ * is kept in the plan and returned in *best (and its time in *best_ms, if
+ * not NULL).  `out` receives the solution.  Synchronises the stream.  Errors:
+ * those of rcr_solve. */
+int rcr_plan_tune(rcr_plan *plan, const rcr_problem *in, rcr_solution *out, const rcr_solve_options *opt,
+                  void *stream, rcr_launch_config *best, float *best_ms);
+
 /* Static name of a status code. */
 const char *rcr_status_string(int status);
 

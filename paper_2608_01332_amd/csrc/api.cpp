@@ -111,6 +111,52 @@ int rcr_plan_upload(const rcr_plan *plan, void *stream) {
   return rcr::plan_upload(pl->obj, (hipStream_t)stream);
 }
 
+int rcr_plan_set_launch(rcr_plan *plan, const rcr_launch_config *cfg) {
+  if (!plan) return RCR_NULL_ARG;
+  rcr::LaunchCfg c;
+  if (cfg) {
+    if (cfg->vec_tail_waves < 0 || cfg->vec_tail_waves > 16) return RCR_BAD_OPTION;
+    c.quad_tail_rounds = cfg->quad_tail_rounds;
+    c.vec_tail_rounds = cfg->vec_tail_rounds;
+    c.vec_tail_waves = cfg->vec_tail_waves;
+  }
+  std::lock_guard<std::mutex> lock(plan->obj.mu);
+  plan->obj.cfg = c;
+  rcr::drop_graphs(plan->obj);
+  return RCR_OK;
+}
+
+int rcr_plan_get_launch(const rcr_plan *plan, rcr_launch_config *cfg) {
+  if (!plan || !cfg) return RCR_NULL_ARG;
+  memset(cfg, 0, sizeof(*cfg));
+  cfg->quad_tail_rounds = plan->obj.cfg.quad_tail_rounds;
+  cfg->vec_tail_rounds = plan->obj.cfg.vec_tail_rounds;
+  cfg->vec_tail_waves = plan->obj.cfg.vec_tail_waves;
+  return RCR_OK;
+}
+
+int rcr_plan_tune(rcr_plan *plan, const rcr_problem *in, rcr_solution *out, const rcr_solve_options *opt,
+                  void *stream, rcr_launch_config *best, float *best_ms) {
+  if (!plan || !in || !out || !best) return RCR_NULL_ARG;
+  rcr_solve_options o;
+  memset(&o, 0, sizeof(o));
+  if (opt) o = *opt;
+  if (o.precision != RCR_FP64 && o.precision != RCR_MIXED32) return RCR_BAD_OPTION;
+  if (o.refine_steps < 0) o.refine_steps = 1;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return RCR_NO_DEVICE;
+  rcr::LaunchCfg b;
+  float ms = 0.f;
+  const int rc = rcr::tune(plan->obj, *in, *out, o, (hipStream_t)stream, b, ms);
+  if (rc) return rc;
+  memset(best, 0, sizeof(*best));
+  best->quad_tail_rounds = b.quad_tail_rounds;
+  best->vec_tail_rounds = b.vec_tail_rounds;
+  best->vec_tail_waves = b.vec_tail_waves;
+  if (best_ms) *best_ms = ms;
+  return RCR_OK;
+}
+
 int rcr_plan_info(const rcr_plan *plan, rcr_plan_stats *out) {
   if (!plan || !out) return RCR_NULL_ARG;
   const rcr::PlanHost &h = plan->obj.host;

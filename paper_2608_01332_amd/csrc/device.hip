@@ -170,9 +170,13 @@ int plan_upload(PlanObj &P, hipStream_t st) {
   return RCR_OK;
 }
 
-void plan_release_device(PlanObj &P) {
+void drop_graphs(PlanObj &P) {
   for (auto &kv : P.graphs) (void)hipGraphExecDestroy(kv.second);
   P.graphs.clear();
+}
+
+void plan_release_device(PlanObj &P) {
+  drop_graphs(P);
   for (hipEvent_t e : P.events) (void)hipEventDestroy(e);
   P.events.clear();
   // release after the last solve that used the plan (its completion event), in
@@ -462,6 +466,54 @@ int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_
     }
   }
   return RCR_OK;
+}
+
+// ------------------------------------------------------------ autotuning
+// Time every candidate launch mapping with HIP events on `st` and keep the
+// fastest (the per-level executor is used, so no graph is captured).
+int tune(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_options &opt, hipStream_t st,
+         LaunchCfg &best, float &best_ms) {
+  rcr_solve_options o = opt;
+  o.executor = RCR_EXEC_LEVELS;
+  o.check = 0;
+  o.kkt_residual = nullptr;
+  o.kernel_ms = nullptr;
+  o.kernel_launches = nullptr;
+  hipEvent_t e0, e1;
+  HIPCK(hipEventCreate(&e0));
+  HIPCK(hipEventCreate(&e1));
+  const LaunchCfg keep = P.cfg;
+  best_ms = -1.f;
+  int rc = RCR_OK;
+  for (int qr : {1, 2, 4, 8})
+    for (int vr : {2, 4, 8})
+      for (int vw : {8, 16}) {
+        {
+          std::lock_guard<std::mutex> lock(P.mu);
+          P.cfg.quad_tail_rounds = qr;
+          P.cfg.vec_tail_rounds = vr;
+          P.cfg.vec_tail_waves = vw;
+        }
+        if ((rc = solve(P, in, out, o, st))) break;  // warm-up
+        float ms = 0.f;
+        if (hipEventRecord(e0, st) != hipSuccess) rc = RCR_HIP_ERROR;
+        for (int k = 0; k < 3 && !rc; ++k) rc = solve(P, in, out, o, st);
+        if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = RCR_HIP_ERROR;
+        if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = RCR_HIP_ERROR;
+        if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = RCR_HIP_ERROR;
+        if (rc) break;
+        ms /= 3.f;
+        if (best_ms < 0.f || ms < best_ms) {
+          best_ms = ms;
+          best = P.cfg;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> lock(P.mu);
+  P.cfg = rc ? keep : best;
+  drop_graphs(P);
+  return rc;
 }
 
 // ------------------------------------------------------------ exact lifting

@@ -56,8 +56,14 @@ struct GraphKey {
   }
 };
 
+// Launch mapping of the narrow levels (rcr_launch_config; 0 = default).
+struct LaunchCfg {
+  int quad_tail_rounds = 0, vec_tail_rounds = 0, vec_tail_waves = 0;
+};
+
 struct PlanObj {
   PlanHost host;
+  LaunchCfg cfg;
   PlanDev dev;
   std::mutex mu;
   void *ws[2] = {nullptr, nullptr};  // plan-owned workspace per precision
@@ -72,6 +78,11 @@ void plan_release_device(PlanObj &P);
 
 int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_options &opt,
           hipStream_t stream);
+
+void drop_graphs(PlanObj &P);
+
+int tune(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_options &opt, hipStream_t stream,
+         LaunchCfg &best, float &best_ms);
 
 int lift_solve(PlanObj &P, const rcr_native_problem &in, rcr_native_solution &out, const rcr_solve_options &opt,
                hipStream_t stream);

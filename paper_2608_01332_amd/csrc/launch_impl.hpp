@@ -154,9 +154,12 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
   int mat_waves = (int)std::min<size_t>(MatLay<NB>::MAXW, kMaxLds / lds_lvl);
   if (mat_waves < 1) mat_waves = 1;
   const size_t lds_tail = (size_t)mat_waves * lds_lvl;
-  const int64_t mat_cap = 2 * (int64_t)mat_waves * MatLay<NB>::PW;
-  const int vec_waves = 16;
-  const int64_t vec_cap = 4 * (int64_t)vec_waves * (64 / TeamW<NB>::TW);
+  const LaunchCfg &cfg = P.cfg;
+  const int qr = cfg.quad_tail_rounds == 0 ? 2 : (cfg.quad_tail_rounds < 0 ? 0 : cfg.quad_tail_rounds);
+  const int64_t mat_cap = (int64_t)qr * mat_waves * MatLay<NB>::PW;
+  const int vec_waves = cfg.vec_tail_waves > 0 ? std::min(cfg.vec_tail_waves, 16) : 16;
+  const int vr = cfg.vec_tail_rounds == 0 ? 4 : (cfg.vec_tail_rounds < 0 ? 0 : cfg.vec_tail_rounds);
+  const int64_t vec_cap = (int64_t)vr * vec_waves * (64 / TeamW<NB>::TW);
   const size_t kVecTailLds = 144 * 1024;
   allow_lds(k_tail_quad<T, NB>, lds_tail);
   allow_lds(k_tail_tc<T, NB>, lds_tail);

@@ -62,6 +62,11 @@ class NativeSolution(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in ("x", "v", "lam")]
 
 
+class LaunchConfig(ctypes.Structure):
+    _fields_ = [("quad_tail_rounds", ctypes.c_int32), ("vec_tail_rounds", ctypes.c_int32),
+                ("vec_tail_waves", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
 class SolveOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("refine_steps", ctypes.c_int32), ("executor", ctypes.c_int32),
                 ("check", ctypes.c_int32), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_int64),
@@ -70,7 +75,8 @@ class SolveOptions(ctypes.Structure):
 
 
 EXPORTED = ("rcr_plan_create", "rcr_plan_info", "rcr_plan_export", "rcr_plan_destroy", "rcr_batch_plan_create",
-            "rcr_plan_upload", "rcr_lift_plan_create", "rcr_lift_solve",
+            "rcr_plan_upload", "rcr_lift_plan_create", "rcr_lift_solve", "rcr_plan_set_launch",
+            "rcr_plan_get_launch", "rcr_plan_tune",
             "rcr_workspace_size", "rcr_solve", "rcr_status_string")
 
 _lib = None
@@ -109,6 +115,14 @@ def lib():
             L.rcr_lift_solve.restype = ctypes.c_int
             L.rcr_lift_solve.argtypes = [ctypes.c_void_p, ctypes.POINTER(NativeProblem),
                                          ctypes.POINTER(NativeSolution), ctypes.POINTER(SolveOptions), ctypes.c_void_p]
+            L.rcr_plan_set_launch.restype = ctypes.c_int
+            L.rcr_plan_set_launch.argtypes = [ctypes.c_void_p, ctypes.POINTER(LaunchConfig)]
+            L.rcr_plan_get_launch.restype = ctypes.c_int
+            L.rcr_plan_get_launch.argtypes = [ctypes.c_void_p, ctypes.POINTER(LaunchConfig)]
+            L.rcr_plan_tune.restype = ctypes.c_int
+            L.rcr_plan_tune.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.POINTER(Solution),
+                                        ctypes.POINTER(SolveOptions), ctypes.c_void_p, ctypes.POINTER(LaunchConfig),
+                                        ctypes.POINTER(ctypes.c_float)]
             L.rcr_plan_upload.restype = ctypes.c_int
             L.rcr_plan_upload.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
             L.rcr_workspace_size.restype = ctypes.c_int64
@@ -207,6 +221,45 @@ class Plan:
         rc = lib().rcr_plan_upload(self._h, ctypes.c_void_p(st.cuda_stream))
         if rc != 0:
             raise RcrError(rc, "rcr_plan_upload")
+
+    def set_launch(self, cfg: dict | None = None):
+        """rcr_plan_set_launch (None: defaults).  Keys: quad_tail_rounds,
+        vec_tail_rounds, vec_tail_waves."""
+        c = None
+        if cfg is not None:
+            c = LaunchConfig(**{k: int(v) for k, v in cfg.items()})
+        rc = lib().rcr_plan_set_launch(self._h, ctypes.byref(c) if c is not None else None)
+        if rc != 0:
+            raise RcrError(rc, "rcr_plan_set_launch")
+
+    def get_launch(self) -> dict:
+        c = LaunchConfig()
+        rc = lib().rcr_plan_get_launch(self._h, ctypes.byref(c))
+        if rc != 0:
+            raise RcrError(rc, "rcr_plan_get_launch")
+        return {k: int(getattr(c, k)) for k in ("quad_tail_rounds", "vec_tail_rounds", "vec_tail_waves")}
+
+    def tune(self, prob: dict, out: dict | None = None, precision: int = FP64, refine_steps: int = -1,
+             stream=None) -> tuple[dict, float]:
+        """rcr_plan_tune: time the candidate launch mappings on this problem and keep
+        the fastest.  Returns (config, ms per solve)."""
+        import torch
+        sh = _shapes(self.N, self.n, self.m)
+        for k in PROBLEM_FIELDS:
+            _check(prob[k], k, sh[k])
+        if out is None:
+            out = alloc_solution(self, prob["Q"].device)
+        p = Problem(**{k: prob[k].data_ptr() for k in PROBLEM_FIELDS})
+        s_ = Solution(**{k: out[k].data_ptr() for k in SOLUTION_FIELDS})
+        o = SolveOptions(precision=precision, refine_steps=refine_steps, executor=EXEC_LEVELS)
+        best = LaunchConfig()
+        ms = ctypes.c_float(0.0)
+        st = stream if stream is not None else torch.cuda.current_stream(prob["Q"].device)
+        rc = lib().rcr_plan_tune(self._h, ctypes.byref(p), ctypes.byref(s_), ctypes.byref(o),
+                                 ctypes.c_void_p(st.cuda_stream), ctypes.byref(best), ctypes.byref(ms))
+        if rc != 0:
+            raise RcrError(rc, "rcr_plan_tune")
+        return {k: int(getattr(best, k)) for k in ("quad_tail_rounds", "vec_tail_rounds", "vec_tail_waves")}, ms.value
 
     def workspace_size(self, precision: int = FP64) -> int:
         return int(lib().rcr_workspace_size(self._h, precision))

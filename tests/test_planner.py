@@ -211,3 +211,15 @@ def test_batched_plan_is_union_of_remapped_trees():
         else:
             got.add((kind, lvl, a, b, c, d, e))
     assert got == want
+
+
+def test_launch_config_set_get_and_validation():
+    plan = rcr.Plan(w.tree_chainprob(200, 0.9, np.random.default_rng(0)), 4, 2)
+    assert plan.get_launch() == {"quad_tail_rounds": 0, "vec_tail_rounds": 0, "vec_tail_waves": 0}
+    plan.set_launch({"quad_tail_rounds": 4, "vec_tail_rounds": -1, "vec_tail_waves": 8})
+    assert plan.get_launch() == {"quad_tail_rounds": 4, "vec_tail_rounds": -1, "vec_tail_waves": 8}
+    with pytest.raises(rcr.RcrError) as ei:
+        plan.set_launch({"vec_tail_waves": 17})
+    assert ei.value.status == rcr.ERR_BAD_OPTION
+    plan.set_launch(None)
+    assert plan.get_launch() == {"quad_tail_rounds": 0, "vec_tail_rounds": 0, "vec_tail_waves": 0}
