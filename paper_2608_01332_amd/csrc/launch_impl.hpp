@@ -11,7 +11,7 @@
 #include "kernels.hpp"
 #include "lfwide.hpp"
 #include "tail.hpp"
-#include "wide.hpp"
+#include "wideops.hpp"
 
 namespace rcr {
 

@@ -12,7 +12,7 @@
 // replicated in registers when m is at most 4.
 #pragma once
 
-#include "wide.hpp"
+#include "mfma.hpp"
 
 namespace rcr {
 
@@ -117,33 +117,22 @@ RCR_MAT_KERNEL(NB) void k_local_factor_wide(Bufs<T> bf) {
   }
   team_sync();
   {  // the system [F | I], F = I + Delta P
-    T f[CQ];
-#pragma unroll
-    for (int c = 0; c < CQ; ++c) f[c] = (q * CQ + c == r) ? (T)1 : (T)0;
-    wmm_AB<T, NB>(f, LDe, LD, LP, LD);
+    const dv4 f = mf_mm<NB, false, false>(mf_ident(NB), LDe, LD, LP, LD);
+    mf_store(LM, LW, f, NB, NB);
     if (r < NB) {
 #pragma unroll
-      for (int c = 0; c < CQ; ++c) {
-        LM[r * LW + q * CQ + c] = f[c];
-        LM[r * LW + NB + q * CQ + c] = (q * CQ + c == r) ? (T)1 : (T)0;
-      }
+      for (int c = 0; c < CQ; ++c) LM[r * LW + NB + q * CQ + c] = (q * CQ + c == r) ? (T)1 : (T)0;
     }
   }
   team_sync();
   gj_wide<T, NB, 2 * NB>(LM, Lp, Lp, bf.status, true);
   const T *LFi = LM + NB;  // Finv, row stride LW
   {
-    T fi[CQ], w[CQ];
-#pragma unroll
-    for (int c = 0; c < CQ; ++c) {
-      fi[c] = LFi[rr * LW + q * CQ + c];
-      w[c] = (T)0;
-    }
-    wstore_piece<T, NB>(bf.Finv + v * nn, fi, n, true);
-    wmm_AB<T, NB>(w, LP, LD, LFi, LW);  // W = P Finv
-    wstore_piece<T, NB>(bf.W + v * nn, w, n, true);
+    mf_store(bf.Finv + v * nn, n, mf_load(LFi, LW, NB, NB), n, n);
+    const dv4 w = mf_mm<NB, false, false>(mf_zero(), LP, LD, LFi, LW);  // W = P Finv
+    mf_store(bf.W + v * nn, n, w, n, n);
     team_sync();  // the reads of P precede its replacement by W
-    wput_piece<T, NB>(LP, LD, w);
+    mf_store(LP, LD, w, NB, NB);
   }
   team_sync();
   for (int c = q; c < MB; c += 4) {  // WB = W B
@@ -253,11 +242,8 @@ RCR_MAT_KERNEL(NB) void k_local_factor_wide(Bufs<T> bf) {
   }
   team_sync();
   {
-    T t[CQ];
-#pragma unroll
-    for (int c = 0; c < CQ; ++c) t[c] = (T)0;
-    wmm_AB<T, NB>(t, LFi, LW, LDe, LD);  // T = Finv A^cl
-    if (edge) wstore_piece<T, NB>(bf.Tm + v * nn, t, n, true);
+    const dv4 t = mf_mm<NB, false, false>(mf_zero(), LFi, LW, LDe, LD);  // T = Finv A^cl
+    if (edge) mf_store(bf.Tm + v * nn, n, t, n, n);
   }
 }
 

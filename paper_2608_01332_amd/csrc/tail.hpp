@@ -12,7 +12,7 @@
 #pragma once
 
 #include "kernels.hpp"
-#include "wide.hpp"
+#include "wideops.hpp"
 
 namespace rcr {
 
