@@ -459,6 +459,8 @@ def main() -> int:
     ap.add_argument("--class-steps", type=int, default=5, help="steps of the per-launch event pass")
     ap.add_argument("--no-mixed", action="store_true", help="skip the MIXED32 + refinement leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch mapping (no autotuning)")
+    ap.add_argument("--launch", default="", help="explicit launch mapping of the single workload, "
+                    "'key=value,...' with the fields of rcr_launch_config (no autotuning)")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--rates", default="100,200,500,1000,2000,5000")
     ap.add_argument("--requests", type=int, default=0, help="requests per rate (0: 10k, or 20 s of arrivals below 500/s)")
@@ -514,7 +516,11 @@ def main() -> int:
     stream = torch.cuda.current_stream(dev)
 
     tuned = None
-    if not args.no_tune:
+    if args.launch:
+        # an explicit launch mapping ("key=value,..."), no autotuning
+        plan.set_launch({k: int(v) for k, v in (kv.split("=") for kv in args.launch.split(","))})
+        tuned = plan.get_launch()
+    elif not args.no_tune:
         # launch mapping of the narrow levels, autotuned on this instance (untimed)
         tuned, tuned_ms = plan.tune(prob, out=out)
     # accuracy at the measured configuration (outside the timed region)

@@ -100,7 +100,8 @@ __host__ __device__ constexpr int lds_quad_words() {
 // A and Delta are overwritten by Abar and Cbar), B, S, Bt, St (NB x MB), R (MB x MB).
 template <int NB, int MB>
 struct CondLay {
-  static constexpr int A = 0, D = NB * NB, P = 2 * NB * NB, B = 3 * NB * NB, S = B + NB * MB, Bt = S + NB * MB,
+  static constexpr int LA = NB + 1, LB = MB + 1;  // padded strides of the tiles read a row per lane
+  static constexpr int A = 0, D = NB * LA, P = 2 * NB * LA, B = 3 * NB * LA, S = B + NB * LB, Bt = S + NB * LB,
                        St = Bt + NB * MB, R = St + NB * MB, words = team_stride<double>(R + MB * MB);
 };
 
@@ -126,10 +127,10 @@ RCR_MAT_KERNEL(NB) void k_condense(Bufs<T> bf) {
     stage_load<PW, NB, MB>(rb, bf.B, v0, cnt, n, m, lane);
     stage_load<PW, NB, MB>(rs, bf.S, v0, cnt, n, m, lane);
     stage_load<PW, MB, MB>(rq, bf.R, v0, cnt, m, m, lane);
-    stage_put<PW, NB, NB>(smd + Ly::A, TS, ra, lane);
-    stage_put<PW, NB, NB>(smd + Ly::D, TS, rd, lane);
-    stage_put<PW, NB, MB>(smd + Ly::B, TS, rb, lane);
-    stage_put<PW, NB, MB>(smd + Ly::S, TS, rs, lane);
+    stage_put<PW, NB, NB, Ly::LA>(smd + Ly::A, TS, ra, lane);
+    stage_put<PW, NB, NB, Ly::LA>(smd + Ly::D, TS, rd, lane);
+    stage_put<PW, NB, MB, Ly::LB>(smd + Ly::B, TS, rb, lane);
+    stage_put<PW, NB, MB, Ly::LB>(smd + Ly::S, TS, rs, lane);
     stage_put<PW, MB, MB>(smd + Ly::R, TS, rq, lane);
   }
   team_sync();
@@ -161,8 +162,8 @@ RCR_MAT_KERNEL(NB) void k_condense(Bufs<T> bf) {
   double bt[MB], st[MB];
 #pragma unroll
   for (int c = 0; c < MB; ++c) {
-    bt[c] = L[Ly::B + rr * MB + c];
-    st[c] = L[Ly::S + rr * MB + c];
+    bt[c] = L[Ly::B + rr * Ly::LB + c];
+    st[c] = L[Ly::S + rr * Ly::LB + c];
   }
 #pragma unroll
   for (int c = 0; c < MB; ++c) {  // forward substitution L y = row^T
@@ -194,8 +195,8 @@ RCR_MAT_KERNEL(NB) void k_condense(Bufs<T> bf) {
       sbs = fma(bt[c], sj, sbs);
       sss = fma(st[c], sj, sss);
     }
-    oa[j] = L[Ly::A + rr * NB + j] - sbs;
-    oc[j] = L[Ly::D + rr * NB + j] + sbb;
+    oa[j] = L[Ly::A + rr * Ly::LA + j] - sbs;
+    oc[j] = L[Ly::D + rr * Ly::LA + j] + sbb;
     op[j] = -sss;
     pin1(oa[j]);
     pin1(oc[j]);
@@ -205,16 +206,16 @@ RCR_MAT_KERNEL(NB) void k_condense(Bufs<T> bf) {
   if (r < NB) {  // each lane overwrites only its own rows of A and Delta
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      L[Ly::A + r * NB + j] = oa[j];
-      L[Ly::D + r * NB + j] = oc[j];
-      L[Ly::P + r * NB + j] = op[j];
+      L[Ly::A + r * Ly::LA + j] = oa[j];
+      L[Ly::D + r * Ly::LA + j] = oc[j];
+      L[Ly::P + r * Ly::LA + j] = op[j];
     }
   }
   team_sync();
   // the edge records of every team but the edge-less ones (the root, idle teams)
-  stage_store<PW, NB, NB>(bf.EA, smd + Ly::A, TS, v0, cnt, n, n, lane, noedge, TW);
-  stage_store<PW, NB, NB>(bf.EC, smd + Ly::D, TS, v0, cnt, n, n, lane, noedge, TW);
-  stage_store<PW, NB, NB>(bf.EP, smd + Ly::P, TS, v0, cnt, n, n, lane, noedge, TW);
+  stage_store<PW, NB, NB, false, Ly::LA>(bf.EA, smd + Ly::A, TS, v0, cnt, n, n, lane, noedge, TW);
+  stage_store<PW, NB, NB, false, Ly::LA>(bf.EC, smd + Ly::D, TS, v0, cnt, n, n, lane, noedge, TW);
+  stage_store<PW, NB, NB, false, Ly::LA>(bf.EP, smd + Ly::P, TS, v0, cnt, n, n, lane, noedge, TW);
 }
 
 // One quadratic-contraction primitive of kind s on a team (lane r, LDS L).
@@ -613,11 +614,12 @@ RCR_MAT_KERNEL(NB) void k_tcompose(Bufs<T> bf, const Op4 *__restrict__ ops, int6
 // Vector primitives: one team per op, lane r computes entry r.  Inputs that
 // every lane needs are read from global memory (broadcast within a team).
 
-// Per-team LDS of k_rhs_init (words of T): W, A^cl (NB x NB), K (MB x NB),
-// c, W c, z (NB), r (MB).
+// Per-team LDS of k_rhs_init (words of T): W (NB rows of stride NB + 1,
+// read a row per lane), A^cl (NB x NB), K (MB x NB), c, W c, z (NB), r (MB).
 template <int NB, int MB>
 struct RhsLay {
-  static constexpr int W = 0, Acl = NB * NB, K = 2 * NB * NB, c = K + MB * NB, wc = c + NB, z = wc + NB,
+  static constexpr int LW = NB + 1;
+  static constexpr int W = 0, Acl = NB * LW, K = Acl + NB * NB, c = K + MB * NB, wc = c + NB, z = wc + NB,
                        r = z + NB, words = r + MB;
 };
 
@@ -641,7 +643,7 @@ __global__ __launch_bounds__(64) void k_rhs_init(Bufs<T> bf) {
     stage_load<PW, MB, NB>(rk, bf.Kw, v0, cnt, m, n, lane);
     stage_load<PW, 1, NB>(rc, bf.sc, v0, cnt, 1, n, lane);
     stage_load<PW, 1, MB>(rr_, bf.sr, v0, cnt, 1, m, lane);
-    stage_put<PW, NB, NB>(smt + Ly::W, TS, rw, lane);
+    stage_put<PW, NB, NB, Ly::LW>(smt + Ly::W, TS, rw, lane);
     stage_put<PW, NB, NB>(smt + Ly::Acl, TS, ra, lane);
     stage_put<PW, MB, NB>(smt + Ly::K, TS, rk, lane);
     stage_put<PW, 1, NB>(smt + Ly::c, TS, rc, lane);
@@ -655,7 +657,7 @@ __global__ __launch_bounds__(64) void k_rhs_init(Bufs<T> bf) {
   const int rr = r < NB ? r : NB - 1;
   T wc = (T)0;
 #pragma unroll
-  for (int k = 0; k < NB; ++k) wc = fmat(L[Ly::W + rr * NB + k], L[Ly::c + k], wc);
+  for (int k = 0; k < NB; ++k) wc = fmat(L[Ly::W + rr * Ly::LW + k], L[Ly::c + k], wc);
   if (r < NB) L[Ly::wc + r] = wc;
   team_sync();
   T s = (T)0;
@@ -731,11 +733,14 @@ __global__ __launch_bounds__(64) void k_aff_expand(Bufs<T> bf, const Op4 *__rest
   affexp_op<T, NB>(bf, ops[off + q0], r);
 }
 
-// Per-team LDS of k_local_affine (words of T): Delta, W, Finv (NB x NB),
-// B (NB x MB), G^-1 (MB x MB), p, c, f, g, B k - f, b (NB), r, t, k (MB).
+// Per-team LDS of k_local_affine (words of T): Delta, W, Finv (NB rows of
+// stride NB + 1), B (NB rows of stride MB + 1), G^-1 (MB x MB), p, c, f, g,
+// B k - f, b (NB), r, t, k (MB).  The padded strides keep the row-per-lane
+// reads free of bank conflicts.
 template <int NB, int MB>
 struct LaLay {
-  static constexpr int D = 0, W = NB * NB, Fi = 2 * NB * NB, B = 3 * NB * NB, Gi = B + NB * MB, p = Gi + MB * MB,
+  static constexpr int LR = NB + 1, LB = MB + 1;
+  static constexpr int D = 0, W = NB * LR, Fi = 2 * NB * LR, B = 3 * NB * LR, Gi = B + NB * LB, p = Gi + MB * MB,
                        c = p + NB, f = c + NB, g = f + NB, wv = g + NB, b = wv + NB, r = b + NB, t = r + MB,
                        k = t + MB, words = k + MB;
 };
@@ -765,10 +770,10 @@ __global__ __launch_bounds__(64) void k_local_affine(Bufs<T> bf) {
     stage_load<PW, 1, NB>(rp, bf.p, v0, cnt, 1, n, lane);
     stage_load<PW, 1, NB>(rc, bf.sc, v0, cnt, 1, n, lane);
     stage_load<PW, 1, MB>(rr_, bf.sr, v0, cnt, 1, m, lane);
-    stage_put<PW, NB, NB>(smt + Ly::D, TS, rd, lane);
-    stage_put<PW, NB, NB>(smt + Ly::W, TS, rw, lane);
-    stage_put<PW, NB, NB>(smt + Ly::Fi, TS, rf, lane);
-    stage_put<PW, NB, MB>(smt + Ly::B, TS, rb, lane);
+    stage_put<PW, NB, NB, Ly::LR>(smt + Ly::D, TS, rd, lane);
+    stage_put<PW, NB, NB, Ly::LR>(smt + Ly::W, TS, rw, lane);
+    stage_put<PW, NB, NB, Ly::LR>(smt + Ly::Fi, TS, rf, lane);
+    stage_put<PW, NB, MB, Ly::LB>(smt + Ly::B, TS, rb, lane);
     stage_put<PW, MB, MB>(smt + Ly::Gi, TS, rg, lane);
     stage_put<PW, 1, NB>(smt + Ly::p, TS, rp, lane);
     stage_put<PW, 1, NB>(smt + Ly::c, TS, rc, lane);
@@ -791,23 +796,23 @@ __global__ __launch_bounds__(64) void k_local_affine(Bufs<T> bf) {
   const int rm = r < MB ? r : MB - 1;
   T f = -L[Ly::c + rr];
 #pragma unroll
-  for (int k = 0; k < NB; ++k) f = fmat(L[Ly::D + rr * NB + k], L[Ly::p + k], f);
+  for (int k = 0; k < NB; ++k) f = fmat(L[Ly::D + rr * Ly::LR + k], L[Ly::p + k], f);
   if (r < NB) L[Ly::f + r] = f;
   team_sync();
   if (isroot) {  // x_root = -F^-1 f  (eq. (xroot))
     T x = (T)0;
 #pragma unroll
-    for (int k = 0; k < NB; ++k) x = fmat(-L[Ly::Fi + rr * NB + k], L[Ly::f + k], x);
+    for (int k = 0; k < NB; ++k) x = fmat(-L[Ly::Fi + rr * Ly::LR + k], L[Ly::f + k], x);
     if (r < n) bf.xw[v * n + r] = x;
   }
   T g = L[Ly::p + rr];
 #pragma unroll
-  for (int k = 0; k < NB; ++k) g = fmat(-L[Ly::W + rr * NB + k], L[Ly::f + k], g);
+  for (int k = 0; k < NB; ++k) g = fmat(-L[Ly::W + rr * Ly::LR + k], L[Ly::f + k], g);
   if (r < NB) L[Ly::g + r] = g;
   team_sync();
   T t = L[Ly::r + rm];  // lane c < m: r_c + (B^T g)_c
 #pragma unroll
-  for (int k = 0; k < NB; ++k) t = fmat(L[Ly::B + k * MB + rm], L[Ly::g + k], t);
+  for (int k = 0; k < NB; ++k) t = fmat(L[Ly::B + k * Ly::LB + rm], L[Ly::g + k], t);
   if (r < MB) L[Ly::t + r] = t;
   team_sync();
   T kk = (T)0;
@@ -817,12 +822,12 @@ __global__ __launch_bounds__(64) void k_local_affine(Bufs<T> bf) {
   team_sync();
   T wv = -f;  // lane r < n: (B k - f)_r
 #pragma unroll
-  for (int d = 0; d < MB; ++d) wv = fmat(L[Ly::B + rr * MB + d], L[Ly::k + d], wv);
+  for (int d = 0; d < MB; ++d) wv = fmat(L[Ly::B + rr * Ly::LB + d], L[Ly::k + d], wv);
   if (r < NB) L[Ly::wv + r] = wv;
   team_sync();
   T bb = (T)0;
 #pragma unroll
-  for (int k = 0; k < NB; ++k) bb = fmat(L[Ly::Fi + rr * NB + k], L[Ly::wv + k], bb);
+  for (int k = 0; k < NB; ++k) bb = fmat(L[Ly::Fi + rr * Ly::LR + k], L[Ly::wv + k], bb);
   if (r < NB) L[Ly::b + r] = bb;
   team_sync();
   stage_store<PW, 1, MB>(bf.kff, smt + Ly::k, TS, v0, cnt, 1, m, lane, noedge, TW);
@@ -877,11 +882,12 @@ __global__ __launch_bounds__(64) void k_state_expand(Bufs<T> bf, const Op4 *__re
   sexp_op<T, NB>(bf, ops[off + q0], r);
 }
 
-// Per-team LDS of k_recover (words of T): P (NB x NB), K (MB x NB), x, p,
-// x of the parent, y (NB), k, u (MB).
+// Per-team LDS of k_recover (words of T): P (NB rows), K (MB rows), both of
+// stride NB + 1 (read a row per lane), x, p, x of the parent, y (NB), k, u (MB).
 template <int NB, int MB>
 struct RecLay {
-  static constexpr int P = 0, K = NB * NB, x = K + MB * NB, p = x + NB, xp = p + NB, y = xp + NB, k = y + NB,
+  static constexpr int LR = NB + 1;
+  static constexpr int P = 0, K = NB * LR, x = K + MB * LR, p = x + NB, xp = p + NB, y = xp + NB, k = y + NB,
                        u = k + MB, words = u + MB;
 };
 
@@ -904,8 +910,8 @@ __global__ __launch_bounds__(64) void k_recover(Bufs<T> bf) {
     stage_load<PW, 1, NB>(rx, bf.xw, v0, cnt, 1, n, lane);
     stage_load<PW, 1, NB>(rv, bf.p, v0, cnt, 1, n, lane);
     stage_load<PW, 1, MB>(rf, bf.kff, v0, cnt, 1, m, lane);
-    stage_put<PW, NB, NB>(smt + Ly::P, TS, rp, lane);
-    stage_put<PW, MB, NB>(smt + Ly::K, TS, rk, lane);
+    stage_put<PW, NB, NB, Ly::LR>(smt + Ly::P, TS, rp, lane);
+    stage_put<PW, MB, NB, Ly::LR>(smt + Ly::K, TS, rk, lane);
     stage_put<PW, 1, NB>(smt + Ly::x, TS, rx, lane);
     stage_put<PW, 1, NB>(smt + Ly::p, TS, rv, lane);
     stage_put<PW, 1, MB>(smt + Ly::k, TS, rf, lane);
@@ -919,7 +925,7 @@ __global__ __launch_bounds__(64) void k_recover(Bufs<T> bf) {
   const int rr = r < NB ? r : NB - 1;
   T y = L[Ly::p + rr];
 #pragma unroll
-  for (int k = 0; k < NB; ++k) y = fmat(L[Ly::P + rr * NB + k], L[Ly::x + k], y);
+  for (int k = 0; k < NB; ++k) y = fmat(L[Ly::P + rr * Ly::LR + k], L[Ly::x + k], y);
   if (r < NB) L[Ly::y + r] = y;
   bool bad = active && r < n && (!isfinite((double)y) || !isfinite((double)L[Ly::x + r]));
   for (int c = r; c < MB; c += TW) {
@@ -927,7 +933,7 @@ __global__ __launch_bounds__(64) void k_recover(Bufs<T> bf) {
     if (i >= 0) {
       u = L[Ly::k + c];
 #pragma unroll
-      for (int k = 0; k < NB; ++k) u = fmat(L[Ly::K + c * NB + k], L[Ly::xp + k], u);
+      for (int k = 0; k < NB; ++k) u = fmat(L[Ly::K + c * Ly::LR + k], L[Ly::xp + k], u);
     }
     L[Ly::u + c] = u;
     bad = bad || (active && c < m && !isfinite((double)u));

@@ -312,7 +312,9 @@ __device__ __forceinline__ void stage_load(S (&reg)[(PW * RB * CB + 63) / 64], c
   }
 }
 
-template <int PW, int RB, int CB, typename S, typename T>
+// LDR: LDS row stride of the tile (>= CB; CB + 1 keeps a row-per-lane access
+// free of bank conflicts).
+template <int PW, int RB, int CB, int LDR = CB, typename S, typename T>
 __device__ __forceinline__ void stage_put(T *lds, int ts, const S (&reg)[(PW * RB * CB + 63) / 64], int lane) {
   constexpr int TOT = Tile<PW, RB, CB>::TOT;
 #pragma unroll
@@ -320,7 +322,7 @@ __device__ __forceinline__ void stage_put(T *lds, int ts, const S (&reg)[(PW * R
     const int p = lane + 64 * k;
     if (p < TOT) {
       const int t = p / (RB * CB), r = (p / CB) % RB, j = p % CB;
-      lds[t * ts + r * CB + j] = (T)reg[k];
+      lds[t * ts + r * LDR + j] = (T)reg[k];
     }
   }
 }
@@ -329,7 +331,7 @@ __device__ __forceinline__ void stage_put(T *lds, int ts, const S (&reg)[(PW * R
 // over lanes, tw = team width) marks a team whose node is not written.  With
 // TRANS, the LDS tile holds the transpose of the global block (LDS row j,
 // column r -> global row r, column j; the LDS tile is CB x RB).
-template <int PW, int RB, int CB, bool TRANS = false, typename T, typename D>
+template <int PW, int RB, int CB, bool TRANS = false, int LDR = CB, typename T, typename D>
 __device__ __forceinline__ void stage_store(D *__restrict__ g, const T *lds, int ts, int64_t v0, int cnt, int rn,
                                            int cn, int lane, uint64_t skip = 0, int tw = 64) {
   constexpr int TOT = Tile<PW, RB, CB>::TOT;
@@ -340,7 +342,7 @@ __device__ __forceinline__ void stage_store(D *__restrict__ g, const T *lds, int
     const int t = p / (RB * CB), r = (p / CB) % RB, j = p % CB;
     const bool skipped = (skip >> ((t * tw) & 63)) & 1;
     if (p < TOT && t < cnt && !skipped && r < rn && j < cn)
-      g[(v0 + t) * w + r * cn + j] = (D)(TRANS ? lds[t * ts + j * RB + r] : lds[t * ts + r * CB + j]);
+      g[(v0 + t) * w + r * cn + j] = (D)(TRANS ? lds[t * ts + j * RB + r] : lds[t * ts + r * LDR + j]);
   }
 }
 

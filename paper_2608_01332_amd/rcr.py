@@ -14,7 +14,8 @@ import threading
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librcr.so")
+# the in-tree build; RCR_LIB names another build of the same library
+LIB_PATH = os.environ.get("RCR_LIB") or os.path.join(HERE, "librcr.so")
 
 ERR_INVALID_TREE, ERR_BAD_DIMS, ERR_NULL_ARG, ERR_NOT_PD, ERR_SINGULAR, ERR_NONFINITE = -1, -2, -3, -4, -5, -6
 ERR_OOM, ERR_HIP_ERROR, ERR_BAD_OPTION, ERR_SMALL_WORKSPACE, ERR_NO_DEVICE = -7, -8, -9, -10, -11
@@ -62,9 +63,11 @@ class NativeSolution(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in ("x", "v", "lam")]
 
 
+LAUNCH_FIELDS = ("quad_tail_rounds", "vec_tail_rounds", "vec_tail_waves")
+
+
 class LaunchConfig(ctypes.Structure):
-    _fields_ = [("quad_tail_rounds", ctypes.c_int32), ("vec_tail_rounds", ctypes.c_int32),
-                ("vec_tail_waves", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+    _fields_ = [(k, ctypes.c_int32) for k in LAUNCH_FIELDS] + [("reserved", ctypes.c_int32 * 5)]
 
 
 class SolveOptions(ctypes.Structure):
@@ -223,8 +226,7 @@ class Plan:
             raise RcrError(rc, "rcr_plan_upload")
 
     def set_launch(self, cfg: dict | None = None):
-        """rcr_plan_set_launch (None: defaults).  Keys: quad_tail_rounds,
-        vec_tail_rounds, vec_tail_waves."""
+        """rcr_plan_set_launch (None: defaults).  Keys: LAUNCH_FIELDS."""
         c = None
         if cfg is not None:
             c = LaunchConfig(**{k: int(v) for k, v in cfg.items()})
@@ -237,7 +239,7 @@ class Plan:
         rc = lib().rcr_plan_get_launch(self._h, ctypes.byref(c))
         if rc != 0:
             raise RcrError(rc, "rcr_plan_get_launch")
-        return {k: int(getattr(c, k)) for k in ("quad_tail_rounds", "vec_tail_rounds", "vec_tail_waves")}
+        return {k: int(getattr(c, k)) for k in LAUNCH_FIELDS}
 
     def tune(self, prob: dict, out: dict | None = None, precision: int = FP64, refine_steps: int = -1,
              stream=None) -> tuple[dict, float]:
@@ -259,7 +261,7 @@ class Plan:
                                  ctypes.c_void_p(st.cuda_stream), ctypes.byref(best), ctypes.byref(ms))
         if rc != 0:
             raise RcrError(rc, "rcr_plan_tune")
-        return {k: int(getattr(best, k)) for k in ("quad_tail_rounds", "vec_tail_rounds", "vec_tail_waves")}, ms.value
+        return {k: int(getattr(best, k)) for k in LAUNCH_FIELDS}, ms.value
 
     def workspace_size(self, precision: int = FP64) -> int:
         return int(lib().rcr_workspace_size(self._h, precision))

@@ -215,11 +215,15 @@ def test_batched_plan_is_union_of_remapped_trees():
 
 def test_launch_config_set_get_and_validation():
     plan = rcr.Plan(w.tree_chainprob(200, 0.9, np.random.default_rng(0)), 4, 2)
-    assert plan.get_launch() == {"quad_tail_rounds": 0, "vec_tail_rounds": 0, "vec_tail_waves": 0}
-    plan.set_launch({"quad_tail_rounds": 4, "vec_tail_rounds": -1, "vec_tail_waves": 8})
-    assert plan.get_launch() == {"quad_tail_rounds": 4, "vec_tail_rounds": -1, "vec_tail_waves": 8}
+    zero = {k: 0 for k in rcr.LAUNCH_FIELDS}
+    assert plan.get_launch() == zero
+    cfg = {"quad_tail_rounds": 4, "vec_tail_rounds": -1, "vec_tail_waves": 8}
+    plan.set_launch(cfg)
+    assert plan.get_launch() == cfg
+    plan.set_launch({"vec_tail_rounds": -1})  # unspecified fields reset to their defaults
+    assert plan.get_launch() == dict(zero, vec_tail_rounds=-1)
     with pytest.raises(rcr.RcrError) as ei:
         plan.set_launch({"vec_tail_waves": 17})
     assert ei.value.status == rcr.ERR_BAD_OPTION
     plan.set_launch(None)
-    assert plan.get_launch() == {"quad_tail_rounds": 0, "vec_tail_rounds": 0, "vec_tail_waves": 0}
+    assert plan.get_launch() == zero
