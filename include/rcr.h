@@ -275,7 +275,7 @@ int rcr_lift_solve(const rcr_plan *plan, const rcr_native_problem *in, rcr_nativ
 typedef struct {
   int32_t quad_tail_rounds; /* quadratic contraction/expansion tail (default 2)            */
   int32_t vec_tail_rounds;  /* affine and state tails (default 4)                           */
-  int32_t vec_tail_waves;   /* wavefronts of the vector tail workgroup, 1..16 (default 16) */
+  int32_t vec_tail_waves;   /* wavefronts of the vector tail workgroup, 1..16 (default 8)  */
   int32_t reserved[5];
 } rcr_launch_config;
 

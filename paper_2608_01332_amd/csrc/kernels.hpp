@@ -678,11 +678,10 @@ __device__ __forceinline__ void aff_op(const Bufs<T> &bf, const OpRec &o, int s,
   if (r >= n) return;
   if (s == OP_RAKE) {  // m = Z h_j + z,  Z = T^T;  p_j = h_j
     const int64_t j = o.a, e = o.b, out = o.c;
-    T acc = bf.z[e * n + r];
-#pragma unroll
-    for (int k = 0; k < NB; ++k)
-      if (k < n) acc = fmat(bf.Tm[e * nn + k * n + r], bf.h[j * n + k], acc);
-    bf.cv[out * n + r] = acc;
+    T tv[NB], hv[NB];
+    gather(tv, n, [&](int k) { return bf.Tm[e * nn + k * n + r]; });
+    gather(hv, n, [&](int k) { return bf.h[j * n + k]; });
+    bf.cv[out * n + r] = dot_n(tv, hv, n, bf.z[e * n + r]);
     bf.p[j * n + r] = bf.h[j * n + r];
   } else if (s == OP_COMBINE) {
     bf.cv[(int64_t)o.c * n + r] = bf.cv[(int64_t)o.a * n + r] + bf.cv[(int64_t)o.b * n + r];
@@ -690,11 +689,13 @@ __device__ __forceinline__ void aff_op(const Bufs<T> &bf, const OpRec &o, int s,
     bf.h[(int64_t)o.a * n + r] += bf.cv[(int64_t)o.b * n + r];
   } else {  // z_new = z_l + Z_l (h_j + z_r)
     const int64_t j = o.a, l = o.b, rs = o.c, sn = o.d;
-    T acc = bf.z[l * n + r];
+    T tv[NB], hv[NB], zv[NB];
+    gather(tv, n, [&](int k) { return bf.Tm[l * nn + k * n + r]; });
+    gather(hv, n, [&](int k) { return bf.h[j * n + k]; });
+    gather(zv, n, [&](int k) { return bf.z[rs * n + k]; });
 #pragma unroll
-    for (int k = 0; k < NB; ++k)
-      if (k < n) acc = fmat(bf.Tm[l * nn + k * n + r], bf.h[j * n + k] + bf.z[rs * n + k], acc);
-    bf.z[sn * n + r] = acc;
+    for (int k = 0; k < NB; ++k) hv[k] += zv[k];
+    bf.z[sn * n + r] = dot_n(tv, hv, n, bf.z[l * n + r]);
   }
 }
 
@@ -716,11 +717,10 @@ __device__ __forceinline__ void affexp_op(const Bufs<T> &bf, const Op4 &o, int r
   const int n = bf.n;
   const int64_t nn = (int64_t)n * n;
   const int64_t j = o.a, rs = o.b, k = o.c;
-  T acc = bf.h[j * n + r] + bf.z[rs * n + r];
-#pragma unroll
-  for (int q = 0; q < NB; ++q)
-    if (q < n) acc = fmat(bf.Tm[rs * nn + q * n + r], bf.p[k * n + q], acc);
-  bf.p[j * n + r] = acc;
+  T tv[NB], pv[NB];
+  gather(tv, n, [&](int q) { return bf.Tm[rs * nn + q * n + r]; });
+  gather(pv, n, [&](int q) { return bf.p[k * n + q]; });
+  bf.p[j * n + r] = dot_n(tv, pv, n, bf.h[j * n + r] + bf.z[rs * n + r]);
 }
 
 template <typename T, int NB>
@@ -841,11 +841,10 @@ __device__ __forceinline__ void state_op(const Bufs<T> &bf, const Op4 &o, int r)
   const int n = bf.n;
   const int64_t nn = (int64_t)n * n;
   const int64_t l = o.a, rs = o.b, sn = o.c;
-  T acc = bf.b[rs * n + r];
-#pragma unroll
-  for (int k = 0; k < NB; ++k)
-    if (k < n) acc = fmat(bf.Tm[rs * nn + r * n + k], bf.b[l * n + k], acc);
-  bf.b[sn * n + r] = acc;
+  T tv[NB], bv[NB];
+  gather(tv, n, [&](int k) { return bf.Tm[rs * nn + r * n + k]; });
+  gather(bv, n, [&](int k) { return bf.b[l * n + k]; });
+  bf.b[sn * n + r] = dot_n(tv, bv, n, bf.b[rs * n + r]);
 }
 
 template <typename T, int NB>
@@ -865,11 +864,10 @@ __device__ __forceinline__ void sexp_op(const Bufs<T> &bf, const Op4 &o, int r) 
   const int n = bf.n;
   const int64_t nn = (int64_t)n * n;
   const int64_t j = o.a, sl = o.b, i = o.c;
-  T acc = bf.b[sl * n + r];
-#pragma unroll
-  for (int k = 0; k < NB; ++k)
-    if (k < n) acc = fmat(bf.Tm[sl * nn + r * n + k], bf.xw[i * n + k], acc);
-  bf.xw[j * n + r] = acc;
+  T tv[NB], xv[NB];
+  gather(tv, n, [&](int k) { return bf.Tm[sl * nn + r * n + k]; });
+  gather(xv, n, [&](int k) { return bf.xw[i * n + k]; });
+  bf.xw[j * n + r] = dot_n(tv, xv, n, bf.b[sl * n + r]);
 }
 
 template <typename T, int NB>

@@ -157,7 +157,7 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
   const LaunchCfg &cfg = P.cfg;
   const int qr = cfg.quad_tail_rounds == 0 ? 2 : (cfg.quad_tail_rounds < 0 ? 0 : cfg.quad_tail_rounds);
   const int64_t mat_cap = (int64_t)qr * mat_waves * MatLay<NB>::PW;
-  const int vec_waves = cfg.vec_tail_waves > 0 ? std::min(cfg.vec_tail_waves, 16) : 16;
+  const int vec_waves = cfg.vec_tail_waves > 0 ? std::min(cfg.vec_tail_waves, 16) : 8;
   const int vr = cfg.vec_tail_rounds == 0 ? 4 : (cfg.vec_tail_rounds < 0 ? 0 : cfg.vec_tail_rounds);
   const int64_t vec_cap = (int64_t)vr * vec_waves * (64 / TeamW<NB>::TW);
   const size_t kVecTailLds = 144 * 1024;
@@ -171,8 +171,10 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
                                     h.sx_off, kVecTailLds);
   const size_t lds_ta = vec_tail_lds(ta, h.kind_off, 5, 4, sizeof(OpRec), h.exp_off);
   const size_t lds_ts = vec_tail_lds(ts, h.tc_off, 1, 1, sizeof(Op4), h.sx_off);
-  allow_lds(k_tail_aff<T, NB>, lds_ta);
-  allow_lds(k_tail_state<T, NB>, lds_ts);
+  allow_lds(k_tail_aff<T, NB, 512>, lds_ta);
+  allow_lds(k_tail_aff<T, NB, 1024>, lds_ta);
+  allow_lds(k_tail_state<T, NB, 512>, lds_ts);
+  allow_lds(k_tail_state<T, NB, 1024>, lds_ts);
 
   auto seg_of = [&](int64_t t, Seg &sg, int per) {
     unsigned total = 0;
@@ -252,8 +254,12 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
   }
   if (ta.levels() > 0) {
     tm.begin(RCR_K_AFF_TAIL);
-    LAUNCH(tm, (k_tail_aff<T, NB>), dim3(1), dim3(64 * vec_waves), lds_ta, st, bf, P.dev.ops, P.dev.koff, ta.c_begin,
-           ta.c_end, P.dev.exp_ops, P.dev.exp_off, ta.e_begin, ta.e_end);
+    if (vec_waves <= 8)
+      LAUNCH(tm, (k_tail_aff<T, NB, 512>), dim3(1), dim3(64 * vec_waves), lds_ta, st, bf, P.dev.ops, P.dev.koff,
+             ta.c_begin, ta.c_end, P.dev.exp_ops, P.dev.exp_off, ta.e_begin, ta.e_end);
+    else
+      LAUNCH(tm, (k_tail_aff<T, NB, 1024>), dim3(1), dim3(64 * vec_waves), lds_ta, st, bf, P.dev.ops, P.dev.koff,
+             ta.c_begin, ta.c_end, P.dev.exp_ops, P.dev.exp_off, ta.e_begin, ta.e_end);
   }
   tm.begin(RCR_K_AFF_EXPAND);
   for (int64_t t = ta.e_end; t < h.expand_levels(); ++t) {
@@ -275,8 +281,12 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
   }
   if (ts.levels() > 0) {
     tm.begin(RCR_K_STATE_TAIL);
-    LAUNCH(tm, (k_tail_state<T, NB>), dim3(1), dim3(64 * vec_waves), lds_ts, st, bf, P.dev.tc_ops, P.dev.tc_off,
-           ts.c_begin, ts.c_end, P.dev.sx_ops, P.dev.sx_off, ts.e_begin, ts.e_end);
+    if (vec_waves <= 8)
+      LAUNCH(tm, (k_tail_state<T, NB, 512>), dim3(1), dim3(64 * vec_waves), lds_ts, st, bf, P.dev.tc_ops,
+             P.dev.tc_off, ts.c_begin, ts.c_end, P.dev.sx_ops, P.dev.sx_off, ts.e_begin, ts.e_end);
+    else
+      LAUNCH(tm, (k_tail_state<T, NB, 1024>), dim3(1), dim3(64 * vec_waves), lds_ts, st, bf, P.dev.tc_ops,
+             P.dev.tc_off, ts.c_begin, ts.c_end, P.dev.sx_ops, P.dev.sx_off, ts.e_begin, ts.e_end);
   }
   tm.begin(RCR_K_STATE_EXPAND);
   for (int64_t t = ts.e_end; t < h.sexp_levels(); ++t) {

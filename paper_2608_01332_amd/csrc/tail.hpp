@@ -159,8 +159,9 @@ __device__ __forceinline__ void vec_tail_stage(char *lds, const RecC *__restrict
 // Column r (COL) or row r of the n x n block at g into registers (zero padded).
 template <typename T, int NB, bool COL>
 __device__ __forceinline__ void vec_mat_line(T (&v)[NB], const T *__restrict__ g, int n, int r) {
-#pragma unroll
-  for (int k = 0; k < NB; ++k) v[k] = (r < n && k < n) ? (COL ? g[k * n + r] : g[r * n + k]) : (T)0;
+  const int rr = r < n ? r : n - 1;
+  gather(v, n, [&](int k) { return COL ? g[k * n + rr] : g[rr * n + k]; });
+  if (r >= n) zero(v);
 }
 
 // Matrix block of an affine-pass primitive (-1: none): rake -> edge slot,
@@ -176,11 +177,9 @@ __device__ __forceinline__ void aff_op_col(const Bufs<T> &bf, const OpRec &o, in
   if (r >= n) return;
   if (o.kind == OP_RAKE) {  // m = Z h_j + z,  p_j = h_j
     const int64_t j = o.a, e = o.b, out = o.c;
-    T acc = bf.z[e * n + r];
-#pragma unroll
-    for (int k = 0; k < NB; ++k)
-      if (k < n) acc = fmat(col[k], bf.h[j * n + k], acc);
-    bf.cv[out * n + r] = acc;
+    T hv[NB];
+    gather(hv, n, [&](int k) { return bf.h[j * n + k]; });
+    bf.cv[out * n + r] = dot_n(col, hv, n, bf.z[e * n + r]);
     bf.p[j * n + r] = bf.h[j * n + r];
   } else if (o.kind == OP_COMBINE) {
     bf.cv[(int64_t)o.c * n + r] = bf.cv[(int64_t)o.a * n + r] + bf.cv[(int64_t)o.b * n + r];
@@ -188,11 +187,12 @@ __device__ __forceinline__ void aff_op_col(const Bufs<T> &bf, const OpRec &o, in
     bf.h[(int64_t)o.a * n + r] += bf.cv[(int64_t)o.b * n + r];
   } else {  // z_new = z_l + Z_l (h_j + z_r)
     const int64_t j = o.a, l = o.b, rs = o.c, sn = o.d;
-    T acc = bf.z[l * n + r];
+    T hv[NB], zv[NB];
+    gather(hv, n, [&](int k) { return bf.h[j * n + k]; });
+    gather(zv, n, [&](int k) { return bf.z[rs * n + k]; });
 #pragma unroll
-    for (int k = 0; k < NB; ++k)
-      if (k < n) acc = fmat(col[k], bf.h[j * n + k] + bf.z[rs * n + k], acc);
-    bf.z[sn * n + r] = acc;
+    for (int k = 0; k < NB; ++k) hv[k] += zv[k];
+    bf.z[sn * n + r] = dot_n(col, hv, n, bf.z[l * n + r]);
   }
 }
 
@@ -201,16 +201,17 @@ __device__ __forceinline__ void affexp_op_col(const Bufs<T> &bf, const Op4 &o, i
   const int n = bf.n;
   if (r >= n) return;
   const int64_t j = o.a, rs = o.b, k = o.c;
-  T acc = bf.h[j * n + r] + bf.z[rs * n + r];
-#pragma unroll
-  for (int q = 0; q < NB; ++q)
-    if (q < n) acc = fmat(col[q], bf.p[k * n + q], acc);
-  bf.p[j * n + r] = acc;
+  T pv[NB];
+  gather(pv, n, [&](int q) { return bf.p[k * n + q]; });
+  bf.p[j * n + r] = dot_n(col, pv, n, bf.h[j * n + r] + bf.z[rs * n + r]);
 }
 
 // Affine contraction levels [t0, t1) then affine expansion levels [e0, e1).
-template <typename T, int NB>
-__global__ __launch_bounds__(1024) void k_tail_aff(Bufs<T> bf, const OpRec *__restrict__ ops,
+// MAXT: the largest workgroup the instance is compiled for (512 leaves each
+// lane up to 256 VGPRs; 1024 allows twice the wavefronts with half the
+// registers).
+template <typename T, int NB, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_tail_aff(Bufs<T> bf, const OpRec *__restrict__ ops,
                                                    const int64_t *__restrict__ koff, int t0, int t1,
                                                    const Op4 *__restrict__ eops, const int64_t *__restrict__ eoff,
                                                    int e0, int e1) {
@@ -262,8 +263,8 @@ __global__ __launch_bounds__(1024) void k_tail_aff(Bufs<T> bf, const OpRec *__re
 
 // State-offset composition levels [t0, t1) then state expansion levels [e0, e1):
 // b_new = T_r b_l + b_r and x_j = T_s x_i + b_s with the lane's row of T.
-template <typename T, int NB>
-__global__ __launch_bounds__(1024) void k_tail_state(Bufs<T> bf, const Op4 *__restrict__ ops,
+template <typename T, int NB, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_tail_state(Bufs<T> bf, const Op4 *__restrict__ ops,
                                                      const int64_t *__restrict__ off, int t0, int t1,
                                                      const Op4 *__restrict__ xops, const int64_t *__restrict__ xoff,
                                                      int e0, int e1) {
@@ -300,20 +301,15 @@ __global__ __launch_bounds__(1024) void k_tail_state(Bufs<T> bf, const Op4 *__re
         vec_mat_line<T, NB, false>(row, bf.Tm + block_of(l, i) * nn, n, r);
       }
       if (r < n) {
+        T v[NB];
         if (l < nc) {
           const Op4 o = lc[i];
-          T acc = bf.b[(int64_t)o.b * n + r];
-#pragma unroll
-          for (int k = 0; k < NB; ++k)
-            if (k < n) acc = fmat(row[k], bf.b[(int64_t)o.a * n + k], acc);
-          bf.b[(int64_t)o.c * n + r] = acc;
+          gather(v, n, [&](int k) { return bf.b[(int64_t)o.a * n + k]; });
+          bf.b[(int64_t)o.c * n + r] = dot_n(row, v, n, bf.b[(int64_t)o.b * n + r]);
         } else {
           const Op4 o = le[i];
-          T acc = bf.b[(int64_t)o.b * n + r];
-#pragma unroll
-          for (int k = 0; k < NB; ++k)
-            if (k < n) acc = fmat(row[k], bf.xw[(int64_t)o.c * n + k], acc);
-          bf.xw[(int64_t)o.a * n + r] = acc;
+          gather(v, n, [&](int k) { return bf.xw[(int64_t)o.c * n + k]; });
+          bf.xw[(int64_t)o.a * n + r] = dot_n(row, v, n, bf.b[(int64_t)o.b * n + r]);
         }
       }
     }

@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
+#include <utility>
 
 #include "plan.hpp"
 
@@ -60,9 +62,42 @@ __host__ __device__ constexpr int team_stride(int words) {
   return words + ((1 - words) % K + K) % K;
 }
 
+// f(std::integral_constant<int, K>) for K = 0 .. N-1 in order: a loop whose
+// index is a compile-time constant in the body.
+template <typename F, int... K>
+__device__ __forceinline__ void static_for_seq(F &&f, std::integer_sequence<int, K...>) {
+  (f(std::integral_constant<int, K>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_seq(f, std::make_integer_sequence<int, N>{});
+}
+
 template <typename T>
 __device__ __forceinline__ T fmat(T a, T b, T c) {
   return fma(a, b, c);
+}
+
+// v[k] = at(k) for k < n and 0 for n <= k < NB, with every load issued
+// unconditionally (k >= n loads at(n - 1), a valid address, and discards it):
+// a load under a per-k condition would be compiled into a branch and a wait
+// per k, one memory round trip each, instead of one for all NB.
+template <int NB, typename T, typename F>
+__device__ __forceinline__ void gather(T (&v)[NB], int n, F at) {
+#pragma unroll
+  for (int k = 0; k < NB; ++k) v[k] = at(k < n ? k : n - 1);
+#pragma unroll
+  for (int k = 0; k < NB; ++k)
+    if (k >= n) v[k] = (T)0;
+}
+
+// acc + sum_{k < n} a[k] b[k], in increasing k
+template <int NB, typename T>
+__device__ __forceinline__ T dot_n(const T (&a)[NB], const T (&b)[NB], int n, T acc) {
+#pragma unroll
+  for (int k = 0; k < NB; ++k)
+    if (k < n) acc = fmat(a[k], b[k], acc);
+  return acc;
 }
 
 // Ordering point for a team's LDS traffic.  A workgroup is one wavefront and
@@ -194,21 +229,45 @@ __device__ __forceinline__ int piv_row(unsigned key) { return 15 - (int)(key & 1
 // no candidate, or a zero (or float32-underflowing) magnitude
 __device__ __forceinline__ bool piv_zero(unsigned key) { return (key >> 4) == 0u; }
 
-template <int CTRL>
-__device__ __forceinline__ unsigned dpp_umax(unsigned v) {
-  const unsigned o = (unsigned)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
-  return v > o ? v : o;
-}
 // Max over the TW lanes of a team, left in every lane: pairs (quad_perm
 // [1,0,3,2]), quads (quad_perm [2,3,0,1]), half rows (row_half_mirror), rows
-// (row_mirror).
+// (row_mirror).  Each step is one v_max_u32 whose first operand is read
+// through the DPP permutation; the two wait states before it cover the
+// hazard of a DPP read of a VGPR that the previous VALU instruction wrote.
+// Every lane of the wavefront must be active.
 template <int TW>
 __device__ __forceinline__ unsigned team_umax(unsigned v) {
-  v = dpp_umax<0xB1>(v);
-  v = dpp_umax<0x4E>(v);
-  if (TW >= 8) v = dpp_umax<0x141>(v);
-  if (TW >= 16) v = dpp_umax<0x140>(v);
+  asm volatile(
+      "s_nop 1\n\tv_max_u32_dpp %0, %0, %0 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n\t"
+      "s_nop 1\n\tv_max_u32_dpp %0, %0, %0 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf"
+      : "+v"(v));
+  if constexpr (TW >= 8)
+    asm volatile("s_nop 1\n\tv_max_u32_dpp %0, %0, %0 row_half_mirror row_mask:0xf bank_mask:0xf" : "+v"(v));
+  if constexpr (TW >= 16)
+    asm volatile("s_nop 1\n\tv_max_u32_dpp %0, %0, %0 row_mirror row_mask:0xf bank_mask:0xf" : "+v"(v));
   return v;
+}
+
+// Row QK (lanes 16 QK .. 16 QK + 15) of x in every row of the wavefront, lane
+// for lane: v_permlane32_swap of x with itself gives [R0 R1 R0 R1] and
+// [R2 R3 R2 R3]; v_permlane16_swap of the half holding QK with itself gives
+// that row in all four rows (first result: the even row, second: the odd).
+template <int QK>
+__device__ __forceinline__ unsigned row_bcast_u32(unsigned x) {
+  const auto s32 = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+  const unsigned c = QK < 2 ? s32[0] : s32[1];
+  const auto s16 = __builtin_amdgcn_permlane16_swap(c, c, false, false);
+  return (QK & 1) ? s16[1] : s16[0];
+}
+template <int QK>
+__device__ __forceinline__ double row_bcast(double x) {
+  const unsigned lo = row_bcast_u32<QK>((unsigned)__double2loint(x));
+  const unsigned hi = row_bcast_u32<QK>((unsigned)__double2hiint(x));
+  return __hiloint2double((int)hi, (int)lo);
+}
+template <int QK>
+__device__ __forceinline__ float row_bcast(float x) {
+  return __uint_as_float(row_bcast_u32<QK>(__float_as_uint(x)));
 }
 
 // 1 / d from the hardware reciprocal refined by Newton steps x <- x (2 - d x)

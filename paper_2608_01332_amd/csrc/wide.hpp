@@ -102,13 +102,16 @@ __device__ __forceinline__ float readlane_t<float>(float v, int lane) {
 // in LDS (LM, row stride W + 1): lane (q, r) works on the piece
 // [q WQ, q WQ + WQ) of row r.  Rows are never swapped.  At step k the pivot
 // key (piv_key) of column k is reduced over the 16 lanes holding that column
-// and made wave-uniform with readlane, which also fetches the exact pivot
-// value from its lane; each lane's multiplier (its row's entry in column k)
-// comes from the lane holding it by a cross-lane permute; only the pivot row
-// travels through LDS (Lp: W words).  The pivot row is scaled by 1 / pivot
-// and eliminated from every other row.  On return LM holds the eliminated
-// system in pivot order: row k is the row that pivoted at step k, so columns
-// [NB, W) are the solution.  (LF is unused scratch kept for the layout.)
+// and made wave-uniform with readlane.  Every lane forms the reciprocal of
+// its own column-k entry while the key is reduced, and readlane fetches the
+// pivot's from its lane, so the reciprocal is off the step's critical path.
+// Each lane's multiplier (its row's entry in column k, held by lane (qk, r))
+// is broadcast across the rows of the wavefront with permlane swaps; only the
+// pivot row travels through LDS (Lp: W words).  The pivot row is scaled by
+// 1 / pivot and eliminated from every other row.  On return LM holds the
+// eliminated system in pivot order: row k is the row that pivoted at step k,
+// so columns [NB, W) are the solution.  (LF is unused scratch kept for the
+// layout.)
 template <typename T, int NB, int W>
 __device__ __forceinline__ void gj_wide(T *LM, T *Lp, T *LF, int *status, bool report) {
   constexpr int WQ = W / 4, LW = W + 1;
@@ -119,20 +122,19 @@ __device__ __forceinline__ void gj_wide(T *LM, T *Lp, T *LF, int *status, bool r
   for (int c = 0; c < WQ; ++c) m[c] = (r < NB) ? LM[r * LW + q * WQ + c] : (T)0;
   bool used = r >= NB, sing = false;
   int step = 0;
-#pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    const int qk = k / WQ, ck = k % WQ;
+  static_for<NB>([&](auto kc) {
+    constexpr int k = decltype(kc)::value, qk = k / WQ, ck = k % WQ;
+    const T rc = rcp_nr(m[ck]);  // this lane's candidate reciprocal
     const unsigned key = (unsigned)__builtin_amdgcn_readlane(
         (int)team_umax<16>(piv_key(m[ck], r, !used && q == qk)), qk * 16);
     const int p = piv_row(key);
     sing = sing || piv_zero(key);
-    const T piv = readlane_t<T>(m[ck], qk * 16 + p);
-    const T f = __shfl(m[ck], qk * 16 + r, 64);  // entry (r, k), held by lane (qk, r)
+    const T inv = readlane_t<T>(rc, qk * 16 + p);
+    const T f = row_bcast<qk>(m[ck]);  // entry (r, k), held by lane (qk, r)
     if (r == p) {
 #pragma unroll
       for (int c = 0; c < WQ; ++c) Lp[q * WQ + c] = m[c];
     }
-    const T inv = rcp_nr(piv);
     team_sync();
     const T g = (r == p) ? inv - (T)1 : -f * inv;  // the pivot row becomes inv * row
 #pragma unroll
@@ -142,7 +144,7 @@ __device__ __forceinline__ void gj_wide(T *LM, T *Lp, T *LF, int *status, bool r
       step = k;
     }
     team_sync();
-  }
+  });
   if (report && (threadIdx.x & 63) == 0 && sing) atomicOr(status, ST_SINGULAR);
   if (r < NB) {
 #pragma unroll
