@@ -95,6 +95,15 @@ RCR_MAT_KERNEL(NB) void k_local_factor_wide(Bufs<T> bf) {
   const int rr = r < NB ? r : NB - 1;
   const bool isroot = bf.parent[v] < 0;
   const bool edge = !isroot;
+  // the lane's entries of M and R, loaded with the blocks (not after the elimination)
+  constexpr int CM = (MB + 3) / 4;
+  double sv[CM], rv[CM];
+#pragma unroll
+  for (int k = 0; k < CM; ++k) {
+    const int c = q + 4 * k;
+    sv[k] = (r < n && c < m) ? bf.S[v * nm + (int64_t)r * m + c] : 0.0;
+    rv[k] = (r < MB && c < MB) ? ((r < m && c < m) ? bf.R[v * m * m + r * m + c] : (r == c ? 1.0 : 0.0)) : 0.0;
+  }
   {
     T tP[TL], tD[TL], tA[TL], tB[TB];
     wfetch<T, NB>(tP, (isroot ? bf.U : bf.PW) + v * nn, n);
@@ -142,15 +151,21 @@ RCR_MAT_KERNEL(NB) void k_local_factor_wide(Bufs<T> bf) {
     if (r < NB) LWB[r * MBP + c] = s;
   }
   team_sync();
-  for (int c = q; c < MB; c += 4) {  // H^T = A^T WB + M (float64)
-    double h = (r < n && c < m) ? bf.S[v * nm + (int64_t)r * m + c] : 0.0;
+#pragma unroll
+  for (int k = 0; k < CM; ++k) {  // H^T = A^T WB + M (float64)
+    const int c = q + 4 * k;
+    if (c >= MB) break;
+    double h = sv[k];
 #pragma unroll
     for (int k = 0; k < NB; ++k) h = fma((double)LA[k * LD + rr], (double)LWB[k * MBP + c], h);
     if (r < NB) LH[r * MBP + c] = h;
   }
   if (r < MB) {
-    for (int c = q; c < MB; c += 4) {  // G = R + B^T WB (float64; padded with the identity)
-      double g = (r < m && c < m) ? bf.R[v * m * m + r * m + c] : (r == c ? 1.0 : 0.0);
+#pragma unroll
+    for (int k = 0; k < CM; ++k) {  // G = R + B^T WB (float64; padded with the identity)
+      const int c = q + 4 * k;
+      if (c >= MB) break;
+      double g = rv[k];
 #pragma unroll
       for (int k = 0; k < NB; ++k) g = fma((double)LB[k * MBP + r], (double)LWB[k * MBP + c], g);
       LG[r * MB + c] = g;

@@ -11,11 +11,11 @@ namespace rcr {
 
 // tau(alpha, Ux) = Pm + A^T Ux (I + C Ux)^{-1} A  (eq. (terminal-fold)),
 // symmetrised.  The caller has staged A, C and Ux in L (blocks at 0, BS, 2 BS,
-// row stride LD) and synchronised; Pm = pm0 (+ pm1 when not null), global
-// n x n blocks; the result is stored to `out` (global).
+// row stride LD) and synchronised, and passes Pm in the product layout (its
+// loads issued with the operand fetches, so they are not a round trip of
+// their own at the end); the result is stored to `out` (global).
 template <typename T, int NB>
-__device__ __forceinline__ void tau_wide(T *__restrict__ out, const T *pm0, const T *pm1, T *L, int n,
-                                         int *status) {
+__device__ __forceinline__ void tau_wide(T *__restrict__ out, const dv4 &p, T *L, int n, int *status) {
   constexpr int CQ = WideCfg<NB>::CQ, W = 2 * NB, LW = W + 1, LD = WideCfg<NB>::LD, BS = WideCfg<NB>::BS;
   T *LA = L, *LC = L + BS, *LU = L + 2 * BS, *LY = L + 3 * BS, *LM = L + 4 * BS;
   T *Lp = LM + NB * LW;
@@ -39,8 +39,6 @@ __device__ __forceinline__ void tau_wide(T *__restrict__ out, const T *pm0, cons
     const dv4 o = mf_mm<NB, true, false>(mf_zero(), LA, LD, LY, LD);  // A^T Y
     mf_store(LC, LD, o, NB, NB);                                        // C is dead: symmetrisation scratch
   }
-  dv4 p = mf_load(pm0, n, n, n);
-  if (pm1) p += mf_load(pm1, n, n, n);
   team_sync();
   mf_store(out, n, mf_sym(LC, LD, NB) + p, n, n);
 }
@@ -57,12 +55,13 @@ __device__ __forceinline__ void quad_op_wide(const Bufs<T> &bf, const OpRec &o, 
     wfetch<T, NB>(tU, bf.U + j * nn, n);
     wfetch<T, NB>(tA, bf.EA + e * nn, n);
     wfetch<T, NB>(tC, bf.EC + e * nn, n);
+    const dv4 pm = mf_load(bf.EP + e * nn, n, n, n);
     wstore_tile<T, NB>(bf.PW + j * nn, tU, n, true);  // expansion of a rake: P_j = U_j
     wput<T, NB>(L, LD, tA);
     wput<T, NB>(L + BS, LD, tC);
     wput<T, NB>(L + 2 * BS, LD, tU);
     team_sync();
-    tau_wide<T, NB>(bf.CT + out * nn, bf.EP + e * nn, (const T *)nullptr, L, n, bf.status);
+    tau_wide<T, NB>(bf.CT + out * nn, pm, L, n, bf.status);
   } else if (s == OP_COMBINE || s == OP_ABSORB) {
     T *dst = (s == OP_COMBINE) ? bf.CT + (int64_t)o.c * nn : bf.U + (int64_t)o.a * nn;
     const T *a = (s == OP_COMBINE) ? bf.CT + (int64_t)o.a * nn : bf.U + (int64_t)o.a * nn;
@@ -146,11 +145,12 @@ __device__ __forceinline__ void qexp_op_wide(const Bufs<T> &bf, const Op4 &o, T 
   wfetch<T, NB>(tA, bf.EA + rs * nn, n);
   wfetch<T, NB>(tC, bf.EC + rs * nn, n);
   wfetch<T, NB>(tPk, bf.PW + k * nn, n);
+  const dv4 pm = mf_load(bf.EP + rs * nn, n, n, n) + mf_load(bf.U + j * nn, n, n, n);
   wput<T, NB>(L, LD, tA);
   wput<T, NB>(L + BS, LD, tC);
   wput<T, NB>(L + 2 * BS, LD, tPk);
   team_sync();
-  tau_wide<T, NB>(bf.PW + j * nn, bf.EP + rs * nn, bf.U + j * nn, L, n, bf.status);
+  tau_wide<T, NB>(bf.PW + j * nn, pm, L, n, bf.status);
 }
 
 // Composite transition of one compression: T_new = T_r T_l.
