@@ -285,14 +285,16 @@ typedef struct {
 int rcr_plan_set_launch(rcr_plan *plan, const rcr_launch_config *cfg);
 int rcr_plan_get_launch(const rcr_plan *plan, rcr_launch_config *cfg);
 
-/* Autotune the launch mapping of a plan on a representative problem: every
- * candidate of a small grid (quad_tail_rounds in {1, 2, 4, 8},
- * vec_tail_rounds in {2, 4, 8}, vec_tail_waves in {8, 16}) is timed with HIP
- * events on `stream` (one warm-up and three timed solves each, with the
- * options in opt; the per-level executor is used for the timing), the fastest
- * is kept in the plan and returned in *best (and its time in *best_ms, if
- * not NULL).  `out` receives the solution.  Synchronises the stream.  Errors:
- * those of rcr_solve. */
+/* Autotune the launch mapping of a plan on a representative problem.  The
+ * candidates are timed with HIP events on `stream` (one warm-up and three
+ * timed solves each, with the options in opt; the per-level executor is used
+ * for the timing).  The quadratic tail only changes the factor's launches and
+ * the vector tails only the solve's, so they are tuned in turn: first
+ * quad_tail_rounds in {-1 (off), 1, 2, 4, 8}, then, with the best of those,
+ * vec_tail_rounds -1 (off) and {2, 4, 8} x vec_tail_waves {8, 16}.  The
+ * fastest is kept in the plan and returned in *best (and its time in
+ * *best_ms, if not NULL).  `out` receives the solution.  Synchronises the
+ * stream.  Errors: those of rcr_solve. */
 int rcr_plan_tune(rcr_plan *plan, const rcr_problem *in, rcr_solution *out, const rcr_solve_options *opt,
                   void *stream, rcr_launch_config *best, float *best_ms);
 

@@ -485,29 +485,47 @@ int tune(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_o
   const LaunchCfg keep = P.cfg;
   best_ms = -1.f;
   int rc = RCR_OK;
-  for (int qr : {1, 2, 4, 8})
-    for (int vr : {2, 4, 8})
-      for (int vw : {8, 16}) {
-        {
-          std::lock_guard<std::mutex> lock(P.mu);
-          P.cfg.quad_tail_rounds = qr;
-          P.cfg.vec_tail_rounds = vr;
-          P.cfg.vec_tail_waves = vw;
-        }
-        if ((rc = solve(P, in, out, o, st))) break;  // warm-up
-        float ms = 0.f;
-        if (hipEventRecord(e0, st) != hipSuccess) rc = RCR_HIP_ERROR;
-        for (int k = 0; k < 3 && !rc; ++k) rc = solve(P, in, out, o, st);
-        if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = RCR_HIP_ERROR;
-        if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = RCR_HIP_ERROR;
-        if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = RCR_HIP_ERROR;
-        if (rc) break;
-        ms /= 3.f;
-        if (best_ms < 0.f || ms < best_ms) {
-          best_ms = ms;
-          best = P.cfg;
-        }
-      }
+  auto trial = [&](const LaunchCfg &c) {
+    {
+      std::lock_guard<std::mutex> lock(P.mu);
+      P.cfg = c;
+    }
+    if ((rc = solve(P, in, out, o, st))) return;  // warm-up
+    float ms = 0.f;
+    if (hipEventRecord(e0, st) != hipSuccess) rc = RCR_HIP_ERROR;
+    for (int k = 0; k < 3 && !rc; ++k) rc = solve(P, in, out, o, st);
+    if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = RCR_HIP_ERROR;
+    if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = RCR_HIP_ERROR;
+    if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = RCR_HIP_ERROR;
+    if (rc) return;
+    ms /= 3.f;
+    if (best_ms < 0.f || ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  };
+  // The quadratic mapping only changes the factor's launches and the vector
+  // mapping only the solve's, so they are tuned one after the other: first
+  // the quadratic tail (off or 1, 2, 4, 8 rounds), then, with the best of
+  // those, the vector tails (off, or 2, 4, 8 rounds of 8 or 16 wavefronts).
+  LaunchCfg c = keep;
+  for (int qr : {-1, 1, 2, 4, 8}) {
+    if (rc) break;
+    c.quad_tail_rounds = qr;
+    trial(c);
+  }
+  if (!rc) c = best;
+  if (!rc) {
+    c.vec_tail_rounds = -1;
+    trial(c);
+  }
+  for (int vr : {2, 4, 8})
+    for (int vw : {8, 16}) {
+      if (rc) break;
+      c.vec_tail_rounds = vr;
+      c.vec_tail_waves = vw;
+      trial(c);
+    }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   std::lock_guard<std::mutex> lock(P.mu);
