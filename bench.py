@@ -89,9 +89,14 @@ def bench_copy(args) -> dict:
             "launches": reps + 3, "ms_per_copy": ms, "copy_GBps": 2 * nbytes / (ms / 1e3) / 1e9}
 
 
-def read_traffic(kernel_class: str):
+def mapping_string(cfg) -> str:
+    return ",".join(f"{k}={v}" for k, v in cfg.items()) if isinstance(cfg, dict) else "default"
+
+
+def read_traffic(kernel_class: str, mapping: str):
     """HBM traffic per launch from the committed rocprofv3 PMC summary, if it was
-    taken on the current kernel source (else None)."""
+    taken on the current kernel source with the same launch mapping (the mapping
+    decides which levels the per-level launches cover), else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel_class}.txt")
     if not os.path.exists(path):
         return None
@@ -100,7 +105,7 @@ def read_traffic(kernel_class: str):
         if "=" in line and not line.lstrip().startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("source_sha") != kernel_source_sha():
+    if kv.get("source_sha") != kernel_source_sha() or kv.get("launch_mapping") != mapping:
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -570,7 +575,7 @@ def main() -> int:
     dom_launches = cls_n[dom] / reps
     bytes_per_solve = measured[dom] * 8
     achieved = bytes_per_solve / (dom_ms / 1e3) / 1e9
-    traffic = read_traffic(dom)
+    traffic = read_traffic(dom, mapping_string(tuned))
     total_words = sum(words.values())
     class_sum_ms = sum(cls_ms.values()) / reps
 
