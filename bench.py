@@ -551,10 +551,12 @@ def main() -> int:
     p50 = float(np.percentile(step_ms, 50))
     p99 = float(np.percentile(step_ms, 99))
 
-    # per-launch HIP-event pass: device time and launch count per kernel class
+    # HIP-event pass on the executor that was timed: device time and launch count
+    # per kernel class (graph: events only where the class changes, so a class's
+    # launches run back to back as in the timed steps)
     cls_ms, cls_n = {}, {}
     for _ in range(max(1, args.class_steps)):
-        r = rcr.solve(plan, prob, out=out, executor=rcr.EXEC_LEVELS, kernel_ms=True, stream=stream)
+        r = rcr.solve(plan, prob, out=out, executor=ex, kernel_ms=True, stream=stream)
         for k, v in r["kernel_ms"].items():
             cls_ms[k] = cls_ms.get(k, 0.0) + v
             cls_n[k] = cls_n.get(k, 0) + r["kernel_launches"][k]

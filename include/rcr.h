@@ -173,9 +173,12 @@ typedef struct {
   double *kkt_residual;     /* optional HOST out: max-abs KKT residual of eq. (kkt) over   */
                             /* all four blocks (forces a synchronisation)                  */
   float *kernel_ms;         /* optional HOST out[RCR_NUM_KERNEL_CLASSES]: per kernel class, */
-                            /* the summed device time of this call's launches, each launch */
-                            /* bracketed by a HIP event pair on `stream` (synchronises;    */
-                            /* the per-level executor is used)                             */
+                            /* the device time of this call's launches from HIP events on  */
+                            /* `stream` (synchronises).  RCR_EXEC_LEVELS: one span per      */
+                            /* launch (boundary events shared by consecutive launches);    */
+                            /* RCR_EXEC_GRAPH: the graph is captured with event-record     */
+                            /* nodes where the kernel class changes, so a span covers a    */
+                            /* run of back-to-back launches of one class                   */
   int32_t *kernel_launches; /* optional HOST out[RCR_NUM_KERNEL_CLASSES]: launch counts     */
   int32_t reserved[4];      /* zero */
 } rcr_solve_options;

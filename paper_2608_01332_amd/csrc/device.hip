@@ -173,6 +173,11 @@ int plan_upload(PlanObj &P, hipStream_t st) {
 void drop_graphs(PlanObj &P) {
   for (auto &kv : P.graphs) (void)hipGraphExecDestroy(kv.second);
   P.graphs.clear();
+  for (auto &kv : P.timed) {
+    for (hipGraphExec_t g : kv.second.execs) (void)hipGraphExecDestroy(g);
+    for (hipEvent_t e : kv.second.events) (void)hipEventDestroy(e);
+  }
+  P.timed.clear();
 }
 
 void plan_release_device(PlanObj &P) {
@@ -400,8 +405,89 @@ int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_
   tm.P = &P;
   tm.st = st;
   tm.on = opt.kernel_ms != nullptr;
-  const bool use_graph = (opt.executor == RCR_EXEC_GRAPH) && !tm.on;
-  if (use_graph) {
+  const bool use_graph = opt.executor == RCR_EXEC_GRAPH;
+  const TimedGraph *tg = nullptr;
+  if (use_graph && tm.on) {
+    // timed replay: one graph per run of same-class launches, HIP events between them
+    GraphKey key;
+    memset(&key, 0, sizeof(key));
+    const void *ptrs[16] = {in.Q, in.q, in.c, in.Delta, in.R, in.S, in.r, in.A, in.B,
+                            out.K, out.P, out.x, out.u, out.lam, ws,
+                            (const void *)(intptr_t)(prec + 4 * opt.refine_steps)};
+    memcpy(key.p, ptrs, sizeof(ptrs));
+    auto it = P.timed.find(key);
+    if (it == P.timed.end()) {
+      struct Cap {
+        hipStream_t cs;
+        TimedGraph rec;
+        int cur = -1;
+        hipError_t err = hipSuccess;
+        void end_run() {  // close the capture of the current run (empty runs are dropped)
+          hipGraph_t g;
+          hipError_t e = hipStreamEndCapture(cs, &g);
+          if (e != hipSuccess) {
+            err = e;
+            return;
+          }
+          size_t nn = 0;
+          if (hipGraphGetNodes(g, nullptr, &nn) == hipSuccess && nn > 0) {
+            hipGraphExec_t ge;
+            e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            if (e == hipSuccess) {
+              rec.execs.push_back(ge);
+              rec.cls.push_back(cur);
+            } else {
+              err = e;
+            }
+          }
+          (void)hipGraphDestroy(g);
+        }
+        static void split(void *self, int c) {
+          Cap *k = static_cast<Cap *>(self);
+          if (k->err != hipSuccess) return;
+          k->end_run();
+          if (k->err == hipSuccess) k->err = hipStreamBeginCapture(k->cs, hipStreamCaptureModeThreadLocal);
+          k->cur = c;
+        }
+      } cap;
+      HIPCK(hipStreamCreateWithFlags(&cap.cs, hipStreamNonBlocking));
+      hipError_t be = hipStreamBeginCapture(cap.cs, hipStreamCaptureModeThreadLocal);
+      if (be != hipSuccess) {
+        (void)hipStreamDestroy(cap.cs);
+        HIPCK(be);
+      }
+      Timer tc;
+      tc.P = &P;
+      tc.st = cap.cs;
+      tc.on = true;
+      tc.split = &Cap::split;
+      tc.split_arg = &cap;
+      int lrc = launch_sequence(P, in, out, opt, L, ws, tc, cap.cs);
+      if (cap.err == hipSuccess) cap.end_run();
+      (void)hipStreamDestroy(cap.cs);
+      for (int c = 0; c < RCR_NUM_KERNEL_CLASSES; ++c) cap.rec.launches[c] = tc.launches[c];
+      bool ok = !lrc && cap.err == hipSuccess;
+      for (size_t i = 0; ok && i <= cap.rec.execs.size(); ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) ok = false;
+        else cap.rec.events.push_back(e);
+      }
+      if (!ok) {
+        for (hipGraphExec_t g : cap.rec.execs) (void)hipGraphExecDestroy(g);
+        for (hipEvent_t e : cap.rec.events) (void)hipEventDestroy(e);
+        if (lrc) return lrc;
+        HIPCK(cap.err);
+        return RCR_HIP_ERROR;
+      }
+      it = P.timed.emplace(key, cap.rec).first;
+    }
+    tg = &it->second;
+    HIPCK(hipEventRecord(tg->events[0], st));
+    for (size_t i = 0; i < tg->execs.size(); ++i) {
+      HIPCK(hipGraphLaunch(tg->execs[i], st));
+      HIPCK(hipEventRecord(tg->events[i + 1], st));
+    }
+  } else if (use_graph) {
     GraphKey key;
     memset(&key, 0, sizeof(key));
     const void *ptrs[16] = {in.Q, in.q, in.c, in.Delta, in.R, in.S, in.r, in.A, in.B,
@@ -434,6 +520,7 @@ int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_
   if (opt.kkt_residual) {
     tm.begin(RCR_K_RESIDUAL);
     // the residual of the returned iterate (the refinement's accumulator is reset first)
+    tm.gap();
     hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, st, ws_status(ws) + 8, ws_resid(ws));
     launch_residual_rhs<double>(P, in, out, nullptr, nullptr, nullptr, ws_resid(ws), st);
     HIPCK(hipGetLastError());
@@ -446,12 +533,21 @@ int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_
         opt.kernel_ms[c] = 0.f;
         if (opt.kernel_launches) opt.kernel_launches[c] = 0;
       }
+      if (tg) {
+        for (size_t i = 0; i < tg->execs.size(); ++i) {
+          if (tg->cls[i] < 0) continue;
+          float ms = 0.f;
+          HIPCK(hipEventElapsedTime(&ms, tg->events[i], tg->events[i + 1]));
+          opt.kernel_ms[tg->cls[i]] += ms;
+        }
+      }
       for (auto &sp : tm.spans) {
         float ms = 0.f;
         HIPCK(hipEventElapsedTime(&ms, sp.second.first, sp.second.second));
         opt.kernel_ms[sp.first] += ms;
-        if (opt.kernel_launches) opt.kernel_launches[sp.first] += 1;
       }
+      if (opt.kernel_launches)
+        for (int c = 0; c < RCR_NUM_KERNEL_CLASSES; ++c) opt.kernel_launches[c] = tg ? tg->launches[c] : tm.launches[c];
     }
     double resid = 0.0;
     int stw = 0;

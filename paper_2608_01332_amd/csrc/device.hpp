@@ -61,6 +61,17 @@ struct LaunchCfg {
   int quad_tail_rounds = 0, vec_tail_rounds = 0, vec_tail_waves = 0;
 };
 
+// The launch sequence captured for timing: one graph per run of same-class
+// launches (cls[i] = -1 for a run of untimed launches), replayed one after the
+// other with a HIP event recorded on the stream between them (events[i] before
+// graph i, events[n] after the last).
+struct TimedGraph {
+  std::vector<hipGraphExec_t> execs;
+  std::vector<int> cls;
+  std::vector<hipEvent_t> events;
+  int launches[RCR_NUM_KERNEL_CLASSES] = {};
+};
+
 struct PlanObj {
   PlanHost host;
   LaunchCfg cfg;
@@ -70,6 +81,7 @@ struct PlanObj {
   size_t ws_bytes[2] = {0, 0};
   hipEvent_t last_done = nullptr;    // completion of the latest solve (stream-ordered release)
   std::map<GraphKey, hipGraphExec_t> graphs;
+  std::map<GraphKey, TimedGraph> timed;  // the per-class-run graphs used for timing
   std::vector<hipEvent_t> events;
 };
 

@@ -28,16 +28,24 @@ namespace rcr {
 
 inline unsigned blocks_for(int64_t cnt, int per) { return (unsigned)((cnt + per - 1) / per); }
 
-// Optional per-launch HIP event bracketing: every launch is enclosed by an
-// event pair on its own stream, so the summed durations per kernel class are
-// device execution times comparable with a kernel trace.
+// Optional HIP event timing on the launch stream, in one of two modes:
+//  - per launch (per-level executor): consecutive launches share their
+//    boundary events, so a launch's span is its execution plus one marker;
+//  - per class run (graph capture): no event is recorded; `split(c)` is
+//    called where the kernel class changes to c, so the caller can end the
+//    captured graph there and start the next one.
 struct Timer {
   PlanObj *P = nullptr;
   hipStream_t st = nullptr;
   bool on = false;
+  void (*split)(void *, int) = nullptr;  // per-class-run mode
+  void *split_arg = nullptr;
+  int run = -2;  // class of the current run (per-class-run mode)
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> spans;
+  int launches[RCR_NUM_KERNEL_CLASSES] = {};
   size_t used = 0;
   int cls = 0;
+  hipEvent_t last = nullptr;  // boundary after the previous timed launch
   hipEvent_t ev() {
     if (used == P->events.size()) {
       hipEvent_t e;
@@ -50,14 +58,35 @@ struct Timer {
   void end() {}
   void pre() {
     if (!on) return;
-    hipEvent_t a = ev(), b = ev();
-    if (!a || !b) return;
-    (void)hipEventRecord(a, st);
-    spans.push_back({cls, {a, b}});
+    launches[cls] += 1;
+    if (split) {
+      if (run != cls) {
+        split(split_arg, cls);
+        run = cls;
+      }
+      return;
+    }
+    if (!last) {
+      if (!(last = ev())) return;
+      (void)hipEventRecord(last, st);
+    }
+    hipEvent_t b = ev();
+    if (!b) return;
+    spans.push_back({cls, {last, b}});
   }
   void post() {
-    if (!on || spans.empty()) return;
+    if (!on || split || spans.empty()) return;
     (void)hipEventRecord(spans.back().second.second, st);
+    last = spans.back().second.second;
+  }
+  // an untimed launch follows: the next timed launch starts a new boundary
+  // (per-class-run mode: a new run)
+  void gap() {
+    last = nullptr;
+    if (on && split && run != -1) {
+      split(split_arg, -1);
+      run = -1;
+    }
   }
 };
 

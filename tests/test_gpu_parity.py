@@ -155,3 +155,24 @@ def test_kernel_timing_option():
     g = _gpu(parent, d, spec.n, spec.m, kernel_ms=True)
     ms = g["kernel_ms"]
     assert ms["quad_contract"] + ms["quad_tail"] > 0 and ms["recover"] > 0 and ms["condense"] > 0
+
+
+def test_kernel_timing_graph_matches_levels():
+    """Timing a graph replay (event nodes where the kernel class changes) leaves
+    the results bitwise unchanged and reports the same launches per class as
+    the per-level timing."""
+    parent, d, spec = w.config_instance(1)
+    print(f"[gpu] timed graph N={len(parent)}", flush=True)
+    plan = rcr.Plan(parent, spec.n, spec.m)
+    dev = rcr.to_device(d)
+    ref = rcr.solve(plan, dev, executor=rcr.EXEC_GRAPH, check=True)
+    ref = {k: ref[k].clone() for k in rcr.SOLUTION_FIELDS}
+    lv = rcr.solve(plan, dev, executor=rcr.EXEC_LEVELS, kernel_ms=True, check=True)
+    for _ in range(2):  # capture, then replay of the cached timed graph
+        gr = rcr.solve(plan, dev, executor=rcr.EXEC_GRAPH, kernel_ms=True, check=True)
+        for k in rcr.SOLUTION_FIELDS:
+            assert torch.equal(gr[k], ref[k]), k
+        assert gr["kernel_launches"] == lv["kernel_launches"]
+        for c, nl in gr["kernel_launches"].items():
+            if nl:
+                assert gr["kernel_ms"][c] > 0, c
