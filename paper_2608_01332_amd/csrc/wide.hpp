@@ -154,17 +154,24 @@ __device__ __forceinline__ void gj_wide(T *LM, T *Lp, T *LF, int *status, bool r
 }
 
 template <typename T, int NB>
-__host__ __device__ constexpr int wide_lds_words() {
-  // compress: Pt, Ar, Al, Cl (4 NB^2 words of T; C_l's block later holds the
-  // symmetrisation scratch) + the float64 system M (3 NB^2, later Z), the
-  // pivot row (3 NB) and 16 spare words; in words of T
-  return 4 * WideCfg<NB>::BS + (NB * (3 * NB + 1) + 3 * NB + 16) * (int)(sizeof(double) / sizeof(T));
-}
-
-template <typename T, int NB>
 __host__ __device__ constexpr int tau_lds_words() {
   // tau_wide: A, C, Ux, Y (4 NB^2) + the system NB x 2 NB + pivot row (2 NB) + 16 spare
   return 4 * WideCfg<NB>::BS + NB * (2 * NB + 1) + 2 * NB + 16;
+}
+
+template <typename T, int NB>
+__host__ __device__ constexpr int compress_lds_words() {
+  // compress: Pt, Ar, Al (3 NB^2 words of T), then the float64 system M
+  // (NB x 3 NB, over C_l's block: C_l is dead once the system is formed; later
+  // the two symmetrisation scratch blocks), the pivot row (3 NB) and 16 spare
+  // words; in words of T
+  return 3 * WideCfg<NB>::BS + (NB * (3 * NB + 1) + 3 * NB + 16) * (int)(sizeof(double) / sizeof(T));
+}
+
+// LDS of a wavefront of the wide contraction-level kernels (rake or compress)
+template <typename T, int NB>
+__host__ __device__ constexpr int wide_lds_words() {
+  return tau_lds_words<T, NB>() > compress_lds_words<T, NB>() ? tau_lds_words<T, NB>() : compress_lds_words<T, NB>();
 }
 
 }  // namespace rcr

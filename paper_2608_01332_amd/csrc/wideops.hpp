@@ -84,9 +84,9 @@ __device__ __forceinline__ void quad_op_wide(const Bufs<T> &bf, const OpRec &o, 
     typedef double ST;  // the (I + C_l Pt) solve is always float64
     const int64_t j = o.a, l = o.b, rs = o.c, sn = o.d;
     T *LPt = L, *LAr = L + BS, *LAl = L + 2 * BS, *LCl = L + 3 * BS;
-    ST *LM = reinterpret_cast<ST *>(L + 4 * BS), *Lp = LM + NB * LW;
-    T *LS = LCl;                        // C_l is dead once S and C_l A_r^T are formed
+    ST *LM = reinterpret_cast<ST *>(LCl), *Lp = LM + NB * LW;  // the system overlays C_l
     T *LZ = reinterpret_cast<T *>(LM);  // the system is dead once X and Y are consumed
+    T *LS = LZ + BS;
     const int q = wq_of(), r = wr_of();
     {
       T tP[TL], tU[TL], tAr[TL], tAl[TL], tCl[TL];
@@ -108,6 +108,7 @@ __device__ __forceinline__ void quad_op_wide(const Bufs<T> &bf, const OpRec &o, 
     {
       const dv4 sb = mf_mm<NB, false, false>(mf_ident(NB), LCl, LD, LPt, LD);  // S = I + C_l Pt
       const dv4 ct = mf_mm<NB, false, true>(mf_zero(), LCl, LD, LAr, LD);      // C_l A_r^T
+      team_sync();  // every read of C_l precedes the system's writes over it
       mf_store(LM, LW, sb, NB, NB);
       mf_store(LM + 2 * NB, LW, ct, NB, NB);
       if (r < NB) {
