@@ -98,6 +98,55 @@ __device__ __forceinline__ float readlane_t<float>(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
+// m[c] += (m[c] of lane P of this 16-lane row) * g for every c: the pivot
+// row's entries reach the other rows through the DPP row_newbcast read of the
+// FMA's first operand, with no LDS round trip.  Two entries per statement;
+// each statement opens with the two wait states that a DPP read of a VGPR
+// just written by a VALU instruction needs, and the last one closes with two
+// more for whatever reads the results next.  Every lane must be active.
+#define RCR_NB_FMAC(OP, A, B, L) OP " %" #A ", %" #A ", %" #B " row_newbcast:%c" #L " row_mask:0xf bank_mask:0xf\n\t"
+template <int P, typename T, int WQ>
+__device__ __forceinline__ void rank1_at(T (&m)[WQ], T g) {
+  static_assert(sizeof(T) == 8 || sizeof(T) == 4, "float or double");
+  static_for<(WQ + 1) / 2>([&](auto h) {
+    constexpr int c = 2 * decltype(h)::value;
+    if constexpr (c + 1 < WQ) {
+      if constexpr (sizeof(T) == 8)
+        asm volatile("s_nop 1\n\t" RCR_NB_FMAC("v_fmac_f64_dpp", 0, 2, 3) RCR_NB_FMAC("v_fmac_f64_dpp", 1, 2, 3)
+                     : "+v"(m[c]), "+v"(m[c + 1])
+                     : "v"(g), "i"(P));
+      else
+        asm volatile("s_nop 1\n\t" RCR_NB_FMAC("v_fmac_f32_dpp", 0, 2, 3) RCR_NB_FMAC("v_fmac_f32_dpp", 1, 2, 3)
+                     : "+v"(m[c]), "+v"(m[c + 1])
+                     : "v"(g), "i"(P));
+    } else {
+      if constexpr (sizeof(T) == 8)
+        asm volatile("s_nop 1\n\t" RCR_NB_FMAC("v_fmac_f64_dpp", 0, 1, 2) : "+v"(m[c]) : "v"(g), "i"(P));
+      else
+        asm volatile("s_nop 1\n\t" RCR_NB_FMAC("v_fmac_f32_dpp", 0, 1, 2) : "+v"(m[c]) : "v"(g), "i"(P));
+    }
+  });
+  asm volatile("s_nop 1");
+}
+#undef RCR_NB_FMAC
+
+// The same with a wave-uniform p in [0, 16): one of 16 instruction sequences,
+// since the broadcast lane is an immediate of the instruction.
+template <typename T, int WQ>
+__device__ __forceinline__ void row_rank1(T (&m)[WQ], T g, int p) {
+#define RCR_NB_CASE(P) \
+  case P:              \
+    rank1_at<P>(m, g); \
+    break;
+  switch (p) {
+    RCR_NB_CASE(0) RCR_NB_CASE(1) RCR_NB_CASE(2) RCR_NB_CASE(3) RCR_NB_CASE(4) RCR_NB_CASE(5) RCR_NB_CASE(6)
+    RCR_NB_CASE(7) RCR_NB_CASE(8) RCR_NB_CASE(9) RCR_NB_CASE(10) RCR_NB_CASE(11) RCR_NB_CASE(12)
+    RCR_NB_CASE(13) RCR_NB_CASE(14) RCR_NB_CASE(15)
+    default: break;
+  }
+#undef RCR_NB_CASE
+}
+
 // Gauss-Jordan elimination with partial pivoting of the NB x W system staged
 // in LDS (LM, row stride W + 1): lane (q, r) works on the piece
 // [q WQ, q WQ + WQ) of row r.  Rows are never swapped.  At step k the pivot
@@ -106,17 +155,19 @@ __device__ __forceinline__ float readlane_t<float>(float v, int lane) {
 // its own column-k entry while the key is reduced, and readlane fetches the
 // pivot's from its lane, so the reciprocal is off the step's critical path.
 // Each lane's multiplier (its row's entry in column k, held by lane (qk, r))
-// is broadcast across the rows of the wavefront with permlane swaps; only the
-// pivot row travels through LDS (Lp: W words).  The pivot row is scaled by
+// is broadcast across the rows of the wavefront with permlane swaps, and the
+// pivot row's piece reaches every lane of its column quarter through the DPP
+// broadcast of row_rank1: no step touches LDS.  The pivot row is scaled by
 // 1 / pivot and eliminated from every other row.  On return LM holds the
 // eliminated system in pivot order: row k is the row that pivoted at step k,
-// so columns [NB, W) are the solution.  (LF is unused scratch kept for the
-// layout.)
+// so columns [NB, W) are the solution.  (Lp and LF are unused scratch kept
+// for the layout.)
 template <typename T, int NB, int W>
 __device__ __forceinline__ void gj_wide(T *LM, T *Lp, T *LF, int *status, bool report) {
   constexpr int WQ = W / 4, LW = W + 1;
   const int q = wq_of(), r = wr_of();
   (void)LF;
+  (void)Lp;
   T m[WQ];
 #pragma unroll
   for (int c = 0; c < WQ; ++c) m[c] = (r < NB) ? LM[r * LW + q * WQ + c] : (T)0;
@@ -131,19 +182,12 @@ __device__ __forceinline__ void gj_wide(T *LM, T *Lp, T *LF, int *status, bool r
     sing = sing || piv_zero(key);
     const T inv = readlane_t<T>(rc, qk * 16 + p);
     const T f = row_bcast<qk>(m[ck]);  // entry (r, k), held by lane (qk, r)
-    if (r == p) {
-#pragma unroll
-      for (int c = 0; c < WQ; ++c) Lp[q * WQ + c] = m[c];
-    }
-    team_sync();
     const T g = (r == p) ? inv - (T)1 : -f * inv;  // the pivot row becomes inv * row
-#pragma unroll
-    for (int c = 0; c < WQ; ++c) m[c] = fmat(g, Lp[q * WQ + c], m[c]);
+    row_rank1(m, g, p);
     if (r == p) {
       used = true;
       step = k;
     }
-    team_sync();
   });
   if (report && (threadIdx.x & 63) == 0 && sing) atomicOr(status, ST_SINGULAR);
   if (r < NB) {
