@@ -98,54 +98,78 @@ __device__ __forceinline__ float readlane_t<float>(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-// m[c] += (m[c] of lane P of this 16-lane row) * g for every c: the pivot
-// row's entries reach the other rows through the DPP row_newbcast read of the
-// FMA's first operand, with no LDS round trip.  Two entries per statement;
-// each statement opens with the two wait states that a DPP read of a VGPR
-// just written by a VALU instruction needs, and the last one closes with two
-// more for whatever reads the results next.  Every lane must be active.
-#define RCR_NB_FMAC(OP, A, B, L) OP " %" #A ", %" #A ", %" #B " row_newbcast:%c" #L " row_mask:0xf bank_mask:0xf\n\t"
-template <int P, typename T, int WQ>
-__device__ __forceinline__ void rank1_at(T (&m)[WQ], T g) {
-  static_assert(sizeof(T) == 8 || sizeof(T) == 4, "float or double");
-  static_for<(WQ + 1) / 2>([&](auto h) {
-    constexpr int c = 2 * decltype(h)::value;
-    if constexpr (c + 1 < WQ) {
-      if constexpr (sizeof(T) == 8)
-        asm volatile("s_nop 1\n\t" RCR_NB_FMAC("v_fmac_f64_dpp", 0, 2, 3) RCR_NB_FMAC("v_fmac_f64_dpp", 1, 2, 3)
-                     : "+v"(m[c]), "+v"(m[c + 1])
-                     : "v"(g), "i"(P));
-      else
-        asm volatile("s_nop 1\n\t" RCR_NB_FMAC("v_fmac_f32_dpp", 0, 2, 3) RCR_NB_FMAC("v_fmac_f32_dpp", 1, 2, 3)
-                     : "+v"(m[c]), "+v"(m[c + 1])
-                     : "v"(g), "i"(P));
-    } else {
-      if constexpr (sizeof(T) == 8)
-        asm volatile("s_nop 1\n\t" RCR_NB_FMAC("v_fmac_f64_dpp", 0, 1, 2) : "+v"(m[c]) : "v"(g), "i"(P));
-      else
-        asm volatile("s_nop 1\n\t" RCR_NB_FMAC("v_fmac_f32_dpp", 0, 1, 2) : "+v"(m[c]) : "v"(g), "i"(P));
-    }
-  });
-  asm volatile("s_nop 1");
-}
-#undef RCR_NB_FMAC
-
-// The same with a wave-uniform p in [0, 16): one of 16 instruction sequences,
-// since the broadcast lane is an immediate of the instruction.
+// m[c] += (m[c] of lane p of this 16-lane row) * g for every c, p in [0, 16)
+// wave-uniform: the pivot row's entries reach the other rows through the DPP
+// row_newbcast read of the FMA's first operand, with no LDS round trip.  The
+// broadcast lane is an immediate of the instruction, so the 16 variants are
+// laid out back to back, each of the same byte length (WQ FMAs of 8 bytes and
+// a 4-byte branch to the end), and a computed jump (s_getpc / s_setpc) enters
+// the variant of p (taken modulo 16).  Seven scalar instructions precede the
+// first DPP read and the end carries two wait states, which covers the hazard
+// of a DPP read of a VGPR that a VALU instruction has just written on either
+// side.  Every lane must be active; s40..s42 are scratch.
+#define RCR_JT_HEAD(CASE_BYTES)                   \
+  "s_getpc_b64 s[40:41]\n"                        \
+  "0:\n\t"                                        \
+  "s_and_b32 s42, %[p], 15\n\t"                  \
+  "s_mul_i32 s42, s42, " #CASE_BYTES "\n\t"       \
+  "s_add_u32 s42, s42, (1f - 0b)\n\t"             \
+  "s_add_u32 s40, s40, s42\n\t"                   \
+  "s_addc_u32 s41, s41, 0\n\t"                    \
+  "s_setpc_b64 s[40:41]\n"                        \
+  "1:\n\t"
+#define RCR_JT_TAIL "2:\n\ts_nop 1"
+#define RCR_FM(OP, I, P) OP " %" #I ", %" #I ", %[g] row_newbcast:" #P " row_mask:0xf bank_mask:0xf\n\t"
+#define RCR_C6(OP, P) \
+  RCR_FM(OP, 0, P) RCR_FM(OP, 1, P) RCR_FM(OP, 2, P) RCR_FM(OP, 3, P) RCR_FM(OP, 4, P) RCR_FM(OP, 5, P)
+#define RCR_C8(OP, P) RCR_C6(OP, P) RCR_FM(OP, 6, P) RCR_FM(OP, 7, P)
+#define RCR_C9(OP, P) RCR_C8(OP, P) RCR_FM(OP, 8, P)
+#define RCR_C12(OP, P) RCR_C9(OP, P) RCR_FM(OP, 9, P) RCR_FM(OP, 10, P) RCR_FM(OP, 11, P)
+#define RCR_CASE(C, OP, P) C(OP, P) "s_branch 2f\n\t"
+#define RCR_ALL(C, OP)                                                                                      \
+  RCR_CASE(C, OP, 0) RCR_CASE(C, OP, 1) RCR_CASE(C, OP, 2) RCR_CASE(C, OP, 3) RCR_CASE(C, OP, 4)            \
+  RCR_CASE(C, OP, 5) RCR_CASE(C, OP, 6) RCR_CASE(C, OP, 7) RCR_CASE(C, OP, 8) RCR_CASE(C, OP, 9)            \
+  RCR_CASE(C, OP, 10) RCR_CASE(C, OP, 11) RCR_CASE(C, OP, 12) RCR_CASE(C, OP, 13) RCR_CASE(C, OP, 14)       \
+  RCR_CASE(C, OP, 15)
+#define RCR_OPS6(m) "+v"(m[0]), "+v"(m[1]), "+v"(m[2]), "+v"(m[3]), "+v"(m[4]), "+v"(m[5])
+#define RCR_OPS8(m) RCR_OPS6(m), "+v"(m[6]), "+v"(m[7])
+#define RCR_OPS9(m) RCR_OPS8(m), "+v"(m[8])
+#define RCR_OPS12(m) RCR_OPS9(m), "+v"(m[9]), "+v"(m[10]), "+v"(m[11])
+#define RCR_JT(WQ, CB, OP)                                                                    \
+  asm volatile(RCR_JT_HEAD(CB) RCR_ALL(RCR_C##WQ, OP) RCR_JT_TAIL                             \
+               : RCR_OPS##WQ(m)                                                               \
+               : [g] "v"(g), [p] "s"(p)                                                       \
+               : "s40", "s41", "s42", "scc")
 template <typename T, int WQ>
 __device__ __forceinline__ void row_rank1(T (&m)[WQ], T g, int p) {
-#define RCR_NB_CASE(P) \
-  case P:              \
-    rank1_at<P>(m, g); \
-    break;
-  switch (p) {
-    RCR_NB_CASE(0) RCR_NB_CASE(1) RCR_NB_CASE(2) RCR_NB_CASE(3) RCR_NB_CASE(4) RCR_NB_CASE(5) RCR_NB_CASE(6)
-    RCR_NB_CASE(7) RCR_NB_CASE(8) RCR_NB_CASE(9) RCR_NB_CASE(10) RCR_NB_CASE(11) RCR_NB_CASE(12)
-    RCR_NB_CASE(13) RCR_NB_CASE(14) RCR_NB_CASE(15)
-    default: break;
+  static_assert(sizeof(T) == 8 || sizeof(T) == 4, "float or double");
+  static_assert(WQ == 6 || WQ == 8 || WQ == 9 || WQ == 12, "row piece of 6, 8, 9 or 12 words");
+  if constexpr (sizeof(T) == 8) {
+    if constexpr (WQ == 6) RCR_JT(6, 52, "v_fmac_f64_dpp");
+    if constexpr (WQ == 8) RCR_JT(8, 68, "v_fmac_f64_dpp");
+    if constexpr (WQ == 9) RCR_JT(9, 76, "v_fmac_f64_dpp");
+    if constexpr (WQ == 12) RCR_JT(12, 100, "v_fmac_f64_dpp");
+  } else {
+    if constexpr (WQ == 6) RCR_JT(6, 52, "v_fmac_f32_dpp");
+    if constexpr (WQ == 8) RCR_JT(8, 68, "v_fmac_f32_dpp");
+    if constexpr (WQ == 9) RCR_JT(9, 76, "v_fmac_f32_dpp");
+    if constexpr (WQ == 12) RCR_JT(12, 100, "v_fmac_f32_dpp");
   }
-#undef RCR_NB_CASE
 }
+#undef RCR_JT
+#undef RCR_OPS12
+#undef RCR_OPS9
+#undef RCR_OPS8
+#undef RCR_OPS6
+#undef RCR_ALL
+#undef RCR_CASE
+#undef RCR_C12
+#undef RCR_C9
+#undef RCR_C8
+#undef RCR_C6
+#undef RCR_FM
+#undef RCR_JT_TAIL
+#undef RCR_JT_HEAD
 
 // Gauss-Jordan elimination with partial pivoting of the NB x W system staged
 // in LDS (LM, row stride W + 1): lane (q, r) works on the piece
