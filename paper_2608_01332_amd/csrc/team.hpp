@@ -249,25 +249,23 @@ __device__ __forceinline__ unsigned team_umax(unsigned v) {
 }
 
 // Row QK (lanes 16 QK .. 16 QK + 15) of x in every row of the wavefront, lane
-// for lane: v_permlane32_swap of x with itself gives [R0 R1 R0 R1] and
-// [R2 R3 R2 R3]; v_permlane16_swap of the half holding QK with itself gives
-// that row in all four rows (first result: the even row, second: the odd).
+// for lane, through the LDS crossbar (ds_bpermute: lane l reads lane
+// 16 QK + l % 16).  It issues on the LDS pipe, not the vector ALU, and the
+// address is the same for every call with this QK.
 template <int QK>
-__device__ __forceinline__ unsigned row_bcast_u32(unsigned x) {
-  const auto s32 = __builtin_amdgcn_permlane32_swap(x, x, false, false);
-  const unsigned c = QK < 2 ? s32[0] : s32[1];
-  const auto s16 = __builtin_amdgcn_permlane16_swap(c, c, false, false);
-  return (QK & 1) ? s16[1] : s16[0];
+__device__ __forceinline__ int row_bcast_addr() {
+  return (int)(((unsigned)(QK << 4) | (threadIdx.x & 15u)) << 2);
 }
 template <int QK>
 __device__ __forceinline__ double row_bcast(double x) {
-  const unsigned lo = row_bcast_u32<QK>((unsigned)__double2loint(x));
-  const unsigned hi = row_bcast_u32<QK>((unsigned)__double2hiint(x));
-  return __hiloint2double((int)hi, (int)lo);
+  const int a = row_bcast_addr<QK>();
+  const int lo = __builtin_amdgcn_ds_bpermute(a, __double2loint(x));
+  const int hi = __builtin_amdgcn_ds_bpermute(a, __double2hiint(x));
+  return __hiloint2double(hi, lo);
 }
 template <int QK>
 __device__ __forceinline__ float row_bcast(float x) {
-  return __uint_as_float(row_bcast_u32<QK>(__float_as_uint(x)));
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(row_bcast_addr<QK>(), __float_as_int(x)));
 }
 
 // 1 / d from the hardware reciprocal refined by Newton steps x <- x (2 - d x)

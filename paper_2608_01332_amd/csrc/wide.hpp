@@ -179,9 +179,9 @@ __device__ __forceinline__ void row_rank1(T (&m)[WQ], T g, int p) {
 // its own column-k entry while the key is reduced, and readlane fetches the
 // pivot's from its lane, so the reciprocal is off the step's critical path.
 // Each lane's multiplier (its row's entry in column k, held by lane (qk, r))
-// is broadcast across the rows of the wavefront with permlane swaps, and the
-// pivot row's piece reaches every lane of its column quarter through the DPP
-// broadcast of row_rank1: no step touches LDS.  The pivot row is scaled by
+// is broadcast across the rows of the wavefront through the LDS crossbar
+// (row_bcast), and the pivot row's piece reaches every lane of its column
+// quarter through the DPP broadcast of row_rank1: no step touches LDS memory.  The pivot row is scaled by
 // 1 / pivot and eliminated from every other row.  On return LM holds the
 // eliminated system in pivot order: row k is the row that pivoted at step k,
 // so columns [NB, W) are the solution.  (Lp and LF are unused scratch kept
