@@ -28,6 +28,18 @@ struct LfwLay {
   static constexpr int Ht = dbeg, G = Ht + NB * MBP, Gi = G + MB * MB, words = Gi + MB * MB;
 };
 
+// 1 / sqrt(s) for s > 0: the hardware estimate refined by two Newton steps
+// y <- y + y (1 - s y^2) / 2.
+__device__ __forceinline__ double rsqrt_nr(double s) {
+  double y = __builtin_amdgcn_rsq(s);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-s * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
 // Cholesky factor and inverse of the MB x MB SPD matrix G (row-major in LDS)
 // in registers; reports a non-positive pivot through `bad`.
 template <int MB>
@@ -44,9 +56,9 @@ __device__ __forceinline__ void chol_inv_regs(const double *LG, double (&Gi)[MB]
 #pragma unroll
     for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
     bad = bad || !(s > 0.0);
-    const double d = sqrt(s);
-    L[j][j] = d;
-    dinv[j] = 1.0 / d;
+    const double y = rsqrt_nr(s);  // 1 / sqrt(s)
+    L[j][j] = s * y;
+    dinv[j] = y;
 #pragma unroll
     for (int i = j + 1; i < MB; ++i) {
       double t = L[i][j];
@@ -79,7 +91,7 @@ __device__ __forceinline__ void chol_inv_regs(const double *LG, double (&Gi)[MB]
 }
 
 template <typename T, int NB, int MB>
-RCR_MAT_KERNEL(NB) void k_local_factor_wide(Bufs<T> bf) {
+__device__ __forceinline__ void local_factor_wide(const Bufs<T> &bf) {
   using Ly = LfwLay<T, NB, MB>;
   constexpr int CQ = WideCfg<NB>::CQ, TL = WideCfg<NB>::TILE, LD = Ly::LD, LW = Ly::LW, MBP = Ly::MBP;
   constexpr int TB = (NB * MB + 63) / 64;
@@ -177,17 +189,19 @@ RCR_MAT_KERNEL(NB) void k_local_factor_wide(Bufs<T> bf) {
     bool bad = false;
     chol_inv_regs<MB>(LG, Gi, bad);
     if (edge && lane == 0 && bad) atomicOr(bf.status, ST_NOT_PD);
-    // row q of G^-1 and the entry (r, q), selected with compile-time indices
-    double gq[MB], grq = 0.0;
+    // G^-1 through LDS: lane 0 writes it, every lane reads row q and entry (r, q)
+    if (lane == 0) {
 #pragma unroll
-    for (int d = 0; d < MB; ++d) gq[d] = 0.0;
+      for (int i = 0; i < MB; ++i)
 #pragma unroll
-    for (int i = 0; i < MB; ++i)
+        for (int d = 0; d < MB; ++d) LGi[i * MB + d] = Gi[i][d];
+    }
+    team_sync();
+    const int qq = q < MB ? q : 0, rq = r < MB ? r : 0;
+    double gq[MB];
 #pragma unroll
-      for (int d = 0; d < MB; ++d) {
-        gq[d] = (i == q) ? Gi[i][d] : gq[d];
-        grq = (i == r && d == q) ? Gi[i][d] : grq;
-      }
+    for (int d = 0; d < MB; ++d) gq[d] = LGi[qq * MB + d];
+    const double grq = LGi[rq * MB + qq];
     if (q < MB) {  // K^T row r, column q = -(G^-1 H^T[r])_q
       double kt = 0.0;
 #pragma unroll
@@ -259,6 +273,20 @@ RCR_MAT_KERNEL(NB) void k_local_factor_wide(Bufs<T> bf) {
   {
     const dv4 t = mf_mm<NB, false, false>(mf_zero(), LFi, LW, LDe, LD);  // T = Finv A^cl
     if (edge) mf_store(bf.Tm + v * nn, n, t, n, n);
+  }
+}
+
+// One node per wavefront; the body is specialised for n = NB and m = MB (no
+// padding), where every bound and stride is a compile-time constant.
+template <typename T, int NB, int MB>
+RCR_MAT_KERNEL(NB) void k_local_factor_wide(Bufs<T> bf) {
+  if (bf.n == NB && bf.m == MB) {
+    Bufs<T> b = bf;
+    b.n = NB;
+    b.m = MB;
+    local_factor_wide<T, NB, MB>(b);
+  } else {
+    local_factor_wide<T, NB, MB>(bf);
   }
 }
 
