@@ -36,9 +36,10 @@ struct MatLay {
 
 // Quadratic contraction levels [t0, t1) then quadratic expansion levels [e0, e1).
 template <typename T, int NB>
-RCR_TAIL_MAT_KERNEL(NB) void k_tail_quad(Bufs<T> bf, const OpRec *__restrict__ ops, const int64_t *__restrict__ koff,
-                                         int t0, int t1, const Op4 *__restrict__ eops,
-                                         const int64_t *__restrict__ eoff, int e0, int e1) {
+__device__ __forceinline__ void tail_quad(const Bufs<T> &bf, const OpRec *__restrict__ ops,
+                                          const int64_t *__restrict__ koff, int t0, int t1,
+                                          const Op4 *__restrict__ eops, const int64_t *__restrict__ eoff, int e0,
+                                          int e1) {
   using Lay = MatLay<NB>;
   extern __shared__ double smd[];
   const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = threadIdx.x & 63;
@@ -73,10 +74,20 @@ RCR_TAIL_MAT_KERNEL(NB) void k_tail_quad(Bufs<T> bf, const OpRec *__restrict__ o
   }
 }
 
+template <typename T, int NB>
+RCR_TAIL_MAT_KERNEL(NB) void k_tail_quad(Bufs<T> bf, const OpRec *__restrict__ ops, const int64_t *__restrict__ koff,
+                                         int t0, int t1, const Op4 *__restrict__ eops,
+                                         const int64_t *__restrict__ eoff, int e0, int e1) {
+  if (MatLay<NB>::WIDE && bf.n == NB)  // the primitives specialised for unpadded blocks
+    tail_quad<T, NB>(exact_n<NB>(bf), ops, koff, t0, t1, eops, eoff, e0, e1);
+  else
+    tail_quad<T, NB>(bf, ops, koff, t0, t1, eops, eoff, e0, e1);
+}
+
 // Composite-transition levels [t0, t1).
 template <typename T, int NB>
-RCR_TAIL_MAT_KERNEL(NB) void k_tail_tc(Bufs<T> bf, const Op4 *__restrict__ ops, const int64_t *__restrict__ off,
-                                       int t0, int t1) {
+__device__ __forceinline__ void tail_tc(const Bufs<T> &bf, const Op4 *__restrict__ ops,
+                                        const int64_t *__restrict__ off, int t0, int t1) {
   using Lay = MatLay<NB>;
   extern __shared__ double smd[];
   const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = threadIdx.x & 63;
@@ -96,6 +107,15 @@ RCR_TAIL_MAT_KERNEL(NB) void k_tail_tc(Bufs<T> bf, const Op4 *__restrict__ ops, 
     }
     __syncthreads();
   }
+}
+
+template <typename T, int NB>
+RCR_TAIL_MAT_KERNEL(NB) void k_tail_tc(Bufs<T> bf, const Op4 *__restrict__ ops, const int64_t *__restrict__ off,
+                                       int t0, int t1) {
+  if (MatLay<NB>::WIDE && bf.n == NB)
+    tail_tc<T, NB>(exact_n<NB>(bf), ops, off, t0, t1);
+  else
+    tail_tc<T, NB>(bf, ops, off, t0, t1);
 }
 
 // ---------------------------------------------------------------- vector tails

@@ -170,25 +170,43 @@ __device__ __forceinline__ void tcomp_op_wide(const Bufs<T> &bf, const Op4 &o, T
   mf_store(bf.Tm + (int64_t)o.c * nn, n, t, n, n);
 }
 
+// The level kernels run the primitive specialised for n = NB (no padding,
+// every bound and stride a compile-time constant) when the problem allows.
+template <int NB, typename T>
+__device__ __forceinline__ Bufs<T> exact_n(const Bufs<T> &bf) {
+  Bufs<T> b = bf;
+  b.n = NB;
+  return b;
+}
+
 template <typename T, int NB>
 RCR_MAT_KERNEL(NB) void k_quad_level_wide(Bufs<T> bf, const OpRec *__restrict__ ops, Seg sg) {
   extern __shared__ double smd[];
   int s = 0;
   while (s < 3 && (int)blockIdx.x >= sg.blk[s + 1]) ++s;
   const OpRec o = ops[sg.off[s] + (int64_t)(blockIdx.x - sg.blk[s])];
-  quad_op_wide<T, NB>(bf, o, s, reinterpret_cast<T *>(smd));
+  if (bf.n == NB)
+    quad_op_wide<T, NB>(exact_n<NB>(bf), o, s, reinterpret_cast<T *>(smd));
+  else
+    quad_op_wide<T, NB>(bf, o, s, reinterpret_cast<T *>(smd));
 }
 
 template <typename T, int NB>
 RCR_MAT_KERNEL(NB) void k_quad_expand_wide(Bufs<T> bf, const Op4 *__restrict__ ops, int64_t off) {
   extern __shared__ double smd[];
-  qexp_op_wide<T, NB>(bf, ops[off + blockIdx.x], reinterpret_cast<T *>(smd));
+  if (bf.n == NB)
+    qexp_op_wide<T, NB>(exact_n<NB>(bf), ops[off + blockIdx.x], reinterpret_cast<T *>(smd));
+  else
+    qexp_op_wide<T, NB>(bf, ops[off + blockIdx.x], reinterpret_cast<T *>(smd));
 }
 
 template <typename T, int NB>
 RCR_MAT_KERNEL(NB) void k_tcompose_wide(Bufs<T> bf, const Op4 *__restrict__ ops, int64_t off) {
   extern __shared__ double smd[];
-  tcomp_op_wide<T, NB>(bf, ops[off + blockIdx.x], reinterpret_cast<T *>(smd));
+  if (bf.n == NB)
+    tcomp_op_wide<T, NB>(exact_n<NB>(bf), ops[off + blockIdx.x], reinterpret_cast<T *>(smd));
+  else
+    tcomp_op_wide<T, NB>(bf, ops[off + blockIdx.x], reinterpret_cast<T *>(smd));
 }
 
 }  // namespace rcr
