@@ -106,7 +106,7 @@ struct CondLay {
 };
 
 template <typename T, int NB, int MB>
-RCR_MAT_KERNEL(NB) void k_condense(Bufs<T> bf) {
+__device__ __forceinline__ void condense_body(const Bufs<T> &bf) {
   // One team per node v: U_v = Q_v; for v != root, in float64 with the
   // Cholesky factor L of R_v:  Bt = B L^{-T},  St = M L^{-T}  (rows, n x m)
   //   Abar = A - Bt St^T,  Cbar = Delta_v + Bt Bt^T,  Pbar = -St St^T.
@@ -216,6 +216,14 @@ RCR_MAT_KERNEL(NB) void k_condense(Bufs<T> bf) {
   stage_store<PW, NB, NB, false, Ly::LA>(bf.EA, smd + Ly::A, TS, v0, cnt, n, n, lane, noedge, TW);
   stage_store<PW, NB, NB, false, Ly::LA>(bf.EC, smd + Ly::D, TS, v0, cnt, n, n, lane, noedge, TW);
   stage_store<PW, NB, NB, false, Ly::LA>(bf.EP, smd + Ly::P, TS, v0, cnt, n, n, lane, noedge, TW);
+}
+
+template <typename T, int NB, int MB>
+RCR_MAT_KERNEL(NB) void k_condense(Bufs<T> bf) {
+  if (bf.n == NB && bf.m == MB)
+    condense_body<T, NB, MB>(exact_nm<NB, MB>(bf));
+  else
+    condense_body<T, NB, MB>(bf);
 }
 
 // One quadratic-contraction primitive of kind s on a team (lane r, LDS L).
@@ -336,7 +344,7 @@ __device__ __forceinline__ void quad_op_team(const Bufs<T> &bf, const OpRec &o, 
 }
 
 template <typename T, int NB>
-RCR_MAT_KERNEL(NB) void k_quad_level(Bufs<T> bf, const OpRec *__restrict__ ops, Seg sg) {
+__device__ __forceinline__ void quad_level_body(const Bufs<T> &bf, const OpRec *__restrict__ ops, const Seg &sg) {
   constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW;
   constexpr int LW = lds_quad_words<T, NB>();
   extern __shared__ double smd[];
@@ -348,6 +356,14 @@ RCR_MAT_KERNEL(NB) void k_quad_level(Bufs<T> bf, const OpRec *__restrict__ ops, 
   const bool active = idx < sg.off[s + 1];
   const OpRec o = ops[active ? idx : sg.off[s + 1] - 1];
   quad_op_team<T, NB>(bf, o, s, L, r, active);
+}
+
+template <typename T, int NB>
+RCR_MAT_KERNEL(NB) void k_quad_level(Bufs<T> bf, const OpRec *__restrict__ ops, Seg sg) {
+  if (bf.n == NB)
+    quad_level_body<T, NB>(exact_n<NB>(bf), ops, sg);
+  else
+    quad_level_body<T, NB>(bf, ops, sg);
 }
 
 // Expansion of one compression on a team: P_j = tau((A_r, C_r, P_r + U_j), P_k).
@@ -368,7 +384,7 @@ __device__ __forceinline__ void qexp_op_team(const Bufs<T> &bf, const Op4 &o, T 
 }
 
 template <typename T, int NB>
-RCR_MAT_KERNEL(NB) void k_quad_expand(Bufs<T> bf, const Op4 *__restrict__ ops, int64_t off, int64_t cnt) {
+__device__ __forceinline__ void quad_expand_body(const Bufs<T> &bf, const Op4 *__restrict__ ops, int64_t off, int64_t cnt) {
   constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW;
   constexpr int LW = lds_quad_words<T, NB>();
   extern __shared__ double smd[];
@@ -378,6 +394,14 @@ RCR_MAT_KERNEL(NB) void k_quad_expand(Bufs<T> bf, const Op4 *__restrict__ ops, i
   const bool active = q0 < cnt;
   const Op4 o = ops[off + (active ? q0 : cnt - 1)];
   qexp_op_team<T, NB>(bf, o, L, r, active);
+}
+
+template <typename T, int NB>
+RCR_MAT_KERNEL(NB) void k_quad_expand(Bufs<T> bf, const Op4 *__restrict__ ops, int64_t off, int64_t cnt) {
+  if (bf.n == NB)
+    quad_expand_body<T, NB>(exact_n<NB>(bf), ops, off, cnt);
+  else
+    quad_expand_body<T, NB>(bf, ops, off, cnt);
 }
 
 // Per-team LDS of k_local_factor.  Words of T: P (then W, then A^cl), Finv,
@@ -394,7 +418,7 @@ struct LfLay {
 };
 
 template <typename T, int NB, int MB>
-RCR_MAT_KERNEL(NB) void k_local_factor(Bufs<T> bf) {
+__device__ __forceinline__ void local_factor_body(const Bufs<T> &bf) {
   // One team per node v:  F = I + Delta P, Finv, W = P F^-1; for v != root and
   // e = (parent, v):  WB = W B,  H^T = A^T WB + M,  G = R + B^T WB (float64
   // Cholesky),  K^T = -H^T G^-1,  G^-1,  A^cl = A + B K,  T = F^-1 A^cl.
@@ -583,6 +607,14 @@ RCR_MAT_KERNEL(NB) void k_local_factor(Bufs<T> bf) {
   stage_store<PW, MB, NB, true>(bf.Kw, smt + Ly::WB, TST, v0, cnt, m, n, lane);  // K = (K^T)^T, m x n
 }
 
+template <typename T, int NB, int MB>
+RCR_MAT_KERNEL(NB) void k_local_factor(Bufs<T> bf) {
+  if (bf.n == NB && bf.m == MB)
+    local_factor_body<T, NB, MB>(exact_nm<NB, MB>(bf));
+  else
+    local_factor_body<T, NB, MB>(bf);
+}
+
 // Composite transition of one compression on a team: T_new = T_r T_l.
 template <typename T, int NB>
 __device__ __forceinline__ void tcomp_op_team(const Bufs<T> &bf, const Op4 &o, T *L, int r, bool active) {
@@ -599,7 +631,7 @@ __device__ __forceinline__ void tcomp_op_team(const Bufs<T> &bf, const Op4 &o, T
 }
 
 template <typename T, int NB>
-RCR_MAT_KERNEL(NB) void k_tcompose(Bufs<T> bf, const Op4 *__restrict__ ops, int64_t off, int64_t cnt) {
+__device__ __forceinline__ void tcompose_body(const Bufs<T> &bf, const Op4 *__restrict__ ops, int64_t off, int64_t cnt) {
   constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW;
   extern __shared__ double smd[];
   const int team = threadIdx.x / TW, r = threadIdx.x % TW;
@@ -608,6 +640,14 @@ RCR_MAT_KERNEL(NB) void k_tcompose(Bufs<T> bf, const Op4 *__restrict__ ops, int6
   const bool active = q0 < cnt;
   const Op4 o = ops[off + (active ? q0 : cnt - 1)];
   tcomp_op_team<T, NB>(bf, o, L, r, active);
+}
+
+template <typename T, int NB>
+RCR_MAT_KERNEL(NB) void k_tcompose(Bufs<T> bf, const Op4 *__restrict__ ops, int64_t off, int64_t cnt) {
+  if (bf.n == NB)
+    tcompose_body<T, NB>(exact_n<NB>(bf), ops, off, cnt);
+  else
+    tcompose_body<T, NB>(bf, ops, off, cnt);
 }
 
 // ---------------------------------------------------------------- solve kernels
@@ -624,7 +664,7 @@ struct RhsLay {
 };
 
 template <typename T, int NB, int MB>
-__global__ __launch_bounds__(64) void k_rhs_init(Bufs<T> bf) {
+__device__ __forceinline__ void rhs_init_body(const Bufs<T> &bf) {
   // h_i = q_i;  z_e = K_e^T r_e + (A^cl_e)^T W_j c_j  (eq. (affine-edge))
   using Ly = RhsLay<NB, MB>;
   constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW, TS = team_stride<T>(Ly::words);
@@ -670,6 +710,14 @@ __global__ __launch_bounds__(64) void k_rhs_init(Bufs<T> bf) {
   stage_store<PW, 1, NB>(bf.z, smt + Ly::z, TS, v0, cnt, 1, n, lane);
 }
 
+template <typename T, int NB, int MB>
+__global__ __launch_bounds__(64) void k_rhs_init(Bufs<T> bf) {
+  if (bf.n == NB && bf.m == MB)
+    rhs_init_body<T, NB, MB>(exact_nm<NB, MB>(bf));
+  else
+    rhs_init_body<T, NB, MB>(bf);
+}
+
 // One affine-contraction primitive of kind s (lane r of its team).
 template <typename T, int NB>
 __device__ __forceinline__ void aff_op(const Bufs<T> &bf, const OpRec &o, int s, int r) {
@@ -700,7 +748,7 @@ __device__ __forceinline__ void aff_op(const Bufs<T> &bf, const OpRec &o, int s,
 }
 
 template <typename T, int NB>
-__global__ __launch_bounds__(64) void k_aff_level(Bufs<T> bf, const OpRec *__restrict__ ops, Seg sg) {
+__device__ __forceinline__ void aff_level_body(const Bufs<T> &bf, const OpRec *__restrict__ ops, const Seg &sg) {
   constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW;
   const int team = threadIdx.x / TW, r = threadIdx.x % TW;
   int s = 0;
@@ -708,6 +756,14 @@ __global__ __launch_bounds__(64) void k_aff_level(Bufs<T> bf, const OpRec *__res
   const int64_t idx = sg.off[s] + (int64_t)(blockIdx.x - sg.blk[s]) * PW + team;
   if (idx >= sg.off[s + 1]) return;
   aff_op<T, NB>(bf, ops[idx], s, r);
+}
+
+template <typename T, int NB>
+__global__ __launch_bounds__(64) void k_aff_level(Bufs<T> bf, const OpRec *__restrict__ ops, Seg sg) {
+  if (bf.n == NB)
+    aff_level_body<T, NB>(exact_n<NB>(bf), ops, sg);
+  else
+    aff_level_body<T, NB>(bf, ops, sg);
 }
 
 // Affine expansion of one compression: p_j = Z_r p_k + h_j + z_r.
@@ -724,13 +780,21 @@ __device__ __forceinline__ void affexp_op(const Bufs<T> &bf, const Op4 &o, int r
 }
 
 template <typename T, int NB>
-__global__ __launch_bounds__(64) void k_aff_expand(Bufs<T> bf, const Op4 *__restrict__ ops, int64_t off,
-                                                   int64_t cnt) {
+__device__ __forceinline__ void aff_expand_body(const Bufs<T> &bf, const Op4 *__restrict__ ops, int64_t off, int64_t cnt) {
   constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW;
   const int team = threadIdx.x / TW, r = threadIdx.x % TW;
   const int64_t q0 = (int64_t)blockIdx.x * PW + team;
   if (q0 >= cnt) return;
   affexp_op<T, NB>(bf, ops[off + q0], r);
+}
+
+template <typename T, int NB>
+__global__ __launch_bounds__(64) void k_aff_expand(Bufs<T> bf, const Op4 *__restrict__ ops, int64_t off,
+                                                   int64_t cnt) {
+  if (bf.n == NB)
+    aff_expand_body<T, NB>(exact_n<NB>(bf), ops, off, cnt);
+  else
+    aff_expand_body<T, NB>(bf, ops, off, cnt);
 }
 
 // Per-team LDS of k_local_affine (words of T): Delta, W, Finv (NB rows of
@@ -746,7 +810,7 @@ struct LaLay {
 };
 
 template <typename T, int NB, int MB>
-__global__ __launch_bounds__(64) void k_local_affine(Bufs<T> bf) {
+__device__ __forceinline__ void local_affine_body(const Bufs<T> &bf) {
   // f = Delta p - c, g = p - W f; e = (parent, v): k = -G^-1 (r + B^T g),
   // b = F^-1 (B k - f); root: x = -F^-1 f.  Teams cover max(NB, MB) lanes.
   using Ly = LaLay<NB, MB>;
@@ -834,6 +898,14 @@ __global__ __launch_bounds__(64) void k_local_affine(Bufs<T> bf) {
   stage_store<PW, 1, NB>(bf.b, smt + Ly::b, TS, v0, cnt, 1, n, lane, noedge, TW);
 }
 
+template <typename T, int NB, int MB>
+__global__ __launch_bounds__(64) void k_local_affine(Bufs<T> bf) {
+  if (bf.n == NB && bf.m == MB)
+    local_affine_body<T, NB, MB>(exact_nm<NB, MB>(bf));
+  else
+    local_affine_body<T, NB, MB>(bf);
+}
+
 // State-offset composition of one compression: b_new = T_r b_l + b_r.
 template <typename T, int NB>
 __device__ __forceinline__ void state_op(const Bufs<T> &bf, const Op4 &o, int r) {
@@ -848,13 +920,21 @@ __device__ __forceinline__ void state_op(const Bufs<T> &bf, const Op4 &o, int r)
 }
 
 template <typename T, int NB>
-__global__ __launch_bounds__(64) void k_state_level(Bufs<T> bf, const Op4 *__restrict__ ops, int64_t off,
-                                                    int64_t cnt) {
+__device__ __forceinline__ void state_level_body(const Bufs<T> &bf, const Op4 *__restrict__ ops, int64_t off, int64_t cnt) {
   constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW;
   const int team = threadIdx.x / TW, r = threadIdx.x % TW;
   const int64_t q0 = (int64_t)blockIdx.x * PW + team;
   if (q0 >= cnt) return;
   state_op<T, NB>(bf, ops[off + q0], r);
+}
+
+template <typename T, int NB>
+__global__ __launch_bounds__(64) void k_state_level(Bufs<T> bf, const Op4 *__restrict__ ops, int64_t off,
+                                                    int64_t cnt) {
+  if (bf.n == NB)
+    state_level_body<T, NB>(exact_n<NB>(bf), ops, off, cnt);
+  else
+    state_level_body<T, NB>(bf, ops, off, cnt);
 }
 
 // State expansion of one removed node: x_j = T_s x_i + b_s.
@@ -871,13 +951,21 @@ __device__ __forceinline__ void sexp_op(const Bufs<T> &bf, const Op4 &o, int r) 
 }
 
 template <typename T, int NB>
-__global__ __launch_bounds__(64) void k_state_expand(Bufs<T> bf, const Op4 *__restrict__ ops, int64_t off,
-                                                     int64_t cnt) {
+__device__ __forceinline__ void state_expand_body(const Bufs<T> &bf, const Op4 *__restrict__ ops, int64_t off, int64_t cnt) {
   constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW;
   const int team = threadIdx.x / TW, r = threadIdx.x % TW;
   const int64_t q0 = (int64_t)blockIdx.x * PW + team;
   if (q0 >= cnt) return;
   sexp_op<T, NB>(bf, ops[off + q0], r);
+}
+
+template <typename T, int NB>
+__global__ __launch_bounds__(64) void k_state_expand(Bufs<T> bf, const Op4 *__restrict__ ops, int64_t off,
+                                                     int64_t cnt) {
+  if (bf.n == NB)
+    state_expand_body<T, NB>(exact_n<NB>(bf), ops, off, cnt);
+  else
+    state_expand_body<T, NB>(bf, ops, off, cnt);
 }
 
 // Per-team LDS of k_recover (words of T): P (NB rows), K (MB rows), both of
@@ -890,7 +978,7 @@ struct RecLay {
 };
 
 template <typename T, int NB, int MB>
-__global__ __launch_bounds__(64) void k_recover(Bufs<T> bf) {
+__device__ __forceinline__ void recover_body(const Bufs<T> &bf) {
   // y_v = P_v x_v + p_v;  u_e = K_e x_parent + k_e;  non-finite check
   using Ly = RecLay<NB, MB>;
   constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW, TS = team_stride<T>(Ly::words);
@@ -940,6 +1028,14 @@ __global__ __launch_bounds__(64) void k_recover(Bufs<T> bf) {
   team_sync();
   stage_store<PW, 1, NB>(bf.yw, smt + Ly::y, TS, v0, cnt, 1, n, lane);
   stage_store<PW, 1, MB>(bf.uw, smt + Ly::u, TS, v0, cnt, 1, m, lane);
+}
+
+template <typename T, int NB, int MB>
+__global__ __launch_bounds__(64) void k_recover(Bufs<T> bf) {
+  if (bf.n == NB && bf.m == MB)
+    recover_body<T, NB, MB>(exact_nm<NB, MB>(bf));
+  else
+    recover_body<T, NB, MB>(bf);
 }
 
 }  // namespace rcr

@@ -231,10 +231,7 @@ __device__ __forceinline__ void affexp_op_col(const Bufs<T> &bf, const Op4 &o, i
 // lane up to 256 VGPRs; 1024 allows twice the wavefronts with half the
 // registers).
 template <typename T, int NB, int MAXT>
-__global__ __launch_bounds__(MAXT) void k_tail_aff(Bufs<T> bf, const OpRec *__restrict__ ops,
-                                                   const int64_t *__restrict__ koff, int t0, int t1,
-                                                   const Op4 *__restrict__ eops, const int64_t *__restrict__ eoff,
-                                                   int e0, int e1) {
+__device__ __forceinline__ void tail_aff_body(const Bufs<T> &bf, const OpRec *__restrict__ ops, const int64_t *__restrict__ koff, int t0, int t1, const Op4 *__restrict__ eops, const int64_t *__restrict__ eoff, int e0, int e1) {
   constexpr int TW = TeamW<NB>::TW;
   extern __shared__ double smd[];
   int64_t cbase, ebase, *lb;
@@ -281,13 +278,21 @@ __global__ __launch_bounds__(MAXT) void k_tail_aff(Bufs<T> bf, const OpRec *__re
   }
 }
 
+template <typename T, int NB, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_tail_aff(Bufs<T> bf, const OpRec *__restrict__ ops,
+                                                   const int64_t *__restrict__ koff, int t0, int t1,
+                                                   const Op4 *__restrict__ eops, const int64_t *__restrict__ eoff,
+                                                   int e0, int e1) {
+  if (bf.n == NB)
+    tail_aff_body<T, NB, MAXT>(exact_n<NB>(bf), ops, koff, t0, t1, eops, eoff, e0, e1);
+  else
+    tail_aff_body<T, NB, MAXT>(bf, ops, koff, t0, t1, eops, eoff, e0, e1);
+}
+
 // State-offset composition levels [t0, t1) then state expansion levels [e0, e1):
 // b_new = T_r b_l + b_r and x_j = T_s x_i + b_s with the lane's row of T.
 template <typename T, int NB, int MAXT>
-__global__ __launch_bounds__(MAXT) void k_tail_state(Bufs<T> bf, const Op4 *__restrict__ ops,
-                                                     const int64_t *__restrict__ off, int t0, int t1,
-                                                     const Op4 *__restrict__ xops, const int64_t *__restrict__ xoff,
-                                                     int e0, int e1) {
+__device__ __forceinline__ void tail_state_body(const Bufs<T> &bf, const Op4 *__restrict__ ops, const int64_t *__restrict__ off, int t0, int t1, const Op4 *__restrict__ xops, const int64_t *__restrict__ xoff, int e0, int e1) {
   constexpr int TW = TeamW<NB>::TW;
   extern __shared__ double smd[];
   int64_t cbase, ebase, *lb;
@@ -337,6 +342,17 @@ __global__ __launch_bounds__(MAXT) void k_tail_state(Bufs<T> bf, const Op4 *__re
 #pragma unroll
     for (int k = 0; k < NB; ++k) pf[k] = nx[k];
   }
+}
+
+template <typename T, int NB, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_tail_state(Bufs<T> bf, const Op4 *__restrict__ ops,
+                                                     const int64_t *__restrict__ off, int t0, int t1,
+                                                     const Op4 *__restrict__ xops, const int64_t *__restrict__ xoff,
+                                                     int e0, int e1) {
+  if (bf.n == NB)
+    tail_state_body<T, NB, MAXT>(exact_n<NB>(bf), ops, off, t0, t1, xops, xoff, e0, e1);
+  else
+    tail_state_body<T, NB, MAXT>(bf, ops, off, t0, t1, xops, xoff, e0, e1);
 }
 
 }  // namespace rcr

@@ -38,6 +38,23 @@ struct Bufs {
   int *status;
 };
 
+// A copy of bf with n (and m) fixed to the padded sizes: kernels run the body
+// specialised this way when the problem has no padding, so every bound and
+// stride in it is a compile-time constant.
+template <int NB, typename T>
+__device__ __forceinline__ Bufs<T> exact_n(const Bufs<T> &bf) {
+  Bufs<T> b = bf;
+  b.n = NB;
+  return b;
+}
+template <int NB, int MB, typename T>
+__device__ __forceinline__ Bufs<T> exact_nm(const Bufs<T> &bf) {
+  Bufs<T> b = bf;
+  b.n = NB;
+  b.m = MB;
+  return b;
+}
+
 template <int NB>
 struct TeamW {
   static constexpr int TW = NB <= 4 ? 4 : (NB <= 8 ? 8 : 16);

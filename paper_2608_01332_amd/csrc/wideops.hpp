@@ -170,15 +170,8 @@ __device__ __forceinline__ void tcomp_op_wide(const Bufs<T> &bf, const Op4 &o, T
   mf_store(bf.Tm + (int64_t)o.c * nn, n, t, n, n);
 }
 
-// The level kernels run the primitive specialised for n = NB (no padding,
-// every bound and stride a compile-time constant) when the problem allows.
-template <int NB, typename T>
-__device__ __forceinline__ Bufs<T> exact_n(const Bufs<T> &bf) {
-  Bufs<T> b = bf;
-  b.n = NB;
-  return b;
-}
-
+// The level kernels run the primitive specialised for n = NB when the problem
+// has no padding (exact_n).
 template <typename T, int NB>
 RCR_MAT_KERNEL(NB) void k_quad_level_wide(Bufs<T> bf, const OpRec *__restrict__ ops, Seg sg) {
   extern __shared__ double smd[];
