@@ -19,9 +19,9 @@ namespace rcr {
 template <typename T, int NB, int MB>
 struct LfwLay {
   static constexpr int LD = WideCfg<NB>::LD, BS = WideCfg<NB>::BS, W = 2 * NB, LW = W + 1, MBP = MB + 1;
-  // words of T: P (later W), Delta (later A^cl), A, the system [F | I], pivot row,
-  // B, WB, K^T (NB x MB each, row stride MB + 1)
-  static constexpr int P = 0, D = BS, A = 2 * BS, M = 3 * BS, Lp = M + NB * LW, B = Lp + W, WB = B + NB * MBP,
+  // words of T: P (later W), Delta (later A^cl), A, the system [F | I], B, WB,
+  // K^T (NB x MB each, row stride MB + 1)
+  static constexpr int P = 0, D = BS, A = 2 * BS, M = 3 * BS, B = M + NB * LW, WB = B + NB * MBP,
                        Kt = WB + NB * MBP, tend = Kt + NB * MBP;
   // doubles: H^T (NB x MB), G and G^-1 (MB x MB)
   static constexpr int dbeg = (tend * (int)sizeof(T) + 7) / 8;
@@ -97,7 +97,7 @@ __device__ __forceinline__ void local_factor_wide(const Bufs<T> &bf) {
   constexpr int TB = (NB * MB + 63) / 64;
   extern __shared__ double smd[];
   T *L = reinterpret_cast<T *>(smd);
-  T *LP = L + Ly::P, *LDe = L + Ly::D, *LA = L + Ly::A, *LM = L + Ly::M, *Lp = L + Ly::Lp;
+  T *LP = L + Ly::P, *LDe = L + Ly::D, *LA = L + Ly::A, *LM = L + Ly::M;
   T *LB = L + Ly::B, *LWB = L + Ly::WB, *LKt = L + Ly::Kt;
   double *LH = smd + Ly::Ht, *LG = smd + Ly::G, *LGi = smd + Ly::Gi;
   const int64_t v = blockIdx.x;
@@ -146,7 +146,7 @@ __device__ __forceinline__ void local_factor_wide(const Bufs<T> &bf) {
     }
   }
   team_sync();
-  gj_wide<T, NB, 2 * NB>(LM, Lp, Lp, bf.status, true);
+  gj_wide<T, NB, 2 * NB>(LM, bf.status, true);
   const T *LFi = LM + NB;  // Finv, row stride LW
   {
     mf_store(bf.Finv + v * nn, n, mf_load(LFi, LW, NB, NB), n, n);

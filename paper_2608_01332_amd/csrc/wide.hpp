@@ -184,14 +184,11 @@ __device__ __forceinline__ void row_rank1(T (&m)[WQ], T g, int p) {
 // quarter through the DPP broadcast of row_rank1: no step touches LDS memory.  The pivot row is scaled by
 // 1 / pivot and eliminated from every other row.  On return LM holds the
 // eliminated system in pivot order: row k is the row that pivoted at step k,
-// so columns [NB, W) are the solution.  (Lp and LF are unused scratch kept
-// for the layout.)
+// so columns [NB, W) are the solution.
 template <typename T, int NB, int W>
-__device__ __forceinline__ void gj_wide(T *LM, T *Lp, T *LF, int *status, bool report) {
+__device__ __forceinline__ void gj_wide(T *LM, int *status, bool report) {
   constexpr int WQ = W / 4, LW = W + 1;
   const int q = wq_of(), r = wr_of();
-  (void)LF;
-  (void)Lp;
   T m[WQ];
 #pragma unroll
   for (int c = 0; c < WQ; ++c) m[c] = (r < NB) ? LM[r * LW + q * WQ + c] : (T)0;
@@ -223,17 +220,16 @@ __device__ __forceinline__ void gj_wide(T *LM, T *Lp, T *LF, int *status, bool r
 
 template <typename T, int NB>
 __host__ __device__ constexpr int tau_lds_words() {
-  // tau_wide: A, C, Ux, Y (4 NB^2) + the system NB x 2 NB + pivot row (2 NB) + 16 spare
-  return 4 * WideCfg<NB>::BS + NB * (2 * NB + 1) + 2 * NB + 16;
+  // tau_wide: A, C (later Y), Ux (3 NB^2) + the system NB x 2 NB (later scratch)
+  return 3 * WideCfg<NB>::BS + NB * (2 * NB + 1);
 }
 
 template <typename T, int NB>
 __host__ __device__ constexpr int compress_lds_words() {
   // compress: Pt, Ar, Al (3 NB^2 words of T), then the float64 system M
   // (NB x 3 NB, over C_l's block: C_l is dead once the system is formed; later
-  // the two symmetrisation scratch blocks), the pivot row (3 NB) and 16 spare
-  // words; in words of T
-  return 3 * WideCfg<NB>::BS + (NB * (3 * NB + 1) + 3 * NB + 16) * (int)(sizeof(double) / sizeof(T));
+  // the two symmetrisation scratch blocks); in words of T
+  return 3 * WideCfg<NB>::BS + NB * (3 * NB + 1) * (int)(sizeof(double) / sizeof(T));
 }
 
 // LDS of a wavefront of the wide contraction-level kernels (rake or compress)

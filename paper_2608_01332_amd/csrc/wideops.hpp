@@ -13,12 +13,13 @@ namespace rcr {
 // symmetrised.  The caller has staged A, C and Ux in L (blocks at 0, BS, 2 BS,
 // row stride LD) and synchronised, and passes Pm in the product layout (its
 // loads issued with the operand fetches, so they are not a round trip of
-// their own at the end); the result is stored to `out` (global).
+// their own at the end); the result is stored to `out` (global).  C's block
+// later holds Y = Ux X, and the system's the symmetrisation scratch.
 template <typename T, int NB>
 __device__ __forceinline__ void tau_wide(T *__restrict__ out, const dv4 &p, T *L, int n, int *status) {
   constexpr int CQ = WideCfg<NB>::CQ, W = 2 * NB, LW = W + 1, LD = WideCfg<NB>::LD, BS = WideCfg<NB>::BS;
-  T *LA = L, *LC = L + BS, *LU = L + 2 * BS, *LY = L + 3 * BS, *LM = L + 4 * BS;
-  T *Lp = LM + NB * LW;
+  T *LA = L, *LC = L + BS, *LU = L + 2 * BS, *LM = L + 3 * BS;
+  T *LY = LC;
   const int q = wq_of(), r = wr_of();
   {
     const dv4 s = mf_mm<NB, false, false>(mf_ident(NB), LC, LD, LU, LD);  // I + C Ux
@@ -29,7 +30,7 @@ __device__ __forceinline__ void tau_wide(T *__restrict__ out, const dv4 &p, T *L
     }
   }
   team_sync();
-  gj_wide<T, NB, W>(LM, Lp, Lp, status, true);  // X = (I + C Ux)^{-1} A
+  gj_wide<T, NB, W>(LM, status, true);  // X = (I + C Ux)^{-1} A
   {
     const dv4 y = mf_mm<NB, false, false>(mf_zero(), LU, LD, LM + NB, LW);  // Y = Ux X
     mf_store(LY, LD, y, NB, NB);
@@ -37,10 +38,10 @@ __device__ __forceinline__ void tau_wide(T *__restrict__ out, const dv4 &p, T *L
   team_sync();
   {
     const dv4 o = mf_mm<NB, true, false>(mf_zero(), LA, LD, LY, LD);  // A^T Y
-    mf_store(LC, LD, o, NB, NB);                                        // C is dead: symmetrisation scratch
+    mf_store(LM, LD, o, NB, NB);  // the system is dead (read by Y before the sync)
   }
   team_sync();
-  mf_store(out, n, mf_sym(LC, LD, NB) + p, n, n);
+  mf_store(out, n, mf_sym(LM, LD, NB) + p, n, n);
 }
 
 // One quadratic-contraction primitive of kind s on a whole wavefront (LDS L).
@@ -84,7 +85,7 @@ __device__ __forceinline__ void quad_op_wide(const Bufs<T> &bf, const OpRec &o, 
     typedef double ST;  // the (I + C_l Pt) solve is always float64
     const int64_t j = o.a, l = o.b, rs = o.c, sn = o.d;
     T *LPt = L, *LAr = L + BS, *LAl = L + 2 * BS, *LCl = L + 3 * BS;
-    ST *LM = reinterpret_cast<ST *>(LCl), *Lp = LM + NB * LW;  // the system overlays C_l
+    ST *LM = reinterpret_cast<ST *>(LCl);  // the system overlays C_l
     T *LZ = reinterpret_cast<T *>(LM);  // the system is dead once X and Y are consumed
     T *LS = LZ + BS;
     const int q = wq_of(), r = wr_of();
@@ -117,7 +118,7 @@ __device__ __forceinline__ void quad_op_wide(const Bufs<T> &bf, const OpRec &o, 
       }
     }
     team_sync();
-    gj_wide<ST, NB, W>(LM, Lp, Lp, bf.status, true);  // [X | Y] = S^{-1} [A_l | C_l A_r^T]
+    gj_wide<ST, NB, W>(LM, bf.status, true);  // [X | Y] = S^{-1} [A_l | C_l A_r^T]
     const dv4 an = mf_mm<NB, false, false>(mf_zero(), LAr, LD, LM + NB, LW);  // A_r X
     const dv4 cr = mf_mm<NB, false, false>(cr0, LAr, LD, LM + 2 * NB, LW);    // C_r + A_r Y
     const dv4 z = mf_mm<NB, false, false>(mf_zero(), LPt, LD, LM + NB, LW);   // Pt X
