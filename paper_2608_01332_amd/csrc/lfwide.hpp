@@ -19,13 +19,15 @@ namespace rcr {
 template <typename T, int NB, int MB>
 struct LfwLay {
   static constexpr int LD = WideCfg<NB>::LD, BS = WideCfg<NB>::BS, W = 2 * NB, LW = W + 1, MBP = MB + 1;
-  // words of T: P (later W), Delta (later A^cl), A, the system [F | I], B, WB,
-  // K^T (NB x MB each, row stride MB + 1)
-  static constexpr int P = 0, D = BS, A = 2 * BS, M = 3 * BS, B = M + NB * LW, WB = B + NB * MBP,
-                       Kt = WB + NB * MBP, tend = Kt + NB * MBP;
-  // doubles: H^T (NB x MB), G and G^-1 (MB x MB)
+  // words of T: P (later W), Delta (later H^T in float64, then A^cl), A, the
+  // system [F | I], B, WB (later K^T) (NB x MB each, row stride MB + 1)
+  static constexpr int P = 0, D = BS, A = 2 * BS, M = 3 * BS, B = M + NB * LW, WB = B + NB * MBP, Kt = WB,
+                       tend = WB + NB * MBP;
+  // doubles: H^T (NB x MB; over Delta where it fits), G and G^-1 (MB x MB)
+  static constexpr bool HD = D * sizeof(T) % 8 == 0 && NB * MBP * 8 <= BS * (int)sizeof(T);
   static constexpr int dbeg = (tend * (int)sizeof(T) + 7) / 8;
-  static constexpr int Ht = dbeg, G = Ht + NB * MBP, Gi = G + MB * MB, words = Gi + MB * MB;
+  static constexpr int Ht = HD ? D * (int)sizeof(T) / 8 : dbeg, G = HD ? dbeg : Ht + NB * MBP, Gi = G + MB * MB,
+                       words = Gi + MB * MB;
 };
 
 // 1 / sqrt(s) for s > 0: the hardware estimate refined by two Newton steps
