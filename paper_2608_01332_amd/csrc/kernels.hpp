@@ -222,6 +222,8 @@ template <typename T, int NB, int MB>
 RCR_MAT_KERNEL(NB) void k_condense(Bufs<T> bf) {
   if (bf.n == NB && bf.m == MB)
     condense_body<T, NB, MB>(exact_nm<NB, MB>(bf));
+  else if (bf.n == NB)
+    condense_body<T, NB, MB>(exact_n<NB>(bf));
   else
     condense_body<T, NB, MB>(bf);
 }
@@ -611,6 +613,8 @@ template <typename T, int NB, int MB>
 RCR_MAT_KERNEL(NB) void k_local_factor(Bufs<T> bf) {
   if (bf.n == NB && bf.m == MB)
     local_factor_body<T, NB, MB>(exact_nm<NB, MB>(bf));
+  else if (bf.n == NB)
+    local_factor_body<T, NB, MB>(exact_n<NB>(bf));
   else
     local_factor_body<T, NB, MB>(bf);
 }
@@ -714,6 +718,8 @@ template <typename T, int NB, int MB>
 __global__ __launch_bounds__(64) void k_rhs_init(Bufs<T> bf) {
   if (bf.n == NB && bf.m == MB)
     rhs_init_body<T, NB, MB>(exact_nm<NB, MB>(bf));
+  else if (bf.n == NB)
+    rhs_init_body<T, NB, MB>(exact_n<NB>(bf));
   else
     rhs_init_body<T, NB, MB>(bf);
 }
@@ -902,6 +908,8 @@ template <typename T, int NB, int MB>
 __global__ __launch_bounds__(64) void k_local_affine(Bufs<T> bf) {
   if (bf.n == NB && bf.m == MB)
     local_affine_body<T, NB, MB>(exact_nm<NB, MB>(bf));
+  else if (bf.n == NB)
+    local_affine_body<T, NB, MB>(exact_n<NB>(bf));
   else
     local_affine_body<T, NB, MB>(bf);
 }
@@ -1034,6 +1042,8 @@ template <typename T, int NB, int MB>
 __global__ __launch_bounds__(64) void k_recover(Bufs<T> bf) {
   if (bf.n == NB && bf.m == MB)
     recover_body<T, NB, MB>(exact_nm<NB, MB>(bf));
+  else if (bf.n == NB)
+    recover_body<T, NB, MB>(exact_n<NB>(bf));
   else
     recover_body<T, NB, MB>(bf);
 }

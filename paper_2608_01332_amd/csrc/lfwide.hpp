@@ -278,18 +278,16 @@ __device__ __forceinline__ void local_factor_wide(const Bufs<T> &bf) {
   }
 }
 
-// One node per wavefront; the body is specialised for n = NB and m = MB (no
-// padding), where every bound and stride is a compile-time constant.
+// One node per wavefront; the body is specialised for n = NB (and m = MB)
+// when the blocks need no padding (exact_n, exact_nm).
 template <typename T, int NB, int MB>
 RCR_MAT_KERNEL(NB) void k_local_factor_wide(Bufs<T> bf) {
-  if (bf.n == NB && bf.m == MB) {
-    Bufs<T> b = bf;
-    b.n = NB;
-    b.m = MB;
-    local_factor_wide<T, NB, MB>(b);
-  } else {
+  if (bf.n == NB && bf.m == MB)
+    local_factor_wide<T, NB, MB>(exact_nm<NB, MB>(bf));
+  else if (bf.n == NB)
+    local_factor_wide<T, NB, MB>(exact_n<NB>(bf));
+  else
     local_factor_wide<T, NB, MB>(bf);
-  }
 }
 
 }  // namespace rcr
