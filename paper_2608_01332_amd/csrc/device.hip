@@ -336,8 +336,8 @@ static int launch_sequence(PlanObj &P, const rcr_problem &in, const rcr_solution
     bf.xw = out.x;
     bf.uw = out.u;
     bf.yw = out.lam;
-    int rc = launch_phase<double>(P, bf, tm, st, 0);
-    if (!rc) rc = launch_phase<double>(P, bf, tm, st, 1);
+    int rc = launch_phase<double>(P, bf, tm, st, 0 | RCR_PHASE_FIRST_RHS);
+    if (!rc) rc = launch_phase<double>(P, bf, tm, st, 1 | RCR_PHASE_FIRST_RHS);
     return rc;
   }
   // MIXED32: float32 factor and solves; float64 R/G Cholesky and compress (I + C P) solve
@@ -357,8 +357,8 @@ static int launch_sequence(PlanObj &P, const rcr_problem &in, const rcr_solution
   LAUNCH(tm, (k_cast<double, float>), dim3(grid_for(Nn)), dim3(256), 0, st, in.q, rq, Nn);
   LAUNCH(tm, (k_cast<double, float>), dim3(grid_for(Nm)), dim3(256), 0, st, in.r, rr, Nm);
   LAUNCH(tm, (k_cast<double, float>), dim3(grid_for(Nn)), dim3(256), 0, st, in.c, rc_, Nn);
-  int rc = launch_phase<float>(P, bf, tm, st, 0);
-  if (!rc) rc = launch_phase<float>(P, bf, tm, st, 1);
+  int rc = launch_phase<float>(P, bf, tm, st, 0 | RCR_PHASE_FIRST_RHS);
+  if (!rc) rc = launch_phase<float>(P, bf, tm, st, 1 | RCR_PHASE_FIRST_RHS);
   if (rc) return rc;
   tm.begin(RCR_K_RESIDUAL);
   LAUNCH(tm, (k_cast<float, double>), dim3(grid_for(Nn)), dim3(256), 0, st, bf.xw, out.x, Nn);

@@ -15,6 +15,10 @@
 
 namespace rcr {
 
+// Phase flag: the factor and the solve of one rcr_solve share its first
+// right-hand side, so the wide local factor may initialise that solve.
+constexpr int RCR_PHASE_FIRST_RHS = 4;
+
 // Device copy of a plan's integer arrays.
 struct PlanDev {
   int device = -1;

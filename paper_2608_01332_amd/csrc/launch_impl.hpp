@@ -154,13 +154,18 @@ inline void allow_lds(K kernel, size_t bytes) {
 
 // Launch one phase for working type T and padded sizes (NB, MB) on `st`:
 // phase 0 = factor (Algorithm 1, Steps 2-3), phase 1 = solve (Steps 4-6).
+// RCR_PHASE_FIRST_RHS on both phases of one solve lets the wide local factor
+// also initialise the solve of the right-hand side in bf (its blocks are
+// still in LDS there), and the solve phase then skips rhs_init.
 template <typename T, int NB, int MB>
-int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase) {
+int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase_flags) {
   const PlanHost &h = P.host;
+  const int phase = phase_flags & 3;
   constexpr int PW = TeamW<NB>::PW;
   constexpr int NM = NB > MB ? NB : MB;
   constexpr int PWm = TeamW<NM>::PW;
   constexpr bool WIDE = MatLay<NB>::WIDE;  // one primitive per wavefront for the level kernels
+  const bool fused_rhs = WIDE && (phase_flags & RCR_PHASE_FIRST_RHS) != 0;
   const size_t lds_cond = (size_t)PW * CondLay<NB, MB>::words * sizeof(double);
   const size_t lds_quad = (size_t)PW * lds_quad_words<T, NB>() * sizeof(T);
   const size_t lds_lf = (size_t)PW * LfLay<T, NB, MB>::words * sizeof(double);
@@ -250,7 +255,7 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
   tm.begin(RCR_K_LOCAL_FACTOR);
   if constexpr (WIDE) {
     allow_lds(k_local_factor_wide<T, NB, MB>, lds_lfw);
-    LAUNCH(tm, (k_local_factor_wide<T, NB, MB>), dim3((unsigned)h.N), dim3(64), lds_lfw, st, bf);
+    LAUNCH(tm, (k_local_factor_wide<T, NB, MB>), dim3((unsigned)h.N), dim3(64), lds_lfw, st, bf, fused_rhs ? 1 : 0);
   } else {
     LAUNCH(tm, (k_local_factor<T, NB, MB>), dim3(NBk), dim3(64), lds_lf, st, bf);
   }
@@ -273,8 +278,10 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
 
   } else {
   // ---- solve: affine contraction and expansion
-  tm.begin(RCR_K_RHS_INIT);
-  LAUNCH(tm, (k_rhs_init<T, NB, MB>), dim3(NBk), dim3(64), lds_rhs, st, bf);
+  if (!fused_rhs) {
+    tm.begin(RCR_K_RHS_INIT);
+    LAUNCH(tm, (k_rhs_init<T, NB, MB>), dim3(NBk), dim3(64), lds_rhs, st, bf);
+  }
   tm.begin(RCR_K_AFF_CONTRACT);
   for (int64_t t = 0; t < ta.c_begin; ++t) {
     Seg sg;

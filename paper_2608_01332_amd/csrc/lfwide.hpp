@@ -93,7 +93,7 @@ __device__ __forceinline__ void chol_inv_regs(const double *LG, double (&Gi)[MB]
 }
 
 template <typename T, int NB, int MB>
-__device__ __forceinline__ void local_factor_wide(const Bufs<T> &bf) {
+__device__ __forceinline__ void local_factor_wide(const Bufs<T> &bf, bool rhs) {
   using Ly = LfwLay<T, NB, MB>;
   constexpr int CQ = WideCfg<NB>::CQ, TL = WideCfg<NB>::TILE, LD = Ly::LD, LW = Ly::LW, MBP = Ly::MBP;
   constexpr int TB = (NB * MB + 63) / 64;
@@ -276,18 +276,40 @@ __device__ __forceinline__ void local_factor_wide(const Bufs<T> &bf) {
     const dv4 t = mf_mm<NB, false, false>(mf_zero(), LFi, LW, LDe, LD);  // T = Finv A^cl
     if (edge) mf_store(bf.Tm + v * nn, n, t, n, n);
   }
+  if (rhs) {
+    // The first right-hand side's h = q and z = K^T r + (A^cl)^T W c (eq.
+    // (affine-edge)) from the blocks still in LDS (W over P, A^cl over Delta,
+    // K^T), in the arithmetic order of the solve's own initialisation, so the
+    // result is the same bit for bit.  B's block (dead) holds W c.
+    T *Lwc = LB;
+    const bool lead = q == 0;
+    T wc = (T)0;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) wc = fmat(LP[rr * LD + k], k < n ? bf.sc[v * n + k] : (T)0, wc);
+    if (lead && r < NB) Lwc[r] = wc;
+    if (lead && r < n) bf.h[v * n + r] = bf.sq[v * n + r];
+    team_sync();
+    T z = (T)0;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) z = fmat(LDe[k * LD + rr], Lwc[k], z);
+#pragma unroll
+    for (int k = 0; k < MB; ++k) z = fmat(LKt[rr * MBP + k], k < m ? bf.sr[v * m + k] : (T)0, z);
+    if (lead && r < n) bf.z[v * n + r] = edge ? z : (T)0;
+  }
 }
 
 // One node per wavefront; the body is specialised for n = NB (and m = MB)
 // when the blocks need no padding (exact_n, exact_nm).
+// With rhs set it also initialises the solve of the right-hand side that
+// Bufs carries (sq, sr, sc), which then skips its own initialisation.
 template <typename T, int NB, int MB>
-RCR_MAT_KERNEL(NB) void k_local_factor_wide(Bufs<T> bf) {
+RCR_MAT_KERNEL(NB) void k_local_factor_wide(Bufs<T> bf, int rhs) {
   if (bf.n == NB && bf.m == MB)
-    local_factor_wide<T, NB, MB>(exact_nm<NB, MB>(bf));
+    local_factor_wide<T, NB, MB>(exact_nm<NB, MB>(bf), rhs != 0);
   else if (bf.n == NB)
-    local_factor_wide<T, NB, MB>(exact_n<NB>(bf));
+    local_factor_wide<T, NB, MB>(exact_n<NB>(bf), rhs != 0);
   else
-    local_factor_wide<T, NB, MB>(bf);
+    local_factor_wide<T, NB, MB>(bf, rhs != 0);
 }
 
 }  // namespace rcr
