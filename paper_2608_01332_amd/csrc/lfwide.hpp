@@ -22,7 +22,7 @@ struct LfwLay {
   // words of T: P (later W), Delta (later H^T in float64, then A^cl), A, the
   // system [F | I], B, WB (later K^T) (NB x MB each, row stride MB + 1)
   static constexpr int P = 0, D = BS, A = 2 * BS, M = 3 * BS, B = M + NB * LW, WB = B + NB * MBP, Kt = WB,
-                       tend = WB + NB * MBP;
+                       Cv = WB + NB * MBP, Rv = Cv + NB, tend = Rv + MB;  // c, r: the first right-hand side
   // doubles: H^T (NB x MB; over Delta where it fits), G and G^-1 (MB x MB)
   static constexpr bool HD = D * sizeof(T) % 8 == 0 && NB * MBP * 8 <= BS * (int)sizeof(T);
   static constexpr int dbeg = (tend * (int)sizeof(T) + 7) / 8;
@@ -100,7 +100,7 @@ __device__ __forceinline__ void local_factor_wide(const Bufs<T> &bf, bool rhs) {
   extern __shared__ double smd[];
   T *L = reinterpret_cast<T *>(smd);
   T *LP = L + Ly::P, *LDe = L + Ly::D, *LA = L + Ly::A, *LM = L + Ly::M;
-  T *LB = L + Ly::B, *LWB = L + Ly::WB, *LKt = L + Ly::Kt;
+  T *LB = L + Ly::B, *LWB = L + Ly::WB, *LKt = L + Ly::Kt, *LCv = L + Ly::Cv, *LRv = L + Ly::Rv;
   double *LH = smd + Ly::Ht, *LG = smd + Ly::G, *LGi = smd + Ly::Gi;
   const int64_t v = blockIdx.x;
   const int n = bf.n, m = bf.m;
@@ -118,6 +118,14 @@ __device__ __forceinline__ void local_factor_wide(const Bufs<T> &bf, bool rhs) {
     sv[k] = (r < n && c < m) ? bf.S[v * nm + (int64_t)r * m + c] : 0.0;
     rv[k] = (r < MB && c < MB) ? ((r < m && c < m) ? bf.R[v * m * m + r * m + c] : (r == c ? 1.0 : 0.0)) : 0.0;
   }
+  // c (lanes 0..NB-1) and r (lanes 16..16+MB-1) of the first right-hand side
+  T crhs = (T)0;
+  if (rhs) {
+    if (lane < n)
+      crhs = bf.sc[v * n + lane];
+    else if (lane >= 16 && lane - 16 < m)
+      crhs = bf.sr[v * m + lane - 16];
+  }
   {
     T tP[TL], tD[TL], tA[TL], tB[TB];
     wfetch<T, NB>(tP, (isroot ? bf.U : bf.PW) + v * nn, n);
@@ -129,6 +137,8 @@ __device__ __forceinline__ void local_factor_wide(const Bufs<T> &bf, bool rhs) {
       tB[u] = (e < NB * MB && i < n && c < m) ? (T)bf.B[v * nm + (int64_t)i * m + c] : (T)0;
     }
     if (isroot) wstore_tile<T, NB>(bf.PW + v * nn, tP, n, true);  // P_root = U_root
+    if (lane < NB) LCv[lane] = crhs;
+    if (lane >= 16 && lane < 16 + MB) LRv[lane - 16] = crhs;
     wput<T, NB>(LP, LD, tP);
     wput<T, NB>(LDe, LD, tD);
     wput<T, NB>(LA, LD, tA);
@@ -285,7 +295,7 @@ __device__ __forceinline__ void local_factor_wide(const Bufs<T> &bf, bool rhs) {
     const bool lead = q == 0;
     T wc = (T)0;
 #pragma unroll
-    for (int k = 0; k < NB; ++k) wc = fmat(LP[rr * LD + k], k < n ? bf.sc[v * n + k] : (T)0, wc);
+    for (int k = 0; k < NB; ++k) wc = fmat(LP[rr * LD + k], LCv[k], wc);
     if (lead && r < NB) Lwc[r] = wc;
     if (lead && r < n) bf.h[v * n + r] = bf.sq[v * n + r];
     team_sync();
@@ -293,7 +303,7 @@ __device__ __forceinline__ void local_factor_wide(const Bufs<T> &bf, bool rhs) {
 #pragma unroll
     for (int k = 0; k < NB; ++k) z = fmat(LDe[k * LD + rr], Lwc[k], z);
 #pragma unroll
-    for (int k = 0; k < MB; ++k) z = fmat(LKt[rr * MBP + k], k < m ? bf.sr[v * m + k] : (T)0, z);
+    for (int k = 0; k < MB; ++k) z = fmat(LKt[rr * MBP + k], LRv[k], z);
     if (lead && r < n) bf.z[v * n + r] = edge ? z : (T)0;
   }
 }
