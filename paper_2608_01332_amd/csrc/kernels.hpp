@@ -32,6 +32,12 @@ constexpr int mat_waves_per_eu() {
 }
 #define RCR_MAT_KERNEL(NBV) \
   __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(mat_waves_per_eu<NBV>())))
+// The team-layout local factor holds more per lane than the level kernels;
+// its LDS already limits it to 3 wavefronts per SIMD from NB = 6 on.
+template <int NB>
+constexpr int lf_waves_per_eu() {
+  return NB <= 4 ? 4 : (NB <= 8 ? 3 : 2);
+}
 
 // ---------------------------------------------------------------- helpers
 // tau(alpha, Ux) = Pm + A^T Ux (I + C Ux)^{-1} A, symmetrised, for a team.
@@ -420,10 +426,12 @@ struct LfLay {
 };
 
 template <typename T, int NB, int MB>
-__device__ __forceinline__ void local_factor_body(const Bufs<T> &bf) {
+__device__ __forceinline__ void local_factor_body(const Bufs<T> &bf, bool rhs) {
   // One team per node v:  F = I + Delta P, Finv, W = P F^-1; for v != root and
   // e = (parent, v):  WB = W B,  H^T = A^T WB + M,  G = R + B^T WB (float64
   // Cholesky),  K^T = -H^T G^-1,  G^-1,  A^cl = A + B K,  T = F^-1 A^cl.
+  // With rhs: also h = q and z = K^T r + (A^cl)^T W c of the right-hand side
+  // in bf (eq. (affine-edge)), in rhs_init's arithmetic order.
   using Ly = LfLay<T, NB, MB>;
   constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW, TS = Ly::words;
   constexpr int TST = TS * (int)(sizeof(double) / sizeof(T));  // team stride in words of T
@@ -455,6 +463,19 @@ __device__ __forceinline__ void local_factor_body(const Bufs<T> &bf) {
   T *LP = L + Ly::P, *LFi = L + Ly::Fi, *LA = L + Ly::A, *LB = L + Ly::B, *LWB = L + Ly::WB;
   T *LKt = LWB, *Lp = L + Ly::Lp;
   double *LG = smd + team * TS + Ly::G;
+  T *Lrhs = reinterpret_cast<T *>(LG);  // c, then r, of the right-hand side (G's block while it is free)
+  constexpr int RPL = (MB + TW - 1) / TW;  // entries of r per lane: r, r + TW, ...
+  T c_own = (T)0, r_own[RPL];
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) r_own[i] = (T)0;
+  if (rhs && active) {
+    if (r < n) c_own = bf.sc[v * n + r];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i)
+      if (r + i * TW < m) r_own[i] = bf.sr[v * m + r + i * TW];
+    if (r < n) bf.h[v * n + r] = bf.sq[v * n + r];
+  }
+  if (r < NB) Lrhs[r] = c_own;
   if (isroot) {  // P_root = U_root (eq. (value-reconstruction) at the root), also its output
     T u[NB];
     ld_row(u, bf.U + v * nn, n, r);
@@ -486,6 +507,11 @@ __device__ __forceinline__ void local_factor_body(const Bufs<T> &bf) {
   zero(wv);
   mac_rowL<T, NB, NB>(wv, 0, pv, LFi);  // W = P F^-1
   lds_put(LP, wv, r);                   // P was last read for F: its tile passes W out
+  T wc = (T)0;                          // (W c)_r of the right-hand side
+  if (rhs) {
+#pragma unroll
+    for (int k = 0; k < NB; ++k) wc = fmat(wv[k], Lrhs[k], wc);
+  }
   team_sync();
   stage_store<PW, NB, NB>(bf.W, smt + Ly::P, TST, v0, cnt, n, n, lane);
   // WB row r
@@ -607,16 +633,30 @@ __device__ __forceinline__ void local_factor_body(const Bufs<T> &bf) {
   stage_store<PW, NB, NB>(bf.Acl, smt + Ly::P, TST, v0, cnt, n, n, lane, noedge, TW);
   stage_store<PW, NB, NB>(bf.Tm, smt + Ly::A, TST, v0, cnt, n, n, lane, noedge, TW);
   stage_store<PW, MB, NB, true>(bf.Kw, smt + Ly::WB, TST, v0, cnt, m, n, lane);  // K = (K^T)^T, m x n
+  if (rhs) {  // G's block is dead since the G^-1 rows, the pivot-row scratch since the elimination
+    if (r < NB) Lp[r] = wc;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i)
+      if (r + i * TW < MB) Lrhs[r + i * TW] = r_own[i];
+    team_sync();
+    T z = (T)0;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) z = fmat(LP[k * NB + rr], Lp[k], z);  // (A^cl)^T W c
+#pragma unroll
+    for (int k = 0; k < MB; ++k) z = fmat(kt[k], Lrhs[k], z);  // + K^T r
+    if (active && r < n) bf.z[v * n + r] = edge ? z : (T)0;
+  }
 }
 
 template <typename T, int NB, int MB>
-RCR_MAT_KERNEL(NB) void k_local_factor(Bufs<T> bf) {
+__global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(lf_waves_per_eu<NB>())))
+void k_local_factor(Bufs<T> bf, int rhs) {
   if (bf.n == NB && bf.m == MB)
-    local_factor_body<T, NB, MB>(exact_nm<NB, MB>(bf));
+    local_factor_body<T, NB, MB>(exact_nm<NB, MB>(bf), rhs != 0);
   else if (bf.n == NB)
-    local_factor_body<T, NB, MB>(exact_n<NB>(bf));
+    local_factor_body<T, NB, MB>(exact_n<NB>(bf), rhs != 0);
   else
-    local_factor_body<T, NB, MB>(bf);
+    local_factor_body<T, NB, MB>(bf, rhs != 0);
 }
 
 // Composite transition of one compression on a team: T_new = T_r T_l.

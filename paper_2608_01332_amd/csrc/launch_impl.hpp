@@ -154,9 +154,9 @@ inline void allow_lds(K kernel, size_t bytes) {
 
 // Launch one phase for working type T and padded sizes (NB, MB) on `st`:
 // phase 0 = factor (Algorithm 1, Steps 2-3), phase 1 = solve (Steps 4-6).
-// RCR_PHASE_FIRST_RHS on both phases of one solve lets the wide local factor
-// also initialise the solve of the right-hand side in bf (its blocks are
-// still in LDS there), and the solve phase then skips rhs_init.
+// RCR_PHASE_FIRST_RHS on both phases of one solve lets the local factor also
+// initialise the solve of the right-hand side in bf (its W, A^cl and K^T are
+// still in LDS or registers there), and the solve phase then skips rhs_init.
 template <typename T, int NB, int MB>
 int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase_flags) {
   const PlanHost &h = P.host;
@@ -165,7 +165,7 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
   constexpr int NM = NB > MB ? NB : MB;
   constexpr int PWm = TeamW<NM>::PW;
   constexpr bool WIDE = MatLay<NB>::WIDE;  // one primitive per wavefront for the level kernels
-  const bool fused_rhs = WIDE && (phase_flags & RCR_PHASE_FIRST_RHS) != 0;
+  const bool fused_rhs = (phase_flags & RCR_PHASE_FIRST_RHS) != 0;
   const size_t lds_cond = (size_t)PW * CondLay<NB, MB>::words * sizeof(double);
   const size_t lds_quad = (size_t)PW * lds_quad_words<T, NB>() * sizeof(T);
   const size_t lds_lf = (size_t)PW * LfLay<T, NB, MB>::words * sizeof(double);
@@ -257,7 +257,7 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
     allow_lds(k_local_factor_wide<T, NB, MB>, lds_lfw);
     LAUNCH(tm, (k_local_factor_wide<T, NB, MB>), dim3((unsigned)h.N), dim3(64), lds_lfw, st, bf, fused_rhs ? 1 : 0);
   } else {
-    LAUNCH(tm, (k_local_factor<T, NB, MB>), dim3(NBk), dim3(64), lds_lf, st, bf);
+    LAUNCH(tm, (k_local_factor<T, NB, MB>), dim3(NBk), dim3(64), lds_lf, st, bf, fused_rhs ? 1 : 0);
   }
 
   // ---- composite transitions along compressions
