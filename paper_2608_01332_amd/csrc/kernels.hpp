@@ -675,12 +675,13 @@ __device__ __forceinline__ void tcomp_op_team(const Bufs<T> &bf, const Op4 &o, T
 }
 
 template <typename T, int NB>
-__device__ __forceinline__ void tcompose_body(const Bufs<T> &bf, const Op4 *__restrict__ ops, int64_t off, int64_t cnt) {
+__device__ __forceinline__ void tcompose_body(const Bufs<T> &bf, const Op4 *__restrict__ ops, int64_t off, int64_t cnt,
+                                              int64_t blk) {
   constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW;
   extern __shared__ double smd[];
   const int team = threadIdx.x / TW, r = threadIdx.x % TW;
   T *L = reinterpret_cast<T *>(smd) + team * lds_quad_words<T, NB>();
-  const int64_t q0 = (int64_t)blockIdx.x * PW + team;
+  const int64_t q0 = blk * PW + team;
   const bool active = q0 < cnt;
   const Op4 o = ops[off + (active ? q0 : cnt - 1)];
   tcomp_op_team<T, NB>(bf, o, L, r, active);
@@ -689,9 +690,9 @@ __device__ __forceinline__ void tcompose_body(const Bufs<T> &bf, const Op4 *__re
 template <typename T, int NB>
 RCR_MAT_KERNEL(NB) void k_tcompose(Bufs<T> bf, const Op4 *__restrict__ ops, int64_t off, int64_t cnt) {
   if (bf.n == NB)
-    tcompose_body<T, NB>(exact_n<NB>(bf), ops, off, cnt);
+    tcompose_body<T, NB>(exact_n<NB>(bf), ops, off, cnt, blockIdx.x);
   else
-    tcompose_body<T, NB>(bf, ops, off, cnt);
+    tcompose_body<T, NB>(bf, ops, off, cnt, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- solve kernels
@@ -794,12 +795,13 @@ __device__ __forceinline__ void aff_op(const Bufs<T> &bf, const OpRec &o, int s,
 }
 
 template <typename T, int NB>
-__device__ __forceinline__ void aff_level_body(const Bufs<T> &bf, const OpRec *__restrict__ ops, const Seg &sg) {
+__device__ __forceinline__ void aff_level_body(const Bufs<T> &bf, const OpRec *__restrict__ ops, const Seg &sg,
+                                               int blk) {
   constexpr int TW = TeamW<NB>::TW, PW = TeamW<NB>::PW;
   const int team = threadIdx.x / TW, r = threadIdx.x % TW;
   int s = 0;
-  while (s < 3 && (int)blockIdx.x >= sg.blk[s + 1]) ++s;
-  const int64_t idx = sg.off[s] + (int64_t)(blockIdx.x - sg.blk[s]) * PW + team;
+  while (s < 3 && blk >= sg.blk[s + 1]) ++s;
+  const int64_t idx = sg.off[s] + (int64_t)(blk - sg.blk[s]) * PW + team;
   if (idx >= sg.off[s + 1]) return;
   aff_op<T, NB>(bf, ops[idx], s, r);
 }
@@ -807,9 +809,9 @@ __device__ __forceinline__ void aff_level_body(const Bufs<T> &bf, const OpRec *_
 template <typename T, int NB>
 __global__ __launch_bounds__(64) void k_aff_level(Bufs<T> bf, const OpRec *__restrict__ ops, Seg sg) {
   if (bf.n == NB)
-    aff_level_body<T, NB>(exact_n<NB>(bf), ops, sg);
+    aff_level_body<T, NB>(exact_n<NB>(bf), ops, sg, blockIdx.x);
   else
-    aff_level_body<T, NB>(bf, ops, sg);
+    aff_level_body<T, NB>(bf, ops, sg, blockIdx.x);
 }
 
 // Affine expansion of one compression: p_j = Z_r p_k + h_j + z_r.

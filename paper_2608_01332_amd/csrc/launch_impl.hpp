@@ -260,9 +260,11 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
     LAUNCH(tm, (k_local_factor<T, NB, MB>), dim3(NBk), dim3(64), lds_lf, st, bf, fused_rhs ? 1 : 0);
   }
 
-  // ---- composite transitions along compressions
+  // ---- composite transitions along compressions (with the first right-hand
+  // side, levels from 1 on run in the solve phase, merged with affine levels)
   tm.begin(RCR_K_TCOMPOSE);
-  for (int64_t t = 0; t < ttc.c_begin; ++t) {
+  const int64_t tc_here = fused_rhs ? std::min<int64_t>(ttc.c_begin, 1) : ttc.c_begin;
+  for (int64_t t = 0; t < tc_here; ++t) {
     const int64_t cnt = h.tc_off[t + 1] - h.tc_off[t];
     if (cnt <= 0) continue;
     if constexpr (WIDE)
@@ -272,7 +274,7 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
       LAUNCH(tm, (k_tcompose<T, NB>), dim3(blocks_for(cnt, PW)), dim3(64), lds_quad, st, bf, P.dev.tc_ops,
              h.tc_off[t], cnt);
   }
-  if (ttc.levels() > 0)
+  if (ttc.levels() > 0 && !fused_rhs)
     LAUNCH(tm, (k_tail_tc<T, NB>), dim3(1), dim3(64 * mat_waves), lds_tail, st, bf, P.dev.tc_ops, P.dev.tc_off,
            ttc.c_begin, ttc.c_end);
 
@@ -283,7 +285,29 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
     LAUNCH(tm, (k_rhs_init<T, NB, MB>), dim3(NBk), dim3(64), lds_rhs, st, bf);
   }
   tm.begin(RCR_K_AFF_CONTRACT);
-  for (int64_t t = 0; t < ta.c_begin; ++t) {
+  int64_t ta0 = 0;  // first affine level not yet launched
+  if (fused_rhs) {
+    // composite-transition level i (left over from the factor phase) together
+    // with affine level i - 1, which reads only composites of levels below i - 1
+    const size_t lds_tcm = WIDE ? lds_wtc : lds_quad;
+    for (int64_t i = 1; i < ttc.c_begin; ++i) {
+      const int64_t tcnt = h.tc_off[i + 1] - h.tc_off[i];
+      const unsigned tcb = tcnt <= 0 ? 0u : (WIDE ? (unsigned)tcnt : blocks_for(tcnt, PW));
+      Seg sg{};
+      unsigned nb = 0;
+      if (ta0 == i - 1 && ta0 < ta.c_begin) nb = seg_of(ta0++, sg, PW);
+      if (tcb + nb)
+        LAUNCH(tm, (k_tc_aff_level<T, NB>), dim3(tcb + nb), dim3(64), lds_tcm, st, bf, P.dev.tc_ops, h.tc_off[i],
+               tcnt, (int)tcb, P.dev.ops, sg);
+    }
+    if (ttc.levels() > 0) {
+      tm.begin(RCR_K_TCOMPOSE);
+      LAUNCH(tm, (k_tail_tc<T, NB>), dim3(1), dim3(64 * mat_waves), lds_tail, st, bf, P.dev.tc_ops, P.dev.tc_off,
+             ttc.c_begin, ttc.c_end);
+      tm.begin(RCR_K_AFF_CONTRACT);
+    }
+  }
+  for (int64_t t = ta0; t < ta.c_begin; ++t) {
     Seg sg;
     const unsigned nb = seg_of(t, sg, PW);
     if (nb) LAUNCH(tm, (k_aff_level<T, NB>), dim3(nb), dim3(64), 0, st, bf, P.dev.ops, sg);

@@ -356,3 +356,38 @@ __global__ __launch_bounds__(MAXT) void k_tail_state(Bufs<T> bf, const Op4 *__re
 }
 
 }  // namespace rcr
+
+namespace rcr {
+
+// One launch holding two independent levels of a factor + solve: composite
+// transitions of contraction level i (workgroups [0, tc_blocks)) and the
+// affine contraction level i - 1 (the rest).  An affine primitive of level
+// i - 1 reads only composites of levels below i - 1, so the two never touch
+// the same data, and the pair costs one launch instead of two.
+template <typename T, int NB>
+__device__ __forceinline__ void tc_aff_level(const Bufs<T> &bf, const Op4 *__restrict__ tc_ops, int64_t tc_off,
+                                             int64_t tc_cnt, int tc_blocks, const OpRec *__restrict__ ops,
+                                             const Seg &sg) {
+  const int b = (int)blockIdx.x;
+  if (b < tc_blocks) {
+    if constexpr (MatLay<NB>::WIDE) {
+      extern __shared__ double smd[];
+      tcomp_op_wide<T, NB>(bf, tc_ops[tc_off + b], reinterpret_cast<T *>(smd));
+    } else {
+      tcompose_body<T, NB>(bf, tc_ops, tc_off, tc_cnt, b);
+    }
+  } else {
+    aff_level_body<T, NB>(bf, ops, sg, b - tc_blocks);
+  }
+}
+
+template <typename T, int NB>
+RCR_MAT_KERNEL(NB) void k_tc_aff_level(Bufs<T> bf, const Op4 *__restrict__ tc_ops, int64_t tc_off, int64_t tc_cnt,
+                                       int tc_blocks, const OpRec *__restrict__ ops, Seg sg) {
+  if (bf.n == NB)
+    tc_aff_level<T, NB>(exact_n<NB>(bf), tc_ops, tc_off, tc_cnt, tc_blocks, ops, sg);
+  else
+    tc_aff_level<T, NB>(bf, tc_ops, tc_off, tc_cnt, tc_blocks, ops, sg);
+}
+
+}  // namespace rcr
