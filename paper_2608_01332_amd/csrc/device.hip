@@ -238,52 +238,81 @@ static unsigned grid_for(int64_t count) {
 // KKT residual blocks of eq. (kkt) in float64, one 16-lane team per node v, written
 // as the right-hand side of the correction solve (q' = r_x, r' = r_u, c'_root = r_root,
 // c'_v = r_dyn) when rq is non-null; the max-abs residual is accumulated into out.
-template <typename OT>
-__global__ __launch_bounds__(256) void k_residual_rhs(int64_t N, int n, int m, int root, const double *Q,
-                                                      const double *q, const double *c, const double *De,
-                                                      const double *R, const double *S, const double *rr,
-                                                      const double *A, const double *B, const double *x,
-                                                      const double *u, const double *y, const int32_t *parent,
-                                                      const int32_t *coff, const int32_t *cidx, OT *rq, OT *rr_out,
-                                                      OT *rc, double *out) {
+// Lane r < n forms the stationarity and dynamics rows r, lane r < m the control
+// row r.  Every operand vector and row is fetched with all its loads issued at
+// once (gather over the padded sizes NB, MB), so a node costs a few memory
+// round trips (one per child for the child terms), not one per entry.
+template <typename OT, int NB, int MB>
+__device__ __forceinline__ void residual_rhs(int64_t N, int n, int m, const double *Q, const double *q,
+                                             const double *c, const double *De, const double *R, const double *S,
+                                             const double *rr, const double *A, const double *B, const double *x,
+                                             const double *u, const double *y, const int32_t *parent,
+                                             const int32_t *coff, const int32_t *cidx, OT *rq, OT *rr_out, OT *rc,
+                                             double *out) {
   const int64_t v = (int64_t)blockIdx.x * TEAMS_PER_BLOCK + threadIdx.x / TEAM;
   const int r = threadIdx.x & (TEAM - 1);
   if (v >= N) return;
   const int nn = n * n, nm = n * m;
+  const int rn = r < n ? r : n - 1, rm = r < m ? r : m - 1;
+  const int64_t pv = parent[v];
+  const bool isroot = pv < 0;
+  const int64_t pi = isroot ? v : pv;  // a valid row for the parent's loads
+  double xv[NB], yv[NB], xp[NB], uv[MB], qr[NB], dr[NB], ar[NB], br[MB];
+  gather(xv, n, [&](int k) { return x[v * n + k]; });
+  gather(yv, n, [&](int k) { return y[v * n + k]; });
+  gather(xp, n, [&](int k) { return x[pi * n + k]; });
+  gather(uv, m, [&](int k) { return u[v * m + k]; });
+  gather(qr, n, [&](int k) { return Q[v * nn + rn * n + k]; });
+  gather(dr, n, [&](int k) { return De[v * nn + rn * n + k]; });
+  gather(ar, n, [&](int k) { return A[v * nn + rn * n + k]; });
+  gather(br, m, [&](int k) { return B[v * nm + rn * m + k]; });
+  double sx[NB], bx[NB], rx[MB];  // control row r: S[:, r], B[:, r], R[r, :]
+  gather(sx, n, [&](int k) { return S[v * nm + k * m + rm]; });
+  gather(bx, n, [&](int k) { return B[v * nm + k * m + rm]; });
+  gather(rx, m, [&](int k) { return R[v * m * m + rm * m + k]; });
+  double s = q[v * n + rn] - y[v * n + rn];
+  s = dot_n(qr, xv, n, s);
+  for (int32_t t = coff[v]; t < coff[v + 1]; ++t) {
+    const int64_t j = cidx[t];
+    double sj[MB], uj[MB], aj[NB], yj[NB];
+    gather(sj, m, [&](int k) { return S[j * nm + rn * m + k]; });
+    gather(uj, m, [&](int k) { return u[j * m + k]; });
+    gather(aj, n, [&](int k) { return A[j * nn + k * n + rn]; });
+    gather(yj, n, [&](int k) { return y[j * n + k]; });
+    s = dot_n(sj, uj, m, s);
+    s = dot_n(aj, yj, n, s);
+  }
   double worst = 0.0;
+  if (r < n) worst = fabs(s);
+  double t = c[v * n + rn] - x[v * n + rn];
+  if (isroot) {
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+      if (k < n) t = fma(-dr[k], yv[k], t);
+  } else {
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+      if (k < n) t = fma(-dr[k], yv[k], fma(ar[k], xp[k], t));
+    t = dot_n(br, uv, m, t);
+  }
   if (r < n) {
-    double s = q[v * n + r] - y[v * n + r];
-    for (int k = 0; k < n; ++k) s += Q[v * nn + r * n + k] * x[v * n + k];
-    for (int32_t t = coff[v]; t < coff[v + 1]; ++t) {
-      const int64_t j = cidx[t];
-      for (int k = 0; k < m; ++k) s += S[j * nm + r * m + k] * u[j * m + k];
-      for (int k = 0; k < n; ++k) s += A[j * nn + k * n + r] * y[j * n + k];
-    }
-    worst = fabs(s);
-    double t = c[v * n + r] - x[v * n + r];
-    if (parent[v] < 0) {
-      for (int k = 0; k < n; ++k) t -= De[v * nn + r * n + k] * y[v * n + k];
-    } else {
-      const int64_t i = parent[v];
-      for (int k = 0; k < n; ++k) t += A[v * nn + r * n + k] * x[i * n + k] - De[v * nn + r * n + k] * y[v * n + k];
-      for (int k = 0; k < m; ++k) t += B[v * nm + r * m + k] * u[v * m + k];
-    }
     worst = fmax(worst, fabs(t));
     if (rq) {
       rq[v * n + r] = (OT)s;
       rc[v * n + r] = (OT)t;
     }
   }
-  for (int cc = r; cc < m; cc += TEAM) {
-    double t = 0.0;
-    const int64_t i = parent[v];
-    if (i >= 0) {
-      t = rr[v * m + cc];
-      for (int k = 0; k < n; ++k) t += S[v * nm + k * m + cc] * x[i * n + k] + B[v * nm + k * m + cc] * y[v * n + k];
-      for (int k = 0; k < m; ++k) t += R[v * m * m + cc * m + k] * u[v * m + k];
+  if (r < m) {
+    double tu = 0.0;
+    if (!isroot) {
+      tu = rr[v * m + r];
+#pragma unroll
+      for (int k = 0; k < NB; ++k)
+        if (k < n) tu = fma(bx[k], yv[k], fma(sx[k], xp[k], tu));
+      tu = dot_n(rx, uv, m, tu);
     }
-    worst = fmax(worst, fabs(t));
-    if (rq) rr_out[v * m + cc] = (OT)t;
+    worst = fmax(worst, fabs(tu));
+    if (rq) rr_out[v * m + r] = (OT)tu;
   }
   if (!(worst == worst)) worst = INFINITY;
   for (int off = 8; off > 0; off >>= 1) worst = fmax(worst, __shfl_xor(worst, off, TEAM));
@@ -291,14 +320,45 @@ __global__ __launch_bounds__(256) void k_residual_rhs(int64_t N, int n, int m, i
     atomicMax(reinterpret_cast<unsigned long long *>(out), (unsigned long long)__double_as_longlong(worst));
 }
 
+template <typename OT, int NB, int MB>
+__global__ __launch_bounds__(256) void k_residual_rhs(int64_t N, int n, int m, const double *Q, const double *q,
+                                                      const double *c, const double *De, const double *R,
+                                                      const double *S, const double *rr, const double *A,
+                                                      const double *B, const double *x, const double *u,
+                                                      const double *y, const int32_t *parent, const int32_t *coff,
+                                                      const int32_t *cidx, OT *rq, OT *rr_out, OT *rc, double *out) {
+  if (n == NB && m == MB)  // unpadded: every bound a compile-time constant
+    residual_rhs<OT, NB, MB>(N, NB, MB, Q, q, c, De, R, S, rr, A, B, x, u, y, parent, coff, cidx, rq, rr_out, rc, out);
+  else
+    residual_rhs<OT, NB, MB>(N, n, m, Q, q, c, De, R, S, rr, A, B, x, u, y, parent, coff, cidx, rq, rr_out, rc, out);
+}
+
+template <typename OT, int NB>
+static void launch_residual_nb(const PlanHost &h, const rcr_problem &in, const rcr_solution &out, OT *rq, OT *rr,
+                               OT *rc, const PlanObj &P, double *resid, hipStream_t st) {
+  const dim3 g(blocks_for(h.N, TEAMS_PER_BLOCK)), b(256);
+#define RCR_RES_ARGS                                                                                           \
+  h.N, h.n, h.m, in.Q, in.q, in.c, in.Delta, in.R, in.S, in.r, in.A, in.B, out.x, out.u, out.lam, P.dev.parent, \
+      P.dev.child_off, P.dev.child_idx, rq, rr, rc, resid
+  switch (pad_m(h.m)) {
+    case 4: hipLaunchKernelGGL((k_residual_rhs<OT, NB, 4>), g, b, 0, st, RCR_RES_ARGS); break;
+    case 8: hipLaunchKernelGGL((k_residual_rhs<OT, NB, 8>), g, b, 0, st, RCR_RES_ARGS); break;
+    default: hipLaunchKernelGGL((k_residual_rhs<OT, NB, 16>), g, b, 0, st, RCR_RES_ARGS); break;
+  }
+#undef RCR_RES_ARGS
+}
+
 template <typename OT>
 static void launch_residual_rhs(PlanObj &P, const rcr_problem &in, const rcr_solution &out, OT *rq, OT *rr, OT *rc,
-                                double *resid,
-                                hipStream_t st) {
+                                double *resid, hipStream_t st) {
   const PlanHost &h = P.host;
-  hipLaunchKernelGGL(k_residual_rhs<OT>, dim3(blocks_for(h.N, TEAMS_PER_BLOCK)), dim3(256), 0, st, h.N, h.n, h.m,
-                     (int)h.root, in.Q, in.q, in.c, in.Delta, in.R, in.S, in.r, in.A, in.B, out.x, out.u, out.lam,
-                     P.dev.parent, P.dev.child_off, P.dev.child_idx, rq, rr, rc, resid);
+  switch (pad_n(h.n)) {
+    case 4: launch_residual_nb<OT, 4>(h, in, out, rq, rr, rc, P, resid, st); break;
+    case 6: launch_residual_nb<OT, 6>(h, in, out, rq, rr, rc, P, resid, st); break;
+    case 8: launch_residual_nb<OT, 8>(h, in, out, rq, rr, rc, P, resid, st); break;
+    case 12: launch_residual_nb<OT, 12>(h, in, out, rq, rr, rc, P, resid, st); break;
+    default: launch_residual_nb<OT, 16>(h, in, out, rq, rr, rc, P, resid, st); break;
+  }
 }
 
 template <typename T>
