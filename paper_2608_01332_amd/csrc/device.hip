@@ -241,17 +241,16 @@ static unsigned grid_for(int64_t count) {
 // Lane r < n forms the stationarity and dynamics rows r, lane r < m the control
 // row r.  Every operand vector and row is fetched with all its loads issued at
 // once (gather over the padded sizes NB, MB), so a node costs a few memory
-// round trips (one per child for the child terms), not one per entry.
+// round trips (one per child for the child terms), not one per entry.  The
+// grid strides over the nodes; each workgroup folds its lanes' maxima and
+// issues one atomic, so the maximum does not serialise on one address.
 template <typename OT, int NB, int MB>
-__device__ __forceinline__ void residual_rhs(int64_t N, int n, int m, const double *Q, const double *q,
-                                             const double *c, const double *De, const double *R, const double *S,
-                                             const double *rr, const double *A, const double *B, const double *x,
-                                             const double *u, const double *y, const int32_t *parent,
-                                             const int32_t *coff, const int32_t *cidx, OT *rq, OT *rr_out, OT *rc,
-                                             double *out) {
-  const int64_t v = (int64_t)blockIdx.x * TEAMS_PER_BLOCK + threadIdx.x / TEAM;
+__device__ __forceinline__ double residual_rhs(int64_t v, int n, int m, const double *Q, const double *q,
+                                               const double *c, const double *De, const double *R, const double *S,
+                                               const double *rr, const double *A, const double *B, const double *x,
+                                               const double *u, const double *y, const int32_t *parent,
+                                               const int32_t *coff, const int32_t *cidx, OT *rq, OT *rr_out, OT *rc) {
   const int r = threadIdx.x & (TEAM - 1);
-  if (v >= N) return;
   const int nn = n * n, nm = n * m;
   const int rn = r < n ? r : n - 1, rm = r < m ? r : m - 1;
   const int64_t pv = parent[v];
@@ -314,10 +313,7 @@ __device__ __forceinline__ void residual_rhs(int64_t N, int n, int m, const doub
     worst = fmax(worst, fabs(tu));
     if (rq) rr_out[v * m + r] = (OT)tu;
   }
-  if (!(worst == worst)) worst = INFINITY;
-  for (int off = 8; off > 0; off >>= 1) worst = fmax(worst, __shfl_xor(worst, off, TEAM));
-  if (r == 0 && worst > 0.0)
-    atomicMax(reinterpret_cast<unsigned long long *>(out), (unsigned long long)__double_as_longlong(worst));
+  return (worst == worst) ? worst : INFINITY;
 }
 
 template <typename OT, int NB, int MB>
@@ -327,16 +323,32 @@ __global__ __launch_bounds__(256) void k_residual_rhs(int64_t N, int n, int m, c
                                                       const double *B, const double *x, const double *u,
                                                       const double *y, const int32_t *parent, const int32_t *coff,
                                                       const int32_t *cidx, OT *rq, OT *rr_out, OT *rc, double *out) {
-  if (n == NB && m == MB)  // unpadded: every bound a compile-time constant
-    residual_rhs<OT, NB, MB>(N, NB, MB, Q, q, c, De, R, S, rr, A, B, x, u, y, parent, coff, cidx, rq, rr_out, rc, out);
-  else
-    residual_rhs<OT, NB, MB>(N, n, m, Q, q, c, De, R, S, rr, A, B, x, u, y, parent, coff, cidx, rq, rr_out, rc, out);
+  __shared__ double wmax[256 / 64];
+  double worst = 0.0;
+  for (int64_t v = (int64_t)blockIdx.x * TEAMS_PER_BLOCK + threadIdx.x / TEAM; v < N;
+       v += (int64_t)gridDim.x * TEAMS_PER_BLOCK) {
+    const double w =
+        (n == NB && m == MB)  // unpadded: every bound a compile-time constant
+            ? residual_rhs<OT, NB, MB>(v, NB, MB, Q, q, c, De, R, S, rr, A, B, x, u, y, parent, coff, cidx, rq,
+                                       rr_out, rc)
+            : residual_rhs<OT, NB, MB>(v, n, m, Q, q, c, De, R, S, rr, A, B, x, u, y, parent, coff, cidx, rq,
+                                       rr_out, rc);
+    worst = fmax(worst, w);
+  }
+  for (int off = 32; off > 0; off >>= 1) worst = fmax(worst, __shfl_xor(worst, off, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = worst;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double w = wmax[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) w = fmax(w, wmax[i]);
+    if (w > 0.0) atomicMax(reinterpret_cast<unsigned long long *>(out), (unsigned long long)__double_as_longlong(w));
+  }
 }
 
 template <typename OT, int NB>
 static void launch_residual_nb(const PlanHost &h, const rcr_problem &in, const rcr_solution &out, OT *rq, OT *rr,
                                OT *rc, const PlanObj &P, double *resid, hipStream_t st) {
-  const dim3 g(blocks_for(h.N, TEAMS_PER_BLOCK)), b(256);
+  const dim3 g(std::min<unsigned>(blocks_for(h.N, TEAMS_PER_BLOCK), 4096u)), b(256);
 #define RCR_RES_ARGS                                                                                           \
   h.N, h.n, h.m, in.Q, in.q, in.c, in.Delta, in.R, in.S, in.r, in.A, in.B, out.x, out.u, out.lam, P.dev.parent, \
       P.dev.child_off, P.dev.child_idx, rq, rr, rc, resid
