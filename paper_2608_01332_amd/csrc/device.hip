@@ -34,8 +34,6 @@
 
 namespace rcr {
 
-#define TEAM 16
-#define TEAMS_PER_BLOCK 16
 
 __global__ void k_zero_status(int *st, double *resid) {
   if (threadIdx.x < 4) st[threadIdx.x] = 0;
@@ -235,7 +233,7 @@ static unsigned grid_for(int64_t count) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 4096));
 }
 
-// KKT residual blocks of eq. (kkt) in float64, one 16-lane team per node v, written
+// KKT residual blocks of eq. (kkt) in float64, one team of lanes per node v, written
 // as the right-hand side of the correction solve (q' = r_x, r' = r_u, c'_root = r_root,
 // c'_v = r_dyn) when rq is non-null; the max-abs residual is accumulated into out.
 // Lane r < n forms the stationarity and dynamics rows r, lane r < m the control
@@ -244,13 +242,22 @@ static unsigned grid_for(int64_t count) {
 // round trips (one per child for the child terms), not one per entry.  The
 // grid strides over the nodes; each workgroup folds its lanes' maxima and
 // issues one atomic, so the maximum does not serialise on one address.
+
+// Lanes per node of the residual kernel: 8 when both padded sizes fit (no
+// lane idle at n, m <= 8), else 16.
+template <int NB, int MB>
+constexpr int res_team() {
+  return NB <= 8 && MB <= 8 ? 8 : 16;
+}
+
 template <typename OT, int NB, int MB>
 __device__ __forceinline__ double residual_rhs(int64_t v, int n, int m, const double *Q, const double *q,
                                                const double *c, const double *De, const double *R, const double *S,
                                                const double *rr, const double *A, const double *B, const double *x,
                                                const double *u, const double *y, const int32_t *parent,
                                                const int32_t *coff, const int32_t *cidx, OT *rq, OT *rr_out, OT *rc) {
-  const int r = threadIdx.x & (TEAM - 1);
+  constexpr int TW = res_team<NB, MB>();
+  const int r = threadIdx.x & (TW - 1);
   const int nn = n * n, nm = n * m;
   const int rn = r < n ? r : n - 1, rm = r < m ? r : m - 1;
   const int64_t pv = parent[v];
@@ -323,10 +330,10 @@ __global__ __launch_bounds__(256) void k_residual_rhs(int64_t N, int n, int m, c
                                                       const double *B, const double *x, const double *u,
                                                       const double *y, const int32_t *parent, const int32_t *coff,
                                                       const int32_t *cidx, OT *rq, OT *rr_out, OT *rc, double *out) {
+  constexpr int TW = res_team<NB, MB>(), TPB = 256 / TW;
   __shared__ double wmax[256 / 64];
   double worst = 0.0;
-  for (int64_t v = (int64_t)blockIdx.x * TEAMS_PER_BLOCK + threadIdx.x / TEAM; v < N;
-       v += (int64_t)gridDim.x * TEAMS_PER_BLOCK) {
+  for (int64_t v = (int64_t)blockIdx.x * TPB + threadIdx.x / TW; v < N; v += (int64_t)gridDim.x * TPB) {
     const double w =
         (n == NB && m == MB)  // unpadded: every bound a compile-time constant
             ? residual_rhs<OT, NB, MB>(v, NB, MB, Q, q, c, De, R, S, rr, A, B, x, u, y, parent, coff, cidx, rq,
@@ -348,7 +355,7 @@ __global__ __launch_bounds__(256) void k_residual_rhs(int64_t N, int n, int m, c
 template <typename OT, int NB>
 static void launch_residual_nb(const PlanHost &h, const rcr_problem &in, const rcr_solution &out, OT *rq, OT *rr,
                                OT *rc, const PlanObj &P, double *resid, hipStream_t st) {
-  const dim3 g(std::min<unsigned>(blocks_for(h.N, TEAMS_PER_BLOCK), 4096u)), b(256);
+  const dim3 g(std::min<unsigned>(blocks_for(h.N, 256 / res_team<NB, 16>()), 4096u)), b(256);
 #define RCR_RES_ARGS                                                                                           \
   h.N, h.n, h.m, in.Q, in.q, in.c, in.Delta, in.R, in.S, in.r, in.A, in.B, out.x, out.u, out.lam, P.dev.parent, \
       P.dev.child_off, P.dev.child_idx, rq, rr, rc, resid
