@@ -5,9 +5,9 @@ The wide elimination step enters one of 16 same-length instruction variants
 case length or base offset would send a wavefront into the middle of an
 instruction, so every table in the built code objects is checked here: for
 each p in [0, 16) the jump target must start the variant of p, every
-instruction of that variant must broadcast lane p, the variant must have the
-stated byte length, and all variants must branch to the common end right after
-the last one.  Runs on the CPU against the objects of the last build.
+broadcast in that variant must read lane p, the variants must be the same
+instructions apart from that lane, each must have the stated byte length, and
+all must branch to the common end right after the last one.  Runs on the CPU against the objects of the last build.
 """
 import os
 import re
@@ -70,10 +70,19 @@ def check_tables(ins: list) -> tuple:
                 problems.append(f"table {n}, p {p}: no instruction starts at {tgt:#x}")
                 continue
             k = at[tgt]
+            body = []
             while k < len(ins) and not ins[k][1].startswith("s_branch"):
-                if re.search(rf"row_newbcast:{p}(\s|$)", ins[k][1]) is None:
-                    problems.append(f"table {n}, p {p}: {ins[k][1]}")
+                text_k = ins[k][1]
+                if "row_newbcast" in text_k and re.search(rf"row_newbcast:{p}(\s|$)", text_k) is None:
+                    problems.append(f"table {n}, p {p}: {text_k}")
+                body.append(re.sub(r"row_newbcast:\d+", "row_newbcast:P", text_k))
                 k += 1
+            if not any("row_newbcast:P" in t for t in body):
+                problems.append(f"table {n}, p {p}: no broadcast of the pivot row")
+            if p == 0:
+                first = body
+            elif body != first:
+                problems.append(f"table {n}, p {p}: the variant differs from the variant of p = 0")
             if k == len(ins):
                 problems.append(f"table {n}, p {p}: no branch to the end")
                 continue
