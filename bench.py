@@ -95,8 +95,9 @@ def mapping_string(cfg) -> str:
 
 def read_traffic(kernel_class: str, mapping: str):
     """HBM traffic per launch from the committed rocprofv3 PMC summary, if it was
-    taken on the current kernel source with the same launch mapping (the mapping
-    decides which levels the per-level launches cover), else None."""
+    taken on the current kernel source, for the quadratic tail setting of this
+    run's launch mapping (it decides which levels the per-level launches
+    cover; the summary holds one record per setting), else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel_class}.txt")
     if not os.path.exists(path):
         return None
@@ -105,10 +106,12 @@ def read_traffic(kernel_class: str, mapping: str):
         if "=" in line and not line.lstrip().startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("source_sha") != kernel_source_sha() or kv.get("launch_mapping") != mapping:
+    if kv.get("source_sha") != kernel_source_sha():
         return None
+    m = dict(x.split("=", 1) for x in mapping.split(",") if "=" in x)
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        q = int(m["quad_tail_rounds"])
+        return float(kv[f"qtr{2 if q == 0 else q}.hbm_bytes_per_launch"])  # 0 selects the default, 2
     except (KeyError, ValueError):
         return None
 
