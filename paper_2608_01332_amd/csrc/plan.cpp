@@ -192,6 +192,9 @@ struct Builder {
     comp_k.assign(N, -1);
     rem_kind.assign(N, 0);
     next_slot = (int32_t)N;
+    raw.reserve((size_t)N * 2);
+    contrib_level.reserve((size_t)N * 2);
+    removal_seq.reserve((size_t)N);
     std::vector<int32_t> live(N);
     for (int64_t i = 0; i < N; ++i) live[i] = (int32_t)i;
     std::vector<int32_t> leaves, elig;
@@ -323,14 +326,15 @@ struct Builder {
           LE = std::max(LE, eP[j]);
         }
       }
-      std::vector<std::vector<Op4>> by(LE);
+      // counting sort by level, stable in removal order
+      P.exp_off.assign((size_t)LE + 1, 0);
       for (int32_t j : removal_seq)
-        if (rem_kind[j] == 2) by[eP[j] - 1].push_back(Op4{j, comp_r[j], comp_k[j], 0});
-      P.exp_off.assign(1, 0);
-      for (auto &v : by) {
-        P.exp_ops.insert(P.exp_ops.end(), v.begin(), v.end());
-        P.exp_off.push_back((int64_t)P.exp_ops.size());
-      }
+        if (rem_kind[j] == 2) P.exp_off[eP[j]]++;
+      for (int32_t t = 0; t < LE; ++t) P.exp_off[t + 1] += P.exp_off[t];
+      P.exp_ops.resize((size_t)P.exp_off[LE]);
+      std::vector<int64_t> fill(P.exp_off.begin(), P.exp_off.end() - 1);
+      for (int32_t j : removal_seq)
+        if (rem_kind[j] == 2) P.exp_ops[fill[eP[j] - 1]++] = Op4{j, comp_r[j], comp_k[j], 0};
     }
     // ---- composition of edge maps over compressions only
     {
@@ -343,13 +347,12 @@ struct Builder {
           LT = std::max(LT, lT[o.d]);
           seq.push_back(Op4{o.b, o.c, o.d, o.a});
         }
-      std::vector<std::vector<Op4>> by(LT);
-      for (const Op4 &q : seq) by[lT[q.c] - 1].push_back(q);
-      P.tc_off.assign(1, 0);
-      for (auto &v : by) {
-        P.tc_ops.insert(P.tc_ops.end(), v.begin(), v.end());
-        P.tc_off.push_back((int64_t)P.tc_ops.size());
-      }
+      P.tc_off.assign((size_t)LT + 1, 0);
+      for (const Op4 &q : seq) P.tc_off[lT[q.c]]++;
+      for (int32_t t = 0; t < LT; ++t) P.tc_off[t + 1] += P.tc_off[t];
+      P.tc_ops.resize((size_t)P.tc_off[LT]);
+      std::vector<int64_t> fill(P.tc_off.begin(), P.tc_off.end() - 1);
+      for (const Op4 &q : seq) P.tc_ops[fill[lT[q.c] - 1]++] = q;
     }
     // ---- state expansion: x_j from the state of its parent at removal time
     {
@@ -360,13 +363,12 @@ struct Builder {
         eX[j] = 1 + eX[rem_par[j]];
         LX = std::max(LX, eX[j]);
       }
-      std::vector<std::vector<Op4>> by(LX);
-      for (int32_t j : removal_seq) by[eX[j] - 1].push_back(Op4{j, rem_slot[j], rem_par[j], 0});
-      P.sx_off.assign(1, 0);
-      for (auto &v : by) {
-        P.sx_ops.insert(P.sx_ops.end(), v.begin(), v.end());
-        P.sx_off.push_back((int64_t)P.sx_ops.size());
-      }
+      P.sx_off.assign((size_t)LX + 1, 0);
+      for (int32_t j : removal_seq) P.sx_off[eX[j]]++;
+      for (int32_t t = 0; t < LX; ++t) P.sx_off[t + 1] += P.sx_off[t];
+      P.sx_ops.resize((size_t)P.sx_off[LX]);
+      std::vector<int64_t> fill(P.sx_off.begin(), P.sx_off.end() - 1);
+      for (int32_t j : removal_seq) P.sx_ops[fill[eX[j] - 1]++] = Op4{j, rem_slot[j], rem_par[j], 0};
     }
     P.crew_ok = verify_crew();
     return RCR_OK;
@@ -382,8 +384,10 @@ struct Builder {
     std::vector<int32_t> produced(ND, -1), wstamp(ND, -1), rstamp(ND, -1);
     for (int64_t i = 0; i < N; ++i) produced[i] = 0;
     for (int64_t s = 0; s < N; ++s) produced[E0 + s] = 0;
+    std::vector<int64_t> reads, writes;
     for (int64_t t = 1; t <= P.levels(); ++t) {
-      std::vector<int64_t> reads, writes;
+      reads.clear();
+      writes.clear();
       for (int64_t k = P.lvl_off[t - 1]; k < P.lvl_off[t]; ++k) {
         const OpRec &o = P.ops[k];
         if (o.level != t) return false;
