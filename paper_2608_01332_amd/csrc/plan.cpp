@@ -265,24 +265,34 @@ struct Builder {
         for (int32_t v : elig)
           if (sel[v] != 1) sel[v] = 0;
       }
-      for (int32_t j : elig) {
-        if (sel[j] != 1) continue;
-        int32_t i = cur_par[j], k = one_child[j];
-        int32_t lv = 1 + std::max(lvlE[j], std::max(lvlU[j], lvlE[k]));
-        int32_t s = next_slot++;
-        raw.push_back(OpRec{OP_COMPRESS, rnd, lv, j, edge_slot[j], edge_slot[k], s, k});
-        rem_kind[j] = 2;
-        rem_slot[j] = edge_slot[j];
-        rem_par[j] = i;
-        comp_r[j] = edge_slot[k];
-        comp_k[j] = k;
-        removal_seq.push_back(j);
-        edge_slot[k] = s;
-        lvlE[k] = lv;
-        cur_par[k] = i;
-        sib_key[k] = sib_key[j];
-        alive[j] = 0;
-        P.n_compress++;
+      {  // raw pointers: the byte-array stores below would otherwise force reloads of every vector's base
+        int32_t *cp = cur_par.data(), *oc = one_child.data(), *lE = lvlE.data(), *lU = lvlU.data();
+        int32_t *es = edge_slot.data(), *rs = rem_slot.data(), *rp = rem_par.data(), *cr = comp_r.data();
+        int32_t *ck = comp_k.data(), *sk = sib_key.data();
+        uint8_t *se = sel.data(), *rk = rem_kind.data(), *al = alive.data();
+        int32_t ns = next_slot;
+        int64_t ncomp = 0;
+        for (int32_t j : elig) {
+          if (se[j] != 1) continue;
+          const int32_t i = cp[j], k = oc[j];
+          const int32_t lv = 1 + std::max(lE[j], std::max(lU[j], lE[k]));
+          const int32_t s = ns++;
+          raw.push_back(OpRec{OP_COMPRESS, rnd, lv, j, es[j], es[k], s, k});
+          rk[j] = 2;
+          rs[j] = es[j];
+          rp[j] = i;
+          cr[j] = es[k];
+          ck[j] = k;
+          removal_seq.push_back(j);
+          es[k] = s;
+          lE[k] = lv;
+          cp[k] = i;
+          sk[k] = sk[j];
+          al[j] = 0;
+          ++ncomp;
+        }
+        next_slot = ns;
+        P.n_compress += ncomp;
       }
       for (int32_t j : elig) sel[j] = 0;
       size_t w = 0;
