@@ -178,7 +178,11 @@ int rcr_plan_info(const rcr_plan *plan, rcr_plan_stats *out) {
   out->n_combine = h.n_combine;
   out->n_absorb = h.n_absorb;
   out->depth_bound = rcr::depth_bound(h.N);
-  out->crew_ok = h.crew_ok ? 1 : 0;
+  {  // checked once per plan, on the first request (kept off plan creation)
+    std::lock_guard<std::mutex> lock(const_cast<rcr::PlanObj &>(plan->obj).mu);
+    if (h.crew < 0) h.crew = rcr::verify_crew(h) ? 1 : 0;
+    out->crew_ok = h.crew;
+  }
   out->workspace_bytes_fp64 = (int64_t)rcr::total_workspace_bytes(h, RCR_FP64);
   out->workspace_bytes_mixed = (int64_t)rcr::total_workspace_bytes(h, RCR_MIXED32);
   out->n_trees = h.tree_off.empty() ? 1 : (int64_t)h.tree_off.size() - 1;

@@ -200,11 +200,12 @@ struct Builder {
     std::vector<int32_t> leaves, elig;
     std::vector<std::pair<int64_t, int32_t>> keyed;  // (parent * N + key, leaf)
     int32_t rnd = 0;
+    // cnt[v]: live children of v.  Rakes decrement it; a compression leaves the
+    // parent's count unchanged (its child j is replaced by j's child), so it is
+    // maintained across rounds instead of recounted.
+    for (int64_t i = 0; i < N; ++i) cnt[i] = deg[i];
     while (live.size() > 1) {
       ++rnd;
-      for (int32_t v : live) cnt[v] = 0;
-      for (int32_t v : live)
-        if (v != root) cnt[cur_par[v]]++;
       leaves.clear();
       for (int32_t v : live)
         if (v != root && cnt[v] == 0) leaves.push_back(v);
@@ -245,12 +246,19 @@ struct Builder {
         alive[j] = 0;
         cnt[cur_par[j]]--;
       }
-      // unary non-root nodes of the post-rake tree and their single child
-      for (int32_t v : live)
-        if (alive[v] && v != root && cnt[cur_par[v]] == 1) one_child[cur_par[v]] = v;
+      // unary non-root nodes of the post-rake tree (increasing id) and the
+      // single child of every unary node
       elig.clear();
-      for (int32_t v : live)
-        if (alive[v] && v != root && cnt[v] == 1) elig.push_back(v);  // increasing id
+      {
+        const int32_t *cp = cur_par.data(), *cn = cnt.data();
+        const uint8_t *al = alive.data();
+        int32_t *oc = one_child.data();
+        for (int32_t v : live) {
+          if (!al[v] || v == root) continue;
+          if (cn[cp[v]] == 1) oc[cp[v]] = v;
+          if (cn[v] == 1) elig.push_back(v);
+        }
+      }
       if (selection == RCR_SELECT_GREEDY_INDEX) {
         for (int32_t v : elig)
           if (!sel[cur_par[v]] && !sel[one_child[v]]) sel[v] = 1;
@@ -380,58 +388,59 @@ struct Builder {
       std::vector<int64_t> fill(P.sx_off.begin(), P.sx_off.end() - 1);
       for (int32_t j : removal_seq) P.sx_ops[fill[eX[j] - 1]++] = Op4{j, rem_slot[j], rem_par[j], 0};
     }
-    P.crew_ok = verify_crew();
     return RCR_OK;
   }
 
-  // Independent check of the level schedule: replay the levels in order and
-  // verify that every input was produced at an earlier level, that each datum
-  // has at most one writer per level, and that no datum written at a level is
-  // read by another op of that level.
-  bool verify_crew() const {
-    // datum ids: U_i -> i; edge slot s -> N + s; contribution c -> N + slots + c
-    const int64_t E0 = N, C0 = N + P.n_edge_slots, ND = C0 + P.n_contrib;
-    std::vector<int32_t> produced(ND, -1), wstamp(ND, -1), rstamp(ND, -1);
-    for (int64_t i = 0; i < N; ++i) produced[i] = 0;
-    for (int64_t s = 0; s < N; ++s) produced[E0 + s] = 0;
-    std::vector<int64_t> reads, writes;
-    for (int64_t t = 1; t <= P.levels(); ++t) {
-      reads.clear();
-      writes.clear();
-      for (int64_t k = P.lvl_off[t - 1]; k < P.lvl_off[t]; ++k) {
-        const OpRec &o = P.ops[k];
-        if (o.level != t) return false;
-        int64_t in[3];
-        int nin = 0;
-        int64_t outd = -1;
-        switch (o.kind) {
-          case OP_RAKE: in[0] = o.a; in[1] = E0 + o.b; nin = 2; outd = C0 + o.c; break;
-          case OP_COMBINE: in[0] = C0 + o.a; in[1] = C0 + o.b; nin = 2; outd = C0 + o.c; break;
-          case OP_ABSORB: in[0] = o.a; in[1] = C0 + o.b; nin = 2; outd = o.a; break;
-          case OP_COMPRESS: in[0] = E0 + o.b; in[1] = o.a; in[2] = E0 + o.c; nin = 3; outd = E0 + o.d; break;
-          default: return false;
-        }
-        for (int q = 0; q < nin; ++q) {
-          if (in[q] < 0 || in[q] >= ND) return false;
-          if (produced[in[q]] < 0 || produced[in[q]] >= t) return false;
-          if (!(o.kind == OP_ABSORB && in[q] == outd)) reads.push_back(in[q]);
-        }
-        if (outd < 0 || outd >= ND) return false;
-        if (wstamp[outd] == t) return false;  // two writers at one level
-        wstamp[outd] = (int32_t)t;
-        writes.push_back(outd);
-      }
-      for (int64_t r : reads) rstamp[r] = (int32_t)t;
-      for (int64_t w : writes) {
-        if (rstamp[w] == t) return false;  // read and written at the same level
-        produced[w] = (int32_t)t;
-      }
-    }
-    return true;
-  }
 };
 
 }  // namespace
+
+// Independent check of the level schedule: replay the levels in order and
+// verify that every input was produced at an earlier level, that each datum
+// has at most one writer per level, and that no datum written at a level is
+// read by another op of that level.
+bool verify_crew(const PlanHost &P) {
+  const int64_t N = P.N;
+  // datum ids: U_i -> i; edge slot s -> N + s; contribution c -> N + slots + c
+  const int64_t E0 = N, C0 = N + P.n_edge_slots, ND = C0 + P.n_contrib;
+  std::vector<int32_t> produced(ND, -1), wstamp(ND, -1), rstamp(ND, -1);
+  for (int64_t i = 0; i < N; ++i) produced[i] = 0;
+  for (int64_t s = 0; s < N; ++s) produced[E0 + s] = 0;
+  std::vector<int64_t> reads, writes;
+  for (int64_t t = 1; t <= P.levels(); ++t) {
+    reads.clear();
+    writes.clear();
+    for (int64_t k = P.lvl_off[t - 1]; k < P.lvl_off[t]; ++k) {
+      const OpRec &o = P.ops[k];
+      if (o.level != t) return false;
+      int64_t in[3];
+      int nin = 0;
+      int64_t outd = -1;
+      switch (o.kind) {
+        case OP_RAKE: in[0] = o.a; in[1] = E0 + o.b; nin = 2; outd = C0 + o.c; break;
+        case OP_COMBINE: in[0] = C0 + o.a; in[1] = C0 + o.b; nin = 2; outd = C0 + o.c; break;
+        case OP_ABSORB: in[0] = o.a; in[1] = C0 + o.b; nin = 2; outd = o.a; break;
+        case OP_COMPRESS: in[0] = E0 + o.b; in[1] = o.a; in[2] = E0 + o.c; nin = 3; outd = E0 + o.d; break;
+        default: return false;
+      }
+      for (int q = 0; q < nin; ++q) {
+        if (in[q] < 0 || in[q] >= ND) return false;
+        if (produced[in[q]] < 0 || produced[in[q]] >= t) return false;
+        if (!(o.kind == OP_ABSORB && in[q] == outd)) reads.push_back(in[q]);
+      }
+      if (outd < 0 || outd >= ND) return false;
+      if (wstamp[outd] == t) return false;  // two writers at one level
+      wstamp[outd] = (int32_t)t;
+      writes.push_back(outd);
+    }
+    for (int64_t r : reads) rstamp[r] = (int32_t)t;
+    for (int64_t w : writes) {
+      if (rstamp[w] == t) return false;  // read and written at the same level
+      produced[w] = (int32_t)t;
+    }
+  }
+  return true;
+}
 
 int build_plan(const int64_t *parent, int64_t N, int n, int m, int selection, PlanHost &out) {
   if (!parent) return RCR_NULL_ARG;
@@ -516,7 +525,6 @@ int merge_plans(const std::vector<const PlanHost *> &parts, PlanHost &out) {
   out.n_contrib = NC;
   out.root = parts[0]->root;
   out.selection = parts[0]->selection;
-  out.crew_ok = true;
   out.tree_off.resize(k + 1);
   out.parent32.resize(N);
   for (size_t t = 0; t < k; ++t) {
@@ -532,7 +540,6 @@ int merge_plans(const std::vector<const PlanHost *> &parts, PlanHost &out) {
     out.n_compress += p.n_compress;
     out.n_combine += p.n_combine;
     out.n_absorb += p.n_absorb;
-    out.crew_ok = out.crew_ok && p.crew_ok;
   }
   out.tree_off[k] = N;
   auto node = [&](size_t t, int32_t v) { return (int32_t)(vb[t] + v); };

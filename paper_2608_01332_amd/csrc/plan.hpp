@@ -35,7 +35,9 @@ struct PlanHost {
   int64_t n_rake = 0, n_compress = 0, n_combine = 0, n_absorb = 0;
   int64_t n_contrib = 0;     // rake + combine output slots
   int64_t n_edge_slots = 0;  // N original slots + one per compression
-  bool crew_ok = false;
+  // CREW check of the level schedule (verify_crew), run on the first request
+  // for the plan's statistics: -1 not yet run, else 0 / 1
+  mutable int crew = -1;
 
   // contraction (quadratic and affine passes): ops sorted by (level, kind);
   // ops of level t (1-based) are [lvl_off[t-1], lvl_off[t]).
@@ -79,6 +81,8 @@ struct PlanHost {
 };
 
 // Returns 0 or a negative RCR_* status.
+// Independent check that the level schedule is CREW (verify_crew in plan.cpp).
+bool verify_crew(const PlanHost &P);
 int build_plan(const int64_t *parent, int64_t N, int n, int m, int selection, PlanHost &out);
 
 // Plan of the lifted edge-control tree of a node-control problem (Sec. II-B,
