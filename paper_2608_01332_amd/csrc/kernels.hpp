@@ -272,6 +272,9 @@ __device__ __forceinline__ void quad_op_team(const Bufs<T> &bf, const OpRec &o, 
     T *Lp = L + 5 * NB * NB;
     typedef double ST;  // the compress composition's (I + C_l Pt) solve is always float64
     ST M[W];
+    T cn[NB], pl[NB];  // C_r and P_l, fetched with the other operands (not a round trip of their own later)
+    ld_row(cn, bf.EC + rs * nn, n, r);
+    ld_row(pl, bf.EP + l * nn, n, r);
     {
       T pt[NB], uj[NB], al[NB], cl[NB];
       ld_row(pt, bf.EP + rs * nn, n, r);
@@ -309,8 +312,6 @@ __device__ __forceinline__ void quad_op_team(const Bufs<T> &bf, const OpRec &o, 
       lds_put_at(LY, y, row, r);
     }
     team_sync();
-    T cn[NB];
-    ld_row(cn, bf.EC + rs * nn, n, r);
     {
       T ar[NB], an[NB];
       lds_row(ar, LAr, r);
@@ -338,8 +339,6 @@ __device__ __forceinline__ void quad_op_team(const Bufs<T> &bf, const OpRec &o, 
       lds_put(LY, cn, r);
       lds_put(LX, pn, r);
       team_sync();
-      T pl[NB];
-      ld_row(pl, bf.EP + l * nn, n, r);
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
         cn[q] = (T)0.5 * (cn[q] + LY[q * NB + rr]);

@@ -130,8 +130,13 @@ __device__ __forceinline__ void team_sync() {
 // row[j] = g[r][j] for r, j < n (row stride n), else 0
 template <typename T, int NB, typename S>
 __device__ __forceinline__ void ld_row(T (&row)[NB], const S *__restrict__ g, int n, int r) {
+  // every load issued at once (gather), at a clamped row for the ghost lanes
+  const int rr = r < n ? r : n - 1;
+  gather(row, n, [&](int j) { return (T)g[(int64_t)rr * n + j]; });
+  if (r >= n) {
 #pragma unroll
-  for (int j = 0; j < NB; ++j) row[j] = (r < n && j < n) ? (T)g[(int64_t)r * n + j] : (T)0;
+    for (int j = 0; j < NB; ++j) row[j] = (T)0;
+  }
 }
 
 template <typename T, int NB>
