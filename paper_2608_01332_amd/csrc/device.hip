@@ -27,6 +27,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <utility>
+#include <vector>
 
 #include "device.hpp"
 #include "kernels.hpp"
@@ -111,60 +116,123 @@ static inline double *ws_resid(void *ws) { return reinterpret_cast<double *>(sta
 // The plan's integer arrays live in one device allocation, made and filled in
 // the order of `st` and released in stream order after the last solve that
 // used them (no device-wide synchronisation on destroy).
+// Pinned staging buffers of plan uploads, reused across uploads: a fresh
+// pageable buffer per upload pays first-touch page faults on the host and a
+// staged pageable copy.  Every pooled buffer holds STAGE_BYTES; the pool grows
+// to the number of uploads that run at once and is never freed (freeing pinned
+// memory waits for the device, which would stall the solves on other streams).
+// A larger upload stages through ordinary heap memory.
+namespace {
+constexpr size_t STAGE_BYTES = size_t(16) << 20;
+struct StagePool {
+  std::mutex mu;
+  std::vector<char *> free_bufs;
+};
+StagePool &stage_pool() {
+  static StagePool *pool = new StagePool();
+  return *pool;
+}
+char *stage_take() {
+  StagePool &sp = stage_pool();
+  {
+    std::lock_guard<std::mutex> lock(sp.mu);
+    if (!sp.free_bufs.empty()) {
+      char *b = sp.free_bufs.back();
+      sp.free_bufs.pop_back();
+      return b;
+    }
+  }
+  void *b = nullptr;
+  if (hipHostMalloc(&b, STAGE_BYTES, hipHostMallocDefault) != hipSuccess) return nullptr;
+  return static_cast<char *>(b);
+}
+void stage_give(char *b) {
+  StagePool &sp = stage_pool();
+  std::lock_guard<std::mutex> lock(sp.mu);
+  sp.free_bufs.push_back(b);
+}
+}  // namespace
+
 int plan_upload(PlanObj &P, hipStream_t st) {
   if (P.dev.base) return RCR_OK;
   const PlanHost &h = P.host;
   int dev = 0;
   HIPCK(hipGetDevice(&dev));
   P.dev.device = dev;
-  std::vector<int32_t> coff(h.N + 1, 0), cidx(std::max<int64_t>(h.N, 1), 0);
-  for (int64_t j = 0; j < h.N; ++j)
-    if (h.parent32[j] >= 0) coff[h.parent32[j] + 1]++;
-  for (int64_t i = 0; i < h.N; ++i) coff[i + 1] += coff[i];
-  {
-    std::vector<int32_t> fill(coff.begin(), coff.end() - 1);
-    for (int64_t j = 0; j < h.N; ++j)
-      if (h.parent32[j] >= 0) cidx[fill[h.parent32[j]]++] = (int32_t)j;
-  }
   struct Piece {
     void **dst;
-    const void *src;
+    const void *src;  // nullptr: the child lists, written in place
     size_t bytes;
   };
+  const int64_t NC = std::max<int64_t>(h.N, 1);
   const Piece pieces[] = {
       {(void **)&P.dev.ops, h.ops.data(), h.ops.size() * sizeof(OpRec)},
       {(void **)&P.dev.exp_ops, h.exp_ops.data(), h.exp_ops.size() * sizeof(Op4)},
       {(void **)&P.dev.tc_ops, h.tc_ops.data(), h.tc_ops.size() * sizeof(Op4)},
       {(void **)&P.dev.sx_ops, h.sx_ops.data(), h.sx_ops.size() * sizeof(Op4)},
       {(void **)&P.dev.parent, h.parent32.data(), h.parent32.size() * sizeof(int32_t)},
-      {(void **)&P.dev.child_off, coff.data(), coff.size() * sizeof(int32_t)},
-      {(void **)&P.dev.child_idx, cidx.data(), cidx.size() * sizeof(int32_t)},
+      {(void **)&P.dev.child_off, nullptr, (size_t)(h.N + 1) * sizeof(int32_t)},
+      {(void **)&P.dev.child_idx, nullptr, (size_t)NC * sizeof(int32_t)},
       {(void **)&P.dev.koff, h.kind_off.data(), h.kind_off.size() * sizeof(int64_t)},
       {(void **)&P.dev.exp_off, h.exp_off.data(), h.exp_off.size() * sizeof(int64_t)},
       {(void **)&P.dev.tc_off, h.tc_off.data(), h.tc_off.size() * sizeof(int64_t)},
       {(void **)&P.dev.sx_off, h.sx_off.data(), h.sx_off.size() * sizeof(int64_t)},
       {(void **)&P.dev.lift_plus, h.lift_plus.data(), h.lift_plus.size() * sizeof(int32_t)},
   };
-  size_t total = 0;
-  for (const Piece &pc : pieces) total = align_up(total + std::max<size_t>(pc.bytes, 16), 256);
-  std::vector<char> stage(total, 0);
-  size_t at = 0;
-  for (const Piece &pc : pieces) {
-    if (pc.bytes) memcpy(stage.data() + at, pc.src, pc.bytes);
-    at = align_up(at + std::max<size_t>(pc.bytes, 16), 256);
+  constexpr int NP = sizeof(pieces) / sizeof(pieces[0]);
+  size_t at[NP], total = 0;
+  for (int k = 0; k < NP; ++k) {
+    at[k] = total;
+    total = align_up(total + std::max<size_t>(pieces[k].bytes, 16), 256);
+  }
+  const bool pooled = total <= STAGE_BYTES;
+  std::unique_ptr<char[]> heap;
+  char *stage = nullptr;
+  if (pooled) {
+    stage = stage_take();
+  } else {
+    heap.reset(new (std::nothrow) char[total]);
+    stage = heap.get();
+  }
+  if (!stage) return RCR_OOM;
+  for (int k = 0; k < NP; ++k) {
+    if (pieces[k].src && pieces[k].bytes) memcpy(stage + at[k], pieces[k].src, pieces[k].bytes);
+    const size_t pad = std::max<size_t>(pieces[k].bytes, 16);
+    if (pieces[k].src && pad > pieces[k].bytes) memset(stage + at[k] + pieces[k].bytes, 0, pad - pieces[k].bytes);
+  }
+  {  // children of each node in increasing id: node i owns cidx[coff[i] .. coff[i + 1])
+    int32_t *coff = reinterpret_cast<int32_t *>(stage + at[5]);
+    int32_t *cidx = reinterpret_cast<int32_t *>(stage + at[6]);
+    const int32_t *par = h.parent32.data();
+    const int64_t N = h.N;
+    memset(cidx, 0, (size_t)NC * sizeof(int32_t));
+    // count node p's children at coff[p + 2] (the last node's count is never needed
+    // as a start); after the prefix sum coff[p + 1] is the start of p, and the
+    // scatter advances it to the end of p, which is the start of p + 1
+    memset(coff, 0, (size_t)(N + 1) * sizeof(int32_t));
+    for (int64_t j = 0; j < N; ++j)
+      if (par[j] >= 0 && par[j] + 2 <= N) coff[par[j] + 2]++;
+    for (int64_t i = 2; i <= N; ++i) coff[i] += coff[i - 1];
+    for (int64_t j = 0; j < N; ++j)
+      if (par[j] >= 0) cidx[coff[par[j] + 1]++] = (int32_t)j;
   }
   char *base = nullptr;
-  if (hipMallocAsync((void **)&base, total, st) != hipSuccess) return RCR_OOM;
+  if (hipMallocAsync((void **)&base, total, st) != hipSuccess) {
+    if (pooled) stage_give(stage);
+    return RCR_OOM;
+  }
+  for (int k = 0; k < NP; ++k) *pieces[k].dst = base + at[k];
   P.dev.base = base;
   P.dev.bytes = total;
-  at = 0;
-  for (const Piece &pc : pieces) {
-    *pc.dst = base + at;
-    at = align_up(at + std::max<size_t>(pc.bytes, 16), 256);
+  // the staging buffer goes back to the pool on return, and solves on other
+  // streams may use the arrays: wait for the copy
+  hipError_t e = hipMemcpyAsync(base, stage, total, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (pooled) stage_give(stage);
+  if (e != hipSuccess) {
+    fprintf(stderr, "rcr: plan upload failed: %s\n", hipGetErrorString(e));
+    return RCR_HIP_ERROR;
   }
-  HIPCK(hipMemcpyAsync(base, stage.data(), total, hipMemcpyHostToDevice, st));
-  // the staging buffer is released on return, and solves on other streams may use the arrays
-  HIPCK(hipStreamSynchronize(st));
   return RCR_OK;
 }
 

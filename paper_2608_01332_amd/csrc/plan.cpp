@@ -18,7 +18,9 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
+#include <utility>
 
 #include "../../include/rcr.h"
 
@@ -27,11 +29,16 @@ namespace {
 
 typedef unsigned __int128 u128;
 
-struct Builder {
-  const int64_t *parent;
-  int64_t N;
-  PlanHost &P;
+struct Code {  // alphabetic code word: the leading d bits of r
+  u128 r;
+  int d;
+};
 
+// Working arrays of one plan construction.  Each thread keeps its set between
+// plans (up to KEEP_NODES nodes): a serving loop plans many topologies on the
+// same threads, and first-touch page faults of fresh arrays would otherwise
+// cost as much as the construction itself.
+struct Work {
   std::vector<int32_t> cur_par, lvlU, lvlE, edge_slot, sib_key, cnt, one_child;
   std::vector<uint8_t> alive, sel;
   std::vector<int32_t> contrib_level;
@@ -40,6 +47,23 @@ struct Builder {
   std::vector<uint8_t> rem_kind;  // 0 none, 1 rake, 2 compress
   std::vector<int32_t> removal_seq;
   std::vector<OpRec> raw;  // forward op sequence before level sorting
+  // validation, rounds and the pass schedules
+  std::vector<int32_t> deg, bfs_start, bfs_kids, bfs_fill, bfs_order, depth;
+  std::vector<int32_t> live, leaves, elig, lvl_tmp;
+  std::vector<std::pair<int64_t, int32_t>> keyed;  // (parent * N + key, contribution)
+  std::vector<Op4> seq;
+  std::vector<int64_t> count, fill;
+  // one sibling group of a readiness-weighted reduction
+  std::vector<Code> codes;
+  std::vector<u128> wts;
+  std::vector<int32_t> g_slot, g_lvl;
+};
+constexpr int64_t KEEP_NODES = int64_t(1) << 17;
+
+struct Builder : Work {
+  const int64_t *parent;
+  int64_t N;
+  PlanHost &P;
   int32_t next_slot = 0, next_contrib = 0;
 
   explicit Builder(const int64_t *p, int64_t n, PlanHost &out) : parent(p), N(n), P(out) {}
@@ -50,12 +74,6 @@ struct Builder {
   }
 
   // ---- readiness-weighted reduction (Lemma 3) -----------------------------
-  struct Code {
-    u128 r;
-    int d;
-  };
-  std::vector<Code> codes;
-  std::vector<int32_t> g_slot, g_lvl;
   int32_t g_parent = 0, g_round = 0;
 
   int bit(int j, int pos) const { return (int)((codes[j].r >> (codes[j].d - 1 - pos)) & 1); }
@@ -104,7 +122,8 @@ struct Builder {
     int cap = 61 - lg;
     codes.resize(k);
     u128 W = 0;
-    std::vector<u128> w(k);
+    std::vector<u128> &w = wts;
+    w.resize(k);
     for (int j = 0; j < k; ++j) {
       int e = std::min<int>(g_lvl[j] - lmin, cap);
       w[j] = (u128)1 << e;
@@ -139,33 +158,36 @@ struct Builder {
     if (N > (int64_t)(INT32_MAX / 2 - 16)) return RCR_BAD_DIMS;
     P.root = root;
     P.parent32.resize(N);
-    std::vector<int32_t> deg(N, 0);
+    deg.assign(N, 0);
     for (int64_t i = 0; i < N; ++i) {
       P.parent32[i] = (int32_t)parent[i];
       if (parent[i] >= 0) deg[parent[i]]++;
     }
     {  // BFS: reachability (rejects cycles) and height
-      std::vector<int64_t> start(N + 1, 0), kids(N > 0 ? N : 1);
+      std::vector<int32_t> &start = bfs_start, &kids = bfs_kids, &fl = bfs_fill, &order = bfs_order;
+      start.resize(N + 1);
+      start[0] = 0;
+      for (int64_t i = 0; i < N; ++i) start[i + 1] = start[i] + deg[i];
+      fl.assign(start.begin(), start.end() - 1);
+      kids.resize(N);
       for (int64_t i = 0; i < N; ++i)
-        if (parent[i] >= 0) start[parent[i] + 1]++;
-      for (int64_t i = 0; i < N; ++i) start[i + 1] += start[i];
-      std::vector<int64_t> fill(start.begin(), start.end() - 1);
-      for (int64_t i = 0; i < N; ++i)
-        if (parent[i] >= 0) kids[fill[parent[i]]++] = i;
-      std::vector<int64_t> order;
-      order.reserve(N);
-      std::vector<int32_t> depth(N, 0);
-      order.push_back(root);
-      for (size_t h = 0; h < order.size(); ++h) {
-        int64_t v = order[h];
-        for (int64_t c = start[v]; c < start[v + 1]; ++c) {
-          depth[kids[c]] = depth[v] + 1;
-          order.push_back(kids[c]);
+        if (parent[i] >= 0) kids[fl[parent[i]]++] = (int32_t)i;
+      order.resize(N);
+      depth.resize(N);
+      int64_t tail = 0;
+      order[tail++] = (int32_t)root;
+      depth[root] = 0;
+      int32_t h = 0;
+      // a node is queued once, by its parent: on a cycle the queue stops short of N
+      for (int64_t q = 0; q < tail; ++q) {
+        const int32_t v = order[q], dv = depth[v] + 1;
+        for (int32_t c = start[v]; c < start[v + 1]; ++c) {
+          depth[kids[c]] = dv;
+          order[tail++] = kids[c];
+          h = std::max(h, dv);
         }
       }
-      if ((int64_t)order.size() != N) return RCR_INVALID_TREE;
-      int32_t h = 0;
-      for (int64_t i = 0; i < N; ++i) h = std::max(h, depth[i]);
+      if (tail != N) return RCR_INVALID_TREE;
       P.height = h;
     }
     P.leaves = 0;
@@ -182,7 +204,6 @@ struct Builder {
     edge_slot.resize(N);
     sib_key.resize(N);
     for (int64_t i = 0; i < N; ++i) edge_slot[i] = sib_key[i] = (int32_t)i;
-    cnt.assign(N, 0);
     one_child.assign(N, -1);
     alive.assign(N, 1);
     sel.assign(N, 0);
@@ -192,18 +213,19 @@ struct Builder {
     comp_k.assign(N, -1);
     rem_kind.assign(N, 0);
     next_slot = (int32_t)N;
+    raw.clear();
+    contrib_level.clear();
+    removal_seq.clear();
     raw.reserve((size_t)N * 2);
     contrib_level.reserve((size_t)N * 2);
     removal_seq.reserve((size_t)N);
-    std::vector<int32_t> live(N);
+    live.resize(N);
     for (int64_t i = 0; i < N; ++i) live[i] = (int32_t)i;
-    std::vector<int32_t> leaves, elig;
-    std::vector<std::pair<int64_t, int32_t>> keyed;  // (parent * N + key, leaf)
     int32_t rnd = 0;
     // cnt[v]: live children of v.  Rakes decrement it; a compression leaves the
     // parent's count unchanged (its child j is replaced by j's child), so it is
     // maintained across rounds instead of recounted.
-    for (int64_t i = 0; i < N; ++i) cnt[i] = deg[i];
+    cnt.assign(deg.begin(), deg.end());
     while (live.size() > 1) {
       ++rnd;
       leaves.clear();
@@ -320,11 +342,11 @@ struct Builder {
     int32_t L = 0;
     for (const OpRec &o : raw) L = std::max(L, o.level);
     {
-      std::vector<int64_t> count((size_t)L * 4 + 1, 0);
+      count.assign((size_t)L * 4 + 1, 0);
       for (const OpRec &o : raw) count[(size_t)(o.level - 1) * 4 + o.kind + 1]++;
       for (size_t t = 1; t < count.size(); ++t) count[t] += count[t - 1];
       P.ops.resize(raw.size());
-      std::vector<int64_t> fill(count.begin(), count.end() - 1);
+      fill.assign(count.begin(), count.end() - 1);
       for (const OpRec &o : raw) P.ops[fill[(size_t)(o.level - 1) * 4 + o.kind]++] = o;
       P.lvl_off.resize(L + 1);
       for (int32_t t = 0; t <= L; ++t) P.lvl_off[t] = count[(size_t)t * 4];
@@ -335,7 +357,8 @@ struct Builder {
 
     // ---- expansion of compressions (reverse graph): level = 1 + level of the child's value
     {
-      std::vector<int32_t> eP(N, 0);
+      std::vector<int32_t> &eP = lvl_tmp;
+      eP.assign(N, 0);
       int32_t LE = 0;
       for (auto it = removal_seq.rbegin(); it != removal_seq.rend(); ++it) {
         int32_t j = *it;
@@ -350,15 +373,16 @@ struct Builder {
         if (rem_kind[j] == 2) P.exp_off[eP[j]]++;
       for (int32_t t = 0; t < LE; ++t) P.exp_off[t + 1] += P.exp_off[t];
       P.exp_ops.resize((size_t)P.exp_off[LE]);
-      std::vector<int64_t> fill(P.exp_off.begin(), P.exp_off.end() - 1);
+      fill.assign(P.exp_off.begin(), P.exp_off.end() - 1);
       for (int32_t j : removal_seq)
         if (rem_kind[j] == 2) P.exp_ops[fill[eP[j] - 1]++] = Op4{j, comp_r[j], comp_k[j], 0};
     }
     // ---- composition of edge maps over compressions only
     {
-      std::vector<int32_t> lT(next_slot, 0);
+      std::vector<int32_t> &lT = lvl_tmp;
+      lT.assign(next_slot, 0);
       int32_t LT = 0;
-      std::vector<Op4> seq;
+      seq.clear();
       for (const OpRec &o : raw)
         if (o.kind == OP_COMPRESS) {
           lT[o.d] = 1 + std::max(lT[o.b], lT[o.c]);
@@ -369,12 +393,13 @@ struct Builder {
       for (const Op4 &q : seq) P.tc_off[lT[q.c]]++;
       for (int32_t t = 0; t < LT; ++t) P.tc_off[t + 1] += P.tc_off[t];
       P.tc_ops.resize((size_t)P.tc_off[LT]);
-      std::vector<int64_t> fill(P.tc_off.begin(), P.tc_off.end() - 1);
+      fill.assign(P.tc_off.begin(), P.tc_off.end() - 1);
       for (const Op4 &q : seq) P.tc_ops[fill[lT[q.c] - 1]++] = q;
     }
     // ---- state expansion: x_j from the state of its parent at removal time
     {
-      std::vector<int32_t> eX(N, 0);
+      std::vector<int32_t> &eX = lvl_tmp;
+      eX.assign(N, 0);
       int32_t LX = 0;
       for (auto it = removal_seq.rbegin(); it != removal_seq.rend(); ++it) {
         int32_t j = *it;
@@ -385,7 +410,7 @@ struct Builder {
       for (int32_t j : removal_seq) P.sx_off[eX[j]]++;
       for (int32_t t = 0; t < LX; ++t) P.sx_off[t + 1] += P.sx_off[t];
       P.sx_ops.resize((size_t)P.sx_off[LX]);
-      std::vector<int64_t> fill(P.sx_off.begin(), P.sx_off.end() - 1);
+      fill.assign(P.sx_off.begin(), P.sx_off.end() - 1);
       for (int32_t j : removal_seq) P.sx_ops[fill[eX[j] - 1]++] = Op4{j, rem_slot[j], rem_par[j], 0};
     }
     return RCR_OK;
@@ -451,8 +476,12 @@ int build_plan(const int64_t *parent, int64_t N, int n, int m, int selection, Pl
   out.n = n;
   out.m = m;
   out.selection = selection;
+  static thread_local Work kept;
   Builder b(parent, N, out);
-  return b.run(selection);
+  std::swap(static_cast<Work &>(b), kept);
+  const int rc = b.run(selection);
+  if (N <= KEEP_NODES) std::swap(static_cast<Work &>(b), kept);
+  return rc;
 }
 
 // Lifted tree (Prop. 2): native node i keeps id i as its predecision node i^-;
