@@ -484,8 +484,9 @@ def main() -> int:
     ap.add_argument("--trees", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the solver shards by tree across GPUs with no communication, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: measures one GPU only; --gpus {args.gpus} is not supported "
+              "(independent trees shard across GPUs with no communication: each GPU runs its own plans)",
+              file=sys.stderr)
         return 2
 
     import numpy as np
