@@ -173,6 +173,7 @@ int plan_upload(PlanObj &P, hipStream_t st) {
       {(void **)&P.dev.parent, h.parent32.data(), h.parent32.size() * sizeof(int32_t)},
       {(void **)&P.dev.child_off, nullptr, (size_t)(h.N + 1) * sizeof(int32_t)},
       {(void **)&P.dev.child_idx, nullptr, (size_t)NC * sizeof(int32_t)},
+      {(void **)&P.dev.hubs, nullptr, (size_t)(h.N / (RES_HUB + 1) + 1) * sizeof(int32_t)},
       {(void **)&P.dev.koff, h.kind_off.data(), h.kind_off.size() * sizeof(int64_t)},
       {(void **)&P.dev.exp_off, h.exp_off.data(), h.exp_off.size() * sizeof(int64_t)},
       {(void **)&P.dev.tc_off, h.tc_off.data(), h.tc_off.size() * sizeof(int64_t)},
@@ -215,6 +216,14 @@ int plan_upload(PlanObj &P, hipStream_t st) {
     for (int64_t i = 2; i <= N; ++i) coff[i] += coff[i - 1];
     for (int64_t j = 0; j < N; ++j)
       if (par[j] >= 0) cidx[coff[par[j] + 1]++] = (int32_t)j;
+    // nodes whose child terms the residual sums in a workgroup of their own
+    // (at most N / (RES_HUB + 1) of them: the children are distinct nodes)
+    int32_t *hubs = reinterpret_cast<int32_t *>(stage + at[7]);
+    int64_t nh = 0;
+    hubs[0] = 0;
+    for (int64_t i = 0; i < N; ++i)
+      if (coff[i + 1] - coff[i] > RES_HUB) hubs[nh++] = (int32_t)i;
+    P.dev.n_hubs = nh;
   }
   char *base = nullptr;
   if (hipMallocAsync((void **)&base, total, st) != hipSuccess) {
@@ -318,12 +327,31 @@ constexpr int res_team() {
   return NB <= 8 && MB <= 8 ? 8 : 16;
 }
 
-template <typename OT, int NB, int MB>
+// The child terms of stationarity row rn of node v: for child j,
+// (S_j u_j)[rn] + (A_j^T lambda_j)[rn], added to s.
+template <int NB, int MB>
+__device__ __forceinline__ double child_terms(int64_t j, int n, int m, int rn, const double *S, const double *u,
+                                              const double *A, const double *y, double s) {
+  const int nn = n * n, nm = n * m;
+  double sj[MB], uj[MB], aj[NB], yj[NB];
+  gather(sj, m, [&](int k) { return S[j * nm + rn * m + k]; });
+  gather(uj, m, [&](int k) { return u[j * m + k]; });
+  gather(aj, n, [&](int k) { return A[j * nn + k * n + rn]; });
+  gather(yj, n, [&](int k) { return y[j * n + k]; });
+  s = dot_n(sj, uj, m, s);
+  return dot_n(aj, yj, n, s);
+}
+
+// HUB: node v has more than RES_HUB children, whose terms (row r) the caller
+// has summed into csum; otherwise they are summed here in child order, and a
+// node with more than RES_HUB children is skipped (returns 0, writes nothing).
+template <typename OT, int NB, int MB, bool HUB = false>
 __device__ __forceinline__ double residual_rhs(int64_t v, int n, int m, const double *Q, const double *q,
                                                const double *c, const double *De, const double *R, const double *S,
                                                const double *rr, const double *A, const double *B, const double *x,
                                                const double *u, const double *y, const int32_t *parent,
-                                               const int32_t *coff, const int32_t *cidx, OT *rq, OT *rr_out, OT *rc) {
+                                               const int32_t *coff, const int32_t *cidx, OT *rq, OT *rr_out, OT *rc,
+                                               double csum = 0.0) {
   constexpr int TW = res_team<NB, MB>();
   const int r = threadIdx.x & (TW - 1);
   const int nn = n * n, nm = n * m;
@@ -346,15 +374,12 @@ __device__ __forceinline__ double residual_rhs(int64_t v, int n, int m, const do
   gather(rx, m, [&](int k) { return R[v * m * m + rm * m + k]; });
   double s = q[v * n + rn] - y[v * n + rn];
   s = dot_n(qr, xv, n, s);
-  for (int32_t t = coff[v]; t < coff[v + 1]; ++t) {
-    const int64_t j = cidx[t];
-    double sj[MB], uj[MB], aj[NB], yj[NB];
-    gather(sj, m, [&](int k) { return S[j * nm + rn * m + k]; });
-    gather(uj, m, [&](int k) { return u[j * m + k]; });
-    gather(aj, n, [&](int k) { return A[j * nn + k * n + rn]; });
-    gather(yj, n, [&](int k) { return y[j * n + k]; });
-    s = dot_n(sj, uj, m, s);
-    s = dot_n(aj, yj, n, s);
+  if constexpr (HUB) {
+    s += csum;
+  } else {
+    const int32_t t0 = coff[v], t1 = coff[v + 1];
+    if (t1 - t0 > RES_HUB) return 0.0;  // a hub: k_residual_hub covers the node
+    for (int32_t t = t0; t < t1; ++t) s = child_terms<NB, MB>(cidx[t], n, m, rn, S, u, A, y, s);
   }
   double worst = 0.0;
   if (r < n) worst = fabs(s);
@@ -420,6 +445,58 @@ __global__ __launch_bounds__(256) void k_residual_rhs(int64_t N, int n, int m, c
   }
 }
 
+// The nodes with more than RES_HUB children, one workgroup each: team k sums
+// the terms of children k, k + teams, ... in that order, the partial sums are
+// added in team order, and team 0 forms the node's residual rows.  The order
+// is fixed by the launch, so results do not vary between runs.
+template <typename OT, int NB, int MB>
+__global__ __launch_bounds__(256) void k_residual_hub(int64_t N, int n, int m, const double *Q, const double *q,
+                                                      const double *c, const double *De, const double *R,
+                                                      const double *S, const double *rr, const double *A,
+                                                      const double *B, const double *x, const double *u,
+                                                      const double *y, const int32_t *parent, const int32_t *coff,
+                                                      const int32_t *cidx, const int32_t *hubs, OT *rq, OT *rr_out,
+                                                      OT *rc, double *out) {
+  constexpr int TW = res_team<NB, MB>(), TEAMS = 256 / TW;
+  __shared__ double part[256];
+  __shared__ double wmax[256 / 64];
+  const int64_t v = hubs[blockIdx.x];
+  const int k = threadIdx.x / TW, r = threadIdx.x & (TW - 1);
+  const bool exact = n == NB && m == MB;
+  const int rn = r < n ? r : n - 1;
+  double s = 0.0;
+  const int32_t te = coff[v + 1];
+  int32_t t = coff[v] + k;
+  int64_t j = t < te ? cidx[t] : 0;
+  while (t < te) {
+    // the next child's id is fetched with this child's operands, not after them
+    const int32_t tn = t + TEAMS;
+    const int64_t jn = tn < te ? cidx[tn] : 0;
+    s = exact ? child_terms<NB, MB>(j, NB, MB, rn, S, u, A, y, s) : child_terms<NB, MB>(j, n, m, rn, S, u, A, y, s);
+    t = tn;
+    j = jn;
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  double worst = 0.0;
+  if (k == 0) {
+    double csum = part[r];
+    for (int i = 1; i < TEAMS; ++i) csum += part[i * TW + r];
+    worst = exact ? residual_rhs<OT, NB, MB, true>(v, NB, MB, Q, q, c, De, R, S, rr, A, B, x, u, y, parent, coff,
+                                                    cidx, rq, rr_out, rc, csum)
+                  : residual_rhs<OT, NB, MB, true>(v, n, m, Q, q, c, De, R, S, rr, A, B, x, u, y, parent, coff,
+                                                    cidx, rq, rr_out, rc, csum);
+  }
+  for (int off = 32; off > 0; off >>= 1) worst = fmax(worst, __shfl_xor(worst, off, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = worst;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double w = wmax[0];
+    for (int i = 1; i < 256 / 64; ++i) w = fmax(w, wmax[i]);
+    if (w > 0.0) atomicMax(reinterpret_cast<unsigned long long *>(out), (unsigned long long)__double_as_longlong(w));
+  }
+}
+
 template <typename OT, int NB>
 static void launch_residual_nb(const PlanHost &h, const rcr_problem &in, const rcr_solution &out, OT *rq, OT *rr,
                                OT *rc, const PlanObj &P, double *resid, hipStream_t st) {
@@ -433,6 +510,18 @@ static void launch_residual_nb(const PlanHost &h, const rcr_problem &in, const r
     default: hipLaunchKernelGGL((k_residual_rhs<OT, NB, 16>), g, b, 0, st, RCR_RES_ARGS); break;
   }
 #undef RCR_RES_ARGS
+  if (P.dev.n_hubs > 0) {
+    const dim3 gh((unsigned)P.dev.n_hubs), bh(256);
+#define RCR_HUB_ARGS                                                                                           \
+  h.N, h.n, h.m, in.Q, in.q, in.c, in.Delta, in.R, in.S, in.r, in.A, in.B, out.x, out.u, out.lam, P.dev.parent, \
+      P.dev.child_off, P.dev.child_idx, P.dev.hubs, rq, rr, rc, resid
+    switch (pad_m(h.m)) {
+      case 4: hipLaunchKernelGGL((k_residual_hub<OT, NB, 4>), gh, bh, 0, st, RCR_HUB_ARGS); break;
+      case 8: hipLaunchKernelGGL((k_residual_hub<OT, NB, 8>), gh, bh, 0, st, RCR_HUB_ARGS); break;
+      default: hipLaunchKernelGGL((k_residual_hub<OT, NB, 16>), gh, bh, 0, st, RCR_HUB_ARGS); break;
+    }
+#undef RCR_HUB_ARGS
+  }
 }
 
 template <typename OT>

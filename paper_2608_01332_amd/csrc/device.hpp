@@ -20,6 +20,10 @@ namespace rcr {
 constexpr int RCR_PHASE_FIRST_RHS = 4;
 
 // Device copy of a plan's integer arrays.
+// The residual kernel sums a node's child terms in one team; a node with more
+// children than this is summed by a workgroup of its own (k_residual_hub).
+constexpr int RES_HUB = 64;
+
 struct PlanDev {
   int device = -1;
   char *base = nullptr;  // one allocation holding every array below
@@ -27,6 +31,8 @@ struct PlanDev {
   Op4 *exp_ops = nullptr, *tc_ops = nullptr, *sx_ops = nullptr;
   int32_t *parent = nullptr;
   int32_t *child_off = nullptr, *child_idx = nullptr;  // children in increasing id (residual)
+  int32_t *hubs = nullptr;  // nodes with more than RES_HUB children, increasing id (residual)
+  int64_t n_hubs = 0;
   int64_t *koff = nullptr, *exp_off = nullptr, *tc_off = nullptr, *sx_off = nullptr;  // level offsets
   int32_t *lift_plus = nullptr;  // lifted plans: decision node of each native non-leaf
   size_t bytes = 0;

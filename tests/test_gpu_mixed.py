@@ -86,3 +86,44 @@ def test_mixed_graph_matches_levels_bitwise():
     for o in outs[1:]:
         for k in rcr.SOLUTION_FIELDS:
             np.testing.assert_array_equal(o[k], outs[0][k])
+
+
+def _hub_tree(rng):
+    """Root with 300 children, node 1 with 65 children and node 2 with 64 (the
+    residual sums more than 64 children of one node in a workgroup of its own),
+    then a chain of 1000 below node 3; labels permuted."""
+    parent = np.empty(1 + 300 + 65 + 64 + 1000, dtype=np.int64)
+    parent[0] = -1
+    parent[1:301] = 0
+    parent[301:366] = 1
+    parent[366:430] = 2
+    parent[430] = 3
+    parent[431:] = np.arange(430, len(parent) - 1)
+    parent, _ = w.permute_labels(parent, rng)
+    return parent
+
+
+@pytest.mark.parametrize("n,m", [(6, 2), (12, 4)])
+def test_mixed_hub_tree(n, m):
+    rng = np.random.default_rng(500 + n)
+    parent = _hub_tree(rng)
+    d = w.lqr_data(parent, w.DataSpec(n, m, delta_rank=n // 2, delta_scale=0.01, cross=True), rng)
+    _check(*_run(parent, d, n, m))
+    _check(*_run(parent, d, n, m, executor=rcr.EXEC_GRAPH))
+
+
+def test_mixed_hub_tree_bitwise_repeatable():
+    rng = np.random.default_rng(77)
+    parent = _hub_tree(rng)
+    n, m = 8, 3
+    d = w.lqr_data(parent, w.DataSpec(n, m, delta_rank=4, delta_scale=0.01, cross=True), rng)
+    plan = rcr.Plan(parent, n, m)
+    dev = rcr.to_device(d)
+    outs = []
+    for ex in (rcr.EXEC_LEVELS, rcr.EXEC_GRAPH, rcr.EXEC_LEVELS):
+        o = rcr.solve(plan, dev, precision=rcr.MIXED32, refine_steps=2, executor=ex, check=True)
+        torch.cuda.synchronize()
+        outs.append({k: o[k].cpu().numpy().copy() for k in rcr.SOLUTION_FIELDS})
+    for o in outs[1:]:
+        for k in rcr.SOLUTION_FIELDS:
+            np.testing.assert_array_equal(o[k], outs[0][k])
