@@ -111,7 +111,7 @@ def read_traffic(kernel_class: str, mapping: str):
     m = dict(x.split("=", 1) for x in mapping.split(",") if "=" in x)
     try:
         q = int(m["quad_tail_rounds"])
-        return float(kv[f"qtr{2 if q == 0 else q}.hbm_bytes_per_launch"])  # 0 selects the default, 2
+        return float(kv[f"qtr{1 if q == 0 else q}.hbm_bytes_per_launch"])  # 0 selects the default, 1 at n = 12
     except (KeyError, ValueError):
         return None
 

@@ -276,8 +276,9 @@ int rcr_lift_solve(const rcr_plan *plan, const rcr_native_problem *in, rcr_nativ
  * that tail.  Results do not depend on the mapping (every primitive runs the
  * same arithmetic wherever it is launched); only the time does. */
 typedef struct {
-  int32_t quad_tail_rounds; /* quadratic contraction/expansion tail (default 2)            */
-  int32_t vec_tail_rounds;  /* affine and state tails (default 4)                           */
+  int32_t quad_tail_rounds; /* quadratic contraction/expansion tail (default: 1 for n > 8,
+                                off for n <= 8)                                            */
+  int32_t vec_tail_rounds;  /* affine and state tails (default: 2 in FP64, 4 in float32)   */
   int32_t vec_tail_waves;   /* wavefronts of the vector tail workgroup, 1..16 (default 8)  */
   int32_t reserved[5];
 } rcr_launch_config;

@@ -189,10 +189,13 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
   if (mat_waves < 1) mat_waves = 1;
   const size_t lds_tail = (size_t)mat_waves * lds_lvl;
   const LaunchCfg &cfg = P.cfg;
-  const int qr = cfg.quad_tail_rounds == 0 ? 2 : (cfg.quad_tail_rounds < 0 ? 0 : cfg.quad_tail_rounds);
+  // Defaults (fields left at 0), from timings of chain-probability trees of 1k
+  // to 64k nodes: the quadratic tail pays off only in the wide layout, at one
+  // round; the vector tails at two rounds in float64 and four in float32.
+  const int qr = cfg.quad_tail_rounds == 0 ? (WIDE ? 1 : 0) : (cfg.quad_tail_rounds < 0 ? 0 : cfg.quad_tail_rounds);
   const int64_t mat_cap = (int64_t)qr * mat_waves * MatLay<NB>::PW;
   const int vec_waves = cfg.vec_tail_waves > 0 ? std::min(cfg.vec_tail_waves, 16) : 8;
-  const int vr = cfg.vec_tail_rounds == 0 ? 4 : (cfg.vec_tail_rounds < 0 ? 0 : cfg.vec_tail_rounds);
+  const int vr = cfg.vec_tail_rounds == 0 ? (sizeof(T) == 4 ? 4 : 2) : (cfg.vec_tail_rounds < 0 ? 0 : cfg.vec_tail_rounds);
   const int64_t vec_cap = (int64_t)vr * vec_waves * (64 / TeamW<NB>::TW);
   const size_t kVecTailLds = 144 * 1024;
   allow_lds(k_tail_quad<T, NB>, lds_tail);
