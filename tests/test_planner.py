@@ -227,3 +227,45 @@ def test_launch_config_set_get_and_validation():
     assert ei.value.status == rcr.ERR_BAD_OPTION
     plan.set_launch(None)
     assert plan.get_launch() == zero
+
+
+def _plan_image(parent, n=6, m=2, selection=rcr.SELECT_GREEDY_INDEX, lift=False):
+    p = rcr.Plan.lift(parent, n, m, selection) if lift else rcr.Plan(parent, n, m, selection)
+    try:
+        return p.stats(), p.export_ops()
+    finally:
+        p.close()
+
+
+def test_plans_do_not_depend_on_earlier_plans_of_the_thread():
+    """Each planner thread keeps its working arrays between plans; a plan built
+    after others (smaller, larger, above the kept size, invalid, lifted) equals
+    the same plan built first on a fresh thread."""
+    from concurrent.futures import ThreadPoolExecutor
+    rng = np.random.default_rng(2024)
+    trees = [w.tree_chainprob(5000, 0.9, rng), w.tree_chainprob(100, 0.5, rng), w.tree_chainprob(20000, 0.97, rng),
+             np.array([-1, 0, 0, 1, 1, 1, 2], dtype=np.int64), w.tree_chainprob(140000, 0.9, rng),
+             w.tree_chainprob(3000, 0.8, rng)]
+
+    def fresh(job):
+        with ThreadPoolExecutor(1) as ex:
+            return ex.submit(_plan_image, *job).result()
+
+    jobs = [(t, 6, 2, sel, lift) for t in trees for sel in (rcr.SELECT_GREEDY_INDEX, rcr.SELECT_LIST_RANK)
+            for lift in (False, True) if not (lift and len(t) > 50000)]
+    alone = [fresh(j) for j in jobs]
+    bad = np.array([1, 2, 0, -1], dtype=np.int64)  # a cycle: rejected part-way through validation
+
+    def sequence():
+        out = []
+        for j in jobs:
+            with pytest.raises(rcr.RcrError):
+                rcr.Plan(bad, 6, 2)
+            out.append(_plan_image(*j))
+        return out
+
+    with ThreadPoolExecutor(1) as ex:
+        seq = ex.submit(sequence).result()
+    for (s0, o0), (s1, o1) in zip(alone, seq):
+        assert s0 == s1
+        np.testing.assert_array_equal(o0, o1)
