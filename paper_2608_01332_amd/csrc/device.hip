@@ -113,9 +113,6 @@ size_t total_workspace_bytes(const PlanHost &ph, int precision) {
 static inline int *ws_status(void *ws) { return reinterpret_cast<int *>(ws); }
 static inline double *ws_resid(void *ws) { return reinterpret_cast<double *>(static_cast<char *>(ws) + 256); }
 
-// The plan's integer arrays live in one device allocation, made and filled in
-// the order of `st` and released in stream order after the last solve that
-// used them (no device-wide synchronisation on destroy).
 // Pinned staging buffers of plan uploads, reused across uploads: a fresh
 // pageable buffer per upload pays first-touch page faults on the host and a
 // staged pageable copy.  Every pooled buffer holds STAGE_BYTES; the pool grows
@@ -153,6 +150,9 @@ void stage_give(char *b) {
 }
 }  // namespace
 
+// The plan's integer arrays live in one device allocation, made and filled in
+// the order of `st` and released in stream order after the last solve that
+// used them (no device-wide synchronisation on destroy).
 int plan_upload(PlanObj &P, hipStream_t st) {
   if (P.dev.base) return RCR_OK;
   const PlanHost &h = P.host;
