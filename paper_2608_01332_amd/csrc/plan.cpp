@@ -50,7 +50,7 @@ struct Work {
   // validation, rounds and the pass schedules
   std::vector<int32_t> deg, bfs_start, bfs_kids, bfs_fill, bfs_order, depth;
   std::vector<int32_t> live, leaves, elig, lvl_tmp;
-  std::vector<std::pair<int64_t, int32_t>> keyed;  // (parent * N + key, contribution)
+  std::vector<std::pair<int64_t, int32_t>> keyed;  // (parent << 32 | sibling key, contribution)
   std::vector<Op4> seq;
   std::vector<int64_t> count, fill;
   // one sibling group of a readiness-weighted reduction
@@ -159,11 +159,22 @@ struct Builder : Work {
     P.root = root;
     P.parent32.resize(N);
     deg.assign(N, 0);
+    bool topo = root == 0;  // every parent precedes its child
     for (int64_t i = 0; i < N; ++i) {
       P.parent32[i] = (int32_t)parent[i];
       if (parent[i] >= 0) deg[parent[i]]++;
+      topo &= parent[i] < i;
     }
-    {  // BFS: reachability (rejects cycles) and height
+    if (topo) {  // parents before children: no cycle, and depths in one forward pass
+      depth.resize(N);
+      depth[0] = 0;
+      int32_t h = 0;
+      for (int64_t i = 1; i < N; ++i) {
+        depth[i] = depth[parent[i]] + 1;
+        h = std::max(h, depth[i]);
+      }
+      P.height = h;
+    } else {  // BFS: reachability (rejects cycles) and height
       std::vector<int32_t> &start = bfs_start, &kids = bfs_kids, &fl = bfs_fill, &order = bfs_order;
       start.resize(N + 1);
       start[0] = 0;
@@ -241,16 +252,16 @@ struct Builder : Work {
         rem_slot[j] = edge_slot[j];
         rem_par[j] = cur_par[j];
         removal_seq.push_back(j);
-        keyed.push_back({(int64_t)cur_par[j] * N + sib_key[j], out});
+        keyed.push_back({(int64_t)cur_par[j] << 32 | (uint32_t)sib_key[j], out});
         P.n_rake++;
       }
       std::sort(keyed.begin(), keyed.end());
       for (size_t g0 = 0; g0 < keyed.size();) {
-        int32_t i = (int32_t)(keyed[g0].first / N);
+        int32_t i = (int32_t)(keyed[g0].first >> 32);
         size_t g1 = g0;
         g_slot.clear();
         g_lvl.clear();
-        while (g1 < keyed.size() && keyed[g1].first / N == i) {
+        while (g1 < keyed.size() && (int32_t)(keyed[g1].first >> 32) == i) {
           g_slot.push_back(keyed[g1].second);
           g_lvl.push_back(contrib_level[keyed[g1].second]);
           ++g1;
