@@ -18,8 +18,12 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <new>
+#include <system_error>
+#include <thread>
 #include <utility>
 
 #include "../../include/rcr.h"
@@ -49,16 +53,51 @@ struct Work {
   std::vector<OpRec> raw;  // forward op sequence before level sorting
   // validation, rounds and the pass schedules
   std::vector<int32_t> deg, bfs_start, bfs_kids, bfs_fill, bfs_order, depth;
-  std::vector<int32_t> live, leaves, elig, lvl_tmp;
+  std::vector<int32_t> live, leaves, elig, lvl_e, lvl_t, lvl_x;
   std::vector<std::pair<int64_t, int32_t>> keyed;  // (parent << 32 | sibling key, contribution)
   std::vector<Op4> seq;
-  std::vector<int64_t> count, fill;
+  std::vector<int64_t> count, fill, fill_e, fill_t, fill_x;
   // one sibling group of a readiness-weighted reduction
   std::vector<Code> codes;
   std::vector<u128> wts;
   std::vector<int32_t> g_slot, g_lvl;
 };
 constexpr int64_t KEEP_NODES = int64_t(1) << 17;
+// Trees from this size on build their four pass schedules on four threads.
+constexpr int64_t PAR_NODES = int64_t(1) << 15;
+
+// Runs the tasks, on threads of their own (the first on the caller's) when
+// `parallel` is set and threads can be started, else one after the other.  An
+// allocation failure in any task is rethrown on the caller's thread.
+template <typename F0, typename... F>
+void run_concurrently(bool parallel, F0 &first, F &...rest) {
+  if (parallel) {
+    constexpr int K = sizeof...(F);
+    std::atomic<bool> failed{false};
+    std::thread th[K];
+    int started = 0;
+    auto guarded = [&failed](auto &task) {
+      try {
+        task();
+      } catch (...) {
+        failed = true;
+      }
+    };
+    try {
+      ((th[started] = std::thread([&guarded, &rest] { guarded(rest); }), ++started), ...);
+    } catch (const std::system_error &) {
+    }
+    guarded(first);
+    for (int k = 0; k < started; ++k) th[k].join();
+    // tasks that did not get a thread run here
+    int k = 0;
+    ((k++ >= started ? guarded(rest) : void()), ...);
+    if (failed) throw std::bad_alloc();
+    return;
+  }
+  first();
+  (rest(), ...);
+}
 
 struct Builder : Work {
   const int64_t *parent;
@@ -349,10 +388,11 @@ struct Builder : Work {
       if (o.kind == OP_ABSORB) P.n_absorb++;
     }
 
-    // ---- contraction levels: sort by (level, kind), stable in creation order
-    int32_t L = 0;
-    for (const OpRec &o : raw) L = std::max(L, o.level);
-    {
+    // The four schedules below read only the round records and write disjoint
+    // parts of the plan; for large trees they are built on four threads.
+    auto levels_task = [&] {  // contraction levels: sort by (level, kind), stable in creation order
+      int32_t L = 0;
+      for (const OpRec &o : raw) L = std::max(L, o.level);
       count.assign((size_t)L * 4 + 1, 0);
       for (const OpRec &o : raw) count[(size_t)(o.level - 1) * 4 + o.kind + 1]++;
       for (size_t t = 1; t < count.size(); ++t) count[t] += count[t - 1];
@@ -364,11 +404,9 @@ struct Builder : Work {
       P.kind_off.resize((size_t)L * 5);
       for (int32_t t = 0; t < L; ++t)
         for (int s = 0; s <= 4; ++s) P.kind_off[(size_t)t * 5 + s] = count[(size_t)t * 4 + s];
-    }
-
-    // ---- expansion of compressions (reverse graph): level = 1 + level of the child's value
-    {
-      std::vector<int32_t> &eP = lvl_tmp;
+    };
+    auto expand_task = [&] {  // expansion of compressions (reverse graph): level = 1 + level of the child's value
+      std::vector<int32_t> &eP = lvl_e;
       eP.assign(N, 0);
       int32_t LE = 0;
       for (auto it = removal_seq.rbegin(); it != removal_seq.rend(); ++it) {
@@ -384,13 +422,12 @@ struct Builder : Work {
         if (rem_kind[j] == 2) P.exp_off[eP[j]]++;
       for (int32_t t = 0; t < LE; ++t) P.exp_off[t + 1] += P.exp_off[t];
       P.exp_ops.resize((size_t)P.exp_off[LE]);
-      fill.assign(P.exp_off.begin(), P.exp_off.end() - 1);
+      fill_e.assign(P.exp_off.begin(), P.exp_off.end() - 1);
       for (int32_t j : removal_seq)
-        if (rem_kind[j] == 2) P.exp_ops[fill[eP[j] - 1]++] = Op4{j, comp_r[j], comp_k[j], 0};
-    }
-    // ---- composition of edge maps over compressions only
-    {
-      std::vector<int32_t> &lT = lvl_tmp;
+        if (rem_kind[j] == 2) P.exp_ops[fill_e[eP[j] - 1]++] = Op4{j, comp_r[j], comp_k[j], 0};
+    };
+    auto compose_task = [&] {  // composition of edge maps over compressions only
+      std::vector<int32_t> &lT = lvl_t;
       lT.assign(next_slot, 0);
       int32_t LT = 0;
       seq.clear();
@@ -404,12 +441,11 @@ struct Builder : Work {
       for (const Op4 &q : seq) P.tc_off[lT[q.c]]++;
       for (int32_t t = 0; t < LT; ++t) P.tc_off[t + 1] += P.tc_off[t];
       P.tc_ops.resize((size_t)P.tc_off[LT]);
-      fill.assign(P.tc_off.begin(), P.tc_off.end() - 1);
-      for (const Op4 &q : seq) P.tc_ops[fill[lT[q.c] - 1]++] = q;
-    }
-    // ---- state expansion: x_j from the state of its parent at removal time
-    {
-      std::vector<int32_t> &eX = lvl_tmp;
+      fill_t.assign(P.tc_off.begin(), P.tc_off.end() - 1);
+      for (const Op4 &q : seq) P.tc_ops[fill_t[lT[q.c] - 1]++] = q;
+    };
+    auto state_task = [&] {  // state expansion: x_j from the state of its parent at removal time
+      std::vector<int32_t> &eX = lvl_x;
       eX.assign(N, 0);
       int32_t LX = 0;
       for (auto it = removal_seq.rbegin(); it != removal_seq.rend(); ++it) {
@@ -421,9 +457,10 @@ struct Builder : Work {
       for (int32_t j : removal_seq) P.sx_off[eX[j]]++;
       for (int32_t t = 0; t < LX; ++t) P.sx_off[t + 1] += P.sx_off[t];
       P.sx_ops.resize((size_t)P.sx_off[LX]);
-      fill.assign(P.sx_off.begin(), P.sx_off.end() - 1);
-      for (int32_t j : removal_seq) P.sx_ops[fill[eX[j] - 1]++] = Op4{j, rem_slot[j], rem_par[j], 0};
-    }
+      fill_x.assign(P.sx_off.begin(), P.sx_off.end() - 1);
+      for (int32_t j : removal_seq) P.sx_ops[fill_x[eX[j] - 1]++] = Op4{j, rem_slot[j], rem_par[j], 0};
+    };
+    run_concurrently(N >= PAR_NODES, levels_task, expand_task, compose_task, state_task);
     return RCR_OK;
   }
 
