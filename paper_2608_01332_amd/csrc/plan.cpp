@@ -638,29 +638,31 @@ int merge_plans(const std::vector<const PlanHost *> &parts, PlanHost &out) {
     out.sx_ops.reserve(n_sx);
   }
   // contraction: level-major, kind-minor, tree order within a (level, kind) group
-  out.lvl_off.assign(1, 0);
-  out.kind_off.resize((size_t)L * 5);
-  for (int64_t lv = 0; lv < L; ++lv) {
-    for (int kind = 0; kind < 4; ++kind) {
-      out.kind_off[(size_t)lv * 5 + kind] = (int64_t)out.ops.size();
-      for (size_t t = 0; t < k; ++t) {
-        const PlanHost &p = *parts[t];
-        if (lv >= p.levels()) continue;
-        for (int64_t i = p.kind_off[(size_t)lv * 5 + kind]; i < p.kind_off[(size_t)lv * 5 + kind + 1]; ++i) {
-          OpRec o = p.ops[i];
-          switch (o.kind) {
-            case OP_RAKE: o.a = node(t, o.a); o.b = slot(t, o.b); o.c = contrib(t, o.c); o.d = node(t, o.d); break;
-            case OP_COMBINE: o.a = contrib(t, o.a); o.b = contrib(t, o.b); o.c = contrib(t, o.c); o.d = node(t, o.d); break;
-            case OP_ABSORB: o.a = node(t, o.a); o.b = contrib(t, o.b); break;
-            default: o.a = node(t, o.a); o.b = slot(t, o.b); o.c = slot(t, o.c); o.d = slot(t, o.d); o.e = node(t, o.e);
+  auto contraction = [&] {
+    out.lvl_off.assign(1, 0);
+    out.kind_off.resize((size_t)L * 5);
+    for (int64_t lv = 0; lv < L; ++lv) {
+      for (int kind = 0; kind < 4; ++kind) {
+        out.kind_off[(size_t)lv * 5 + kind] = (int64_t)out.ops.size();
+        for (size_t t = 0; t < k; ++t) {
+          const PlanHost &p = *parts[t];
+          if (lv >= p.levels()) continue;
+          for (int64_t i = p.kind_off[(size_t)lv * 5 + kind]; i < p.kind_off[(size_t)lv * 5 + kind + 1]; ++i) {
+            OpRec o = p.ops[i];
+            switch (o.kind) {
+              case OP_RAKE: o.a = node(t, o.a); o.b = slot(t, o.b); o.c = contrib(t, o.c); o.d = node(t, o.d); break;
+              case OP_COMBINE: o.a = contrib(t, o.a); o.b = contrib(t, o.b); o.c = contrib(t, o.c); o.d = node(t, o.d); break;
+              case OP_ABSORB: o.a = node(t, o.a); o.b = contrib(t, o.b); break;
+              default: o.a = node(t, o.a); o.b = slot(t, o.b); o.c = slot(t, o.c); o.d = slot(t, o.d); o.e = node(t, o.e);
+            }
+            out.ops.push_back(o);
           }
-          out.ops.push_back(o);
         }
       }
+      out.kind_off[(size_t)lv * 5 + 4] = (int64_t)out.ops.size();
+      out.lvl_off.push_back((int64_t)out.ops.size());
     }
-    out.kind_off[(size_t)lv * 5 + 4] = (int64_t)out.ops.size();
-    out.lvl_off.push_back((int64_t)out.ops.size());
-  }
+  };
   auto merge4 = [&](int64_t levels, const std::vector<Op4> PlanHost::*ops, const std::vector<int64_t> PlanHost::*off,
                     std::vector<Op4> &dst, std::vector<int64_t> &doff, int kind) {
     doff.assign(1, 0);
@@ -684,9 +686,11 @@ int merge_plans(const std::vector<const PlanHost *> &parts, PlanHost &out) {
       doff.push_back((int64_t)dst.size());
     }
   };
-  merge4(LE, &PlanHost::exp_ops, &PlanHost::exp_off, out.exp_ops, out.exp_off, 0);
-  merge4(LT, &PlanHost::tc_ops, &PlanHost::tc_off, out.tc_ops, out.tc_off, 1);
-  merge4(LX, &PlanHost::sx_ops, &PlanHost::sx_off, out.sx_ops, out.sx_off, 2);
+  auto expansion = [&] { merge4(LE, &PlanHost::exp_ops, &PlanHost::exp_off, out.exp_ops, out.exp_off, 0); };
+  auto composition = [&] { merge4(LT, &PlanHost::tc_ops, &PlanHost::tc_off, out.tc_ops, out.tc_off, 1); };
+  auto state = [&] { merge4(LX, &PlanHost::sx_ops, &PlanHost::sx_off, out.sx_ops, out.sx_off, 2); };
+  // the four parts write disjoint arrays of the merged plan
+  run_concurrently(N >= PAR_NODES, contraction, expansion, composition, state);
   return RCR_OK;
 }
 
