@@ -64,7 +64,7 @@ struct Work {
 };
 constexpr int64_t KEEP_NODES = int64_t(1) << 17;
 // Trees from this size on build their four pass schedules on four threads.
-constexpr int64_t PAR_NODES = int64_t(1) << 15;
+constexpr int64_t PAR_NODES = int64_t(1) << 14;
 
 // Runs the tasks, on threads of their own (the first on the caller's) when
 // `parallel` is set and threads can be started, else one after the other.  An
