@@ -170,11 +170,12 @@ def test_workspace_size_scales_linearly():
     assert a.workspace_size(rcr.MIXED32) < a.workspace_size(rcr.FP64) * 1.2
 
 
-def test_batched_plan_is_union_of_remapped_trees():
+@pytest.mark.parametrize("max_nodes", [300, 8000])  # 8000: the merged forest is filled on four threads
+def test_batched_plan_is_union_of_remapped_trees(max_nodes):
     """rcr_batch_plan_create: level t of the forest plan is the union of every tree's
     level t with node/edge/contribution slots offset per tree."""
     rng = np.random.default_rng(31)
-    pars = [w.tree_chainprob(int(rng.integers(1, 300)), float(rng.uniform(0.5, 0.98)), rng) for _ in range(7)]
+    pars = [w.tree_chainprob(int(rng.integers(1, max_nodes)), float(rng.uniform(0.5, 0.98)), rng) for _ in range(7)]
     plans = [rcr.Plan(p, 4, 2) for p in pars]
     B = rcr.Plan.batch(plans)
     st = B.stats()
