@@ -28,30 +28,59 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+METRIC = "tree-LQR nodes/sec vs CPU Riccati at KKT res 1e-8; p50/p99 solve latency"
 
 
-def algorithmic_words(st: dict, n: int, m: int) -> dict:
-    """Algorithmic FP words moved per solve, per kernel class: every primitive
-    reads each operand block once and writes each result block once (s = n^2,
-    t = n m, v = m^2)."""
+def alg_words(st: dict, n: int, m: int) -> dict:
+    """Algorithmic FP words of one factor + solve by primitive, the fixed model
+    of the measurement plan: every primitive reads each operand block once and
+    writes each result block once, symmetric blocks full (s = n^2, t = n m,
+    v = m^2; N nodes, E = N - 1 edges; the plan's op counts)."""
     s, t, v = n * n, n * m, m * m
     N = st["N"]
     E = N - 1
-    R, B, A, C = st["n_rake"], st["n_combine"], st["n_absorb"], st["n_compress"]
+    R, Cb, A, C = st["n_rake"], st["n_combine"], st["n_absorb"], st["n_compress"]
     return {
-        "condense": N * 2 * s + E * (5 * s + 2 * t + v),
-        "quad_contract": R * 6 * s + B * 3 * s + A * 3 * s + C * 10 * s,
-        "quad_expand": C * 6 * s,
-        "local_factor": N * 4 * s + E * (3 * s + 3 * t + 2 * v),
-        "tcompose": C * 3 * s,
-        "rhs_init": N * 2 * n + E * (2 * s + t + 2 * n + m),
-        "aff_contract": R * (s + 4 * n) + (B + A) * 3 * n + C * (s + 4 * n),
-        "aff_expand": C * (s + 4 * n),
-        "local_affine": N * (3 * s + t + v + 3 * n + 2 * m),
-        "state_contract": C * (s + 3 * n),
-        "state_expand": E * (s + 3 * n),
-        "recover": N * (s + 4 * n) + E * (t + n + 2 * m),
+        # factor
+        "condense": E * (5 * s + 2 * t + v),
+        "rake": R * 5 * s, "combine": Cb * 3 * s, "absorb": A * 3 * s, "compress": C * 10 * s,
+        "expand_rake": R * 2 * s, "expand_compress": C * 6 * s,
+        "node_factor": N * 4 * s, "edge_factor": E * (4 * s + 3 * t + 2 * v),
+        # solve
+        "z": E * (2 * s + 2 * t + 2 * n + m),
+        "aff_rake": R * (s + 3 * n), "aff_combine_absorb": (Cb + A) * 3 * n, "aff_compress": C * (3 * s + 4 * n),
+        "aff_expand": R * 2 * n + C * (s + 4 * n),
+        "local": N * (2 * s + 4 * n) + E * (s + t + v + 3 * n + 2 * m),
+        "state_compress": C * (s + 3 * n), "state_expand": E * (s + 3 * n),
+        "u": E * (t + n + 2 * m), "y": N * (s + 3 * n),
     }
+
+
+def io_words(N: int, n: int, m: int) -> int:
+    """Inputs read once and outputs written once: (4s + v + 3t + 4n + 2m) words per node."""
+    s, t, v = n * n, n * m, m * m
+    return N * (4 * s + v + 3 * t + 4 * n + 2 * m)
+
+
+# words per primitive of the quadratic contraction, by op kind (rake, combine, absorb, compress)
+CONTRACT_WORDS = {0: 5, 1: 3, 2: 3, 3: 10}
+
+
+def host_cpu() -> dict:
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": os.cpu_count() or 1, "cpus_available": avail}
 
 
 def kernel_source_sha() -> str:
@@ -93,12 +122,13 @@ def mapping_string(cfg) -> str:
     return ",".join(f"{k}={v}" for k, v in cfg.items()) if isinstance(cfg, dict) else "default"
 
 
-def read_traffic(kernel_class: str, mapping: str):
-    """HBM traffic per launch from the committed rocprofv3 PMC summary, if it was
-    taken on the current kernel source, for the quadratic tail setting of this
-    run's launch mapping (it decides which levels the per-level launches
-    cover; the summary holds one record per setting), else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_class}.txt")
+def read_profile_value(name: str, mapping: str, key: str):
+    """A per-launch figure (HBM bytes, FP64 flops) of the dominant kernel class
+    from a committed rocprofv3 PMC summary, if it was taken on the current
+    kernel source, for the quadratic tail setting of this run's launch mapping
+    (it decides which levels the per-level launches cover; the summary holds one
+    record per setting), else None."""
+    path = os.path.join(ROOT, "profiles", f"{name}.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -111,14 +141,17 @@ def read_traffic(kernel_class: str, mapping: str):
     m = dict(x.split("=", 1) for x in mapping.split(",") if "=" in x)
     try:
         q = int(m["quad_tail_rounds"])
-        return float(kv[f"qtr{1 if q == 0 else q}.hbm_bytes_per_launch"])  # 0 selects the default, 1 at n = 12
+        return float(kv[f"qtr{1 if q == 0 else q}.{key}"])  # 0 selects the default, 1 at n = 12
     except (KeyError, ValueError):
         return None
 
 
 def cpu_baseline(parent, data, seconds: float) -> dict:
+    """The oracle (sequential FP64 tree Riccati, one thread) timed on a bounded
+    sample: repeated whole solves of the same instance for about `seconds`."""
     from oracle import riccati as orc
     N = len(parent)
+    n, m = data["Q"].shape[-1], data["R"].shape[-1]
     runs, t0 = 0, time.perf_counter()
     while True:
         orc.tree_riccati(parent, data)
@@ -126,107 +159,105 @@ def cpu_baseline(parent, data, seconds: float) -> dict:
         el = time.perf_counter() - t0
         if el >= seconds:
             break
-    return {"value": N * runs / el, "unit": "nodes/s", "cores": 1, "kind": "oracle",
-            "sample": f"{runs} sequential FP64 solves of the N={N}, n=12, m=4 instance on 1 thread "
-                      f"({el:.1f} s)"}
+    rec = {"value": N * runs / el, "unit": "nodes/s", "cores": 1, "kind": "oracle",
+           "sample": f"{runs} sequential FP64 solves of the N={N}, n={n}, m={m} instance on 1 thread "
+                     f"({el:.1f} s)", "build": orc.BUILD_FLAGS}
+    rec.update(host_cpu())
+    return rec
 
 
-def bench_batch(args) -> dict:
+def batch_record(args, steps: int, cpu_seconds: float) -> dict:
     """512 independent trees (N log-uniform in [256, 16384], p ~ U(0.8, 0.98), n = 8,
-    m = 3), MIXED32 with one refinement step: one merged launch sequence for the whole
-    batch against one solve per tree, both checked at KKT residual <= 1e-8."""
+    m = 3), MIXED32 with one refinement step: rcr_batch_solve (each tree's own
+    buffers, one merged launch sequence) against one rcr_solve per tree, both at
+    KKT residual <= 1e-8, and the oracle on all host cores."""
     import numpy as np
     import torch
     from paper_2608_01332_amd import rcr
     from paper_2608_01332_amd import workloads as w
     dev = torch.device("cuda:0")
     T = args.trees
+    t0 = time.perf_counter()
     pars, datas = [], []
     for t in range(T):
         p_, d_, spec = w.config_instance(3, tree=t)
         pars.append(p_)
         datas.append(d_)
+    gen_s = time.perf_counter() - t0
     n, m = spec.n, spec.m
-    plans = [rcr.Plan(p_, n, m) for p_ in pars]
     t0 = time.perf_counter()
-    B = rcr.Plan.batch(plans)
+    plans = [rcr.Plan(p_, n, m) for p_ in pars]
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    rcr.batch_prepare(plans)
     merge_ms = (time.perf_counter() - t0) * 1e3
-    Ntot = B.N
-    big = rcr.to_device(rcr.concat_problems(datas), dev)
-    out = rcr.alloc_solution(B, dev)
+    Ntot = sum(len(p_) for p_ in pars)
+    probs = [rcr.to_device(d_, dev) for d_ in datas]
+    outs = [rcr.alloc_solution(p_, dev) for p_ in plans]
     stream = torch.cuda.current_stream(dev)
     kw = dict(precision=rcr.MIXED32, refine_steps=1, executor=rcr.EXEC_GRAPH)
+    chk = rcr.batch_solve(plans, probs, outs, check=True, kkt_residual=True, **kw)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-
-    def time_batched():
-        for _ in range(args.warmup):
-            rcr.solve(B, big, out=out, **kw)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for _ in range(args.steps):
-            rcr.solve(B, big, out=out, stream=stream, **kw)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / args.steps
-
-    default_ms = time_batched()
-    # the launch mapping of the narrow levels, autotuned on this batch (untimed)
-    t0 = time.perf_counter()
-    tuned_cfg, _ = B.tune(big, out=out, precision=rcr.MIXED32, refine_steps=1)
-    tune_s = time.perf_counter() - t0
-    chk = rcr.solve(B, big, out=out, check=True, kkt_residual=True, **kw)
-    batched_ms = time_batched()
-    # one solve per tree, on views of the same device arrays
-    offs = B.offsets
-    views = []
-    worst = 0.0
-    for t, p_ in enumerate(plans):
-        lo, hi = int(offs[t]), int(offs[t + 1])
-        pv = {k: big[k][lo:hi] for k in rcr.PROBLEM_FIELDS}
-        ov = {k: out[k][lo:hi] for k in rcr.SOLUTION_FIELDS}
-        views.append((p_, pv, ov))
-        r = rcr.solve(p_, pv, out=ov, check=True, kkt_residual=True, **kw)
-        worst = max(worst, r["kkt_residual"])
-    for p_, pv, ov in views:
-        rcr.solve(p_, pv, out=ov, **kw)
+    for _ in range(2):
+        rcr.batch_solve(plans, probs, outs, **kw)
     torch.cuda.synchronize()
-    reps = max(1, args.steps // 4)
+    e0.record(stream)
+    for _ in range(steps):
+        rcr.batch_solve(plans, probs, outs, stream=stream, **kw)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    batched_ms = e0.elapsed_time(e1) / steps
+    # one solve per tree (each tree's own plan, launch sequence and buffers)
+    worst = 0.0
+    for p_, pr, ou in zip(plans, probs, outs):
+        r = rcr.solve(p_, pr, out=ou, check=True, kkt_residual=True, **kw)
+        worst = max(worst, r["kkt_residual"])
+    torch.cuda.synchronize()
+    reps = max(1, steps // 4)
     e0.record(stream)
     for _ in range(reps):
-        for p_, pv, ov in views:
-            rcr.solve(p_, pv, out=ov, stream=stream, **kw)
+        for p_, pr, ou in zip(plans, probs, outs):
+            rcr.solve(p_, pr, out=ou, stream=stream, **kw)
     e1.record(stream)
     torch.cuda.synchronize()
     separate_ms = e0.elapsed_time(e1) / reps
-    st = B.stats()
-    rec = {
-        "metric": "tree-LQR nodes/sec vs CPU Riccati at KKT res 1e-8; p50/p99 solve latency",
-        "value": Ntot / (batched_ms / 1e3), "unit": "nodes/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": batched_ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32+f64-refine", "data": "synthetic",
-        "config": {"workload": f"{T} trees, N log-uniform [256,16384], p~U(0.8,0.98), n=8, m=3, MIXED32 + 1 "
-                               "refinement, one merged launch sequence", "trees": T, "nodes": int(Ntot),
-                   "levels": st["levels"], "height_max": st["height"]},
-        "kkt_residual_batched": chk["kkt_residual"], "kkt_residual_separate_max": worst,
-        "separate_ms_per_step": separate_ms, "separate_nodes_per_s": Ntot / (separate_ms / 1e3),
-        "batched_speedup": separate_ms / batched_ms, "merge_plan_ms": merge_ms,
-        "launch_mapping": {"tuned": tuned_cfg, "tune_s": tune_s, "default_ms_per_step": default_ms,
-                           "tuned_ms_per_step": batched_ms},
-    }
-    if args.cpu_seconds > 0:
+    rec = {"workload": f"{T} trees, N log-uniform [256,16384], p~U(0.8,0.98), n=8, m=3, MIXED32 + 1 refinement",
+           "trees": T, "nodes": int(Ntot), "nodes_per_s": Ntot / (batched_ms / 1e3), "ms_per_batch": batched_ms,
+           "separate_ms": separate_ms, "separate_nodes_per_s": Ntot / (separate_ms / 1e3),
+           "speedup": separate_ms / batched_ms, "kkt_residual_batched": chk["kkt_residual"],
+           "kkt_residual_separate_max": worst, "steps": steps, "merge_plan_ms": merge_ms, "plan_ms": plan_ms,
+           "generate_s": gen_s}
+    if cpu_seconds > 0:
         from oracle import riccati as orc
-        nth = min(16, os.cpu_count() or 1)
+        nth = min(16, host_cpu()["cpus_available"])
         tt0 = time.perf_counter()
         done, nodes = 0, 0
-        while time.perf_counter() - tt0 < args.cpu_seconds and done < T:
+        while time.perf_counter() - tt0 < cpu_seconds and done < T:
             chunk = list(zip(pars[done:done + 32], datas[done:done + 32]))
             orc.tree_riccati_batch(chunk, nth)
             nodes += sum(len(p_) for p_, _ in chunk)
             done += len(chunk)
         el = time.perf_counter() - tt0
-        rec["cpu_baseline"] = {"value": nodes / el, "unit": "nodes/s", "cores": nth, "kind": "oracle",
-                               "sample": f"first {done} of the {T} trees ({nodes} nodes), FP64, {nth} threads, {el:.1f} s"}
+        cb = {"value": nodes / el, "unit": "nodes/s", "cores": nth, "kind": "oracle",
+              "sample": f"first {done} of the {T} trees ({nodes} nodes), FP64, {nth} threads, {el:.1f} s"}
+        cb.update(host_cpu())
+        rec["cpu_baseline"] = cb
+    for p_ in plans:
+        p_.close()
+    del probs, outs
+    torch.cuda.empty_cache()
     return rec
+
+
+def bench_batch(args) -> dict:
+    rec = batch_record(args, args.steps, args.cpu_seconds)
+    out = {"metric": METRIC, "value": rec["nodes_per_s"], "unit": "nodes/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": 2, "ms_per_step": rec["ms_per_batch"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32+f64-refine", "data": "synthetic",
+           "config": {"workload": rec["workload"] + ", one rcr_batch_solve", "trees": rec["trees"],
+                      "nodes": rec["nodes"]}}
+    out.update({k: v for k, v in rec.items() if k not in ("workload", "trees", "nodes")})
+    return out
 
 
 def bench_extreme(args) -> dict:
@@ -335,6 +366,52 @@ def run_serving(specs, pars, pool, dev, slots: int, batching: bool, budget: int,
     return reqs, wall, groups, stats
 
 
+def serve_rate(rate: float, specs, pool, dev, args, mode: str = "continuous", sample: int = 97) -> dict:
+    """One rate of the serving stream: latency percentiles, throughput, grouping,
+    and (continuous mode) sampled results checked against the same request
+    solved alone."""
+    import numpy as np
+    import torch
+    from paper_2608_01332_amd import rcr
+    from paper_2608_01332_amd import workloads as w
+    pars = {}
+    for e in specs:
+        if e["topo"] not in pars:
+            pars[e["topo"]] = w.serve_tree(e)
+    slots, batching = (4, True) if mode == "continuous" else (1, False)
+    if mode != "continuous":
+        sample = 0
+    reqs, wall, groups, hstats = run_serving(specs, pars, pool, dev, slots, batching, args.hbm_budget_gib << 30,
+                                             args.planner_threads, sample_every=sample)
+    lat = np.array([(r.t_done - r.arrival) * 1e3 for r in reqs])
+    nodes = sum(r.N for r in reqs)
+    row = {"rate_per_s": rate, "mode": mode, "slots": slots, "requests": len(reqs),
+           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "mean_ms": float(lat.mean()), "nodes_per_s": nodes / wall, "solves_per_s": len(reqs) / wall,
+           "groups": groups, "mean_group": len(reqs) / max(groups, 1),
+           "plan_cache_hits": float(np.mean([r.cache_hit for r in reqs])),
+           "host_s": {k: round(v, 3) for k, v in hstats.items()}, "wall_s": wall}
+    if sample:
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()  # the run's cached group buffers
+        worst_diff, worst_kkt = 0.0, 0.0
+        for r in reqs:
+            if not r.out:
+                continue
+            plan = rcr.Plan(r.parent, r.n, r.m)
+            alone = rcr.solve(plan, r.prob, precision=rcr.MIXED32, refine_steps=1, kkt_residual=True)
+            for k in rcr.SOLUTION_FIELDS:
+                worst_diff = max(worst_diff, float((alone[k] - r.out[k]).abs().max()))
+            worst_kkt = max(worst_kkt, alone["kkt_residual"])
+            r.out = {}
+        row["sampled"] = sum(1 for r in reqs if r.rid % sample == 0)
+        row["max_abs_diff_alone_vs_mix"] = worst_diff
+        row["max_kkt_residual"] = worst_kkt
+    del reqs
+    torch.cuda.empty_cache()
+    return row
+
+
 def bench_serve(args) -> dict:
     """Serving stream: Poisson arrivals (rates swept) of tree-LQR solves with N
     log-uniform in [1k, 128k], n in {4, 8, 12, 16}, m in {2, 4}, p ~ U(0.85, 0.97),
@@ -342,9 +419,7 @@ def bench_serve(args) -> dict:
     with new data; admitted by HBM footprint into 4 stream slots with continuous
     batching.  Latency from arrival to completion, planning of cache misses
     included; the request data is resident in HBM when it arrives."""
-    import numpy as np
     import torch
-    from paper_2608_01332_amd import rcr
     from paper_2608_01332_amd import workloads as w
     dev = torch.device("cuda:0")
     rates = [float(x) for x in args.rates.split(",")]
@@ -356,50 +431,16 @@ def bench_serve(args) -> dict:
     t_gen = time.perf_counter()
     pool = _serve_pool([e for _, sp in streams for e in sp], dev)
     print(f"[serve] data pool {len(pool)} blocks in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
-    budget = args.hbm_budget_gib << 30
     rows = []
     for ri, (rate, specs) in enumerate(streams):
-        pars = {}
-        for e in specs:
-            if e["topo"] not in pars:
-                pars[e["topo"]] = w.serve_tree(e)
-        modes = [("continuous", 4, True)] + ([("fifo", 1, False)] if rate in args.fifo_rates else [])
-        for mode, slots, batching in modes:
-            sample = 97 if mode == "continuous" else 0
-            reqs, wall, groups, hstats = run_serving(specs, pars, pool, dev, slots, batching, budget,
-                                                     args.planner_threads, sample_every=sample)
-            lat = np.array([(r.t_done - r.arrival) * 1e3 for r in reqs])
-            nodes = sum(r.N for r in reqs)
-            row = {"rate_per_s": rate, "mode": mode, "slots": slots, "requests": len(reqs),
-                   "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                   "mean_ms": float(lat.mean()), "nodes_per_s": nodes / wall, "solves_per_s": len(reqs) / wall,
-                   "groups": groups, "mean_group": len(reqs) / max(groups, 1),
-                   "plan_cache_hits": float(np.mean([r.cache_hit for r in reqs])),
-                   "host_s": {k: round(v, 3) for k, v in hstats.items()}, "wall_s": wall}
-            if sample:
-                torch.cuda.synchronize()
-                torch.cuda.empty_cache()  # the run's cached group buffers
-                # each sampled result against the same request solved alone
-                worst_diff, worst_kkt = 0.0, 0.0
-                for r in reqs:
-                    if not r.out:
-                        continue
-                    plan = rcr.Plan(r.parent, r.n, r.m)
-                    alone = rcr.solve(plan, r.prob, precision=rcr.MIXED32, refine_steps=1, kkt_residual=True)
-                    for k in rcr.SOLUTION_FIELDS:
-                        worst_diff = max(worst_diff, float((alone[k] - r.out[k]).abs().max()))
-                    worst_kkt = max(worst_kkt, alone["kkt_residual"])
-                    r.out = {}
-                row["sampled"] = sum(1 for r in reqs if r.rid % sample == 0)
-                row["max_abs_diff_alone_vs_mix"] = worst_diff
-                row["max_kkt_residual"] = worst_kkt
+        modes = ["continuous"] + (["fifo"] if rate in args.fifo_rates else [])
+        for mode in modes:
+            row = serve_rate(rate, specs, pool, dev, args, mode)
             rows.append(row)
             print(f"[serve] {json.dumps(row)}", file=sys.stderr, flush=True)
-            del reqs
-            torch.cuda.empty_cache()
     cont = [r for r in rows if r["mode"] == "continuous"]
     best = max(cont, key=lambda r: r["nodes_per_s"])
-    return {"metric": "tree-LQR nodes/sec vs CPU Riccati at KKT res 1e-8; p50/p99 solve latency",
+    return {"metric": METRIC,
             "value": best["nodes_per_s"], "unit": "nodes/s", "n_gpus": 1, "steps": sum(r["requests"] for r in cont),
             "warmup": 0, "ms_per_step": best["mean_ms"], "p50_ms": best["p50_ms"], "p99_ms": best["p99_ms"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64-refine",
@@ -482,6 +523,10 @@ def main() -> int:
                          "serve: the request stream at swept arrival rates; lift: the node-control variant through the lifting")
     ap.add_argument("--resolves", type=int, default=8)
     ap.add_argument("--trees", type=int, default=512)
+    ap.add_argument("--no-batch", action="store_true", help="single workload: skip the batched sub-record")
+    ap.add_argument("--no-serve", action="store_true", help="single workload: skip the serving sub-record")
+    ap.add_argument("--serve-rate", type=float, default=1000.0, help="arrival rate of the serving sub-record")
+    ap.add_argument("--serve-requests", type=int, default=10000, help="requests of the serving sub-record")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: measures one GPU only; --gpus {args.gpus} is not supported "
@@ -535,6 +580,7 @@ def main() -> int:
     # accuracy at the measured configuration (outside the timed region)
     chk = rcr.solve(plan, prob, out=out, executor=ex, check=True, kkt_residual=True)
     kkt = chk["kkt_residual"]
+    fp64_out = {k: v.cpu().numpy() for k, v in out.items()}
 
     for _ in range(args.warmup):
         rcr.solve(plan, prob, out=out, executor=ex)
@@ -565,28 +611,31 @@ def main() -> int:
             cls_ms[k] = cls_ms.get(k, 0.0) + v
             cls_n[k] = cls_n.get(k, 0) + r["kernel_launches"][k]
     reps = max(1, args.class_steps)
-    words = algorithmic_words(st, n, m)
-    # The per-level quadratic contraction launches cover levels 1..k (k = their launch
-    # count); the narrow levels after them run in the tail kernel.  Its algorithmic
-    # bytes are those of the ops in its own levels.
+    words = alg_words(st, n, m)
+    b_alg = sum(words.values()) * 8
+    b_io = io_words(N, n, m) * 8
+    # Dominant kernel class: the per-level quadratic contraction launches, which
+    # cover levels 1..k (k = their launch count; the narrow levels after them run
+    # in the tail kernel).  Its algorithmic bytes are those of the ops in its own
+    # levels, at the fixed words per primitive (rake 5s, combine 3s, absorb 3s,
+    # compress 10s; a rake's expansion P_j = U_j, fused into it, is not counted).
     ops = plan.export_ops()
     k_q = cls_n.get("quad_contract", 0) // reps
     sel = ops[ops[:, 2] <= k_q]
-    s_, per_kind = n * n, {0: 6, 1: 3, 2: 3, 3: 10}
-    words_q = sum(int((sel[:, 0] == kind).sum()) * mult * s_ for kind, mult in per_kind.items())
-    measured = dict(words)
-    measured["quad_contract"] = words_q
-    dom = max(measured, key=lambda k: cls_ms.get(k, 0.0))
+    words_q = sum(int((sel[:, 0] == kind).sum()) * mult * n * n for kind, mult in CONTRACT_WORDS.items())
+    dom = "quad_contract"
     dom_ms = cls_ms[dom] / reps
     dom_launches = cls_n[dom] / reps
-    bytes_per_solve = measured[dom] * 8
+    bytes_per_solve = words_q * 8
     achieved = bytes_per_solve / (dom_ms / 1e3) / 1e9
-    traffic = read_traffic(dom, mapping_string(tuned))
-    total_words = sum(words.values())
+    mapping = mapping_string(tuned)
+    traffic = read_profile_value("traffic_quad_contract", mapping, "hbm_bytes_per_launch")
+    flops = read_profile_value("flops_quad_contract", mapping, "fp64_flops_per_launch")
     class_sum_ms = sum(cls_ms.values()) / reps
+    avg_launch_s = dom_ms / 1e3 / dom_launches
 
     rec = {
-        "metric": "tree-LQR nodes/sec vs CPU Riccati at KKT res 1e-8; p50/p99 solve latency",
+        "metric": METRIC,
         "value": value,
         "unit": "nodes/s",
         "n_gpus": 1,
@@ -610,15 +659,26 @@ def main() -> int:
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                      "traffic": traffic,
                      "bytes_per_launch": bytes_per_solve / dom_launches,
-                     "avg_launch_us": dom_ms * 1e3 / dom_launches,
-                     "launches_per_step": dom_launches},
-        "solve_alg_bytes": total_words * 8,
-        "solve_alg_frac": total_words * 8 / (ms_per_step / 1e3) / 1e9 / PEAK_HBM_GBS,
+                     "avg_launch_us": avg_launch_s * 1e6,
+                     "launches_per_step": dom_launches,
+                     "fp64_tflops": (flops / avg_launch_s / 1e12) if flops is not None else None,
+                     "fp64_peak_tflops": PEAK_FP64_TFLOPS,
+                     "fp64_flop_frac": (flops / avg_launch_s / 1e12 / PEAK_FP64_TFLOPS) if flops is not None else None},
+        "headline": {"B_alg_bytes": b_alg, "B_alg_frac": b_alg / (ms_per_step / 1e3) / 1e9 / PEAK_HBM_GBS,
+                     "B_io_bytes": b_io, "B_io_frac": b_io / (ms_per_step / 1e3) / 1e9 / PEAK_HBM_GBS,
+                     "dominant_class_frac": achieved / PEAK_HBM_GBS},
         "kernel_ms_per_step": {k: round(v / reps, 4) for k, v in cls_ms.items()},
+        "kernel_launches_per_step": {k: v // reps for k, v in cls_n.items() if v},
         "kernel_sum_ms_per_step": class_sum_ms,
         "plan_ms": plan_s * 1e3,
         "wall_ms_per_step": wall * 1e3 / args.steps,
     }
+    oracle_ref = None
+    if args.cpu_seconds > 0:
+        from oracle import riccati as orc
+        oracle_ref = orc.tree_riccati(parent, data)
+        rec["rel_err_vs_oracle"] = {k: float(np.abs(fp64_out[k] - oracle_ref[k]).max() /
+                                             max(np.abs(oracle_ref[k]).max(), 1e-300)) for k in rcr.SOLUTION_FIELDS}
     if not args.no_mixed:
         # the same workload in MIXED32: float32 factor/solves (float64 R/G Cholesky and
         # compress solves), one refinement step on the float64 KKT residual
@@ -636,20 +696,38 @@ def main() -> int:
         torch.cuda.synchronize()
         mms = [mev[k].elapsed_time(mev[k + 1]) for k in range(args.steps)]
         mtot = mev[0].elapsed_time(mev[-1])
-        rel = {}
-        for k in rcr.SOLUTION_FIELDS:
-            a, b = mout[k], out[k]
-            rel[k] = float((a - b).abs().max() / b.abs().max().clamp_min(1e-300))
-        rec["mixed32"] = {"value": N * args.steps / (mtot / 1e3), "unit": "nodes/s",
-                          "ms_per_step": mtot / args.steps, "p50_ms": float(np.percentile(mms, 50)),
-                          "p99_ms": float(np.percentile(mms, 99)), "refine_steps": 1,
-                          "kkt_residual": chk["kkt_residual"], "rel_err_vs_fp64": rel}
+        mrec = {"value": N * args.steps / (mtot / 1e3), "unit": "nodes/s",
+                "ms_per_step": mtot / args.steps, "p50_ms": float(np.percentile(mms, 50)),
+                "p99_ms": float(np.percentile(mms, 99)), "refine_steps": 1,
+                "kkt_residual": chk["kkt_residual"]}
+        if oracle_ref is not None:
+            mrec["rel_err_vs_oracle"] = {
+                k: float(np.abs(mout[k].cpu().numpy() - oracle_ref[k]).max() / max(np.abs(oracle_ref[k]).max(), 1e-300))
+                for k in rcr.SOLUTION_FIELDS}
+        rec["mixed32"] = mrec
+        del mout
     if args.cpu_seconds > 0:
         cb = cpu_baseline(parent, data, args.cpu_seconds)
         rec["cpu_baseline"] = cb
         rec["speedup_vs_cpu_oracle"] = value / cb["value"]
     else:
         rec["cpu_baseline"] = None
+    del prob, out
+    plan.close()
+    torch.cuda.empty_cache()
+    if not args.no_batch:
+        print("[bench] batched workload", file=sys.stderr, flush=True)
+        rec["batch"] = batch_record(args, max(3, args.steps // 4), min(args.cpu_seconds, 8.0))
+    if not args.no_serve:
+        print("[bench] serving workload", file=sys.stderr, flush=True)
+        specs = w.serve_requests(args.serve_requests, args.serve_rate, seed=w.config_seed(5, 0, 3))
+        t_gen = time.perf_counter()
+        pool = _serve_pool(specs, dev)
+        row = serve_rate(args.serve_rate, specs, pool, dev, args)
+        row["data_pool_s"] = time.perf_counter() - t_gen - row["wall_s"]
+        rec["serve"] = row
+        del pool
+        torch.cuda.empty_cache()
     print(json.dumps(rec), flush=True)
     return 0
 

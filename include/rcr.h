@@ -92,7 +92,17 @@ typedef struct {
   int64_t workspace_bytes_fp64;  /* device scratch of one FP64 solve                    */
   int64_t workspace_bytes_mixed; /* device scratch of one MIXED32 solve                 */
   int64_t n_trees;               /* 1, or the number of trees of a batched plan         */
+  int64_t plan_device_bytes;     /* bytes of the plan's device copy (made by the first  */
+                                 /* solve or rcr_plan_upload), whether made yet or not  */
+  int64_t graph_cache_entries;   /* captured launch sequences the plan holds (at most   */
+                                 /* RCR_GRAPH_CACHE_CAP of each of its two caches)      */
 } rcr_plan_stats;
+
+/* Captured launch sequences (RCR_EXEC_GRAPH) are cached per plan under the
+ * buffer addresses they were captured with, at most this many per cache; the
+ * least recently used is destroyed, once its own latest replay has completed,
+ * to make room. */
+#define RCR_GRAPH_CACHE_CAP 8
 
 /* Build the topology plan of Sec. VII from a HOST parent array (int64, N
  * entries).  Host-only work: structural rounds, readiness-weighted sibling
@@ -107,6 +117,10 @@ int rcr_plan_create(const int64_t *parent, int64_t N, int32_t n, int32_t m,
 
 /* Summary of a plan (host only).  Errors: RCR_NULL_ARG. */
 int rcr_plan_info(const rcr_plan *plan, rcr_plan_stats *out);
+
+/* Bytes of the plan's device copy (as rcr_plan_stats.plan_device_bytes,
+ * without the plan's other statistics); 0 for NULL. */
+int64_t rcr_plan_device_bytes(const rcr_plan *plan);
 
 /* Copy the plan's primitive operations to HOST arrays, for inspection and
  * tests.  Each op is 8 int32 words:
@@ -217,6 +231,103 @@ int64_t rcr_workspace_size(const rcr_plan *plan, int32_t precision);
  * opt->check is set, RCR_SINGULAR, RCR_NOT_PD, RCR_NONFINITE. */
 int rcr_solve(const rcr_plan *plan, const rcr_problem *in, rcr_solution *out,
               const rcr_solve_options *opt, void *stream);
+
+/* ------------------------------------------- factor once, solve many times */
+/* The factor of Algorithm 1 (Steps 2-3: condensation, the quadratic
+ * contraction and expansion of Sec. IV, the local factors of eqs. (FW),
+ * (factor-local)) does not depend on the right-hand side (q, r, c); Steps 4-6
+ * (the affine and state passes of Sec. V and the recovery eq. (recover)) are
+ * matrix-vector passes on it.  rcr_factor runs Steps 2-3 once; rcr_solve_rhs
+ * then solves any number of right-hand sides on the same matrices. */
+typedef struct {
+  const double *q, *r, *c; /* q[N][n]  r[N][m] (edge slots)  c[N][n]: device, float64 */
+} rcr_rhs;
+
+typedef struct {
+  double *x, *u, *lam;     /* x[N][n]  u[N][m] (edge slots)  lam[N][n]: device, float64 */
+} rcr_rhs_solution;
+
+/* Factor the matrices of `in` (Q, Delta, R, S, A, B; q, r and c are not read)
+ * on `stream`.  Writes out->K and out->P (out->x, u, lam are not touched) and
+ * keeps the rest of the factor (W, F^-1, G^-1, A^cl and the composite
+ * transitions of every compression) in the workspace: opt->workspace when
+ * given (at least rcr_workspace_size(plan, precision) bytes), else the
+ * plan-owned workspace of opt->precision.  The factor stays valid until the
+ * next rcr_factor, rcr_solve or rcr_batch_solve that uses the same workspace.
+ * Options as for rcr_solve (opt->kkt_residual is ignored: there is no iterate
+ * yet).  Errors: those of rcr_solve. */
+int rcr_factor(const rcr_plan *plan, const rcr_problem *in, rcr_solution *out, const rcr_solve_options *opt,
+               void *stream);
+
+/* Solve k >= 1 right-hand sides rhs[0..k) on the factor made by rcr_factor
+ * (same plan, precision and workspace; factor->K, factor->P are its outputs;
+ * Delta and B of `in` are read, and in MIXED32 also Q, R, S, A for the
+ * refinement's residual), writing sol[i] for rhs[i], one after the other on
+ * `stream`.  MIXED32 refines each solution with opt->refine_steps correction
+ * solves on the float64 KKT residual.  opt->kkt_residual receives the largest
+ * residual over the k solutions.  Only the solve passes run: no factor-class
+ * kernel is launched.  Errors: those of rcr_solve; RCR_BAD_OPTION when no
+ * workspace is given and the plan has not factored in this precision. */
+int rcr_solve_rhs(const rcr_plan *plan, const rcr_problem *in, const rcr_solution *factor, int32_t k,
+                  const rcr_rhs *rhs, rcr_rhs_solution *sol, const rcr_solve_options *opt, void *stream);
+
+/* Gradients of a scalar loss L(x, u, lam) of the solution with respect to the
+ * problem data (sensitivity / reverse-mode differentiation through the solve;
+ * the paper checks differentiation through a right-hand side, Sec. IX-A).
+ * The KKT matrix of eq. (kkt) is symmetric, so the adjoint system is the same
+ * system: with seed = (dL/dx, dL/du, dL/dlam) passed as (q, r, c) of an
+ * rcr_rhs, rcr_adjoint solves it on the factor (as rcr_solve_rhs) and writes
+ *   grad->q = dL/dq, grad->r = dL/dr, grad->c = dL/dc   (required)
+ * and, for each of grad->Q, Delta, R, S, A, B that is not NULL, the gradient
+ * with respect to that array (unsymmetrised outer products; the root's edge
+ * slot is written as zero).  `fwd` holds the factor's K, P and the forward
+ * solution x, u, lam of the same problem.  Arrays have the layouts of
+ * rcr_problem.  Errors: those of rcr_solve_rhs. */
+typedef struct {
+  double *Q, *q, *c, *Delta, *R, *S, *r, *A, *B;
+} rcr_gradient;
+
+int rcr_adjoint(const rcr_plan *plan, const rcr_problem *in, const rcr_solution *fwd, const rcr_rhs *seed,
+                rcr_gradient *grad, const rcr_solve_options *opt, void *stream);
+
+/* Max-abs residual of eq. (kkt) over all four blocks for the iterate
+ * (sol->x, u, lam) of problem `in` (float64, on `stream`; synchronises).  The
+ * result goes to *opt->kkt_residual (required); a NaN anywhere in the rows
+ * gives +Inf.  opt->workspace, when given, needs 512 bytes.  Errors:
+ * RCR_NULL_ARG, RCR_OOM, RCR_HIP_ERROR, RCR_NO_DEVICE. */
+int rcr_kkt_residual(const rcr_plan *plan, const rcr_problem *in, const rcr_solution *sol,
+                     const rcr_solve_options *opt, void *stream);
+
+/* ------------------------------------------------------- batched solves */
+/* Solve k independent trees with one merged launch sequence (the forest plan
+ * of rcr_batch_plan_create; Sec. VIII suggests batches of equal-shaped
+ * operations).  plans[t] is tree t's plan (all with the same n and m), in[t]
+ * and out[t] its own problem and solution buffers, laid out as for rcr_solve
+ * with that tree's N.  The merged plan is built on the first call for this
+ * sequence of plans (or by rcr_batch_prepare) and cached by the library
+ * (least recently used of 32 dropped; entries holding a destroyed plan are
+ * dropped with it).  The trees' inputs are gathered into staging arrays of
+ * the workspace, solved together, and the outputs scattered back, one launch
+ * each; results equal those of solving each tree alone, bit for bit.  A
+ * caller workspace needs rcr_batch_workspace_size bytes.  Options and errors
+ * as for rcr_solve (opt->kkt_residual: the largest over the trees). */
+int rcr_batch_solve(const rcr_plan *const *plans, int32_t k, const rcr_problem *in, rcr_solution *out,
+                    const rcr_solve_options *opt, void *stream);
+
+/* Build, cache and upload (in the order of `stream`, waiting for the copy)
+ * the merged plan rcr_batch_solve uses for these plans, ahead of the solve.
+ * Errors: those of rcr_batch_plan_create and rcr_plan_upload. */
+int rcr_batch_prepare(const rcr_plan *const *plans, int32_t k, void *stream);
+
+/* Drop the cached merged plan of these plans, if any (its device copy is
+ * released in stream order after its last solve).  For callers whose batches
+ * rarely repeat.  NULL or unknown sequences are ignored. */
+void rcr_batch_release(const rcr_plan *const *plans, int32_t k);
+
+/* Device bytes one rcr_batch_solve of these plans needs in this precision:
+ * the merged plan's solver workspace, the staged inputs and outputs, and the
+ * copy table.  Builds and caches the merged plan if needed; 0 on error. */
+int64_t rcr_batch_workspace_size(const rcr_plan *const *plans, int32_t k, int32_t precision);
 
 /* ------------------------------------------------- node-control problems */
 /* Scenario MPC with one control v_i per non-leaf node, shared by all its

@@ -19,4 +19,8 @@ Contents
               Shannon-Fano-Elias sibling reductions, earliest-start levels).
   algebra     the rake fold and compress composition of Sec. IV-A written
               out literally, for the elimination-identity pins.
+  adjoint     gradients of a scalar loss through the solve: the same solve
+              with the seeds as right-hand side (the KKT matrix of eq. (kkt)
+              is symmetric) and the outer products of each block's place in
+              eq. (kkt).
 """

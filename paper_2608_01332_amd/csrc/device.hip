@@ -150,6 +150,40 @@ void stage_give(char *b) {
 }
 }  // namespace
 
+// Byte sizes of the pieces of a plan's device copy, in their order in the
+// allocation (each piece starts on a 256-byte boundary); returns the total.
+constexpr int PLAN_PIECES = 13;
+static size_t plan_pieces(const PlanHost &h, size_t bytes[PLAN_PIECES], size_t at[PLAN_PIECES]) {
+  const int64_t NC = std::max<int64_t>(h.N, 1);
+  const size_t b[PLAN_PIECES] = {
+      h.ops.size() * sizeof(OpRec),
+      h.exp_ops.size() * sizeof(Op4),
+      h.tc_ops.size() * sizeof(Op4),
+      h.sx_ops.size() * sizeof(Op4),
+      h.parent32.size() * sizeof(int32_t),
+      (size_t)(h.N + 1) * sizeof(int32_t),                   // child offsets
+      (size_t)NC * sizeof(int32_t),                          // child ids
+      (size_t)(h.N / (RES_HUB + 1) + 1) * sizeof(int32_t),  // hubs
+      h.kind_off.size() * sizeof(int64_t),
+      h.exp_off.size() * sizeof(int64_t),
+      h.tc_off.size() * sizeof(int64_t),
+      h.sx_off.size() * sizeof(int64_t),
+      h.lift_plus.size() * sizeof(int32_t),
+  };
+  size_t total = 0;
+  for (int k = 0; k < PLAN_PIECES; ++k) {
+    bytes[k] = b[k];
+    at[k] = total;
+    total = align_up(total + std::max<size_t>(b[k], 16), 256);
+  }
+  return total;
+}
+
+size_t plan_device_bytes(const PlanHost &h) {
+  size_t b[PLAN_PIECES], at[PLAN_PIECES];
+  return plan_pieces(h, b, at);
+}
+
 // The plan's integer arrays live in one device allocation, made and filled in
 // the order of `st` and released in stream order after the last solve that
 // used them (no device-wide synchronisation on destroy).
@@ -162,30 +196,26 @@ int plan_upload(PlanObj &P, hipStream_t st) {
   struct Piece {
     void **dst;
     const void *src;  // nullptr: the child lists, written in place
-    size_t bytes;
   };
+  const Piece pieces[PLAN_PIECES] = {
+      {(void **)&P.dev.ops, h.ops.data()},
+      {(void **)&P.dev.exp_ops, h.exp_ops.data()},
+      {(void **)&P.dev.tc_ops, h.tc_ops.data()},
+      {(void **)&P.dev.sx_ops, h.sx_ops.data()},
+      {(void **)&P.dev.parent, h.parent32.data()},
+      {(void **)&P.dev.child_off, nullptr},
+      {(void **)&P.dev.child_idx, nullptr},
+      {(void **)&P.dev.hubs, nullptr},
+      {(void **)&P.dev.koff, h.kind_off.data()},
+      {(void **)&P.dev.exp_off, h.exp_off.data()},
+      {(void **)&P.dev.tc_off, h.tc_off.data()},
+      {(void **)&P.dev.sx_off, h.sx_off.data()},
+      {(void **)&P.dev.lift_plus, h.lift_plus.data()},
+  };
+  constexpr int NP = PLAN_PIECES;
   const int64_t NC = std::max<int64_t>(h.N, 1);
-  const Piece pieces[] = {
-      {(void **)&P.dev.ops, h.ops.data(), h.ops.size() * sizeof(OpRec)},
-      {(void **)&P.dev.exp_ops, h.exp_ops.data(), h.exp_ops.size() * sizeof(Op4)},
-      {(void **)&P.dev.tc_ops, h.tc_ops.data(), h.tc_ops.size() * sizeof(Op4)},
-      {(void **)&P.dev.sx_ops, h.sx_ops.data(), h.sx_ops.size() * sizeof(Op4)},
-      {(void **)&P.dev.parent, h.parent32.data(), h.parent32.size() * sizeof(int32_t)},
-      {(void **)&P.dev.child_off, nullptr, (size_t)(h.N + 1) * sizeof(int32_t)},
-      {(void **)&P.dev.child_idx, nullptr, (size_t)NC * sizeof(int32_t)},
-      {(void **)&P.dev.hubs, nullptr, (size_t)(h.N / (RES_HUB + 1) + 1) * sizeof(int32_t)},
-      {(void **)&P.dev.koff, h.kind_off.data(), h.kind_off.size() * sizeof(int64_t)},
-      {(void **)&P.dev.exp_off, h.exp_off.data(), h.exp_off.size() * sizeof(int64_t)},
-      {(void **)&P.dev.tc_off, h.tc_off.data(), h.tc_off.size() * sizeof(int64_t)},
-      {(void **)&P.dev.sx_off, h.sx_off.data(), h.sx_off.size() * sizeof(int64_t)},
-      {(void **)&P.dev.lift_plus, h.lift_plus.data(), h.lift_plus.size() * sizeof(int32_t)},
-  };
-  constexpr int NP = sizeof(pieces) / sizeof(pieces[0]);
-  size_t at[NP], total = 0;
-  for (int k = 0; k < NP; ++k) {
-    at[k] = total;
-    total = align_up(total + std::max<size_t>(pieces[k].bytes, 16), 256);
-  }
+  size_t bytes[NP], at[NP];
+  const size_t total = plan_pieces(h, bytes, at);
   const bool pooled = total <= STAGE_BYTES;
   std::unique_ptr<char[]> heap;
   char *stage = nullptr;
@@ -197,9 +227,9 @@ int plan_upload(PlanObj &P, hipStream_t st) {
   }
   if (!stage) return RCR_OOM;
   for (int k = 0; k < NP; ++k) {
-    if (pieces[k].src && pieces[k].bytes) memcpy(stage + at[k], pieces[k].src, pieces[k].bytes);
-    const size_t pad = std::max<size_t>(pieces[k].bytes, 16);
-    if (pieces[k].src && pad > pieces[k].bytes) memset(stage + at[k] + pieces[k].bytes, 0, pad - pieces[k].bytes);
+    if (pieces[k].src && bytes[k]) memcpy(stage + at[k], pieces[k].src, bytes[k]);
+    const size_t pad = std::max<size_t>(bytes[k], 16);
+    if (pieces[k].src && pad > bytes[k]) memset(stage + at[k] + bytes[k], 0, pad - bytes[k]);
   }
   {  // children of each node in increasing id: node i owns cidx[coff[i] .. coff[i + 1])
     int32_t *coff = reinterpret_cast<int32_t *>(stage + at[5]);
@@ -245,15 +275,45 @@ int plan_upload(PlanObj &P, hipStream_t st) {
   return RCR_OK;
 }
 
-void drop_graphs(PlanObj &P) {
-  for (auto &kv : P.graphs) (void)hipGraphExecDestroy(kv.second);
-  P.graphs.clear();
-  for (auto &kv : P.timed) {
-    for (hipGraphExec_t g : kv.second.execs) (void)hipGraphExecDestroy(g);
-    for (hipEvent_t e : kv.second.events) (void)hipEventDestroy(e);
+// A graph is destroyed only after its latest replay has completed (its `done`
+// event, or the event recorded after a timed sequence's last graph).
+static void destroy_graph(GraphEntry &e) {
+  if (e.done) {
+    (void)hipEventSynchronize(e.done);
+    (void)hipEventDestroy(e.done);
   }
+  if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  e = GraphEntry();
+}
+
+static void destroy_timed(TimedGraph &t) {
+  if (!t.events.empty()) (void)hipEventSynchronize(t.events.back());
+  for (hipGraphExec_t g : t.execs) (void)hipGraphExecDestroy(g);
+  for (hipEvent_t e : t.events) (void)hipEventDestroy(e);
+  t = TimedGraph();
+}
+
+// Make room for one more entry in a graph cache: the least recently used
+// entry goes once the cache holds GRAPH_CACHE_CAP entries.
+template <typename Map, typename Destroy>
+static void evict_lru(Map &cache, Destroy destroy) {
+  while (cache.size() >= GRAPH_CACHE_CAP) {
+    auto victim = cache.begin();
+    for (auto it = cache.begin(); it != cache.end(); ++it)
+      if (it->second.tick < victim->second.tick) victim = it;
+    destroy(victim->second);
+    cache.erase(victim);
+  }
+}
+
+void drop_graphs(PlanObj &P) {
+  for (auto &kv : P.graphs) destroy_graph(kv.second);
+  P.graphs.clear();
+  for (auto &kv : P.timed) destroy_timed(kv.second);
   P.timed.clear();
 }
+
+size_t graph_cache_size(const PlanObj &P) { return P.graphs.size() + P.timed.size(); }
 
 void plan_release_device(PlanObj &P) {
   drop_graphs(P);
@@ -261,7 +321,7 @@ void plan_release_device(PlanObj &P) {
   P.events.clear();
   // release after the last solve that used the plan (its completion event), in
   // the order of the default stream, without blocking the host
-  void *ptrs[] = {P.dev.base, P.ws[0], P.ws[1]};
+  void *ptrs[] = {P.dev.base, P.ws[0], P.ws[1], P.resid_buf};
   if (P.last_done) (void)hipStreamWaitEvent(nullptr, P.last_done, 0);
   for (void *p : ptrs)
     if (p) (void)hipFreeAsync(p, nullptr);
@@ -270,6 +330,7 @@ void plan_release_device(PlanObj &P) {
   P.dev = PlanDev();
   P.ws[0] = P.ws[1] = nullptr;
   P.ws_bytes[0] = P.ws_bytes[1] = 0;
+  P.resid_buf = nullptr;
 }
 
 #define RCR_DECL_NB(NBV)                                                                                 \
@@ -319,6 +380,12 @@ static unsigned grid_for(int64_t count) {
 // round trips (one per child for the child terms), not one per entry.  The
 // grid strides over the nodes; each workgroup folds its lanes' maxima and
 // issues one atomic, so the maximum does not serialise on one address.
+
+// Max-abs fold of the residual rows that keeps a NaN: fmax returns its non-NaN
+// operand, so a NaN reaching only some rows would otherwise be dropped.
+__device__ __forceinline__ double fold_max(double a, double b) {
+  return (a != a || b != b) ? INFINITY : fmax(a, b);
+}
 
 // Lanes per node of the residual kernel: 8 when both padded sizes fit (no
 // lane idle at n, m <= 8), else 16.
@@ -382,7 +449,7 @@ __device__ __forceinline__ double residual_rhs(int64_t v, int n, int m, const do
     for (int32_t t = t0; t < t1; ++t) s = child_terms<NB, MB>(cidx[t], n, m, rn, S, u, A, y, s);
   }
   double worst = 0.0;
-  if (r < n) worst = fabs(s);
+  if (r < n) worst = fold_max(worst, fabs(s));
   double t = c[v * n + rn] - x[v * n + rn];
   if (isroot) {
 #pragma unroll
@@ -395,7 +462,7 @@ __device__ __forceinline__ double residual_rhs(int64_t v, int n, int m, const do
     t = dot_n(br, uv, m, t);
   }
   if (r < n) {
-    worst = fmax(worst, fabs(t));
+    worst = fold_max(worst, fabs(t));
     if (rq) {
       rq[v * n + r] = (OT)s;
       rc[v * n + r] = (OT)t;
@@ -410,10 +477,10 @@ __device__ __forceinline__ double residual_rhs(int64_t v, int n, int m, const do
         if (k < n) tu = fma(bx[k], yv[k], fma(sx[k], xp[k], tu));
       tu = dot_n(rx, uv, m, tu);
     }
-    worst = fmax(worst, fabs(tu));
+    worst = fold_max(worst, fabs(tu));
     if (rq) rr_out[v * m + r] = (OT)tu;
   }
-  return (worst == worst) ? worst : INFINITY;
+  return worst;
 }
 
 template <typename OT, int NB, int MB>
@@ -556,234 +623,277 @@ static Bufs<T> make_bufs(PlanObj &P, const WsLayout &L, void *ws, const rcr_prob
   return bf;
 }
 
-// The whole launch sequence of one rcr_solve on `st` (directly, or while a graph is captured).
-static int launch_sequence(PlanObj &P, const rcr_problem &in, const rcr_solution &out, const rcr_solve_options &opt,
-                           const WsLayout &L, void *ws, Timer &tm, hipStream_t st) {
-  const PlanHost &h = P.host;
-  const int64_t Nn = h.N * h.n, Nm = h.N * h.m, Nnn = h.N * h.n * h.n, Nmn = h.N * h.m * h.n;
-  hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, st, ws_status(ws), ws_resid(ws));
-  if (opt.precision == RCR_FP64) {
-    Bufs<double> bf = make_bufs<double>(P, L, ws, in);
-    bf.sq = in.q;
-    bf.sr = in.r;
-    bf.sc = in.c;
-    bf.PW = out.P;
-    bf.Kw = out.K;
-    bf.xw = out.x;
-    bf.uw = out.u;
-    bf.yw = out.lam;
-    int rc = launch_phase<double>(P, bf, tm, st, 0 | RCR_PHASE_FIRST_RHS);
-    if (!rc) rc = launch_phase<double>(P, bf, tm, st, 1 | RCR_PHASE_FIRST_RHS);
-    return rc;
+// Working buffers of a factor (K, P: the caller's float64 outputs) and, when io
+// is given, of the solve of one right-hand side.  Float64 works in the caller's
+// arrays; float32 in the workspace copies (right-hand side, K, P, x, u, lam).
+template <typename T>
+static Bufs<T> bufs_for(PlanObj &P, const WsLayout &L, void *ws, const rcr_problem &in, double *K, double *Pm,
+                        const RhsIO *io) {
+  Bufs<T> bf = make_bufs<T>(P, L, ws, in);
+  if constexpr (sizeof(T) == sizeof(double)) {
+    bf.PW = Pm;
+    bf.Kw = K;
+    if (io) {
+      bf.sq = io->q;
+      bf.sr = io->r;
+      bf.sc = io->c;
+      bf.xw = io->x;
+      bf.uw = io->u;
+      bf.yw = io->lam;
+    }
+  } else {
+    T *base = reinterpret_cast<T *>(ws);
+    bf.sq = base + L.rq;
+    bf.sr = base + L.rr;
+    bf.sc = base + L.rc;
+    bf.PW = base + L.PW;
+    bf.Kw = base + L.Kw;
+    bf.xw = base + L.xw;
+    bf.uw = base + L.uw;
+    bf.yw = base + L.yw;
   }
-  // MIXED32: float32 factor and solves; float64 R/G Cholesky and compress (I + C P) solve
-  // inside the kernels; float64 residual, correction right-hand side and update.
+  return bf;
+}
+
+// The problem a residual or correction sees: the matrices of `in`, the
+// right-hand side (q, r, c) of `io`.
+static rcr_problem with_rhs(const rcr_problem &in, const RhsIO &io) {
+  rcr_problem p = in;
+  p.q = io.q;
+  p.r = io.r;
+  p.c = io.c;
+  return p;
+}
+
+static rcr_solution sol_of(const RhsIO &io, double *K, double *Pm) { return rcr_solution{K, Pm, io.x, io.u, io.lam}; }
+
+// MIXED32: the float32 copy of a right-hand side that the solve passes read.
+static void cast_rhs(PlanObj &P, const WsLayout &L, void *ws, const RhsIO &io, Timer &tm, hipStream_t st) {
+  const PlanHost &h = P.host;
+  const int64_t Nn = h.N * h.n, Nm = h.N * h.m;
   float *base = reinterpret_cast<float *>(ws);
-  Bufs<float> bf = make_bufs<float>(P, L, ws, in);
-  float *rq = base + L.rq, *rr = base + L.rr, *rc_ = base + L.rc;
-  bf.sq = rq;
-  bf.sr = rr;
-  bf.sc = rc_;
-  bf.PW = base + L.PW;
-  bf.Kw = base + L.Kw;
-  bf.xw = base + L.xw;
-  bf.uw = base + L.uw;
-  bf.yw = base + L.yw;
   tm.begin(RCR_K_RESIDUAL);
-  LAUNCH(tm, (k_cast<double, float>), dim3(grid_for(Nn)), dim3(256), 0, st, in.q, rq, Nn);
-  LAUNCH(tm, (k_cast<double, float>), dim3(grid_for(Nm)), dim3(256), 0, st, in.r, rr, Nm);
-  LAUNCH(tm, (k_cast<double, float>), dim3(grid_for(Nn)), dim3(256), 0, st, in.c, rc_, Nn);
-  int rc = launch_phase<float>(P, bf, tm, st, 0 | RCR_PHASE_FIRST_RHS);
-  if (!rc) rc = launch_phase<float>(P, bf, tm, st, 1 | RCR_PHASE_FIRST_RHS);
-  if (rc) return rc;
+  LAUNCH(tm, (k_cast<double, float>), dim3(grid_for(Nn)), dim3(256), 0, st, io.q, base + L.rq, Nn);
+  LAUNCH(tm, (k_cast<double, float>), dim3(grid_for(Nm)), dim3(256), 0, st, io.r, base + L.rr, Nm);
+  LAUNCH(tm, (k_cast<double, float>), dim3(grid_for(Nn)), dim3(256), 0, st, io.c, base + L.rc, Nn);
+}
+
+// MIXED32, after the float32 solve of io's right-hand side: x, u, lam in float64,
+// then `refine` correction solves on the float64 KKT residual of eq. (kkt)
+// (q' = r_x, r' = r_u, c'_root = r_root, c'_j = r_dyn), each reusing the factor.
+static int finish_mixed(PlanObj &P, const rcr_problem &in, const RhsIO &io, int refine, Bufs<float> bf,
+                        const WsLayout &L, void *ws, Timer &tm, hipStream_t st) {
+  const PlanHost &h = P.host;
+  const int64_t Nn = h.N * h.n, Nm = h.N * h.m;
+  float *base = reinterpret_cast<float *>(ws);
   tm.begin(RCR_K_RESIDUAL);
-  LAUNCH(tm, (k_cast<float, double>), dim3(grid_for(Nn)), dim3(256), 0, st, bf.xw, out.x, Nn);
-  LAUNCH(tm, (k_cast<float, double>), dim3(grid_for(Nm)), dim3(256), 0, st, bf.uw, out.u, Nm);
-  LAUNCH(tm, (k_cast<float, double>), dim3(grid_for(Nn)), dim3(256), 0, st, bf.yw, out.lam, Nn);
-  for (int it = 0; it < opt.refine_steps; ++it) {
+  LAUNCH(tm, (k_cast<float, double>), dim3(grid_for(Nn)), dim3(256), 0, st, bf.xw, io.x, Nn);
+  LAUNCH(tm, (k_cast<float, double>), dim3(grid_for(Nm)), dim3(256), 0, st, bf.uw, io.u, Nm);
+  LAUNCH(tm, (k_cast<float, double>), dim3(grid_for(Nn)), dim3(256), 0, st, bf.yw, io.lam, Nn);
+  const rcr_problem pin = with_rhs(in, io);
+  const rcr_solution sol = sol_of(io, nullptr, nullptr);
+  for (int it = 0; it < refine; ++it) {
     tm.begin(RCR_K_RESIDUAL);
     tm.pre();
-    launch_residual_rhs<float>(P, in, out, rq, rr, rc_, ws_resid(ws), st);
+    launch_residual_rhs<float>(P, pin, sol, base + L.rq, base + L.rr, base + L.rc, ws_resid(ws), st);
     tm.post();
-    rc = launch_phase<float>(P, bf, tm, st, 1);
+    const int rc = launch_phase<float>(P, bf, tm, st, 1);
     if (rc) return rc;
     tm.begin(RCR_K_RESIDUAL);
-    LAUNCH(tm, k_accumulate, dim3(grid_for(Nn)), dim3(256), 0, st, bf.xw, out.x, Nn);
-    LAUNCH(tm, k_accumulate, dim3(grid_for(Nm)), dim3(256), 0, st, bf.uw, out.u, Nm);
-    LAUNCH(tm, k_accumulate, dim3(grid_for(Nn)), dim3(256), 0, st, bf.yw, out.lam, Nn);
+    LAUNCH(tm, k_accumulate, dim3(grid_for(Nn)), dim3(256), 0, st, bf.xw, io.x, Nn);
+    LAUNCH(tm, k_accumulate, dim3(grid_for(Nm)), dim3(256), 0, st, bf.uw, io.u, Nm);
+    LAUNCH(tm, k_accumulate, dim3(grid_for(Nn)), dim3(256), 0, st, bf.yw, io.lam, Nn);
   }
-  tm.begin(RCR_K_RESIDUAL);
-  LAUNCH(tm, (k_cast<float, double>), dim3(grid_for(Nmn)), dim3(256), 0, st, bf.Kw, out.K, Nmn);
-  LAUNCH(tm, (k_cast<float, double>), dim3(grid_for(Nnn)), dim3(256), 0, st, bf.PW, out.P, Nnn);
   HIPCK(hipGetLastError());
   return RCR_OK;
 }
 
-int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_options &opt, hipStream_t st) {
-  std::lock_guard<std::mutex> lock(P.mu);
-  int rc = plan_upload(P, st);
-  if (rc) return rc;
-  const int prec = opt.precision;
-  const WsLayout L = workspace_layout(P.host, prec);
-  void *ws = opt.workspace;
-  if (ws) {
-    if ((size_t)opt.workspace_bytes < L.total_bytes) return RCR_SMALL_WORKSPACE;
-  } else {
-    if (!P.ws[prec]) {
-      const size_t nb = total_workspace_bytes(P.host, prec);
-      if (hipMallocAsync(&P.ws[prec], nb, st) != hipSuccess) return RCR_OOM;
-      P.ws_bytes[prec] = nb;
-    }
-    ws = P.ws[prec];
+// MIXED32: the float32 K, P of the factor into the caller's float64 arrays.
+static void cast_factor_out(PlanObj &P, const WsLayout &L, void *ws, double *K, double *Pm, Timer &tm,
+                            hipStream_t st) {
+  const PlanHost &h = P.host;
+  const int64_t Nnn = h.N * h.n * h.n, Nmn = h.N * h.m * h.n;
+  float *base = reinterpret_cast<float *>(ws);
+  tm.begin(RCR_K_RESIDUAL);
+  LAUNCH(tm, (k_cast<float, double>), dim3(grid_for(Nmn)), dim3(256), 0, st, base + L.Kw, K, Nmn);
+  LAUNCH(tm, (k_cast<float, double>), dim3(grid_for(Nnn)), dim3(256), 0, st, base + L.PW, Pm, Nnn);
+}
+
+// The whole launch sequence of one rcr_solve on `st` (directly, or while a
+// graph is captured): the factor and the solve of the problem's own
+// right-hand side, the two phases sharing it (RCR_PHASE_FIRST_RHS).
+static int launch_sequence(PlanObj &P, const rcr_problem &in, const rcr_solution &out, const rcr_solve_options &opt,
+                           const WsLayout &L, void *ws, Timer &tm, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, st, ws_status(ws), ws_resid(ws));
+  const RhsIO io{in.q, in.r, in.c, out.x, out.u, out.lam};
+  if (opt.precision == RCR_FP64) {
+    Bufs<double> bf = bufs_for<double>(P, L, ws, in, out.K, out.P, &io);
+    int rc = launch_phase<double>(P, bf, tm, st, 0 | RCR_PHASE_FIRST_RHS);
+    if (!rc) rc = launch_phase<double>(P, bf, tm, st, 1 | RCR_PHASE_FIRST_RHS);
+    return rc;
   }
-  if (!P.last_done) HIPCK(hipEventCreateWithFlags(&P.last_done, hipEventDisableTiming));
-  Timer tm;
-  tm.P = &P;
-  tm.st = st;
-  tm.on = opt.kernel_ms != nullptr;
-  const bool use_graph = opt.executor == RCR_EXEC_GRAPH;
-  const TimedGraph *tg = nullptr;
-  if (use_graph && tm.on) {
-    // timed replay: one graph per run of same-class launches, HIP events between them
-    GraphKey key;
-    memset(&key, 0, sizeof(key));
-    const void *ptrs[16] = {in.Q, in.q, in.c, in.Delta, in.R, in.S, in.r, in.A, in.B,
-                            out.K, out.P, out.x, out.u, out.lam, ws,
-                            (const void *)(intptr_t)(prec + 4 * opt.refine_steps)};
-    memcpy(key.p, ptrs, sizeof(ptrs));
-    auto it = P.timed.find(key);
-    if (it == P.timed.end()) {
-      struct Cap {
-        hipStream_t cs;
-        TimedGraph rec;
-        int cur = -1;
-        hipError_t err = hipSuccess;
-        void end_run() {  // close the capture of the current run (empty runs are dropped)
-          hipGraph_t g;
-          hipError_t e = hipStreamEndCapture(cs, &g);
-          if (e != hipSuccess) {
-            err = e;
-            return;
-          }
-          size_t nn = 0;
-          if (hipGraphGetNodes(g, nullptr, &nn) == hipSuccess && nn > 0) {
-            hipGraphExec_t ge;
-            e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-            if (e == hipSuccess) {
-              rec.execs.push_back(ge);
-              rec.cls.push_back(cur);
-            } else {
-              err = e;
-            }
-          }
-          (void)hipGraphDestroy(g);
-        }
-        static void split(void *self, int c) {
-          Cap *k = static_cast<Cap *>(self);
-          if (k->err != hipSuccess) return;
-          k->end_run();
-          if (k->err == hipSuccess) k->err = hipStreamBeginCapture(k->cs, hipStreamCaptureModeThreadLocal);
-          k->cur = c;
-        }
-      } cap;
-      HIPCK(hipStreamCreateWithFlags(&cap.cs, hipStreamNonBlocking));
-      hipError_t be = hipStreamBeginCapture(cap.cs, hipStreamCaptureModeThreadLocal);
-      if (be != hipSuccess) {
-        (void)hipStreamDestroy(cap.cs);
-        HIPCK(be);
-      }
-      Timer tc;
-      tc.P = &P;
-      tc.st = cap.cs;
-      tc.on = true;
-      tc.split = &Cap::split;
-      tc.split_arg = &cap;
-      int lrc = launch_sequence(P, in, out, opt, L, ws, tc, cap.cs);
-      if (cap.err == hipSuccess) cap.end_run();
-      (void)hipStreamDestroy(cap.cs);
-      for (int c = 0; c < RCR_NUM_KERNEL_CLASSES; ++c) cap.rec.launches[c] = tc.launches[c];
-      bool ok = !lrc && cap.err == hipSuccess;
-      for (size_t i = 0; ok && i <= cap.rec.execs.size(); ++i) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) ok = false;
-        else cap.rec.events.push_back(e);
-      }
-      if (!ok) {
-        for (hipGraphExec_t g : cap.rec.execs) (void)hipGraphExecDestroy(g);
-        for (hipEvent_t e : cap.rec.events) (void)hipEventDestroy(e);
-        if (lrc) return lrc;
-        HIPCK(cap.err);
-        return RCR_HIP_ERROR;
-      }
-      it = P.timed.emplace(key, cap.rec).first;
+  // MIXED32: float32 factor and solves; float64 R/G Cholesky and compress (I + C P)
+  // solve inside the kernels; float64 residual, correction right-hand side and update.
+  cast_rhs(P, L, ws, io, tm, st);
+  Bufs<float> bf = bufs_for<float>(P, L, ws, in, out.K, out.P, &io);
+  int rc = launch_phase<float>(P, bf, tm, st, 0 | RCR_PHASE_FIRST_RHS);
+  if (!rc) rc = launch_phase<float>(P, bf, tm, st, 1 | RCR_PHASE_FIRST_RHS);
+  if (!rc) rc = finish_mixed(P, in, io, opt.refine_steps, bf, L, ws, tm, st);
+  if (rc) return rc;
+  cast_factor_out(P, L, ws, out.K, out.P, tm, st);
+  HIPCK(hipGetLastError());
+  return RCR_OK;
+}
+
+// Algorithm 1, Steps 2-3 only: the factor stays in the workspace (and in the
+// caller's K, P), ready for any number of right-hand sides.
+static int factor_sequence(PlanObj &P, const rcr_problem &in, double *K, double *Pm, int prec, const WsLayout &L,
+                           void *ws, Timer &tm, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, st, ws_status(ws), ws_resid(ws));
+  if (prec == RCR_FP64) return launch_phase<double>(P, bufs_for<double>(P, L, ws, in, K, Pm, nullptr), tm, st, 0);
+  const int rc = launch_phase<float>(P, bufs_for<float>(P, L, ws, in, K, Pm, nullptr), tm, st, 0);
+  if (rc) return rc;
+  cast_factor_out(P, L, ws, K, Pm, tm, st);
+  HIPCK(hipGetLastError());
+  return RCR_OK;
+}
+
+// Algorithm 1, Steps 4-6 for each of k right-hand sides, in order, on the
+// factor in the workspace (K, Pm: the factor's float64 outputs).
+static int rhs_sequence(PlanObj &P, const rcr_problem &in, const double *K, const double *Pm, int32_t k,
+                        const RhsIO *ios, int prec, int refine, const WsLayout &L, void *ws, Timer &tm,
+                        hipStream_t st) {
+  double *Kd = const_cast<double *>(K), *Pd = const_cast<double *>(Pm);  // read only by the solve passes
+  for (int32_t i = 0; i < k; ++i) {
+    int rc;
+    if (prec == RCR_FP64) {
+      rc = launch_phase<double>(P, bufs_for<double>(P, L, ws, in, Kd, Pd, &ios[i]), tm, st, 1);
+    } else {
+      cast_rhs(P, L, ws, ios[i], tm, st);
+      Bufs<float> bf = bufs_for<float>(P, L, ws, in, Kd, Pd, &ios[i]);
+      rc = launch_phase<float>(P, bf, tm, st, 1);
+      if (!rc) rc = finish_mixed(P, in, ios[i], refine, bf, L, ws, tm, st);
     }
-    tg = &it->second;
-    HIPCK(hipEventRecord(tg->events[0], st));
-    for (size_t i = 0; i < tg->execs.size(); ++i) {
-      HIPCK(hipGraphLaunch(tg->execs[i], st));
-      HIPCK(hipEventRecord(tg->events[i + 1], st));
-    }
-  } else if (use_graph) {
-    GraphKey key;
-    memset(&key, 0, sizeof(key));
-    const void *ptrs[16] = {in.Q, in.q, in.c, in.Delta, in.R, in.S, in.r, in.A, in.B,
-                            out.K, out.P, out.x, out.u, out.lam, ws,
-                            (const void *)(intptr_t)(prec + 4 * opt.refine_steps)};
-    memcpy(key.p, ptrs, sizeof(ptrs));
-    auto it = P.graphs.find(key);
-    if (it == P.graphs.end()) {
-      hipStream_t cs;
-      HIPCK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-      hipGraph_t g;
-      HIPCK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-      Timer off;
-      int lrc = launch_sequence(P, in, out, opt, L, ws, off, cs);
-      hipError_t ce = hipStreamEndCapture(cs, &g);
-      (void)hipStreamDestroy(cs);
-      if (lrc) return lrc;
-      HIPCK(ce);
-      hipGraphExec_t ge;
-      hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      HIPCK(ie);
-      it = P.graphs.emplace(key, ge).first;
-    }
-    HIPCK(hipGraphLaunch(it->second, st));
-  } else {
-    rc = launch_sequence(P, in, out, opt, L, ws, tm, st);
     if (rc) return rc;
   }
+  HIPCK(hipGetLastError());
+  return RCR_OK;
+}
+
+// Replay the launch sequence `seq(timer, stream)` from the plan's graph cache
+// under `key`, capturing it into a graph on a miss.
+template <typename F>
+static int replay_graph(PlanObj &P, const GraphKey &key, hipStream_t st, F &&seq) {
+  auto it = P.graphs.find(key);
+  if (it == P.graphs.end()) {
+    hipStream_t cs;
+    HIPCK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    const hipError_t be = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (be != hipSuccess) {
+      (void)hipStreamDestroy(cs);
+      HIPCK(be);
+    }
+    Timer off;
+    const int lrc = seq(off, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (lrc || ce != hipSuccess) {
+      if (ce == hipSuccess && g) (void)hipGraphDestroy(g);
+      if (lrc) return lrc;
+      HIPCK(ce);
+    }
+    GraphEntry e;
+    const hipError_t ie = hipGraphInstantiate(&e.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCK(ie);
+    if (hipEventCreateWithFlags(&e.done, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGraphExecDestroy(e.exec);
+      return RCR_HIP_ERROR;
+    }
+    evict_lru(P.graphs, destroy_graph);
+    it = P.graphs.emplace(key, e).first;
+  }
+  it->second.tick = ++P.tick;
+  HIPCK(hipGraphLaunch(it->second.exec, st));
+  HIPCK(hipEventRecord(it->second.done, st));
+  return RCR_OK;
+}
+
+static GraphKey key_of(std::initializer_list<const void *> ptrs, int64_t tag) {
+  GraphKey k;
+  k.reserve(ptrs.size() + 1);
+  k.push_back((uintptr_t)tag);
+  for (const void *p : ptrs) k.push_back((uintptr_t)p);
+  return k;
+}
+
+// Device memory of a call: the caller's workspace, or the plan-owned one of
+// this precision (made on first use, in the order of `st`).
+static int take_workspace(PlanObj &P, const rcr_solve_options &opt, size_t need_solver, size_t need_total,
+                          hipStream_t st, void *&ws) {
+  const int prec = opt.precision;
+  ws = opt.workspace;
+  if (ws) {
+    if ((size_t)opt.workspace_bytes < need_solver) return RCR_SMALL_WORKSPACE;
+    return RCR_OK;
+  }
+  if (P.ws[prec] && P.ws_bytes[prec] < need_total) {
+    (void)hipFreeAsync(P.ws[prec], st);
+    P.ws[prec] = nullptr;
+  }
+  if (!P.ws[prec]) {
+    if (hipMallocAsync(&P.ws[prec], need_total, st) != hipSuccess) return RCR_OOM;
+    P.ws_bytes[prec] = need_total;
+  }
+  ws = P.ws[prec];
+  return RCR_OK;
+}
+
+// Device time and launch counts per kernel class from a per-launch Timer.
+static int report_timer(const Timer &tm, const TimedGraph *tg, const rcr_solve_options &opt) {
+  for (int c = 0; c < RCR_NUM_KERNEL_CLASSES; ++c) {
+    opt.kernel_ms[c] = 0.f;
+    if (opt.kernel_launches) opt.kernel_launches[c] = 0;
+  }
+  if (tg) {
+    for (size_t i = 0; i < tg->execs.size(); ++i) {
+      if (tg->cls[i] < 0) continue;
+      float ms = 0.f;
+      HIPCK(hipEventElapsedTime(&ms, tg->events[i], tg->events[i + 1]));
+      opt.kernel_ms[tg->cls[i]] += ms;
+    }
+  }
+  for (auto &sp : tm.spans) {
+    float ms = 0.f;
+    HIPCK(hipEventElapsedTime(&ms, sp.second.first, sp.second.second));
+    opt.kernel_ms[sp.first] += ms;
+  }
+  if (opt.kernel_launches)
+    for (int c = 0; c < RCR_NUM_KERNEL_CLASSES; ++c) opt.kernel_launches[c] = tg ? tg->launches[c] : tm.launches[c];
+  return RCR_OK;
+}
+
+// After a call's launches: optional residual, completion event, optional
+// synchronisation with the status and residual read back.
+static int finish_call(PlanObj &P, void *ws, const rcr_solve_options &opt, Timer &tm, const TimedGraph *tg,
+                       const std::vector<std::pair<rcr_problem, rcr_solution>> &resid_of, hipStream_t st) {
   if (opt.kkt_residual) {
     tm.begin(RCR_K_RESIDUAL);
-    // the residual of the returned iterate (the refinement's accumulator is reset first)
+    // the residual of the returned iterates (the refinement's accumulator is reset first)
     tm.gap();
     hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, st, ws_status(ws) + 8, ws_resid(ws));
-    launch_residual_rhs<double>(P, in, out, nullptr, nullptr, nullptr, ws_resid(ws), st);
+    for (const auto &ps : resid_of)
+      launch_residual_rhs<double>(P, ps.first, ps.second, nullptr, nullptr, nullptr, ws_resid(ws), st);
     HIPCK(hipGetLastError());
   }
+  if (!P.last_done) HIPCK(hipEventCreateWithFlags(&P.last_done, hipEventDisableTiming));
   HIPCK(hipEventRecord(P.last_done, st));
   if (opt.check || opt.kkt_residual || tm.on) {
     HIPCK(hipStreamSynchronize(st));
     if (tm.on) {
-      for (int c = 0; c < RCR_NUM_KERNEL_CLASSES; ++c) {
-        opt.kernel_ms[c] = 0.f;
-        if (opt.kernel_launches) opt.kernel_launches[c] = 0;
-      }
-      if (tg) {
-        for (size_t i = 0; i < tg->execs.size(); ++i) {
-          if (tg->cls[i] < 0) continue;
-          float ms = 0.f;
-          HIPCK(hipEventElapsedTime(&ms, tg->events[i], tg->events[i + 1]));
-          opt.kernel_ms[tg->cls[i]] += ms;
-        }
-      }
-      for (auto &sp : tm.spans) {
-        float ms = 0.f;
-        HIPCK(hipEventElapsedTime(&ms, sp.second.first, sp.second.second));
-        opt.kernel_ms[sp.first] += ms;
-      }
-      if (opt.kernel_launches)
-        for (int c = 0; c < RCR_NUM_KERNEL_CLASSES; ++c) opt.kernel_launches[c] = tg ? tg->launches[c] : tm.launches[c];
+      const int rc = report_timer(tm, tg, opt);
+      if (rc) return rc;
     }
     double resid = 0.0;
     int stw = 0;
@@ -797,6 +907,477 @@ int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_
       if (stw & ST_NONFINITE) return RCR_NONFINITE;
     }
   }
+  return RCR_OK;
+}
+
+// Timed replay (kernel_ms with the graph executor): the sequence is captured
+// as one graph per run of same-class launches, replayed with HIP events
+// between them, so a class's launches run back to back as in a plain replay.
+static int timed_replay(PlanObj &P, const GraphKey &key, const rcr_problem &in, const rcr_solution &out,
+                        const rcr_solve_options &opt, const WsLayout &L, void *ws, hipStream_t st,
+                        const TimedGraph *&tg) {
+  auto it = P.timed.find(key);
+  if (it == P.timed.end()) {
+    struct Cap {
+      hipStream_t cs;
+      TimedGraph rec;
+      int cur = -1;
+      hipError_t err = hipSuccess;
+      void end_run() {  // close the capture of the current run (empty runs are dropped)
+        hipGraph_t g;
+        hipError_t e = hipStreamEndCapture(cs, &g);
+        if (e != hipSuccess) {
+          err = e;
+          return;
+        }
+        size_t nn = 0;
+        if (hipGraphGetNodes(g, nullptr, &nn) == hipSuccess && nn > 0) {
+          hipGraphExec_t ge;
+          e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+          if (e == hipSuccess) {
+            rec.execs.push_back(ge);
+            rec.cls.push_back(cur);
+          } else {
+            err = e;
+          }
+        }
+        (void)hipGraphDestroy(g);
+      }
+      static void split(void *self, int c) {
+        Cap *k = static_cast<Cap *>(self);
+        if (k->err != hipSuccess) return;
+        k->end_run();
+        if (k->err == hipSuccess) k->err = hipStreamBeginCapture(k->cs, hipStreamCaptureModeThreadLocal);
+        k->cur = c;
+      }
+    } cap;
+    HIPCK(hipStreamCreateWithFlags(&cap.cs, hipStreamNonBlocking));
+    const hipError_t be = hipStreamBeginCapture(cap.cs, hipStreamCaptureModeThreadLocal);
+    if (be != hipSuccess) {
+      (void)hipStreamDestroy(cap.cs);
+      HIPCK(be);
+    }
+    Timer tc;
+    tc.P = &P;
+    tc.st = cap.cs;
+    tc.on = true;
+    tc.split = &Cap::split;
+    tc.split_arg = &cap;
+    const int lrc = launch_sequence(P, in, out, opt, L, ws, tc, cap.cs);
+    if (cap.err == hipSuccess) cap.end_run();
+    (void)hipStreamDestroy(cap.cs);
+    for (int c = 0; c < RCR_NUM_KERNEL_CLASSES; ++c) cap.rec.launches[c] = tc.launches[c];
+    bool ok = !lrc && cap.err == hipSuccess;
+    for (size_t i = 0; ok && i <= cap.rec.execs.size(); ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) ok = false;
+      else cap.rec.events.push_back(e);
+    }
+    if (!ok) {
+      for (hipGraphExec_t g : cap.rec.execs) (void)hipGraphExecDestroy(g);
+      for (hipEvent_t e : cap.rec.events) (void)hipEventDestroy(e);
+      if (lrc) return lrc;
+      HIPCK(cap.err);
+      return RCR_HIP_ERROR;
+    }
+    evict_lru(P.timed, destroy_timed);
+    it = P.timed.emplace(key, cap.rec).first;
+  }
+  it->second.tick = ++P.tick;
+  tg = &it->second;
+  HIPCK(hipEventRecord(tg->events[0], st));
+  for (size_t i = 0; i < tg->execs.size(); ++i) {
+    HIPCK(hipGraphLaunch(tg->execs[i], st));
+    HIPCK(hipEventRecord(tg->events[i + 1], st));
+  }
+  return RCR_OK;
+}
+
+int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_options &opt, hipStream_t st) {
+  std::lock_guard<std::mutex> lock(P.mu);
+  int rc = plan_upload(P, st);
+  if (rc) return rc;
+  const int prec = opt.precision;
+  const WsLayout L = workspace_layout(P.host, prec);
+  void *ws = nullptr;
+  if ((rc = take_workspace(P, opt, L.total_bytes, total_workspace_bytes(P.host, prec), st, ws))) return rc;
+  Timer tm;
+  tm.P = &P;
+  tm.st = st;
+  tm.on = opt.kernel_ms != nullptr;
+  const TimedGraph *tg = nullptr;
+  const GraphKey key = key_of({in.Q, in.q, in.c, in.Delta, in.R, in.S, in.r, in.A, in.B, out.K, out.P, out.x,
+                               out.u, out.lam, ws},
+                              1 + 16 * prec + 256 * (int64_t)opt.refine_steps);
+  if (opt.executor == RCR_EXEC_GRAPH && tm.on) {
+    rc = timed_replay(P, key, in, out, opt, L, ws, st, tg);
+  } else if (opt.executor == RCR_EXEC_GRAPH) {
+    rc = replay_graph(P, key, st, [&](Timer &t, hipStream_t cs) { return launch_sequence(P, in, out, opt, L, ws, t, cs); });
+  } else {
+    rc = launch_sequence(P, in, out, opt, L, ws, tm, st);
+  }
+  if (rc) return rc;
+  return finish_call(P, ws, opt, tm, tg, {{in, out}}, st);
+}
+
+int factor(PlanObj &P, const rcr_problem &in, double *K, double *Pm, const rcr_solve_options &opt,
+           hipStream_t st) {
+  std::lock_guard<std::mutex> lock(P.mu);
+  int rc = plan_upload(P, st);
+  if (rc) return rc;
+  const int prec = opt.precision;
+  const WsLayout L = workspace_layout(P.host, prec);
+  void *ws = nullptr;
+  if ((rc = take_workspace(P, opt, L.total_bytes, total_workspace_bytes(P.host, prec), st, ws))) return rc;
+  Timer tm;
+  tm.P = &P;
+  tm.st = st;
+  tm.on = opt.kernel_ms != nullptr;
+  if (opt.executor == RCR_EXEC_GRAPH && !tm.on) {
+    const GraphKey key = key_of({in.Q, in.Delta, in.R, in.S, in.A, in.B, K, Pm, ws}, 2 + 16 * prec);
+    rc = replay_graph(P, key, st, [&](Timer &t, hipStream_t cs) {
+      return factor_sequence(P, in, K, Pm, prec, L, ws, t, cs);
+    });
+  } else {
+    rc = factor_sequence(P, in, K, Pm, prec, L, ws, tm, st);
+  }
+  if (rc) return rc;
+  rcr_solve_options o = opt;
+  o.kkt_residual = nullptr;  // no iterate yet
+  return finish_call(P, ws, o, tm, nullptr, {}, st);
+}
+
+int solve_rhs(PlanObj &P, const rcr_problem &in, const double *K, const double *Pm, int32_t k, const RhsIO *ios,
+              const rcr_solve_options &opt, hipStream_t st) {
+  std::lock_guard<std::mutex> lock(P.mu);
+  int rc = plan_upload(P, st);
+  if (rc) return rc;
+  const int prec = opt.precision;
+  const WsLayout L = workspace_layout(P.host, prec);
+  void *ws = opt.workspace ? opt.workspace : P.ws[prec];
+  if (!ws) return RCR_BAD_OPTION;  // no factor of this precision in the plan's workspace
+  if (opt.workspace && (size_t)opt.workspace_bytes < L.total_bytes) return RCR_SMALL_WORKSPACE;
+  Timer tm;
+  tm.P = &P;
+  tm.st = st;
+  tm.on = opt.kernel_ms != nullptr;
+  if (opt.executor == RCR_EXEC_GRAPH && !tm.on) {
+    GraphKey key = key_of({in.Q, in.Delta, in.R, in.S, in.A, in.B, K, Pm, ws},
+                          3 + 16 * prec + 256 * (int64_t)opt.refine_steps);
+    for (int32_t i = 0; i < k; ++i)
+      for (const void *p : {(const void *)ios[i].q, (const void *)ios[i].r, (const void *)ios[i].c,
+                            (const void *)ios[i].x, (const void *)ios[i].u, (const void *)ios[i].lam})
+        key.push_back((uintptr_t)p);
+    rc = replay_graph(P, key, st, [&](Timer &t, hipStream_t cs) {
+      return rhs_sequence(P, in, K, Pm, k, ios, prec, opt.refine_steps, L, ws, t, cs);
+    });
+  } else {
+    rc = rhs_sequence(P, in, K, Pm, k, ios, prec, opt.refine_steps, L, ws, tm, st);
+  }
+  if (rc) return rc;
+  std::vector<std::pair<rcr_problem, rcr_solution>> rs;
+  if (opt.kkt_residual)
+    for (int32_t i = 0; i < k; ++i) rs.push_back({with_rhs(in, ios[i]), sol_of(ios[i], nullptr, nullptr)});
+  return finish_call(P, ws, opt, tm, nullptr, rs, st);
+}
+
+// ------------------------------------------------------------ adjoint
+// Gradients of a scalar loss L with respect to the matrices of the problem,
+// from the forward solution (x, u, y) and the adjoint vector a = (a_x, a_u, a_y)
+// (the solve of the seeds dL/dx, dL/du, dL/dy, which is also dL/d(q, r, c)).
+// With M the symmetric KKT matrix of eq. (kkt) and M (x, u, y) = -(q, r, c),
+// dL = a^T dM (x, u, y), and dM pairs each block with its place in eq. (kkt):
+//   dQ_i = a_x,i x_i^T          (Q_i x_i in the stationarity of x_i)
+//   dDelta_j = -a_y,j y_j^T     (-Delta_j y_j in the dynamics into j / root)
+//   dR_e = a_u,e u_e^T          (R_e u_e in the control stationarity)
+//   dS_e = a_x,i u_e^T + x_i a_u,e^T          (M_e u_e and M_e^T x_i)
+//   dA_e = a_y,j x_i^T + y_j a_x,i^T          (A_e x_i and A_e^T y_j)
+//   dB_e = a_y,j u_e^T + y_j a_u,e^T          (B_e u_e and B_e^T y_j)
+// for e = (i, j) in edge slot j; the root's edge slot is written as zero.
+// One thread per output entry; a null output is skipped.
+__global__ __launch_bounds__(256) void k_adjoint_grads(int64_t N, int n, int m, const int32_t *__restrict__ parent,
+                                                       const double *__restrict__ x, const double *__restrict__ u,
+                                                       const double *__restrict__ y, const double *__restrict__ ax,
+                                                       const double *__restrict__ au, const double *__restrict__ ay,
+                                                       double *dQ, double *dD, double *dR, double *dS, double *dA,
+                                                       double *dB) {
+  const int64_t nn = (int64_t)n * n, nm = (int64_t)n * m, mm = (int64_t)m * m;
+  const int64_t per = 3 * nn + mm + 2 * nm;  // entries of dQ, dDelta, dA, dR, dS, dB per node
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < N * per; t += stride) {
+    const int64_t v = t / per;
+    int64_t e = t - v * per;
+    const int64_t pi = parent[v];
+    const bool edge = pi >= 0;
+    if (e < nn) {
+      const int a = (int)(e / n), b = (int)(e % n);
+      if (dQ) dQ[v * nn + e] = ax[v * n + a] * x[v * n + b];
+      continue;
+    }
+    e -= nn;
+    if (e < nn) {
+      const int a = (int)(e / n), b = (int)(e % n);
+      if (dD) dD[v * nn + e] = -ay[v * n + a] * y[v * n + b];
+      continue;
+    }
+    e -= nn;
+    if (e < nn) {
+      const int a = (int)(e / n), b = (int)(e % n);
+      if (dA) dA[v * nn + e] = edge ? fma(ay[v * n + a], x[pi * n + b], y[v * n + a] * ax[pi * n + b]) : 0.0;
+      continue;
+    }
+    e -= nn;
+    if (e < mm) {
+      const int a = (int)(e / m), b = (int)(e % m);
+      if (dR) dR[v * mm + e] = edge ? au[v * m + a] * u[v * m + b] : 0.0;
+      continue;
+    }
+    e -= mm;
+    if (e < nm) {
+      const int a = (int)(e / m), b = (int)(e % m);
+      if (dS) dS[v * nm + e] = edge ? fma(ax[pi * n + a], u[v * m + b], x[pi * n + a] * au[v * m + b]) : 0.0;
+      continue;
+    }
+    e -= nm;
+    {
+      const int a = (int)(e / m), b = (int)(e % m);
+      if (dB) dB[v * nm + e] = edge ? fma(ay[v * n + a], u[v * m + b], y[v * n + a] * au[v * m + b]) : 0.0;
+    }
+  }
+}
+
+int adjoint(PlanObj &P, const rcr_problem &in, const rcr_solution &fwd, const double *gx, const double *gu,
+            const double *gy, const rcr_gradient &g, const rcr_solve_options &opt, hipStream_t st) {
+  // a = the solve of the seeds (the KKT matrix is symmetric), written to dq, dr, dc
+  const RhsIO io{gx, gu, gy, g.q, g.r, g.c};
+  int rc = solve_rhs(P, in, fwd.K, fwd.P, 1, &io, opt, st);
+  if (rc) return rc;
+  if (!(g.Q || g.Delta || g.R || g.S || g.A || g.B)) return RCR_OK;
+  std::lock_guard<std::mutex> lock(P.mu);
+  const PlanHost &h = P.host;
+  const int64_t per = 3 * (int64_t)h.n * h.n + (int64_t)h.m * h.m + 2 * (int64_t)h.n * h.m;
+  hipLaunchKernelGGL(k_adjoint_grads, dim3(grid_for(h.N * per)), dim3(256), 0, st, h.N, h.n, h.m, P.dev.parent,
+                     fwd.x, fwd.u, fwd.lam, io.x, io.u, io.lam, g.Q, g.Delta, g.R, g.S, g.A, g.B);
+  HIPCK(hipGetLastError());
+  HIPCK(hipEventRecord(P.last_done, st));
+  if (opt.check || opt.kkt_residual) HIPCK(hipStreamSynchronize(st));
+  return RCR_OK;
+}
+
+// Max-abs KKT residual of eq. (kkt) for a given iterate (float64, synchronises).
+int kkt_residual(PlanObj &P, const rcr_problem &in, const rcr_solution &sol, const rcr_solve_options &opt,
+                 hipStream_t st) {
+  std::lock_guard<std::mutex> lock(P.mu);
+  int rc = plan_upload(P, st);
+  if (rc) return rc;
+  void *ws = opt.workspace;
+  if (ws) {
+    if ((size_t)opt.workspace_bytes < WS_HEADER_BYTES) return RCR_SMALL_WORKSPACE;
+  } else {
+    if (!P.resid_buf && hipMallocAsync((void **)&P.resid_buf, WS_HEADER_BYTES, st) != hipSuccess) return RCR_OOM;
+    ws = P.resid_buf;
+  }
+  hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, st, ws_status(ws), ws_resid(ws));
+  launch_residual_rhs<double>(P, in, sol, nullptr, nullptr, nullptr, ws_resid(ws), st);
+  HIPCK(hipGetLastError());
+  if (!P.last_done) HIPCK(hipEventCreateWithFlags(&P.last_done, hipEventDisableTiming));
+  HIPCK(hipEventRecord(P.last_done, st));
+  double resid = 0.0;
+  HIPCK(hipMemcpyAsync(&resid, ws_resid(ws), sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  *opt.kkt_residual = resid;
+  return RCR_OK;
+}
+
+// ------------------------------------------------------------ batched solve
+// rcr_batch_solve: k trees, each with its own problem and solution buffers,
+// solved with the merged plan of their forest.  The trees' inputs are gathered
+// into contiguous staging arrays in the workspace (tree t at its node offset),
+// the merged launch sequence runs on them, and the outputs are scattered back;
+// the gather and the scatter are one launch each, driven by a table of copy
+// chunks that is uploaded with the call.
+namespace {
+constexpr int BATCH_IN = 9, BATCH_OUT = 5;
+constexpr int64_t COPY_CHUNK = 32768;  // words per copy chunk (one workgroup each)
+
+struct CopyChunk {
+  const double *src;
+  double *dst;
+  int64_t words;
+  int64_t pad;
+};
+
+// Words per node of each staged field: Q q c Delta R S r A B, then K P x u lam.
+void batch_words(int n, int m, int64_t w[BATCH_IN + BATCH_OUT]) {
+  const int64_t nn = (int64_t)n * n, nm = (int64_t)n * m, mm = (int64_t)m * m;
+  const int64_t v[BATCH_IN + BATCH_OUT] = {nn, n, n, nn, mm, nm, m, nn, nm, nm, nn, n, m, n};
+  for (int f = 0; f < BATCH_IN + BATCH_OUT; ++f) w[f] = v[f];
+}
+
+// Copy chunks of one direction over all trees and fields.
+int64_t batch_chunks(const PlanHost &B, int f0, int f1) {
+  int64_t w[BATCH_IN + BATCH_OUT];
+  batch_words(B.n, B.m, w);
+  const int64_t T = (int64_t)B.tree_off.size() - 1;
+  int64_t c = 0;
+  for (int f = f0; f < f1; ++f)
+    for (int64_t t = 0; t < T; ++t) c += (w[f] * (B.tree_off[t + 1] - B.tree_off[t]) + COPY_CHUNK - 1) / COPY_CHUNK;
+  return c;
+}
+
+struct BatchLayout {
+  size_t stage[BATCH_IN + BATCH_OUT];  // byte offsets of the staged fields
+  size_t table;                        // byte offset of the chunk table (gather, then scatter)
+  int64_t n_gather, n_scatter;
+  size_t total;
+};
+
+BatchLayout batch_layout(const PlanHost &B, int precision) {
+  BatchLayout L;
+  size_t cur = workspace_layout(B, precision).total_bytes;
+  int64_t w[BATCH_IN + BATCH_OUT];
+  batch_words(B.n, B.m, w);
+  for (int f = 0; f < BATCH_IN + BATCH_OUT; ++f) {
+    L.stage[f] = cur;
+    cur = align_up(cur + (size_t)w[f] * (size_t)B.N * sizeof(double), 256);
+  }
+  L.n_gather = batch_chunks(B, 0, BATCH_IN);
+  L.n_scatter = batch_chunks(B, BATCH_IN, BATCH_IN + BATCH_OUT);
+  L.table = cur;
+  cur = align_up(cur + (size_t)(L.n_gather + L.n_scatter) * sizeof(CopyChunk), 256);
+  L.total = cur;
+  return L;
+}
+
+__global__ __launch_bounds__(256) void k_copy_chunks(const CopyChunk *__restrict__ ch, int64_t nch) {
+  for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+    const CopyChunk k = ch[c];
+    for (int64_t i = threadIdx.x; i < k.words; i += 4 * 256) {
+      double a[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t q = i + j * 256;
+        a[j] = q < k.words ? k.src[q] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t q = i + j * 256;
+        if (q < k.words) k.dst[q] = a[j];
+      }
+    }
+  }
+}
+
+// Pinned host buffers for the chunk tables, reused once the copy that read
+// them has completed (their event); the list grows to the number of tables in
+// flight and is never freed.
+struct PinSlot {
+  char *buf = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;
+};
+std::mutex pin_mu;
+std::vector<PinSlot> &pin_free() {
+  static std::vector<PinSlot> *v = new std::vector<PinSlot>();
+  return *v;
+}
+int pin_take(size_t need, PinSlot &out) {
+  {
+    std::lock_guard<std::mutex> lock(pin_mu);
+    auto &fl = pin_free();
+    for (size_t i = 0; i < fl.size(); ++i)
+      if (fl[i].bytes >= need && hipEventQuery(fl[i].done) == hipSuccess) {
+        out = fl[i];
+        fl.erase(fl.begin() + (long)i);
+        return RCR_OK;
+      }
+  }
+  PinSlot s;
+  s.bytes = std::max<size_t>(need, size_t(1) << 20);
+  if (hipHostMalloc((void **)&s.buf, s.bytes, hipHostMallocDefault) != hipSuccess) return RCR_OOM;
+  if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) return RCR_HIP_ERROR;
+  out = s;
+  return RCR_OK;
+}
+void pin_give(const PinSlot &s, hipStream_t st) {
+  (void)hipEventRecord(s.done, st);
+  std::lock_guard<std::mutex> lock(pin_mu);
+  pin_free().push_back(s);
+}
+}  // namespace
+
+size_t batch_workspace_bytes(const PlanHost &B, int precision) { return batch_layout(B, precision).total; }
+
+int batch_solve(PlanObj &Bp, int32_t k, const rcr_problem *in, rcr_solution *out, const rcr_solve_options &opt,
+                hipStream_t st) {
+  const PlanHost &h = Bp.host;
+  const int64_t T = h.tree_off.empty() ? 1 : (int64_t)h.tree_off.size() - 1;
+  if (k != T || h.tree_off.empty()) return RCR_BAD_OPTION;
+  const int prec = opt.precision;
+  const BatchLayout BL = batch_layout(h, prec);
+  const size_t solver = workspace_layout(h, prec).total_bytes;
+  void *ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(Bp.mu);
+    int rc = plan_upload(Bp, st);
+    if (rc) return rc;
+    if ((rc = take_workspace(Bp, opt, BL.total, BL.total, st, ws))) return rc;
+  }
+  char *wsb = static_cast<char *>(ws);
+  double *stg[BATCH_IN + BATCH_OUT];
+  for (int f = 0; f < BATCH_IN + BATCH_OUT; ++f) stg[f] = reinterpret_cast<double *>(wsb + BL.stage[f]);
+  int64_t w[BATCH_IN + BATCH_OUT];
+  batch_words(h.n, h.m, w);
+  const int64_t nch = BL.n_gather + BL.n_scatter;
+  PinSlot pin;
+  int rc = pin_take((size_t)nch * sizeof(CopyChunk), pin);
+  if (rc) return rc;
+  CopyChunk *tab = reinterpret_cast<CopyChunk *>(pin.buf);
+  int64_t c = 0;
+  for (int f = 0; f < BATCH_IN + BATCH_OUT; ++f)
+    for (int64_t t = 0; t < T; ++t) {
+      const int64_t off = h.tree_off[t], words = w[f] * (h.tree_off[t + 1] - off);
+      double *tree_buf;
+      switch (f) {
+        case 0: tree_buf = const_cast<double *>(in[t].Q); break;
+        case 1: tree_buf = const_cast<double *>(in[t].q); break;
+        case 2: tree_buf = const_cast<double *>(in[t].c); break;
+        case 3: tree_buf = const_cast<double *>(in[t].Delta); break;
+        case 4: tree_buf = const_cast<double *>(in[t].R); break;
+        case 5: tree_buf = const_cast<double *>(in[t].S); break;
+        case 6: tree_buf = const_cast<double *>(in[t].r); break;
+        case 7: tree_buf = const_cast<double *>(in[t].A); break;
+        case 8: tree_buf = const_cast<double *>(in[t].B); break;
+        case 9: tree_buf = out[t].K; break;
+        case 10: tree_buf = out[t].P; break;
+        case 11: tree_buf = out[t].x; break;
+        case 12: tree_buf = out[t].u; break;
+        default: tree_buf = out[t].lam; break;
+      }
+      double *staged = stg[f] + off * w[f];
+      for (int64_t q = 0; q < words; q += COPY_CHUNK) {
+        const int64_t len = std::min<int64_t>(COPY_CHUNK, words - q);
+        tab[c++] = f < BATCH_IN ? CopyChunk{tree_buf + q, staged + q, len, 0} : CopyChunk{staged + q, tree_buf + q, len, 0};
+      }
+    }
+  CopyChunk *dtab = reinterpret_cast<CopyChunk *>(wsb + BL.table);
+  const hipError_t ce = hipMemcpyAsync(dtab, tab, (size_t)nch * sizeof(CopyChunk), hipMemcpyHostToDevice, st);
+  pin_give(pin, st);
+  HIPCK(ce);
+  auto grid = [](int64_t n) { return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(n, 65535))); };
+  hipLaunchKernelGGL(k_copy_chunks, grid(BL.n_gather), dim3(256), 0, st, dtab, BL.n_gather);
+  HIPCK(hipGetLastError());
+  const rcr_problem sin{stg[0], stg[1], stg[2], stg[3], stg[4], stg[5], stg[6], stg[7], stg[8]};
+  rcr_solution sout{stg[9], stg[10], stg[11], stg[12], stg[13]};
+  rcr_solve_options o = opt;
+  o.workspace = ws;
+  o.workspace_bytes = (int64_t)solver;
+  rc = solve(Bp, sin, sout, o, st);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_copy_chunks, grid(BL.n_scatter), dim3(256), 0, st, dtab + BL.n_gather, BL.n_scatter);
+  HIPCK(hipGetLastError());
+  std::lock_guard<std::mutex> lock(Bp.mu);
+  HIPCK(hipEventRecord(Bp.last_done, st));
   return RCR_OK;
 }
 

@@ -57,13 +57,19 @@ WsLayout workspace_layout(const PlanHost &ph, int precision);
 // for a lifted plan, the float64 lifted problem and solution that follow it.
 size_t total_workspace_bytes(const PlanHost &ph, int precision);
 
-struct GraphKey {
-  const void *p[16];
-  bool operator<(const GraphKey &o) const {
-    for (int i = 0; i < 16; ++i)
-      if (p[i] != o.p[i]) return p[i] < o.p[i];
-    return false;
-  }
+// Cache key of a captured launch sequence: the buffer addresses it was
+// captured with and a tag for the entry point and its options.
+using GraphKey = std::vector<uintptr_t>;
+
+// At most this many captured sequences are kept per plan (least recently used
+// evicted); an evicted or dropped graph is destroyed only after its own latest
+// replay has completed.
+constexpr size_t GRAPH_CACHE_CAP = 8;
+
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;  // recorded after every replay of exec
+  uint64_t tick = 0;          // last use
 };
 
 // Launch mapping of the narrow levels (rcr_launch_config; 0 = default).
@@ -80,6 +86,7 @@ struct TimedGraph {
   std::vector<int> cls;
   std::vector<hipEvent_t> events;
   int launches[RCR_NUM_KERNEL_CLASSES] = {};
+  uint64_t tick = 0;
 };
 
 struct PlanObj {
@@ -90,18 +97,48 @@ struct PlanObj {
   void *ws[2] = {nullptr, nullptr};  // plan-owned workspace per precision
   size_t ws_bytes[2] = {0, 0};
   hipEvent_t last_done = nullptr;    // completion of the latest solve (stream-ordered release)
-  std::map<GraphKey, hipGraphExec_t> graphs;
+  std::map<GraphKey, GraphEntry> graphs;
   std::map<GraphKey, TimedGraph> timed;  // the per-class-run graphs used for timing
+  uint64_t tick = 0;                     // use counter of the graph caches
   std::vector<hipEvent_t> events;
+  double *resid_buf = nullptr;           // device scratch of rcr_kkt_residual (status words + accumulator)
+  uint64_t serial = 0;                   // unique id of the plan (never reused)
+};
+
+// One right-hand side (q, r, c) and the buffers of its solution (x, u, lam):
+// caller-owned float64 device arrays in the layouts of rcr.h.
+struct RhsIO {
+  const double *q, *r, *c;
+  double *x, *u, *lam;
 };
 
 int plan_upload(PlanObj &P, hipStream_t st);
+// Bytes of a plan's device copy (its integer arrays), made by plan_upload.
+size_t plan_device_bytes(const PlanHost &h);
 void plan_release_device(PlanObj &P);
 
 int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_options &opt,
           hipStream_t stream);
 
 void drop_graphs(PlanObj &P);
+size_t graph_cache_size(const PlanObj &P);
+
+// Algorithm 1, Steps 2-3 (factor into the workspace and K, P) and Steps 4-6
+// for k right-hand sides on that factor.
+int factor(PlanObj &P, const rcr_problem &in, double *K, double *Pm, const rcr_solve_options &opt,
+           hipStream_t stream);
+int solve_rhs(PlanObj &P, const rcr_problem &in, const double *K, const double *Pm, int32_t k, const RhsIO *ios,
+              const rcr_solve_options &opt, hipStream_t stream);
+// Gradients of a scalar loss through the solve, from its seeds dL/dx, dL/du, dL/dy.
+int adjoint(PlanObj &P, const rcr_problem &in, const rcr_solution &fwd, const double *gx, const double *gu,
+            const double *gy, const rcr_gradient &g, const rcr_solve_options &opt, hipStream_t stream);
+// Max-abs residual of eq. (kkt) of a given iterate into *opt.kkt_residual.
+int kkt_residual(PlanObj &P, const rcr_problem &in, const rcr_solution &sol, const rcr_solve_options &opt,
+                 hipStream_t stream);
+// k trees with their own buffers through the merged plan B of their forest.
+int batch_solve(PlanObj &B, int32_t k, const rcr_problem *in, rcr_solution *out, const rcr_solve_options &opt,
+                hipStream_t stream);
+size_t batch_workspace_bytes(const PlanHost &B, int precision);
 
 int tune(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_options &opt, hipStream_t stream,
          LaunchCfg &best, float &best_ms);

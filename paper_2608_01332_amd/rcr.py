@@ -44,7 +44,10 @@ class PlanStats(ctypes.Structure):
                 ("n_rake", ctypes.c_int64), ("n_compress", ctypes.c_int64), ("n_combine", ctypes.c_int64),
                 ("n_absorb", ctypes.c_int64), ("depth_bound", ctypes.c_int64), ("crew_ok", ctypes.c_int64),
                 ("workspace_bytes_fp64", ctypes.c_int64), ("workspace_bytes_mixed", ctypes.c_int64),
-                ("n_trees", ctypes.c_int64)]
+                ("n_trees", ctypes.c_int64), ("plan_device_bytes", ctypes.c_int64),
+                ("graph_cache_entries", ctypes.c_int64)]
+
+GRAPH_CACHE_CAP = 8
 
 
 class Problem(ctypes.Structure):
@@ -53,6 +56,18 @@ class Problem(ctypes.Structure):
 
 class Solution(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in ("K", "P", "x", "u", "lam")]
+
+
+class Rhs(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("q", "r", "c")]
+
+
+class RhsSolution(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("x", "u", "lam")]
+
+
+class Gradient(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("Q", "q", "c", "Delta", "R", "S", "r", "A", "B")]
 
 
 class NativeProblem(ctypes.Structure):
@@ -77,10 +92,12 @@ class SolveOptions(ctypes.Structure):
                 ("kernel_launches", ctypes.POINTER(ctypes.c_int32)), ("reserved", ctypes.c_int32 * 4)]
 
 
-EXPORTED = ("rcr_plan_create", "rcr_plan_info", "rcr_plan_export", "rcr_plan_destroy", "rcr_batch_plan_create",
+EXPORTED = ("rcr_plan_create", "rcr_plan_info", "rcr_plan_device_bytes", "rcr_plan_export", "rcr_plan_destroy", "rcr_batch_plan_create",
             "rcr_plan_upload", "rcr_lift_plan_create", "rcr_lift_solve", "rcr_plan_set_launch",
             "rcr_plan_get_launch", "rcr_plan_tune",
-            "rcr_workspace_size", "rcr_solve", "rcr_status_string")
+            "rcr_workspace_size", "rcr_solve", "rcr_factor", "rcr_solve_rhs", "rcr_adjoint", "rcr_kkt_residual",
+            "rcr_batch_solve", "rcr_batch_prepare", "rcr_batch_release", "rcr_batch_workspace_size",
+            "rcr_status_string")
 
 _lib = None
 _lock = threading.Lock()
@@ -105,6 +122,8 @@ def lib():
                                           ctypes.POINTER(PlanOptions), ctypes.POINTER(ctypes.c_void_p)]
             L.rcr_plan_info.restype = ctypes.c_int
             L.rcr_plan_info.argtypes = [ctypes.c_void_p, ctypes.POINTER(PlanStats)]
+            L.rcr_plan_device_bytes.restype = ctypes.c_int64
+            L.rcr_plan_device_bytes.argtypes = [ctypes.c_void_p]
             L.rcr_plan_export.restype = ctypes.c_int
             L.rcr_plan_export.argtypes = [ctypes.c_void_p, _i32p, ctypes.c_int64, _i64p]
             L.rcr_plan_destroy.restype = None
@@ -133,6 +152,29 @@ def lib():
             L.rcr_solve.restype = ctypes.c_int
             L.rcr_solve.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.POINTER(Solution),
                                     ctypes.POINTER(SolveOptions), ctypes.c_void_p]
+            L.rcr_factor.restype = ctypes.c_int
+            L.rcr_factor.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.POINTER(Solution),
+                                     ctypes.POINTER(SolveOptions), ctypes.c_void_p]
+            L.rcr_solve_rhs.restype = ctypes.c_int
+            L.rcr_solve_rhs.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.POINTER(Solution),
+                                        ctypes.c_int32, ctypes.POINTER(Rhs), ctypes.POINTER(RhsSolution),
+                                        ctypes.POINTER(SolveOptions), ctypes.c_void_p]
+            L.rcr_adjoint.restype = ctypes.c_int
+            L.rcr_adjoint.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.POINTER(Solution),
+                                      ctypes.POINTER(Rhs), ctypes.POINTER(Gradient), ctypes.POINTER(SolveOptions),
+                                      ctypes.c_void_p]
+            L.rcr_kkt_residual.restype = ctypes.c_int
+            L.rcr_kkt_residual.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.POINTER(Solution),
+                                           ctypes.POINTER(SolveOptions), ctypes.c_void_p]
+            L.rcr_batch_solve.restype = ctypes.c_int
+            L.rcr_batch_solve.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.POINTER(Problem),
+                                          ctypes.POINTER(Solution), ctypes.POINTER(SolveOptions), ctypes.c_void_p]
+            L.rcr_batch_prepare.restype = ctypes.c_int
+            L.rcr_batch_prepare.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_void_p]
+            L.rcr_batch_release.restype = None
+            L.rcr_batch_release.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32]
+            L.rcr_batch_workspace_size.restype = ctypes.c_int64
+            L.rcr_batch_workspace_size.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_int32]
             L.rcr_status_string.restype = ctypes.c_char_p
             L.rcr_status_string.argtypes = [ctypes.c_int]
             _lib = L
@@ -204,6 +246,10 @@ class Plan:
         if rc != 0:
             raise RcrError(rc, "rcr_plan_info")
         return {k: int(getattr(s, k)) for k, _ in PlanStats._fields_}
+
+    def device_bytes(self) -> int:
+        """rcr_plan_device_bytes: bytes of the plan's device copy (cheap; no CREW check)."""
+        return int(lib().rcr_plan_device_bytes(self._h))
 
     def export_ops(self) -> np.ndarray:
         cnt = ctypes.c_int64()
@@ -340,6 +386,207 @@ def solve(plan: Plan, prob: dict, out: dict | None = None, precision: int = FP64
         result["kernel_ms"] = {KERNEL_CLASSES[i]: float(kms[i]) for i in range(NUM_KERNEL_CLASSES)}
         result["kernel_launches"] = {KERNEL_CLASSES[i]: int(kln[i]) for i in range(NUM_KERNEL_CLASSES)}
     return result
+
+
+def _options(precision, executor, check, refine_steps, workspace, kkt_residual, kernel_ms):
+    """SolveOptions plus the host cells the library writes into."""
+    o = SolveOptions(precision=precision, refine_steps=refine_steps, executor=executor, check=int(check))
+    if workspace is not None:
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    res = ctypes.c_double(-1.0)
+    if kkt_residual:
+        o.kkt_residual = ctypes.pointer(res)
+    kms = (ctypes.c_float * NUM_KERNEL_CLASSES)()
+    kln = (ctypes.c_int32 * NUM_KERNEL_CLASSES)()
+    if kernel_ms:
+        o.kernel_ms = ctypes.cast(kms, ctypes.POINTER(ctypes.c_float))
+        o.kernel_launches = ctypes.cast(kln, ctypes.POINTER(ctypes.c_int32))
+    return o, res, kms, kln
+
+
+def _extras(result, kkt_residual, kernel_ms, res, kms, kln):
+    if kkt_residual:
+        result["kkt_residual"] = res.value
+    if kernel_ms:
+        result["kernel_ms"] = {KERNEL_CLASSES[i]: float(kms[i]) for i in range(NUM_KERNEL_CLASSES)}
+        result["kernel_launches"] = {KERNEL_CLASSES[i]: int(kln[i]) for i in range(NUM_KERNEL_CLASSES)}
+    return result
+
+
+def _stream(stream, device):
+    import torch
+    return stream if stream is not None else torch.cuda.current_stream(device)
+
+
+RHS_FIELDS = ("q", "r", "c")
+RHS_SOLUTION_FIELDS = ("x", "u", "lam")
+MATRIX_FIELDS = ("Q", "Delta", "R", "S", "A", "B")
+
+
+def factor(plan: Plan, prob: dict, out: dict | None = None, precision: int = FP64, executor: int = EXEC_LEVELS,
+           check: bool = False, kernel_ms: bool = False, workspace=None, stream=None) -> dict:
+    """rcr_factor: Algorithm 1, Steps 2-3 on the matrices of `prob` (q, r, c not
+    read).  Returns {'K', 'P'}; the rest of the factor stays in the workspace."""
+    import torch
+    sh = _shapes(plan.N, plan.n, plan.m)
+    for k in MATRIX_FIELDS:
+        _check(prob[k], k, sh[k])
+    dev = prob["Q"].device
+    if out is None:
+        out = {k: torch.empty(sh[k], dtype=torch.float64, device=dev) for k in ("K", "P")}
+    for k in ("K", "P"):
+        _check(out[k], k, sh[k])
+    p = Problem(**{k: (prob[k].data_ptr() if k in prob else None) for k in PROBLEM_FIELDS})
+    s = Solution(K=out["K"].data_ptr(), P=out["P"].data_ptr())
+    o, res, kms, kln = _options(precision, executor, check, -1, workspace, False, kernel_ms)
+    rc = lib().rcr_factor(plan._h, ctypes.byref(p), ctypes.byref(s), ctypes.byref(o),
+                          ctypes.c_void_p(_stream(stream, dev).cuda_stream))
+    if rc != 0:
+        raise RcrError(rc, "rcr_factor")
+    return _extras({"K": out["K"], "P": out["P"]}, False, kernel_ms, res, kms, kln)
+
+
+def solve_rhs(plan: Plan, prob: dict, fac: dict, rhs: list, outs: list | None = None, precision: int = FP64,
+              executor: int = EXEC_LEVELS, check: bool = False, kkt_residual: bool = False,
+              kernel_ms: bool = False, refine_steps: int = -1, workspace=None, stream=None) -> dict:
+    """rcr_solve_rhs: Steps 4-6 for each right-hand side dict (q, r, c) of `rhs`
+    on the factor of rcr_factor (fac holds its K, P).  Returns {'solutions': [...]}
+    with x, u, lam per right-hand side."""
+    import torch
+    sh = _shapes(plan.N, plan.n, plan.m)
+    for k in MATRIX_FIELDS:
+        _check(prob[k], k, sh[k])
+    for k in ("K", "P"):
+        _check(fac[k], k, sh[k])
+    dev = prob["Q"].device
+    if outs is None:
+        outs = [{k: torch.empty(sh[k], dtype=torch.float64, device=dev) for k in RHS_SOLUTION_FIELDS} for _ in rhs]
+    if len(outs) != len(rhs) or not rhs:
+        raise ValueError("one solution dict per right-hand side, at least one")
+    for r_, o_ in zip(rhs, outs):
+        for k in RHS_FIELDS:
+            _check(r_[k], k, sh[k])
+        for k in RHS_SOLUTION_FIELDS:
+            _check(o_[k], k, sh[k])
+    kk = len(rhs)
+    ra = (Rhs * kk)(*[Rhs(**{k: r_[k].data_ptr() for k in RHS_FIELDS}) for r_ in rhs])
+    sa = (RhsSolution * kk)(*[RhsSolution(**{k: o_[k].data_ptr() for k in RHS_SOLUTION_FIELDS}) for o_ in outs])
+    p = Problem(**{k: (prob[k].data_ptr() if k in prob else None) for k in PROBLEM_FIELDS})
+    f = Solution(K=fac["K"].data_ptr(), P=fac["P"].data_ptr())
+    o, res, kms, kln = _options(precision, executor, check, refine_steps, workspace, kkt_residual, kernel_ms)
+    rc = lib().rcr_solve_rhs(plan._h, ctypes.byref(p), ctypes.byref(f), kk, ra, sa, ctypes.byref(o),
+                             ctypes.c_void_p(_stream(stream, dev).cuda_stream))
+    if rc != 0:
+        raise RcrError(rc, "rcr_solve_rhs")
+    return _extras({"solutions": outs}, kkt_residual, kernel_ms, res, kms, kln)
+
+
+GRADIENT_FIELDS = PROBLEM_FIELDS
+
+
+def adjoint(plan: Plan, prob: dict, fwd: dict, seed: dict, grads: dict | None = None, want=GRADIENT_FIELDS,
+            precision: int = FP64, executor: int = EXEC_LEVELS, check: bool = False, refine_steps: int = -1,
+            workspace=None, stream=None) -> dict:
+    """rcr_adjoint: gradients of L with respect to the problem data from the seeds
+    seed = {'x': dL/dx, 'u': dL/du, 'lam': dL/dlam}; fwd holds the factor's K, P
+    and the forward x, u, lam.  Returns the gradient dict (fields of `want`; q, r,
+    c always)."""
+    import torch
+    sh = _shapes(plan.N, plan.n, plan.m)
+    dev = prob["Q"].device
+    for k in MATRIX_FIELDS:
+        _check(prob[k], k, sh[k])
+    for k in SOLUTION_FIELDS:
+        _check(fwd[k], k, sh[k])
+    for k, f_ in (("x", "q"), ("u", "r"), ("lam", "c")):
+        _check(seed[k], k, sh[f_])
+    want = set(want) | {"q", "r", "c"}
+    if grads is None:
+        grads = {k: torch.empty(sh[k], dtype=torch.float64, device=dev) for k in GRADIENT_FIELDS if k in want}
+    for k, v in grads.items():
+        _check(v, k, sh[k])
+    g = Gradient(**{k: (grads[k].data_ptr() if k in grads else None) for k in GRADIENT_FIELDS})
+    sd = Rhs(q=seed["x"].data_ptr(), r=seed["u"].data_ptr(), c=seed["lam"].data_ptr())
+    p = Problem(**{k: (prob[k].data_ptr() if k in prob else None) for k in PROBLEM_FIELDS})
+    f = Solution(**{k: fwd[k].data_ptr() for k in SOLUTION_FIELDS})
+    o, res, kms, kln = _options(precision, executor, check, refine_steps, workspace, False, False)
+    rc = lib().rcr_adjoint(plan._h, ctypes.byref(p), ctypes.byref(f), ctypes.byref(sd), ctypes.byref(g),
+                           ctypes.byref(o), ctypes.c_void_p(_stream(stream, dev).cuda_stream))
+    if rc != 0:
+        raise RcrError(rc, "rcr_adjoint")
+    return grads
+
+
+def kkt_residual(plan: Plan, prob: dict, sol: dict, workspace=None, stream=None) -> float:
+    """rcr_kkt_residual: max-abs residual of eq. (kkt) of the iterate sol (x, u, lam)."""
+    sh = _shapes(plan.N, plan.n, plan.m)
+    for k in PROBLEM_FIELDS:
+        _check(prob[k], k, sh[k])
+    for k in RHS_SOLUTION_FIELDS:
+        _check(sol[k], k, sh[k])
+    dev = prob["Q"].device
+    p = Problem(**{k: prob[k].data_ptr() for k in PROBLEM_FIELDS})
+    s = Solution(**{k: (sol[k].data_ptr() if k in sol else None) for k in SOLUTION_FIELDS})
+    o, res, _, _ = _options(FP64, EXEC_LEVELS, False, -1, workspace, True, False)
+    rc = lib().rcr_kkt_residual(plan._h, ctypes.byref(p), ctypes.byref(s), ctypes.byref(o),
+                                ctypes.c_void_p(_stream(stream, dev).cuda_stream))
+    if rc != 0:
+        raise RcrError(rc, "rcr_kkt_residual")
+    return res.value
+
+
+def _plan_array(plans):
+    return (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
+
+
+def batch_prepare(plans, stream=None):
+    """rcr_batch_prepare: build, cache and upload the merged plan of these plans."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    rc = lib().rcr_batch_prepare(_plan_array(plans), len(plans), ctypes.c_void_p(st.cuda_stream))
+    if rc != 0:
+        raise RcrError(rc, "rcr_batch_prepare")
+
+
+def batch_release(plans):
+    """rcr_batch_release: drop the library's cached merged plan of these plans."""
+    lib().rcr_batch_release(_plan_array(plans), len(plans))
+
+
+def batch_workspace_size(plans, precision: int = FP64) -> int:
+    return int(lib().rcr_batch_workspace_size(_plan_array(plans), len(plans), precision))
+
+
+def batch_solve(plans, probs: list, outs: list | None = None, precision: int = FP64, executor: int = EXEC_LEVELS,
+                check: bool = False, kkt_residual: bool = False, refine_steps: int = -1, workspace=None,
+                stream=None) -> dict:
+    """rcr_batch_solve: tree t (plans[t]) with its own problem probs[t] and solution
+    outs[t] (device tensors), all solved in one merged launch sequence.  Returns
+    {'solutions': outs} (plus 'kkt_residual', the largest over the trees)."""
+    import torch
+    if not plans or len(probs) != len(plans):
+        raise ValueError("one problem per plan, at least one plan")
+    dev = probs[0]["Q"].device
+    if outs is None:
+        outs = [alloc_solution(p_, dev) for p_ in plans]
+    if len(outs) != len(plans):
+        raise ValueError("one solution per plan")
+    for p_, pr, ou in zip(plans, probs, outs):
+        sh = _shapes(p_.N, p_.n, p_.m)
+        for k in PROBLEM_FIELDS:
+            _check(pr[k], k, sh[k])
+        for k in SOLUTION_FIELDS:
+            _check(ou[k], k, sh[k])
+    kk = len(plans)
+    pa = (Problem * kk)(*[Problem(**{k: pr[k].data_ptr() for k in PROBLEM_FIELDS}) for pr in probs])
+    sa = (Solution * kk)(*[Solution(**{k: ou[k].data_ptr() for k in SOLUTION_FIELDS}) for ou in outs])
+    o, res, kms, kln = _options(precision, executor, check, refine_steps, workspace, kkt_residual, False)
+    rc = lib().rcr_batch_solve(_plan_array(plans), kk, pa, sa, ctypes.byref(o),
+                               ctypes.c_void_p(_stream(stream, dev).cuda_stream))
+    if rc != 0:
+        raise RcrError(rc, "rcr_batch_solve")
+    return _extras({"solutions": outs}, kkt_residual, False, res, kms, kln)
 
 
 NATIVE_FIELDS = ("Q", "q", "c", "Delta", "M", "R", "r", "A", "B")

@@ -7,20 +7,22 @@ problem data already resident on the device -- arrive over time.  The server
     releases the interpreter lock); a topology seen before reuses its cached
     plan, whose device copy stays resident;
   * admits ready requests into execution slots, one HIP stream each, when a
-    slot is free and the group's HBM footprint (workspace of rcr_solve, the
-    concatenated inputs of a merged group, and the outputs) fits the budget;
+    slot is free and the group's HBM footprint fits the budget left after
+    the device copies of the cached plans: its workspace (for a merged group
+    that of rcr_batch_solve, which stages the requests' inputs and outputs),
+    its outputs and the device copy of its plan;
   * merges the requests of equal (n, m) that are ready at admission time,
-    oldest first, into one batched plan (their forest) solved by one merged
-    launch sequence, so that requests which arrived while others were on the
-    GPU join the next free slot together and their work overlaps on the
-    device with the groups running in the other slots;
+    oldest first, into one rcr_batch_solve over their plans (the library
+    merges them into the plan of their forest, one launch sequence), so that
+    requests which arrived while others were on the GPU join the next free
+    slot together and their work overlaps on the device with the groups
+    running in the other slots;
   * completes a group when its stream's completion event has fired.
 
-A request's results are views into its group's output buffers; every
-request's arithmetic is that of the same kernels on its own nodes, so the
-result does not depend on the group it ran in.  Latency runs from the
-request's arrival time to the host observing its completion event (planning
-on a plan-cache miss included).
+Every request gets its own output buffers; its arithmetic is that of the same
+kernels on its own nodes, so the result does not depend on the group it ran
+in.  Latency runs from the request's arrival time to the host observing its
+completion event (planning on a plan-cache miss included).
 """
 from __future__ import annotations
 
@@ -32,8 +34,6 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import rcr
-
-_FP64_WORDS_IN = ("Q", "q", "c", "Delta", "R", "S", "r", "A", "B")
 
 
 def io_words(N: int, n: int, m: int) -> tuple[int, int]:
@@ -64,13 +64,29 @@ class Request:
         return int(self.parent.shape[0])
 
 
-def group_footprint(reqs, precision: int, ws_bytes: int) -> int:
-    """HBM bytes a group holds while it runs: the solve's workspace, the
-    concatenated inputs (merged groups only) and the outputs."""
+COPY_CHUNK = 32768  # words per copy chunk of rcr_batch_solve's gather and scatter
+
+
+def batch_staging_bytes(sizes, n: int, m: int) -> int:
+    """Device bytes rcr_batch_solve adds to the merged plan's solver workspace
+    for trees of these sizes: the staged inputs and outputs (each field 256-byte
+    aligned) and the table of copy chunks (32 bytes each)."""
+    s, t, v = n * n, n * m, m * m
+    words = (s, n, n, s, v, t, m, s, t, t, s, n, m, n)  # Q q c Delta R S r A B, K P x u lam
+    N = sum(sizes)
+    stage = sum(-(-8 * w * N // 256) * 256 for w in words)
+    chunks = sum(-(-w * Nt // COPY_CHUNK) for w in words for Nt in sizes)
+    return stage + -(-32 * chunks // 256) * 256
+
+
+def group_footprint(reqs, precision: int, ws_bytes: int, plan_bytes: int = 0) -> int:
+    """HBM bytes a group holds while it runs: its workspace (ws_bytes, staging
+    included for a merged group), its outputs and the device copy of its plan
+    when that is not a cached plan's (plan_bytes)."""
     n, m = reqs[0].n, reqs[0].m
     N = sum(r.N for r in reqs)
     w_in, w_out = io_words(N, n, m)
-    return ws_bytes + 8 * w_out + (8 * w_in if len(reqs) > 1 else 0)
+    return ws_bytes + 8 * w_out + plan_bytes
 
 
 def form_group(ready, free_bytes: int, max_nodes: int, ws_of, precision: int):
@@ -82,7 +98,7 @@ def form_group(ready, free_bytes: int, max_nodes: int, ws_of, precision: int):
         return [], 0
     head = ready[0]
     group = [head]
-    fp = group_footprint(group, precision, ws_of(group))
+    fp = group_footprint(group, precision, *ws_of(group))
     if fp > free_bytes:
         return [], 0
     nodes = head.N
@@ -90,7 +106,7 @@ def form_group(ready, free_bytes: int, max_nodes: int, ws_of, precision: int):
         if (r.n, r.m) != (head.n, head.m) or nodes + r.N > max_nodes:
             continue
         cand = group + [r]
-        f2 = group_footprint(cand, precision, ws_of(cand))
+        f2 = group_footprint(cand, precision, *ws_of(cand))
         if f2 > free_bytes:
             continue
         group, fp, nodes = cand, f2, nodes + r.N
@@ -123,6 +139,7 @@ class Server:
         self.pool = cf.ThreadPoolExecutor(max_workers=planner_threads)
         self.cache = collections.OrderedDict()  # topo -> [Plan, in-flight count]
         self.cache_cap = plan_cache
+        self.cached_plan_bytes = 0              # device copies held by cached plans
         self.planning = []                      # (future, request)
         self.ready = collections.deque()
         self.done = []
@@ -171,10 +188,16 @@ class Server:
         while len(self.cache) > self.cache_cap:
             for k, ent in self.cache.items():
                 if ent[1] == 0:
+                    if getattr(ent[0], "_uploaded", False):
+                        self.cached_plan_bytes -= ent[0].device_bytes()
                     del self.cache[k]
                     break
             else:
                 return
+
+    def _is_cached(self, req) -> bool:
+        key = None if req.topo is None else (req.topo, req.n, req.m)
+        return key is not None and key in self.cache and self.cache[key][0] is req.plan
 
     def _pin(self, reqs, delta):
         for r in reqs:
@@ -184,18 +207,30 @@ class Server:
 
     # ---- execution ------------------------------------------------------------
     def _ws_of(self, group):
+        """(workspace bytes, plan device bytes not already charged) of a group.
+        A merged plan's workspace and device copy are at most the sums of its
+        parts' (every array is per node, per slot or per level), so the sums
+        bound the footprint before the merged plan exists."""
         if len(group) == 1:
-            return group[0].plan.workspace_size(self.precision)
-        # the merged plan's workspace is the sum of its parts' (all per-node arrays)
-        return sum(r.plan.workspace_size(self.precision) for r in group)
+            r = group[0]
+            charged = getattr(r.plan, "_uploaded", False) and self._is_cached(r)
+            return r.plan.workspace_size(self.precision), 0 if charged else r.plan.device_bytes()
+        ws = sum(r.plan.workspace_size(self.precision) for r in group)
+        ws += batch_staging_bytes([r.N for r in group], group[0].n, group[0].m)
+        return ws, sum(r.plan.device_bytes() for r in group)
 
     def _prepare(self, group, stream):
-        """Worker thread: the group's plan (merged for several requests) and its
-        device copy, made in the order of the slot's idle stream."""
+        """Worker thread: the group's plan (for several requests the merged plan
+        of rcr_batch_solve, built and cached by the library) and its device
+        copy, made in the order of the slot's idle stream."""
         t = time.perf_counter()
-        plan = rcr.Plan.batch([r.plan for r in group]) if len(group) > 1 else group[0].plan
-        plan.upload(stream)
-        plan._uploaded = True
+        if len(group) > 1:
+            plans = [r.plan for r in group]
+            rcr.batch_prepare(plans, stream)
+            plan = plans
+        else:
+            plan = group[0].plan
+            plan.upload(stream)
         self.stats["prep_s"] += time.perf_counter() - t
         return plan
 
@@ -218,22 +253,24 @@ class Server:
         t = time.perf_counter()
         group = slot.group
         with torch.cuda.stream(slot.stream):
+            outs = [rcr.alloc_solution(r.plan, self.device) for r in group]
             if len(group) == 1:
-                prob = group[0].prob
+                ws = torch.empty(plan.workspace_size(self.precision), dtype=torch.uint8, device=self.device)
+                rcr.solve(plan, group[0].prob, out=outs[0], precision=self.precision,
+                          refine_steps=self.refine_steps, executor=rcr.EXEC_LEVELS, workspace=ws,
+                          stream=slot.stream)
             else:
-                prob = {k: torch.cat([r.prob[k] for r in group]) for k in _FP64_WORDS_IN}
-            ws = torch.empty(plan.workspace_size(self.precision), dtype=torch.uint8, device=self.device)
-            out = rcr.alloc_solution(plan, self.device)
-            rcr.solve(plan, prob, out=out, precision=self.precision, refine_steps=self.refine_steps,
-                      executor=rcr.EXEC_LEVELS, workspace=ws, stream=slot.stream)
+                ws = torch.empty(rcr.batch_workspace_size(plan, self.precision), dtype=torch.uint8,
+                                 device=self.device)
+                rcr.batch_solve(plan, [r.prob for r in group], outs, precision=self.precision,
+                                refine_steps=self.refine_steps, executor=rcr.EXEC_LEVELS, workspace=ws,
+                                stream=slot.stream)
             ev = torch.cuda.Event()
             ev.record(slot.stream)
-        off = 0
-        for r in group:
-            r.out = {k: v[off:off + r.N] for k, v in out.items()}
-            off += r.N
+        for r, o in zip(group, outs):
+            r.out = o
         slot.event = ev
-        slot.keep = (plan if len(group) > 1 else None, prob if len(group) > 1 else None, ws)
+        slot.keep = (plan if len(group) > 1 else None, ws)
         self.stats["launch_s"] += time.perf_counter() - t
 
     def poll(self) -> int:
@@ -243,9 +280,15 @@ class Server:
             if slot.prep is not None and slot.prep.done():
                 plan = slot.prep.result()
                 slot.prep = None
+                if len(slot.group) == 1 and not getattr(plan, "_uploaded", False):
+                    plan._uploaded = True  # its device copy stays with the plan
+                    if self._is_cached(slot.group[0]):
+                        self.cached_plan_bytes += plan.device_bytes()
                 self._launch(slot, plan)
             if slot.event is not None and slot.event.query():
                 t = time.perf_counter()
+                if slot.keep[0] is not None:
+                    rcr.batch_release(slot.keep[0])  # merged groups rarely repeat
                 for r in slot.group:
                     r.t_done = t
                     r.plan = None  # the cache keeps reusable plans; others are released
@@ -259,15 +302,31 @@ class Server:
         for slot in self.slots:
             if slot.group is not None or not self.ready:
                 continue
-            group, fp = form_group(self.ready, self.budget - self.in_use, self.max_group_nodes, self._ws_of,
-                                   self.precision)
+            while True:
+                group, fp = form_group(self.ready, self.budget - self.in_use - self.cached_plan_bytes,
+                                       self.max_group_nodes, self._ws_of, self.precision)
+                if group or not self._evict_for_room():
+                    break
             if not group:
+                if not any(s_.group is not None or s_.prep is not None for s_ in self.slots):
+                    raise RuntimeError(f"request {self.ready[0].rid} does not fit the HBM budget of "
+                                       f"{self.budget} bytes on an idle device")
                 break
             ids = {id(r) for r in group}
             self.ready = collections.deque(r for r in self.ready if id(r) not in ids)
             self._dispatch(slot, group, fp)
         self._evict()
         return finished
+
+    def _evict_for_room(self) -> bool:
+        """Release the device copy of the least recently used cached plan that no
+        running group uses (the head of the queue did not fit); False if none."""
+        for k, ent in self.cache.items():
+            if ent[1] == 0 and getattr(ent[0], "_uploaded", False):
+                self.cached_plan_bytes -= ent[0].device_bytes()
+                del self.cache[k]
+                return True
+        return False
 
     def busy(self) -> bool:
         return bool(self.planning or self.ready or any(s.group is not None for s in self.slots))

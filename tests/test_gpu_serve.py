@@ -82,7 +82,8 @@ def test_serve_tight_budget_stays_within_budget():
     print("[gpu-serve] tight HBM budget", flush=True)
     reqs = _requests(8, seed=7, n_choices=(8,))
     plans = [rcr.Plan(r.parent, r.n, r.m) for r in reqs]
-    need = max(serve.group_footprint([r], rcr.MIXED32, p.workspace_size(rcr.MIXED32)) for r, p in zip(reqs, plans))
+    need = max(serve.group_footprint([r], rcr.MIXED32, p.workspace_size(rcr.MIXED32), p.stats()["plan_device_bytes"])
+               for r, p in zip(reqs, plans))
     srv = serve.Server("cuda:0", slots=4, hbm_budget=need, planner_threads=2)
     for r in reqs:
         srv.submit(r)

@@ -21,7 +21,7 @@ def _req(rid, N, n, m, ws=1000):
 
 
 def _ws_of(g):
-    return sum(r.plan.workspace_size(rcr.MIXED32) for r in g)
+    return sum(r.plan.workspace_size(rcr.MIXED32) for r in g), 0
 
 
 def test_io_words_counts_problem_and_solution():
@@ -37,10 +37,10 @@ def test_group_oldest_head_same_dims_only():
     ready = [_req(0, 100, 4, 2), _req(1, 100, 8, 2), _req(2, 100, 4, 2), _req(3, 100, 4, 4), _req(4, 50, 4, 2)]
     g, fp = serve.form_group(ready, 1 << 40, 10 ** 9, _ws_of, rcr.MIXED32)
     assert [r.rid for r in g] == [0, 2, 4]
-    assert fp == serve.group_footprint(g, rcr.MIXED32, _ws_of(g))
+    assert fp == serve.group_footprint(g, rcr.MIXED32, *_ws_of(g))
 
 
-def test_group_node_cap_and_single_request_has_no_input_copy():
+def test_group_node_cap_and_footprint():
     ready = [_req(0, 100, 4, 2), _req(1, 100, 4, 2), _req(2, 30, 4, 2)]
     g, fp = serve.form_group(ready, 1 << 40, 130, _ws_of, rcr.MIXED32)
     assert [r.rid for r in g] == [0, 2]
@@ -49,7 +49,8 @@ def test_group_node_cap_and_single_request_has_no_input_copy():
     w_in, w_out = serve.io_words(100, 4, 2)
     assert fp1 == 1000 + 8 * w_out
     w_in2, w_out2 = serve.io_words(130, 4, 2)
-    assert fp == 2000 + 8 * (w_in2 + w_out2)
+    assert fp == 2000 + 8 * w_out2
+    assert serve.group_footprint(g, rcr.MIXED32, 2000, 77) == fp + 77
 
 
 def test_group_respects_budget_and_blocks_when_head_does_not_fit():
@@ -81,3 +82,21 @@ def test_serve_stream_statistics():
             assert reqs[e["resend_of"]]["topo"] == e["topo"]
     par = w.serve_tree(reqs[0])
     assert par[0] == -1 and np.all(par[1:] < np.arange(1, len(par)))
+
+
+def test_batch_workspace_bound():
+    """The serving admission bounds a merged group's workspace by the sum of its
+    parts' plus the staging of rcr_batch_solve; the library's exact figure is the
+    merged plan's workspace plus that same staging (host only, no GPU)."""
+    rng = np.random.default_rng(4)
+    for n, m in ((4, 2), (8, 3), (12, 4)):
+        pars = [w.tree_chainprob(int(rng.integers(300, 5000)), 0.9, rng) for _ in range(7)]
+        plans = [rcr.Plan(p, n, m) for p in pars]
+        merged = rcr.Plan.batch(plans)
+        for prec in (rcr.FP64, rcr.MIXED32):
+            stage = serve.batch_staging_bytes([len(p) for p in pars], n, m)
+            exact = rcr.batch_workspace_size(plans, prec)
+            assert exact == merged.workspace_size(prec) + stage
+            assert exact <= sum(p.workspace_size(prec) for p in plans) + stage
+        assert merged.stats()["plan_device_bytes"] <= sum(p.stats()["plan_device_bytes"] for p in plans)
+        rcr.batch_release(plans)
