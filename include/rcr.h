@@ -329,6 +329,26 @@ void rcr_batch_release(const rcr_plan *const *plans, int32_t k);
  * copy table.  Builds and caches the merged plan if needed; 0 on error. */
 int64_t rcr_batch_workspace_size(const rcr_plan *const *plans, int32_t k, int32_t precision);
 
+/* ------------------------------------------------ solve without allocating */
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): rcr_solve
+ * with its workspace in a static device array of the library, one per GPU,
+ * rcr_noalloc_scratch_bytes() (64 MiB) large and held until the process
+ * ends.  The call makes no allocation: the plan must have been prepared by
+ * rcr_plan_upload on the current device (else RCR_BAD_OPTION), opt->executor
+ * must be RCR_EXEC_LEVELS and opt->workspace, kernel_ms and kernel_launches
+ * must be unset (else RCR_BAD_OPTION); a problem whose workspace
+ * (rcr_workspace_size) exceeds the array is rejected with
+ * RCR_SMALL_WORKSPACE.  All calls on one GPU share its array, which keeps the
+ * last call's contents: calls that overlap on one GPU (other streams, other
+ * threads) race and must be ordered by the caller.  Results equal those of
+ * rcr_solve bit for bit.  Errors: those of rcr_solve. */
+int rcr_solve_noalloc(const rcr_plan *plan, const rcr_problem *in, rcr_solution *out, const rcr_solve_options *opt,
+                      void *stream);
+
+/* Size in bytes of the per-GPU array of rcr_solve_noalloc. */
+int64_t rcr_noalloc_scratch_bytes(void);
+
 /* ------------------------------------------------- node-control problems */
 /* Scenario MPC with one control v_i per non-leaf node, shared by all its
  * outgoing transitions x_j = A_j x_i + B_j v_i + c_j (Sec. II-B, eq.

@@ -466,6 +466,23 @@ int64_t rcr_batch_workspace_size(const rcr_plan *const *plans, int32_t k, int32_
   return (int64_t)rcr::batch_workspace_bytes(B->obj.host, precision);
 }
 
+int rcr_solve_noalloc(const rcr_plan *plan, const rcr_problem *in, rcr_solution *out, const rcr_solve_options *opt,
+                      void *stream) {
+  if (!plan || !in || !out) return RCR_NULL_ARG;
+  const double *need[] = {in->Q, in->q, in->c, in->Delta, in->R, in->S, in->r, in->A, in->B,
+                          out->K, out->P, out->x, out->u, out->lam};
+  for (const double *p : need)
+    if (!p) return RCR_NULL_ARG;
+  rcr_solve_options o;
+  int rc = read_options(opt, o);
+  if (rc) return rc;
+  if (!has_device()) return RCR_NO_DEVICE;
+  rcr_plan *pl = const_cast<rcr_plan *>(plan);
+  return rcr::solve_noalloc(pl->obj, *in, *out, o, (hipStream_t)stream);
+}
+
+int64_t rcr_noalloc_scratch_bytes(void) { return (int64_t)rcr::noalloc_scratch_bytes(); }
+
 const char *rcr_status_string(int s) {
   switch (s) {
     case RCR_OK: return "ok";

@@ -267,6 +267,7 @@ int plan_upload(PlanObj &P, hipStream_t st) {
   // streams may use the arrays: wait for the copy
   hipError_t e = hipMemcpyAsync(base, stage, total, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess && !P.last_done) e = hipEventCreateWithFlags(&P.last_done, hipEventDisableTiming);
   if (pooled) stage_give(stage);
   if (e != hipSuccess) {
     fprintf(stderr, "rcr: plan upload failed: %s\n", hipGetErrorString(e));
@@ -1379,6 +1380,64 @@ int batch_solve(PlanObj &Bp, int32_t k, const rcr_problem *in, rcr_solution *out
   std::lock_guard<std::mutex> lock(Bp.mu);
   HIPCK(hipEventRecord(Bp.last_done, st));
   return RCR_OK;
+}
+
+
+// ------------------------------------------------------ no-allocation solve
+// rcr_solve_noalloc: rcr_solve on a workspace that is a static device array
+// (one per GPU, NOALLOC_SCRATCH_BYTES, held until the process ends), for
+// callers that cannot allocate.  Its address is looked up once per device with
+// that device current; the host-side name of the array is never handed to a
+// kernel or a copy.  Every call on a GPU shares that GPU's array: overlapping
+// calls race, and each call starts by clearing its status words and residual
+// accumulator with a fill kernel (no other part of the workspace needs to start
+// at zero).  Nothing here allocates: the plan's device copy and completion
+// event must exist (rcr_plan_upload), only the per-level executor is allowed
+// (capturing a graph allocates) and no timing events are made.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+}  // namespace
+
+static int scratch_address(int dev, void *&ptr) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return RCR_NO_DEVICE;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      fprintf(stderr, "rcr: hipGetSymbolAddress(scratch) failed on device %d: %s\n", dev, hipGetErrorString(e));
+      return RCR_HIP_ERROR;
+    }
+    scratch_ptr[dev] = p;
+  }
+  ptr = scratch_ptr[dev];
+  return RCR_OK;
+}
+
+size_t noalloc_scratch_bytes() { return NOALLOC_SCRATCH_BYTES; }
+
+int solve_noalloc(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_options &opt,
+                  hipStream_t st) {
+  if (opt.executor != RCR_EXEC_LEVELS || opt.kernel_ms || opt.kernel_launches || opt.workspace) return RCR_BAD_OPTION;
+  int dev = 0;
+  HIPCK(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lock(P.mu);
+    if (!P.dev.base || !P.last_done || P.dev.device != dev) return RCR_BAD_OPTION;  // rcr_plan_upload first
+  }
+  if (workspace_layout(P.host, opt.precision).total_bytes > NOALLOC_SCRATCH_BYTES) return RCR_SMALL_WORKSPACE;
+  void *ptr = nullptr;
+  const int rc = scratch_address(dev, ptr);
+  if (rc) return rc;
+  rcr_solve_options o = opt;
+  o.workspace = ptr;
+  o.workspace_bytes = (int64_t)NOALLOC_SCRATCH_BYTES;
+  return solve(P, in, out, o, st);
 }
 
 // ------------------------------------------------------------ autotuning

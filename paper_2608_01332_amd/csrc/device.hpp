@@ -139,6 +139,10 @@ int kkt_residual(PlanObj &P, const rcr_problem &in, const rcr_solution &sol, con
 int batch_solve(PlanObj &B, int32_t k, const rcr_problem *in, rcr_solution *out, const rcr_solve_options &opt,
                 hipStream_t stream);
 size_t batch_workspace_bytes(const PlanHost &B, int precision);
+// rcr_solve on the per-device static scratch array (no allocation).
+int solve_noalloc(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_options &opt,
+                  hipStream_t stream);
+size_t noalloc_scratch_bytes();
 
 int tune(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_options &opt, hipStream_t stream,
          LaunchCfg &best, float &best_ms);

@@ -97,7 +97,7 @@ EXPORTED = ("rcr_plan_create", "rcr_plan_info", "rcr_plan_device_bytes", "rcr_pl
             "rcr_plan_get_launch", "rcr_plan_tune",
             "rcr_workspace_size", "rcr_solve", "rcr_factor", "rcr_solve_rhs", "rcr_adjoint", "rcr_kkt_residual",
             "rcr_batch_solve", "rcr_batch_prepare", "rcr_batch_release", "rcr_batch_workspace_size",
-            "rcr_status_string")
+            "rcr_solve_noalloc", "rcr_noalloc_scratch_bytes", "rcr_status_string")
 
 _lib = None
 _lock = threading.Lock()
@@ -175,6 +175,11 @@ def lib():
             L.rcr_batch_release.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32]
             L.rcr_batch_workspace_size.restype = ctypes.c_int64
             L.rcr_batch_workspace_size.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_int32]
+            L.rcr_solve_noalloc.restype = ctypes.c_int
+            L.rcr_solve_noalloc.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.POINTER(Solution),
+                                            ctypes.POINTER(SolveOptions), ctypes.c_void_p]
+            L.rcr_noalloc_scratch_bytes.restype = ctypes.c_int64
+            L.rcr_noalloc_scratch_bytes.argtypes = []
             L.rcr_status_string.restype = ctypes.c_char_p
             L.rcr_status_string.argtypes = [ctypes.c_int]
             _lib = L
@@ -534,6 +539,29 @@ def kkt_residual(plan: Plan, prob: dict, sol: dict, workspace=None, stream=None)
     if rc != 0:
         raise RcrError(rc, "rcr_kkt_residual")
     return res.value
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(lib().rcr_noalloc_scratch_bytes())
+
+
+def solve_noalloc(plan: Plan, prob: dict, out: dict, precision: int = FP64, check: bool = False,
+                  kkt_residual: bool = False, refine_steps: int = -1, stream=None) -> dict:
+    """rcr_solve_noalloc: rcr_solve on the library's static per-GPU scratch array.
+    The plan must be uploaded (Plan.upload) and `out` preallocated."""
+    sh = _shapes(plan.N, plan.n, plan.m)
+    for k in PROBLEM_FIELDS:
+        _check(prob[k], k, sh[k])
+    for k in SOLUTION_FIELDS:
+        _check(out[k], k, sh[k])
+    p = Problem(**{k: prob[k].data_ptr() for k in PROBLEM_FIELDS})
+    s = Solution(**{k: out[k].data_ptr() for k in SOLUTION_FIELDS})
+    o, res, kms, kln = _options(precision, EXEC_LEVELS, check, refine_steps, None, kkt_residual, False)
+    rc = lib().rcr_solve_noalloc(plan._h, ctypes.byref(p), ctypes.byref(s), ctypes.byref(o),
+                                 ctypes.c_void_p(_stream(stream, prob["Q"].device).cuda_stream))
+    if rc != 0:
+        raise RcrError(rc, "rcr_solve_noalloc")
+    return _extras(dict(out), kkt_residual, False, res, kms, kln)
 
 
 def _plan_array(plans):
