@@ -397,6 +397,50 @@ int rcr_lift_plan_create(const int64_t *parent, int64_t N, int32_t n, int32_t m,
 int rcr_lift_solve(const rcr_plan *plan, const rcr_native_problem *in, rcr_native_solution *out,
                    const rcr_solve_options *opt, void *stream);
 
+/* ------------------------------------------- non-uniform dimensions */
+/* Trees whose node v has its own state dimension n_v and whose edge into v
+ * has its own control dimension m_v (uniform dimensions are a convenience of
+ * the presentation, Sec. II-A; static-shape backends may pad, Sec. VIII).
+ * Blocks are rectangular: for the edge e = (p, v), A_e is n_v x n_p, B_e
+ * n_v x m_v, S_e (the cross term M_e) n_p x m_v, K_e m_v x n_p.  The arrays are
+ * PACKED: field f holds the blocks of nodes (or edge slots) 0..N-1 one after
+ * another, row-major, each block of its own size (the root's edge blocks are
+ * empty); rcr_ragged_offsets gives where each block starts.  Fields, in the
+ * order of the offsets (index f):
+ *   0 Q (n_v^2)   1 q (n_v)   2 c (n_v)   3 Delta (n_v^2)   4 R (m_v^2)
+ *   5 S (n_p m_v) 6 r (m_v)   7 A (n_v n_p)   8 B (n_v m_v)
+ *   9 K (m_v n_p) 10 P (n_v^2) 11 x (n_v) 12 u (m_v) 13 lam (n_v)
+ * The solve pads every block to the largest dimensions (zeros, and the
+ * identity in the unused part of R): the padded coordinates decouple from the
+ * rest and solve to zero, so the real blocks of the padded solution are the
+ * solution. */
+#define RCR_RAGGED_FIELDS 14
+
+/* Plan of a tree with per-node state dimensions n_node[N] and per-edge control
+ * dimensions m_edge[N] (HOST int32 arrays; m_edge[root] is ignored), each in
+ * 1..RCR_MAX_DIM.  rcr_plan_info reports the padded n and m.  Errors: those of
+ * rcr_plan_create. */
+int rcr_ragged_plan_create(const int64_t *parent, int64_t N, const int32_t *n_node, const int32_t *m_edge,
+                           const rcr_plan_options *opt, rcr_plan **out);
+
+/* Element offsets of the blocks of a ragged plan: offsets[f * (N + 1) + v] is
+ * where node (or edge slot) v's block of field f starts in the packed array,
+ * offsets[f * (N + 1) + N] the array's length (HOST int64 array of
+ * RCR_RAGGED_FIELDS * (N + 1) entries).  Errors: RCR_NULL_ARG, RCR_BAD_OPTION
+ * (not a ragged plan). */
+int rcr_ragged_offsets(const rcr_plan *plan, int64_t *offsets);
+
+/* Factor and solve a ragged problem (packed DEVICE float64 arrays in the
+ * rcr_problem / rcr_solution structs, layouts above) with a plan from
+ * rcr_ragged_plan_create.  Options as for rcr_solve; a caller workspace must
+ * hold rcr_workspace_size(plan, precision) bytes (it includes the padded
+ * problem and solution); opt->kkt_residual reports the residual of the
+ * padded system, whose real rows are those of eq. (kkt).  A field of length 0
+ * (the edge arrays of a one-node tree) may be NULL.  Errors: those of
+ * rcr_solve; RCR_BAD_OPTION when the plan is not a ragged plan. */
+int rcr_ragged_solve(const rcr_plan *plan, const rcr_problem *in, rcr_solution *out, const rcr_solve_options *opt,
+                     void *stream);
+
 /* ------------------------------------------------------- launch mapping */
 /* How a plan maps its narrow dependency levels onto single-workgroup tail
  * kernels (the levels near the root hold few primitives; running them inside

@@ -19,6 +19,9 @@ Contents
               Shannon-Fano-Elias sibling reductions, earliest-start levels).
   algebra     the rake fold and compress composition of Sec. IV-A written
               out literally, for the elimination-identity pins.
+  ragged      per-node state and per-edge control dimensions: eq. (kkt)
+              assembled densely with rectangular blocks, and the sequential
+              recursion with rectangular blocks.
   adjoint     gradients of a scalar loss through the solve: the same solve
               with the seeds as right-hand side (the KKT matrix of eq. (kkt)
               is symmetric) and the outer products of each block's place in

@@ -201,6 +201,52 @@ int rcr_lift_solve(const rcr_plan *plan, const rcr_native_problem *in, rcr_nativ
   return rcr::lift_solve(pl->obj, *in, *out, o, (hipStream_t)stream);
 }
 
+int rcr_ragged_plan_create(const int64_t *parent, int64_t N, const int32_t *n_node, const int32_t *m_edge,
+                           const rcr_plan_options *opt, rcr_plan **out) {
+  if (!parent || !n_node || !m_edge || !out) return RCR_NULL_ARG;
+  *out = nullptr;
+  int selection = opt ? opt->selection : RCR_SELECT_GREEDY_INDEX;
+  rcr_plan *p = new_plan();
+  if (!p) return RCR_OOM;
+  int rc;
+  try {
+    rc = rcr::build_ragged_plan(parent, N, n_node, m_edge, selection, p->obj.host);
+  } catch (const std::bad_alloc &) {
+    rc = RCR_OOM;
+  }
+  if (rc) {
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return RCR_OK;
+}
+
+int rcr_ragged_offsets(const rcr_plan *plan, int64_t *offsets) {
+  if (!plan || !offsets) return RCR_NULL_ARG;
+  const rcr::PlanHost &h = plan->obj.host;
+  if (h.rg_off.empty()) return RCR_BAD_OPTION;
+  memcpy(offsets, h.rg_off.data(), h.rg_off.size() * sizeof(int64_t));
+  return RCR_OK;
+}
+
+int rcr_ragged_solve(const rcr_plan *plan, const rcr_problem *in, rcr_solution *out, const rcr_solve_options *opt,
+                     void *stream) {
+  if (!plan || !in || !out) return RCR_NULL_ARG;
+  const rcr::PlanHost &h = plan->obj.host;
+  if (h.rg_n.empty()) return RCR_BAD_OPTION;
+  const double *need[] = {in->Q, in->q, in->c, in->Delta, in->R, in->S, in->r, in->A, in->B,
+                          out->K, out->P, out->x, out->u, out->lam};
+  for (int f = 0; f < rcr::RG_FIELDS; ++f)  // an empty field (a one-node tree's edge arrays) may be NULL
+    if (!need[f] && h.rg_off[(size_t)(f * (h.N + 1) + h.N)] > 0) return RCR_NULL_ARG;
+  rcr_solve_options o;
+  int rc = read_options(opt, o);
+  if (rc) return rc;
+  if (!has_device()) return RCR_NO_DEVICE;
+  rcr_plan *pl = const_cast<rcr_plan *>(plan);
+  return rcr::ragged_solve(pl->obj, *in, *out, o, (hipStream_t)stream);
+}
+
 int rcr_batch_plan_create(const rcr_plan *const *plans, int32_t k, rcr_plan **out) {
   if (!plans || !out || k < 1) return RCR_NULL_ARG;
   *out = nullptr;

@@ -102,7 +102,7 @@ static void lift_words(int d, int m, size_t in_w[9], size_t out_w[5]) {
 
 size_t total_workspace_bytes(const PlanHost &ph, int precision) {
   size_t cur = workspace_layout(ph, precision).total_bytes;
-  if (!ph.lift_N) return cur;
+  if (!ph.lift_N && ph.rg_n.empty()) return cur;  // lifted and ragged plans stage a uniform problem
   size_t iw[9], ow[5];
   lift_words(ph.n, ph.m, iw, ow);
   for (int k = 0; k < 9; ++k) cur = align_up(cur + iw[k] * 8 * (size_t)ph.N, 256);
@@ -152,7 +152,7 @@ void stage_give(char *b) {
 
 // Byte sizes of the pieces of a plan's device copy, in their order in the
 // allocation (each piece starts on a 256-byte boundary); returns the total.
-constexpr int PLAN_PIECES = 13;
+constexpr int PLAN_PIECES = 16;
 static size_t plan_pieces(const PlanHost &h, size_t bytes[PLAN_PIECES], size_t at[PLAN_PIECES]) {
   const int64_t NC = std::max<int64_t>(h.N, 1);
   const size_t b[PLAN_PIECES] = {
@@ -169,6 +169,9 @@ static size_t plan_pieces(const PlanHost &h, size_t bytes[PLAN_PIECES], size_t a
       h.tc_off.size() * sizeof(int64_t),
       h.sx_off.size() * sizeof(int64_t),
       h.lift_plus.size() * sizeof(int32_t),
+      h.rg_n.size() * sizeof(int32_t),
+      h.rg_m.size() * sizeof(int32_t),
+      h.rg_off.size() * sizeof(int64_t),
   };
   size_t total = 0;
   for (int k = 0; k < PLAN_PIECES; ++k) {
@@ -211,6 +214,9 @@ int plan_upload(PlanObj &P, hipStream_t st) {
       {(void **)&P.dev.tc_off, h.tc_off.data()},
       {(void **)&P.dev.sx_off, h.sx_off.data()},
       {(void **)&P.dev.lift_plus, h.lift_plus.data()},
+      {(void **)&P.dev.rg_n, h.rg_n.data()},
+      {(void **)&P.dev.rg_m, h.rg_m.data()},
+      {(void **)&P.dev.rg_off, h.rg_off.data()},
   };
   constexpr int NP = PLAN_PIECES;
   const int64_t NC = std::max<int64_t>(h.N, 1);
@@ -1575,6 +1581,113 @@ __global__ __launch_bounds__(256) void k_project(int64_t N, int n, int m, const 
     const int32_t k = plus[i];
     vv[t] = k >= 0 ? ul[(int64_t)k * m + b] : 0.0;
   }
+}
+
+// The uniform float64 problem and solution that lifted and ragged plans stage
+// after the solver's workspace (9 problem arrays, then 5 solution arrays).
+static void staged_ptrs(const PlanHost &h, void *ws, int prec, double *ptr[14]) {
+  size_t iw[9], ow[5];
+  lift_words(h.n, h.m, iw, ow);
+  size_t cur = workspace_layout(h, prec).total_bytes;
+  for (int k = 0; k < 14; ++k) {
+    ptr[k] = reinterpret_cast<double *>(static_cast<char *>(ws) + cur);
+    cur = align_up(cur + (k < 9 ? iw[k] : ow[k - 9]) * 8 * (size_t)h.N, 256);
+  }
+}
+
+// Ragged problems (node v of state dimension nv = rg_n[v], the edge into it of
+// control dimension mv = rg_m[v], the parent's dimension np) padded to the
+// uniform n, m: every block sits in the top-left corner of its padded block,
+// zeros elsewhere, except the control cost, padded with the identity.  The
+// padded coordinates decouple (their rows of the dynamics give x = 0, of the
+// stationarities y = 0 and u = 0) and the standing assumptions still hold, so
+// the padded solution restricted to the real coordinates is the solution,
+// and P, K are the padded ones' top-left blocks.  One wavefront per node.
+// Offsets off[f * (N + 1) + v] locate v's block of field f in the packed arrays.
+__global__ __launch_bounds__(256) void k_ragged_pack(int64_t N, int n, int m, const int32_t *__restrict__ parent,
+                                                     const int32_t *__restrict__ rn, const int32_t *__restrict__ rm,
+                                                     const int64_t *__restrict__ off, rcr_problem in, LiftedPtrs o) {
+  const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (v >= N) return;
+  const int64_t N1 = N + 1;
+  const int nv = rn[v], mv = rm[v], pv = parent[v], np = pv >= 0 ? rn[pv] : 0;
+  const int64_t nn = (int64_t)n * n, nm = (int64_t)n * m, mm = (int64_t)m * m;
+  for (int e = lane; e < n * n; e += 64) {
+    const int a = e / n, b = e % n;
+    const bool xx = a < nv && b < nv;
+    o.Q[v * nn + e] = xx ? in.Q[off[0 * N1 + v] + a * nv + b] : 0.0;
+    o.De[v * nn + e] = xx ? in.Delta[off[3 * N1 + v] + a * nv + b] : 0.0;
+    o.A[v * nn + e] = (a < nv && b < np) ? in.A[off[7 * N1 + v] + a * np + b] : 0.0;
+  }
+  for (int e = lane; e < n; e += 64) {
+    o.q[v * n + e] = e < nv ? in.q[off[1 * N1 + v] + e] : 0.0;
+    o.c[v * n + e] = e < nv ? in.c[off[2 * N1 + v] + e] : 0.0;
+  }
+  for (int e = lane; e < m * m; e += 64) {
+    const int a = e / m, b = e % m;
+    o.R[v * mm + e] = (a < mv && b < mv) ? in.R[off[4 * N1 + v] + a * mv + b] : (a == b ? 1.0 : 0.0);
+  }
+  for (int e = lane; e < n * m; e += 64) {
+    const int a = e / m, b = e % m;
+    o.S[v * nm + e] = (a < np && b < mv) ? in.S[off[5 * N1 + v] + a * mv + b] : 0.0;
+    o.B[v * nm + e] = (a < nv && b < mv) ? in.B[off[8 * N1 + v] + a * mv + b] : 0.0;
+  }
+  for (int e = lane; e < m; e += 64) o.r[v * m + e] = e < mv ? in.r[off[6 * N1 + v] + e] : 0.0;
+}
+
+// The real blocks of the padded solution into the caller's packed arrays.
+__global__ __launch_bounds__(256) void k_ragged_unpack(int64_t N, int n, int m, const int32_t *__restrict__ parent,
+                                                       const int32_t *__restrict__ rn, const int32_t *__restrict__ rm,
+                                                       const int64_t *__restrict__ off, rcr_solution po,
+                                                       rcr_solution out) {
+  const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (v >= N) return;
+  const int64_t N1 = N + 1;
+  const int nv = rn[v], mv = rm[v], pv = parent[v], np = pv >= 0 ? rn[pv] : 0;
+  for (int e = lane; e < nv * nv; e += 64) out.P[off[10 * N1 + v] + e] = po.P[v * n * n + (e / nv) * n + e % nv];
+  for (int e = lane; e < mv * np; e += 64) out.K[off[9 * N1 + v] + e] = po.K[v * m * n + (e / np) * n + e % np];
+  for (int e = lane; e < nv; e += 64) {
+    out.x[off[11 * N1 + v] + e] = po.x[v * n + e];
+    out.lam[off[13 * N1 + v] + e] = po.lam[v * n + e];
+  }
+  for (int e = lane; e < mv; e += 64) out.u[off[12 * N1 + v] + e] = po.u[v * m + e];
+}
+
+int ragged_solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_options &opt,
+                 hipStream_t st) {
+  const PlanHost &h = P.host;
+  if (h.rg_n.empty()) return RCR_BAD_OPTION;
+  const int prec = opt.precision;
+  void *ws = opt.workspace;
+  const size_t need = total_workspace_bytes(h, prec);
+  {
+    std::lock_guard<std::mutex> lock(P.mu);
+    int rc = plan_upload(P, st);
+    if (rc) return rc;
+    if ((rc = take_workspace(P, opt, need, need, st, ws))) return rc;
+  }
+  double *ptr[14];
+  staged_ptrs(h, ws, prec, ptr);
+  const LiftedPtrs lp{ptr[0], ptr[1], ptr[2], ptr[3], ptr[4], ptr[5], ptr[6], ptr[7], ptr[8]};
+  const dim3 g((unsigned)((h.N + 3) / 4)), b(256);
+  hipLaunchKernelGGL(k_ragged_pack, g, b, 0, st, h.N, h.n, h.m, P.dev.parent, P.dev.rg_n, P.dev.rg_m, P.dev.rg_off,
+                     in, lp);
+  HIPCK(hipGetLastError());
+  const rcr_problem pin{ptr[0], ptr[1], ptr[2], ptr[3], ptr[4], ptr[5], ptr[6], ptr[7], ptr[8]};
+  rcr_solution pout{ptr[9], ptr[10], ptr[11], ptr[12], ptr[13]};
+  rcr_solve_options o2 = opt;
+  o2.workspace = ws;
+  o2.workspace_bytes = (int64_t)workspace_layout(h, prec).total_bytes;
+  int rc = solve(P, pin, pout, o2, st);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_ragged_unpack, g, b, 0, st, h.N, h.n, h.m, P.dev.parent, P.dev.rg_n, P.dev.rg_m,
+                     P.dev.rg_off, pout, out);
+  HIPCK(hipGetLastError());
+  std::lock_guard<std::mutex> lock(P.mu);
+  HIPCK(hipEventRecord(P.last_done, st));
+  return RCR_OK;
 }
 
 int lift_solve(PlanObj &P, const rcr_native_problem &in, rcr_native_solution &out, const rcr_solve_options &opt,

@@ -35,6 +35,8 @@ struct PlanDev {
   int64_t n_hubs = 0;
   int64_t *koff = nullptr, *exp_off = nullptr, *tc_off = nullptr, *sx_off = nullptr;  // level offsets
   int32_t *lift_plus = nullptr;  // lifted plans: decision node of each native non-leaf
+  int32_t *rg_n = nullptr, *rg_m = nullptr;  // ragged plans: per-node dimensions
+  int64_t *rg_off = nullptr;                 // ragged plans: block offsets of the packed arrays
   size_t bytes = 0;
 };
 
@@ -146,6 +148,10 @@ size_t noalloc_scratch_bytes();
 
 int tune(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_options &opt, hipStream_t stream,
          LaunchCfg &best, float &best_ms);
+
+// Non-uniform dimensions: pack into the padded uniform problem, solve, unpack.
+int ragged_solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_options &opt,
+                 hipStream_t stream);
 
 int lift_solve(PlanObj &P, const rcr_native_problem &in, rcr_native_solution &out, const rcr_solve_options &opt,
                hipStream_t stream);

@@ -562,10 +562,42 @@ int build_lift_plan(const int64_t *parent, int64_t N, int n, int m, int selectio
   return RCR_OK;
 }
 
+int build_ragged_plan(const int64_t *parent, int64_t N, const int32_t *n_node, const int32_t *m_edge, int selection,
+                      PlanHost &out) {
+  if (!parent || !n_node || !m_edge) return RCR_NULL_ARG;
+  if (N < 1) return RCR_BAD_DIMS;
+  int nmax = 1, mmax = 1;
+  for (int64_t v = 0; v < N; ++v) {
+    if (parent[v] < -1 || parent[v] >= N) return RCR_INVALID_TREE;
+    if (n_node[v] < 1 || n_node[v] > RCR_MAX_DIM) return RCR_BAD_DIMS;
+    nmax = std::max(nmax, (int)n_node[v]);
+    if (parent[v] >= 0) {
+      if (m_edge[v] < 1 || m_edge[v] > RCR_MAX_DIM) return RCR_BAD_DIMS;
+      mmax = std::max(mmax, (int)m_edge[v]);
+    }
+  }
+  const int rc = build_plan(parent, N, nmax, mmax, selection, out);
+  if (rc) return rc;
+  out.rg_n.assign(n_node, n_node + N);
+  out.rg_m.resize((size_t)N);
+  for (int64_t v = 0; v < N; ++v) out.rg_m[(size_t)v] = parent[v] >= 0 ? m_edge[v] : 0;
+  // block sizes per field (node v, edge slot v = (parent, v)): Q q c Delta R S r A B, K P x u lam
+  const int64_t N1 = N + 1;
+  out.rg_off.assign((size_t)(RG_FIELDS * N1), 0);
+  for (int64_t v = 0; v < N; ++v) {
+    const int64_t nv = out.rg_n[(size_t)v], mv = out.rg_m[(size_t)v];
+    const int64_t np = parent[v] >= 0 ? out.rg_n[(size_t)parent[v]] : 0;
+    const int64_t sz[RG_FIELDS] = {nv * nv, nv, nv, nv * nv, mv * mv, np * mv, mv,
+                                   nv * np, nv * mv, mv * np, nv * nv, nv, mv, nv};
+    for (int f = 0; f < RG_FIELDS; ++f) out.rg_off[(size_t)(f * N1 + v + 1)] = out.rg_off[(size_t)(f * N1 + v)] + sz[f];
+  }
+  return RCR_OK;
+}
+
 int merge_plans(const std::vector<const PlanHost *> &parts, PlanHost &out) {
   if (parts.empty()) return RCR_NULL_ARG;
   for (const PlanHost *p : parts)
-    if (p && p->lift_N) return RCR_BAD_OPTION;  // lifted plans are solved through rcr_lift_solve
+    if (p && (p->lift_N || !p->rg_n.empty())) return RCR_BAD_OPTION;  // solved through their own entry points
   const int n = parts[0]->n, m = parts[0]->m;
   out = PlanHost();
   out.n = n;

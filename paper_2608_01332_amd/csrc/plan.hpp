@@ -74,6 +74,14 @@ struct PlanHost {
   int lift_n = 0;
   std::vector<int32_t> lift_plus;
 
+  // ragged plans: node v has state dimension rg_n[v] and the edge into it
+  // control dimension rg_m[v] (0 at the root), all padded to n and m for the
+  // solve; rg_off[f * (N + 1) + v] is the element offset of v's block of field
+  // f (RG_FIELDS, in the order of rcr_ragged_offsets) in the caller's packed
+  // arrays, rg_off[f * (N + 1) + N] the field's length.  Empty otherwise.
+  std::vector<int32_t> rg_n, rg_m;
+  std::vector<int64_t> rg_off;
+
   int64_t levels() const { return (int64_t)lvl_off.size() - 1; }
   int64_t expand_levels() const { return (int64_t)exp_off.size() - 1; }
   int64_t state_levels() const { return (int64_t)tc_off.size() - 1; }
@@ -90,6 +98,16 @@ int build_plan(const int64_t *parent, int64_t N, int n, int m, int selection, Pl
 // dimension m: the lifted state has dimension n + m.  Returns 0 or a negative
 // RCR_* status.
 int build_lift_plan(const int64_t *parent, int64_t N, int n, int m, int selection, PlanHost &out);
+
+// Fields of a ragged problem and solution, in the order of rcr_ragged_offsets.
+constexpr int RG_FIELDS = 14;
+
+// Plan of a tree whose node v has state dimension n_node[v] and whose edge into
+// v has control dimension m_edge[v] (ignored at the root): the topology plan
+// of build_plan for the largest dimensions, plus the block offsets of the
+// packed (ragged) arrays.  Returns 0 or a negative RCR_* status.
+int build_ragged_plan(const int64_t *parent, int64_t N, const int32_t *n_node, const int32_t *m_edge, int selection,
+                      PlanHost &out);
 
 // Merge the plans of independent trees into one plan of their forest: node,
 // edge and contribution slots are offset per tree, and dependency level t of

@@ -97,7 +97,8 @@ EXPORTED = ("rcr_plan_create", "rcr_plan_info", "rcr_plan_device_bytes", "rcr_pl
             "rcr_plan_get_launch", "rcr_plan_tune",
             "rcr_workspace_size", "rcr_solve", "rcr_factor", "rcr_solve_rhs", "rcr_adjoint", "rcr_kkt_residual",
             "rcr_batch_solve", "rcr_batch_prepare", "rcr_batch_release", "rcr_batch_workspace_size",
-            "rcr_solve_noalloc", "rcr_noalloc_scratch_bytes", "rcr_status_string")
+            "rcr_solve_noalloc", "rcr_noalloc_scratch_bytes", "rcr_ragged_plan_create", "rcr_ragged_offsets",
+            "rcr_ragged_solve", "rcr_status_string")
 
 _lib = None
 _lock = threading.Lock()
@@ -180,6 +181,14 @@ def lib():
                                             ctypes.POINTER(SolveOptions), ctypes.c_void_p]
             L.rcr_noalloc_scratch_bytes.restype = ctypes.c_int64
             L.rcr_noalloc_scratch_bytes.argtypes = []
+            L.rcr_ragged_plan_create.restype = ctypes.c_int
+            L.rcr_ragged_plan_create.argtypes = [_i64p, ctypes.c_int64, _i32p, _i32p, ctypes.POINTER(PlanOptions),
+                                                 ctypes.POINTER(ctypes.c_void_p)]
+            L.rcr_ragged_offsets.restype = ctypes.c_int
+            L.rcr_ragged_offsets.argtypes = [ctypes.c_void_p, _i64p]
+            L.rcr_ragged_solve.restype = ctypes.c_int
+            L.rcr_ragged_solve.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.POINTER(Solution),
+                                           ctypes.POINTER(SolveOptions), ctypes.c_void_p]
             L.rcr_status_string.restype = ctypes.c_char_p
             L.rcr_status_string.argtypes = [ctypes.c_int]
             _lib = L
@@ -230,6 +239,34 @@ class Plan:
         st = self.stats()
         self.N, self.n, self.m = st["N"], st["n"], st["m"]
         self.native_N, self.native_n = int(self._parent.shape[0]), int(n)
+        return self
+
+    @classmethod
+    def ragged(cls, parent, n_node, m_edge, selection: int = SELECT_GREEDY_INDEX) -> "Plan":
+        """Plan of a tree with per-node state and per-edge control dimensions
+        (rcr_ragged_plan_create); solve it with ragged_solve on packed arrays."""
+        L = lib()
+        self = cls.__new__(cls)
+        self._parent = np.ascontiguousarray(parent, dtype=np.int64)
+        nn = np.ascontiguousarray(n_node, dtype=np.int32)
+        mm = np.ascontiguousarray(m_edge, dtype=np.int32)
+        self.N = int(self._parent.shape[0])
+        if nn.shape != (self.N,) or mm.shape != (self.N,):
+            raise ValueError("n_node and m_edge need one entry per node")
+        h = ctypes.c_void_p()
+        opt = PlanOptions(selection=selection)
+        rc = L.rcr_ragged_plan_create(self._parent.ctypes.data_as(_i64p), self.N, nn.ctypes.data_as(_i32p),
+                                      mm.ctypes.data_as(_i32p), ctypes.byref(opt), ctypes.byref(h))
+        if rc != 0:
+            raise RcrError(rc, "rcr_ragged_plan_create")
+        self._h = h
+        st = self.stats()
+        self.n, self.m = st["n"], st["m"]
+        off = np.zeros(RAGGED_FIELDS_COUNT * (self.N + 1), dtype=np.int64)
+        rc = L.rcr_ragged_offsets(self._h, off.ctypes.data_as(_i64p))
+        if rc != 0:
+            raise RcrError(rc, "rcr_ragged_offsets")
+        self.ragged_offsets = {f: off[i * (self.N + 1):(i + 1) * (self.N + 1)] for i, f in enumerate(RAGGED_FIELDS)}
         return self
 
     def __init__(self, parent, n: int, m: int, selection: int = SELECT_GREEDY_INDEX):
@@ -331,6 +368,8 @@ class Plan:
 
 PROBLEM_FIELDS = ("Q", "q", "c", "Delta", "R", "S", "r", "A", "B")
 SOLUTION_FIELDS = ("K", "P", "x", "u", "lam")
+RAGGED_FIELDS = PROBLEM_FIELDS + SOLUTION_FIELDS  # the order of rcr_ragged_offsets
+RAGGED_FIELDS_COUNT = len(RAGGED_FIELDS)
 
 
 def _shapes(N, n, m):
@@ -561,6 +600,33 @@ def solve_noalloc(plan: Plan, prob: dict, out: dict, precision: int = FP64, chec
                                  ctypes.c_void_p(_stream(stream, prob["Q"].device).cuda_stream))
     if rc != 0:
         raise RcrError(rc, "rcr_solve_noalloc")
+    return _extras(dict(out), kkt_residual, False, res, kms, kln)
+
+
+def ragged_solve(plan: Plan, prob: dict, out: dict | None = None, precision: int = FP64, executor: int = EXEC_LEVELS,
+                 check: bool = False, kkt_residual: bool = False, refine_steps: int = -1, workspace=None,
+                 stream=None) -> dict:
+    """rcr_ragged_solve: packed 1-D float64 device tensors (lengths from
+    plan.ragged_offsets) for the problem fields; returns the packed solution."""
+    import torch
+    off = getattr(plan, "ragged_offsets", None)
+    if off is None:
+        raise ValueError("ragged_solve needs a plan from Plan.ragged")
+    for k in PROBLEM_FIELDS:
+        _check(prob[k], k, (int(off[k][-1]),))
+    dev = prob["Q"].device
+    if out is None:
+        out = {k: torch.empty(max(int(off[k][-1]), 1), dtype=torch.float64, device=dev)[:int(off[k][-1])]
+               for k in SOLUTION_FIELDS}
+    for k in SOLUTION_FIELDS:
+        _check(out[k], k, (int(off[k][-1]),))
+    p = Problem(**{k: prob[k].data_ptr() for k in PROBLEM_FIELDS})
+    s = Solution(**{k: out[k].data_ptr() for k in SOLUTION_FIELDS})
+    o, res, kms, kln = _options(precision, executor, check, refine_steps, workspace, kkt_residual, False)
+    rc = lib().rcr_ragged_solve(plan._h, ctypes.byref(p), ctypes.byref(s), ctypes.byref(o),
+                                ctypes.c_void_p(_stream(stream, dev).cuda_stream))
+    if rc != 0:
+        raise RcrError(rc, "rcr_ragged_solve")
     return _extras(dict(out), kkt_residual, False, res, kms, kln)
 
 

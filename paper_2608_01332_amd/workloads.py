@@ -358,3 +358,66 @@ def config2_lift_instance(resolve: int = 0):
     data = native_node_control_data(parent, DataSpec(12, 4, delta_rank=6, delta_scale=1e-2),
                                     np.random.default_rng(seed + 104729))
     return parent, data
+
+
+# --------------------------------------------------------------------------- ragged
+def ragged_instance(N: int, nmax: int, mmax: int, rng: np.random.Generator, p: float = 0.9, delta: bool = True,
+                    cross: bool = True, nmin: int = 1, mmin: int = 1):
+    """A tree with per-node state dimensions n_v in [nmin, nmax] and per-edge
+    control dimensions m_v in [mmin, mmax] (m at the root: 0), and data as lists
+    of per-node blocks with the distributions of lqr_data (A_e = the n_j x n_i
+    corner of I plus 0.1 G / sqrt(n_i); S_e = L_Q Xi L_R^T / (2 sqrt(deg)) keeps
+    Definition 1).  Returns (parent, n_node, m_edge, blocks)."""
+    parent = tree_chainprob(N, p, rng)
+    n_node = rng.integers(nmin, nmax + 1, size=N).astype(np.int32)
+    m_edge = rng.integers(mmin, mmax + 1, size=N).astype(np.int32)
+    m_edge[parent < 0] = 0
+    deg = np.bincount(parent[parent >= 0], minlength=N)
+    d = {k: [] for k in ("Q", "q", "c", "Delta", "R", "S", "r", "A", "B")}
+    for v in range(N):
+        nv, mv = int(n_node[v]), int(m_edge[v])
+        pv = int(parent[v])
+        npar = int(n_node[pv]) if pv >= 0 else 0
+        G = rng.standard_normal((nv, nv))
+        d["Q"].append(G @ G.T / nv + 0.1 * np.eye(nv))
+        d["q"].append(rng.standard_normal(nv))
+        d["c"].append(rng.standard_normal(nv) * 0.1)
+        if delta and nv > 1:
+            k = nv // 2
+            V, _ = np.linalg.qr(rng.standard_normal((nv, k)))
+            d["Delta"].append(V @ np.diag(rng.random(k) * 1e-2) @ V.T)
+        else:
+            d["Delta"].append(np.zeros((nv, nv)))
+        d["A"].append(np.eye(nv, npar) + 0.1 * rng.standard_normal((nv, npar)) / np.sqrt(max(npar, 1)))
+        d["B"].append(rng.standard_normal((nv, mv)) / np.sqrt(nv))
+        Wm = rng.standard_normal((mv, mv))
+        d["R"].append(Wm @ Wm.T / max(mv, 1) + np.eye(mv))
+        d["r"].append(rng.standard_normal(mv))
+        d["S"].append(np.zeros((npar, mv)))
+    if cross:
+        for v in range(N):
+            pv = int(parent[v])
+            if pv < 0:
+                continue
+            LQ = np.linalg.cholesky(d["Q"][pv])
+            LR = np.linalg.cholesky(d["R"][v])
+            Xi = rng.standard_normal((LQ.shape[0], LR.shape[0]))
+            Xi /= np.linalg.norm(Xi, ord=2)
+            d["S"][v] = LQ @ Xi @ LR.T / (2.0 * np.sqrt(max(deg[pv], 1)))
+    return parent, n_node, m_edge, d
+
+
+def pack_ragged(blocks: dict) -> dict:
+    """Packed arrays of a ragged problem (the blocks of every node, row-major, one
+    after another in node order: the layout of rcr_ragged_solve)."""
+    return {k: (np.concatenate([np.ravel(b) for b in v]) if v else np.zeros(0)) for k, v in blocks.items()}
+
+
+def unpack_ragged(flat: np.ndarray, shapes) -> list:
+    """The per-node blocks of a packed array, given each block's shape."""
+    out, at = [], 0
+    for sh in shapes:
+        size = int(np.prod(sh)) if len(sh) else 1
+        out.append(flat[at:at + size].reshape(sh))
+        at += size
+    return out

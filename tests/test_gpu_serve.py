@@ -62,6 +62,28 @@ def test_serve_results_identical_alone_and_in_mix():
     srv.close()
 
 
+def test_serve_full_request_distribution():
+    """Requests drawn from the full serving distribution (N log-uniform in [1k, 128k],
+    n in {4, 8, 12, 16}, m in {2, 4}; this seed has three n = 16, m = 4 requests of
+    more than 100k nodes): each served result equals the request solved alone, bit
+    for bit, and merged groups occur."""
+    print("[gpu-serve] 20 requests of the full distribution, 4 slots", flush=True)
+    reqs = _requests(20, seed=8, n_choices=(4, 8, 12, 16), m_choices=(2, 4), N_range=(1024, 131072))
+    assert max(r.N for r in reqs if (r.n, r.m) == (16, 4)) > 100000
+    srv = serve.Server("cuda:0", slots=4, planner_threads=4)
+    for r in reqs:  # all at once: the slots fill and the rest queue, so groups form
+        srv.submit(r)
+    srv.drain()
+    assert len(srv.done) == len(reqs) and srv.in_use == 0
+    assert max(r.group_size for r in reqs) > 1, "no request was merged into a group"
+    for r in reqs:
+        a = _alone(r)
+        assert a["kkt_residual"] <= 1e-8, (r.rid, a["kkt_residual"])
+        for k in rcr.SOLUTION_FIELDS:
+            assert torch.equal(a[k], r.out[k]), (r.rid, r.group_size, k)
+    srv.close()
+
+
 def test_serve_mixed32_against_oracle():
     print("[gpu-serve] oracle parity of served results", flush=True)
     reqs = _requests(6, seed=5, n_choices=(4, 12), m_choices=(2, 4))
