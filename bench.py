@@ -619,10 +619,15 @@ def main() -> int:
     # in the tail kernel).  Its algorithmic bytes are those of the ops in its own
     # levels, at the fixed words per primitive (rake 5s, combine 3s, absorb 3s,
     # compress 10s; a rake's expansion P_j = U_j, fused into it, is not counted).
+    # When the first level is fused with the condensation, that launch also
+    # condenses every edge: the condensation's words E (5s + 2t + v) count too.
     ops = plan.export_ops()
     k_q = cls_n.get("quad_contract", 0) // reps
     sel = ops[ops[:, 2] <= k_q]
     words_q = sum(int((sel[:, 0] == kind).sum()) * mult * n * n for kind, mult in CONTRACT_WORDS.items())
+    fused_condense = cls_n.get("condense", 0) == 0  # level 1 condenses every edge in its own launch
+    if fused_condense:
+        words_q += words["condense"]
     dom = "quad_contract"
     dom_ms = cls_ms[dom] / reps
     dom_launches = cls_n[dom] / reps
@@ -661,6 +666,7 @@ def main() -> int:
                      "bytes_per_launch": bytes_per_solve / dom_launches,
                      "avg_launch_us": avg_launch_s * 1e6,
                      "launches_per_step": dom_launches,
+                     "includes_condensation": fused_condense,
                      "fp64_tflops": (flops / avg_launch_s / 1e12) if flops is not None else None,
                      "fp64_peak_tflops": PEAK_FP64_TFLOPS,
                      "fp64_flop_frac": (flops / avg_launch_s / 1e12 / PEAK_FP64_TFLOPS) if flops is not None else None},

@@ -152,7 +152,7 @@ void stage_give(char *b) {
 
 // Byte sizes of the pieces of a plan's device copy, in their order in the
 // allocation (each piece starts on a 256-byte boundary); returns the total.
-constexpr int PLAN_PIECES = 16;
+constexpr int PLAN_PIECES = 18;
 static size_t plan_pieces(const PlanHost &h, size_t bytes[PLAN_PIECES], size_t at[PLAN_PIECES]) {
   const int64_t NC = std::max<int64_t>(h.N, 1);
   const size_t b[PLAN_PIECES] = {
@@ -172,6 +172,8 @@ static size_t plan_pieces(const PlanHost &h, size_t bytes[PLAN_PIECES], size_t a
       h.rg_n.size() * sizeof(int32_t),
       h.rg_m.size() * sizeof(int32_t),
       h.rg_off.size() * sizeof(int64_t),
+      (size_t)NC * sizeof(int32_t),  // U liveness per node
+      (size_t)NC * sizeof(int32_t),  // edge slots condensed on their own
   };
   size_t total = 0;
   for (int k = 0; k < PLAN_PIECES; ++k) {
@@ -217,6 +219,8 @@ int plan_upload(PlanObj &P, hipStream_t st) {
       {(void **)&P.dev.rg_n, h.rg_n.data()},
       {(void **)&P.dev.rg_m, h.rg_m.data()},
       {(void **)&P.dev.rg_off, h.rg_off.data()},
+      {(void **)&P.dev.uabs, nullptr},
+      {(void **)&P.dev.rest, nullptr},
   };
   constexpr int NP = PLAN_PIECES;
   const int64_t NC = std::max<int64_t>(h.N, 1);
@@ -260,6 +264,53 @@ int plan_upload(PlanObj &P, hipStream_t st) {
     for (int64_t i = 0; i < N; ++i)
       if (coff[i + 1] - coff[i] > RES_HUB) hubs[nh++] = (int32_t)i;
     P.dev.n_hubs = nh;
+  }
+  {  // flags of the device records and the lists of the fused first level (flags_and_lists)
+    OpRec *dops = reinterpret_cast<OpRec *>(stage + at[0]);
+    Op4 *dexp = reinterpret_cast<Op4 *>(stage + at[1]);
+    int32_t *uabs = reinterpret_cast<int32_t *>(stage + at[16]);
+    int32_t *rest = reinterpret_cast<int32_t *>(stage + at[17]);
+    const size_t nops = h.ops.size(), nexp = h.exp_ops.size();
+    const int64_t N = h.N;
+    memset(uabs, 0, (size_t)NC * sizeof(int32_t));
+    // ops are sorted by level: the first absorb of a node is the first one met
+    for (size_t i = 0; i < nops; ++i) {
+      OpRec &o = dops[i];
+      int32_t f = 0;
+      if (o.kind == OP_ABSORB) {
+        if (!uabs[o.a]) f |= OPF_FIRST_ABSORB;
+        uabs[o.a] = 1;
+      }
+      o.round = f;
+    }
+    for (size_t i = 0; i < nops; ++i) {
+      OpRec &o = dops[i];
+      if ((o.kind == OP_RAKE || o.kind == OP_COMPRESS) && uabs[o.a]) o.round |= OPF_U_LIVE;
+    }
+    for (size_t i = 0; i < nexp; ++i) dexp[i].d = uabs[dexp[i].a] ? OPF_U_LIVE : 0;
+    // level 1 can be fused with the condensation when it holds only rakes and
+    // compresses whose edges are original slots (the first round's)
+    bool ok = h.levels() >= 1 && h.kind_off.size() >= 5 && h.kind_off[1] == h.kind_off[2] &&
+              h.kind_off[2] == h.kind_off[3];
+    std::vector<char> used(ok ? (size_t)N : 0, 0);
+    for (int64_t i = ok ? h.kind_off[0] : 0; ok && i < h.kind_off[4]; ++i) {
+      const OpRec &o = h.ops[(size_t)i];
+      if (o.kind == OP_RAKE) {
+        ok = o.b == o.a && o.a < N;
+        if (ok) used[(size_t)o.a] = 1;
+      } else if (o.kind == OP_COMPRESS) {
+        ok = o.b == o.a && o.a < N && o.c >= 0 && o.c < N;
+        if (ok) used[(size_t)o.a] = used[(size_t)o.c] = 1;
+      } else {
+        ok = false;
+      }
+    }
+    int64_t nr = 0;
+    if (ok)
+      for (int64_t v = 0; v < N; ++v)
+        if (h.parent32[(size_t)v] >= 0 && !used[(size_t)v]) rest[nr++] = (int32_t)v;
+    P.dev.l1_fusable = ok;
+    P.dev.n_rest = nr;
   }
   char *base = nullptr;
   if (hipMallocAsync((void **)&base, total, st) != hipSuccess) {
@@ -626,6 +677,7 @@ static Bufs<T> make_bufs(PlanObj &P, const WsLayout &L, void *ws, const rcr_prob
   bf.Finv = base + L.Finv; bf.W = base + L.W; bf.Ginv = base + L.Ginv; bf.Acl = base + L.Acl; bf.Tm = base + L.Tm;
   bf.h = base + L.h; bf.cv = base + L.cv; bf.z = base + L.z; bf.p = base + L.p; bf.kff = base + L.kff; bf.b = base + L.b;
   bf.parent = P.dev.parent;
+  bf.uabs = P.dev.uabs;
   bf.status = ws_status(ws);
   return bf;
 }

@@ -35,6 +35,10 @@ struct PlanDev {
   int64_t n_hubs = 0;
   int64_t *koff = nullptr, *exp_off = nullptr, *tc_off = nullptr, *sx_off = nullptr;  // level offsets
   int32_t *lift_plus = nullptr;  // lifted plans: decision node of each native non-leaf
+  int32_t *uabs = nullptr;  // per node: 1 when it is absorbed into (its U is kept in U)
+  int32_t *rest = nullptr;  // edge slots that no level-1 primitive consumes (condensed on their own)
+  int64_t n_rest = 0;
+  bool l1_fusable = false;  // level 1 holds only rakes and compresses of original edge slots
   int32_t *rg_n = nullptr, *rg_m = nullptr;  // ragged plans: per-node dimensions
   int64_t *rg_off = nullptr;                 // ragged plans: block offsets of the packed arrays
   size_t bytes = 0;

@@ -224,12 +224,32 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
     return total;
   };
   if (phase == 0) {
-  tm.begin(RCR_K_CONDENSE);
-  LAUNCH(tm, (k_condense<T, NB, MB>), dim3(NBk), dim3(64), lds_cond, st, bf);
+  // ---- condensation.  Wide layout, control size up to 4: condensed in the
+  // wide layout, where level 1 (launched on its own) does it for its own
+  // edges and the rest in the same launch; U is never copied from Q (readers
+  // of a node that no absorb has touched read Q).  Otherwise the team-layout
+  // kernel, which also copies U = Q.
+  int64_t t_first = 0;
+  if constexpr (WIDE && MB == 4) {
+    if (P.dev.l1_fusable && tq.c_begin > 0) {
+      const int64_t r0 = h.kind_off[0], nr = h.kind_off[1] - r0, c0 = h.kind_off[3], nc = h.kind_off[4] - c0;
+      tm.begin(RCR_K_QUAD_CONTRACT);
+      allow_lds(k_level1_wide<T, NB>, lds_wide);
+      LAUNCH(tm, (k_level1_wide<T, NB>), dim3((unsigned)(nr + nc + P.dev.n_rest)), dim3(64), lds_wide, st, bf,
+             P.dev.ops, r0, (int)nr, c0, (int)nc, P.dev.rest);
+      t_first = 1;
+    } else {
+      tm.begin(RCR_K_CONDENSE);
+      LAUNCH(tm, (k_condense_wide<T, NB>), dim3((unsigned)h.N), dim3(64), 0, st, bf);
+    }
+  } else {
+    tm.begin(RCR_K_CONDENSE);
+    LAUNCH(tm, (k_condense<T, NB, MB>), dim3(NBk), dim3(64), lds_cond, st, bf);
+  }
 
   // ---- quadratic contraction and expansion
   tm.begin(RCR_K_QUAD_CONTRACT);
-  for (int64_t t = 0; t < tq.c_begin; ++t) {
+  for (int64_t t = t_first; t < tq.c_begin; ++t) {
     Seg sg;
     if constexpr (WIDE) {
       const unsigned nb = seg_of(t, sg, 1);

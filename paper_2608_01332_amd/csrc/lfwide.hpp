@@ -30,18 +30,6 @@ struct LfwLay {
                        words = Gi + MB * MB;
 };
 
-// 1 / sqrt(s) for s > 0: the hardware estimate refined by two Newton steps
-// y <- y + y (1 - s y^2) / 2.
-__device__ __forceinline__ double rsqrt_nr(double s) {
-  double y = __builtin_amdgcn_rsq(s);
-#pragma unroll
-  for (int it = 0; it < 2; ++it) {
-    const double e = fma(-s * y, y, 1.0);
-    y = fma(0.5 * y, e, y);
-  }
-  return y;
-}
-
 // Cholesky factor and inverse of the MB x MB SPD matrix G (row-major in LDS)
 // in registers; reports a non-positive pivot through `bad`.
 template <int MB>
@@ -128,7 +116,10 @@ __device__ __forceinline__ void local_factor_wide(const Bufs<T> &bf, bool rhs) {
   }
   {
     T tP[TL], tD[TL], tA[TL], tB[TB];
-    wfetch<T, NB>(tP, (isroot ? bf.U : bf.PW) + v * nn, n);
+    if (isroot && !bf.uabs[v])
+      wfetch<T, NB>(tP, bf.Q + v * nn, n);  // a root never absorbed into (a one-node tree): U = Q
+    else
+      wfetch<T, NB>(tP, (isroot ? bf.U : bf.PW) + v * nn, n);
     wfetch<T, NB>(tD, bf.De + v * nn, n);
     wfetch<T, NB>(tA, bf.A + v * nn, n);
 #pragma unroll

@@ -59,6 +59,28 @@ __device__ __forceinline__ void mf_store(D *__restrict__ p, int ld, const dv4 &x
   }
 }
 
+// 1 / sqrt(s) for s > 0: the hardware estimate refined by two Newton steps
+// y <- y + y (1 - s y^2) / 2.
+__device__ __forceinline__ double rsqrt_nr(double s) {
+  double y = __builtin_amdgcn_rsq(s);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-s * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
+// x rounded to the working type T and back, per component (what storing x as T
+// and loading it again gives).
+template <typename T>
+__device__ __forceinline__ dv4 mf_round(const dv4 &x) {
+  dv4 d;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) d[v] = (double)(T)x[v];
+  return d;
+}
+
 // acc + op(A) op(B) for NB x NB blocks (TA / TB: use the transpose), rows and
 // columns at or beyond NB read as zero.
 template <int NB, bool TA, bool TB, typename SA, typename SB>

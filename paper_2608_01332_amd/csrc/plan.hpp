@@ -20,6 +20,13 @@ struct OpRec {
   int32_t kind, round, level, a, b, c, d, e;
 };
 
+// Flags carried, on the device, in the `round` word of an op record (the
+// host plan keeps the round): OPF_U_LIVE, node a's U is kept in U (the node
+// is absorbed into before it is raked or compressed), else U_a = Q_a;
+// OPF_FIRST_ABSORB, the first absorb of node a, which starts from Q_a.  In the
+// expansion records the flag OPF_U_LIVE of node j is the fourth word.
+enum : int32_t { OPF_U_LIVE = 1, OPF_FIRST_ABSORB = 2 };
+
 // Four int32 words: the records of the expansion and state passes.
 struct Op4 {
   int32_t a, b, c, d;

@@ -35,6 +35,9 @@ struct Bufs {
   T *U, *EA, *EC, *EP, *CT, *PW, *Finv, *W, *Ginv, *Acl, *Tm, *Kw;
   T *h, *cv, *z, *p, *kff, *b, *xw, *uw, *yw;
   const int32_t *parent;
+  // uabs[v] != 0: node v is absorbed into at least once, so its U_v is kept in
+  // U; otherwise U_v = Q_v is read from Q (the wide layout writes no copy)
+  const int32_t *uabs;
   int *status;
 };
 

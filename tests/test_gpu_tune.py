@@ -1,7 +1,11 @@
 """Launch-mapping autotuner (rcr_plan_tune) and explicit mappings: the narrow
 levels may run in per-level launches or in the single-workgroup tail kernels,
 and the results must be bitwise the same for every mapping (each primitive
-runs the same arithmetic wherever it is launched)."""
+runs the same arithmetic wherever it is launched).  In the wide layout with
+control size up to 4, the first level runs fused with the condensation when
+it is launched on its own and after a separate condensation when the tail
+covers it: the wide tails mapping below puts level 1 of these trees in the
+tail, so the two paths are compared bit for bit."""
 import numpy as np
 import pytest
 
@@ -19,7 +23,8 @@ MAPPINGS = [
 
 
 @pytest.mark.parametrize("n,m,N,prec", [(4, 2, 255, rcr.FP64), (12, 4, 3000, rcr.FP64), (8, 3, 4000, rcr.MIXED32),
-                                        (6, 2, 2000, rcr.MIXED32), (16, 4, 1500, rcr.FP64)])
+                                        (6, 2, 2000, rcr.MIXED32), (16, 4, 1500, rcr.FP64),
+                                        (12, 4, 3000, rcr.MIXED32), (12, 2, 2500, rcr.FP64), (12, 8, 2000, rcr.FP64)])
 def test_mappings_bitwise_equal(n, m, N, prec):
     print(f"[gpu-tune] mappings n={n} m={m} N={N} prec={prec}", flush=True)
     par = w.tree_chainprob(N, 0.9, np.random.default_rng(N))
