@@ -472,7 +472,7 @@ struct Builder : Work {
 // verify that every input was produced at an earlier level, that each datum
 // has at most one writer per level, and that no datum written at a level is
 // read by another op of that level.
-bool verify_crew(const PlanHost &P) {
+static bool verify_contraction(const PlanHost &P) {
   const int64_t N = P.N;
   // datum ids: U_i -> i; edge slot s -> N + s; contribution c -> N + slots + c
   const int64_t E0 = N, C0 = N + P.n_edge_slots, ND = C0 + P.n_contrib;
@@ -513,6 +513,92 @@ bool verify_crew(const PlanHost &P) {
     }
   }
   return true;
+}
+
+// Expansion of compressions: P_j from the tape of its out-edge slot r (final
+// after the contraction), U_j (final) and P_k of its child k, which is a raked
+// node (P_k written by the rake) or a compressed node expanded at a lower
+// level.  Every compressed node is expanded exactly once.
+static bool verify_expansion(const PlanHost &P) {
+  const int64_t N = P.N;
+  std::vector<char> compressed((size_t)N, 0), raked((size_t)N, 0);
+  for (const OpRec &o : P.ops) {
+    if (o.kind == OP_COMPRESS) compressed[(size_t)o.a] = 1;
+    if (o.kind == OP_RAKE) raked[(size_t)o.a] = 1;
+  }
+  std::vector<int32_t> done((size_t)N, -1);  // expansion level that wrote P_j
+  int64_t count = 0;
+  for (int64_t e = 0; e < P.expand_levels(); ++e)
+    for (int64_t i = P.exp_off[e]; i < P.exp_off[e + 1]; ++i) {
+      const Op4 &q = P.exp_ops[(size_t)i];
+      if (q.a < 0 || q.a >= N || q.c < 0 || q.c >= N || q.b < 0 || q.b >= P.n_edge_slots) return false;
+      if (!compressed[(size_t)q.a] || done[(size_t)q.a] >= 0) return false;
+      const bool child_ready = raked[(size_t)q.c] || (compressed[(size_t)q.c] && done[(size_t)q.c] >= 0 &&
+                                                      done[(size_t)q.c] < e);
+      if (!child_ready) return false;
+      done[(size_t)q.a] = (int32_t)e;
+      ++count;
+    }
+  return count == P.n_compress;
+}
+
+// Composition of edge maps over compressions (composite transitions, and the
+// same schedule for the state offsets): the new slot from slots l and r, each
+// original (ready before the first level) or written at a lower level; every
+// compression's slot written once.  The solve launches composition level i
+// together with affine contraction level i (1-based), so an affine primitive
+// of contraction level t may only read composites of composition levels
+// below t + 1; the two halves touch disjoint arrays otherwise (transitions
+// against vectors).
+static bool verify_composition(const PlanHost &P) {
+  const int64_t N = P.N, S = P.n_edge_slots;
+  std::vector<int32_t> lvl((size_t)S, -1);  // composition level that wrote the slot (0: original)
+  for (int64_t s = 0; s < N; ++s) lvl[(size_t)s] = 0;
+  int64_t count = 0;
+  for (int64_t t = 0; t < P.state_levels(); ++t)
+    for (int64_t i = P.tc_off[t]; i < P.tc_off[t + 1]; ++i) {
+      const Op4 &q = P.tc_ops[(size_t)i];
+      if (q.a < 0 || q.a >= S || q.b < 0 || q.b >= S || q.c < N || q.c >= S) return false;
+      if (lvl[(size_t)q.a] < 0 || lvl[(size_t)q.a] > t || lvl[(size_t)q.b] < 0 || lvl[(size_t)q.b] > t) return false;
+      if (lvl[(size_t)q.c] >= 0) return false;
+      lvl[(size_t)q.c] = (int32_t)(t + 1);
+      ++count;
+    }
+  if (count != P.n_compress) return false;
+  for (int64_t t = 0; t < P.levels(); ++t)
+    for (int64_t k = P.lvl_off[t]; k < P.lvl_off[t + 1]; ++k) {
+      const OpRec &o = P.ops[(size_t)k];
+      if (o.kind != OP_RAKE && o.kind != OP_COMPRESS) continue;
+      const int32_t l = lvl[(size_t)o.b];
+      if (l < 0 || l > t + 1) return false;
+    }
+  return true;
+}
+
+// State expansion: x_j from the state of its parent at removal time through
+// the composite map of its slot; the parent is the root (state from the local
+// solve) or a node expanded at a lower level; every removed node once.
+static bool verify_state_expansion(const PlanHost &P) {
+  const int64_t N = P.N;
+  std::vector<int32_t> done((size_t)N, -1);
+  for (int64_t v = 0; v < N; ++v)
+    if (P.parent32[(size_t)v] < 0) done[(size_t)v] = -2;  // roots: known before the first level
+  int64_t count = 0;
+  for (int64_t e = 0; e < P.sexp_levels(); ++e)
+    for (int64_t i = P.sx_off[e]; i < P.sx_off[e + 1]; ++i) {
+      const Op4 &q = P.sx_ops[(size_t)i];
+      if (q.a < 0 || q.a >= N || q.c < 0 || q.c >= N || q.b < 0 || q.b >= P.n_edge_slots) return false;
+      if (done[(size_t)q.a] != -1) return false;
+      const int32_t pd = done[(size_t)q.c];
+      if (!(pd == -2 || (pd >= 0 && pd < e))) return false;
+      done[(size_t)q.a] = (int32_t)e;
+      ++count;
+    }
+  return count == P.n_rake + P.n_compress;
+}
+
+bool verify_crew(const PlanHost &P) {
+  return verify_contraction(P) && verify_expansion(P) && verify_composition(P) && verify_state_expansion(P);
 }
 
 int build_plan(const int64_t *parent, int64_t N, int n, int m, int selection, PlanHost &out) {

@@ -96,7 +96,10 @@ struct PlanHost {
 };
 
 // Returns 0 or a negative RCR_* status.
-// Independent check that the level schedule is CREW (verify_crew in plan.cpp).
+// Independent check that every pass schedule is CREW (one writer per datum,
+// reads only of data written at a lower level): the contraction, the
+// expansion of compressions, the composition of edge maps (with its pairing
+// with the affine contraction) and the state expansion (verify_crew in plan.cpp).
 bool verify_crew(const PlanHost &P);
 int build_plan(const int64_t *parent, int64_t N, int n, int m, int selection, PlanHost &out);
 
