@@ -70,8 +70,11 @@ typedef struct rcr_plan rcr_plan; /* opaque, immutable after creation */
 #define RCR_SELECT_LIST_RANK 1    /* alternate positions along each maximal unary path       */
 
 typedef struct {
-  int32_t selection;   /* RCR_SELECT_*; any maximal non-adjacent set is valid (Lemma 2) */
-  int32_t reserved[7]; /* zero */
+  int32_t selection;     /* RCR_SELECT_*; any maximal non-adjacent set is valid (Lemma 2) */
+  int32_t single_thread; /* nonzero: build on the calling thread only (by default trees of
+                            16384 nodes or more build their four pass schedules on four
+                            threads); for callers that build many plans at once          */
+  int32_t reserved[6];   /* zero */
 } rcr_plan_options;
 
 typedef struct {

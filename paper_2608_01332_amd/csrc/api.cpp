@@ -22,6 +22,12 @@ namespace {
 // confuse a destroyed plan with a new one at the same address.
 std::atomic<uint64_t> next_serial{1};
 
+// Sets rcr::build_on_caller_only for the duration of one plan construction.
+struct CallerOnly {
+  explicit CallerOnly(const rcr_plan_options *opt) { rcr::build_on_caller_only = opt && opt->single_thread; }
+  ~CallerOnly() { rcr::build_on_caller_only = false; }
+};
+
 rcr_plan *new_plan() {
   rcr_plan *p = new (std::nothrow) rcr_plan();
   if (p) p->obj.serial = next_serial.fetch_add(1);
@@ -152,6 +158,7 @@ int rcr_plan_create(const int64_t *parent, int64_t N, int32_t n, int32_t m, cons
   if (!p) return RCR_OOM;
   int rc;
   try {
+    CallerOnly only(opt);
     rc = rcr::build_plan(parent, N, n, m, selection, p->obj.host);
   } catch (const std::bad_alloc &) {
     rc = RCR_OOM;
@@ -173,6 +180,7 @@ int rcr_lift_plan_create(const int64_t *parent, int64_t N, int32_t n, int32_t m,
   if (!p) return RCR_OOM;
   int rc;
   try {
+    CallerOnly only(opt);
     rc = rcr::build_lift_plan(parent, N, n, m, selection, p->obj.host);
   } catch (const std::bad_alloc &) {
     rc = RCR_OOM;
@@ -210,6 +218,7 @@ int rcr_ragged_plan_create(const int64_t *parent, int64_t N, const int32_t *n_no
   if (!p) return RCR_OOM;
   int rc;
   try {
+    CallerOnly only(opt);
     rc = rcr::build_ragged_plan(parent, N, n_node, m_edge, selection, p->obj.host);
   } catch (const std::bad_alloc &) {
     rc = RCR_OOM;

@@ -120,7 +120,7 @@ static inline double *ws_resid(void *ws) { return reinterpret_cast<double *>(sta
 // memory waits for the device, which would stall the solves on other streams).
 // A larger upload stages through ordinary heap memory.
 namespace {
-constexpr size_t STAGE_BYTES = size_t(16) << 20;
+constexpr size_t STAGE_BYTES = size_t(32) << 20;
 struct StagePool {
   std::mutex mu;
   std::vector<char *> free_bufs;
@@ -149,6 +149,46 @@ void stage_give(char *b) {
   sp.free_bufs.push_back(b);
 }
 }  // namespace
+
+// Device memory of the library (plan copies, plan-owned workspaces, residual
+// buffers) comes from one stream-ordered pool per GPU that keeps up to
+// POOL_KEEP_BYTES of freed memory mapped for reuse.  With a release threshold of
+// zero (the default pool's), each allocation after a free maps fresh pages,
+// which serialises with the other device allocations of the process; a serving
+// loop uploads a plan per request.  The pools live until the process ends.
+namespace {
+constexpr uint64_t POOL_KEEP_BYTES = uint64_t(4) << 30;
+constexpr int POOL_MAX_DEVICES = 64;
+std::mutex pool_mu;
+hipMemPool_t pools[POOL_MAX_DEVICES] = {};
+}  // namespace
+
+static hipError_t dev_alloc(void **p, size_t bytes, hipStream_t st) {
+  int dev = 0;
+  hipError_t e = hipStreamGetDevice(st, &dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= POOL_MAX_DEVICES) return hipMallocAsync(p, bytes, st);
+  hipMemPool_t pool = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(pool_mu);
+    if (!pools[dev]) {
+      hipMemPoolProps props = {};
+      props.allocType = hipMemAllocationTypePinned;
+      props.handleTypes = hipMemHandleTypeNone;
+      props.location.type = hipMemLocationTypeDevice;
+      props.location.id = dev;
+      if ((e = hipMemPoolCreate(&pool, &props)) != hipSuccess) return e;
+      uint64_t keep = POOL_KEEP_BYTES;
+      if ((e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep)) != hipSuccess) {
+        (void)hipMemPoolDestroy(pool);
+        return e;
+      }
+      pools[dev] = pool;
+    }
+    pool = pools[dev];
+  }
+  return hipMallocFromPoolAsync(p, bytes, pool, st);
+}
 
 // Byte sizes of the pieces of a plan's device copy, in their order in the
 // allocation (each piece starts on a 256-byte boundary); returns the total.
@@ -313,7 +353,7 @@ int plan_upload(PlanObj &P, hipStream_t st) {
     P.dev.n_rest = nr;
   }
   char *base = nullptr;
-  if (hipMallocAsync((void **)&base, total, st) != hipSuccess) {
+  if (dev_alloc((void **)&base, total, st) != hipSuccess) {
     if (pooled) stage_give(stage);
     return RCR_OOM;
   }
@@ -902,7 +942,7 @@ static int take_workspace(PlanObj &P, const rcr_solve_options &opt, size_t need_
     P.ws[prec] = nullptr;
   }
   if (!P.ws[prec]) {
-    if (hipMallocAsync(&P.ws[prec], need_total, st) != hipSuccess) return RCR_OOM;
+    if (dev_alloc(&P.ws[prec], need_total, st) != hipSuccess) return RCR_OOM;
     P.ws_bytes[prec] = need_total;
   }
   ws = P.ws[prec];
@@ -1233,7 +1273,7 @@ int kkt_residual(PlanObj &P, const rcr_problem &in, const rcr_solution &sol, con
   if (ws) {
     if ((size_t)opt.workspace_bytes < WS_HEADER_BYTES) return RCR_SMALL_WORKSPACE;
   } else {
-    if (!P.resid_buf && hipMallocAsync((void **)&P.resid_buf, WS_HEADER_BYTES, st) != hipSuccess) return RCR_OOM;
+    if (!P.resid_buf && dev_alloc((void **)&P.resid_buf, WS_HEADER_BYTES, st) != hipSuccess) return RCR_OOM;
     ws = P.resid_buf;
   }
   hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, st, ws_status(ws), ws_resid(ws));
@@ -1757,7 +1797,7 @@ int lift_solve(PlanObj &P, const rcr_native_problem &in, rcr_native_solution &ou
       if ((size_t)opt.workspace_bytes < need) return RCR_SMALL_WORKSPACE;
     } else {
       if (!P.ws[prec]) {
-        if (hipMallocAsync(&P.ws[prec], need, st) != hipSuccess) return RCR_OOM;
+        if (dev_alloc(&P.ws[prec], need, st) != hipSuccess) return RCR_OOM;
         P.ws_bytes[prec] = need;
       }
       ws = P.ws[prec];

@@ -65,6 +65,9 @@ struct Work {
 constexpr int64_t KEEP_NODES = int64_t(1) << 17;
 // Trees from this size on build their four pass schedules on four threads.
 constexpr int64_t PAR_NODES = int64_t(1) << 14;
+}  // namespace
+thread_local bool build_on_caller_only = false;
+namespace {
 
 // Runs the tasks, on threads of their own (the first on the caller's) when
 // `parallel` is set and threads can be started, else one after the other.  An
@@ -460,7 +463,7 @@ struct Builder : Work {
       fill_x.assign(P.sx_off.begin(), P.sx_off.end() - 1);
       for (int32_t j : removal_seq) P.sx_ops[fill_x[eX[j] - 1]++] = Op4{j, rem_slot[j], rem_par[j], 0};
     };
-    run_concurrently(N >= PAR_NODES, levels_task, expand_task, compose_task, state_task);
+    run_concurrently(N >= PAR_NODES && !build_on_caller_only, levels_task, expand_task, compose_task, state_task);
     return RCR_OK;
   }
 
@@ -808,7 +811,7 @@ int merge_plans(const std::vector<const PlanHost *> &parts, PlanHost &out) {
   auto composition = [&] { merge4(LT, &PlanHost::tc_ops, &PlanHost::tc_off, out.tc_ops, out.tc_off, 1); };
   auto state = [&] { merge4(LX, &PlanHost::sx_ops, &PlanHost::sx_off, out.sx_ops, out.sx_off, 2); };
   // the four parts write disjoint arrays of the merged plan
-  run_concurrently(N >= PAR_NODES, contraction, expansion, composition, state);
+  run_concurrently(N >= PAR_NODES && !build_on_caller_only, contraction, expansion, composition, state);
   return RCR_OK;
 }
 

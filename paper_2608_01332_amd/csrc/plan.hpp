@@ -101,6 +101,9 @@ struct PlanHost {
 // expansion of compressions, the composition of edge maps (with its pairing
 // with the affine contraction) and the state expansion (verify_crew in plan.cpp).
 bool verify_crew(const PlanHost &P);
+// While set on a thread, the plans and merges it builds use no helper threads.
+extern thread_local bool build_on_caller_only;
+
 int build_plan(const int64_t *parent, int64_t N, int n, int m, int selection, PlanHost &out);
 
 // Plan of the lifted edge-control tree of a node-control problem (Sec. II-B,

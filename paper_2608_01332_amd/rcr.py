@@ -33,7 +33,7 @@ _dp = ctypes.POINTER(ctypes.c_double)
 
 
 class PlanOptions(ctypes.Structure):
-    _fields_ = [("selection", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("selection", ctypes.c_int32), ("single_thread", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class PlanStats(ctypes.Structure):
@@ -223,14 +223,14 @@ class Plan:
         return self
 
     @classmethod
-    def lift(cls, parent, n: int, m: int, selection: int = SELECT_GREEDY_INDEX) -> "Plan":
+    def lift(cls, parent, n: int, m: int, selection: int = SELECT_GREEDY_INDEX, single_thread: bool = False) -> "Plan":
         """Plan of the lifted tree of a node-control problem (rcr_lift_plan_create)
         on the native parent array, state n and control m; solve it with lift_solve."""
         L = lib()
         self = cls.__new__(cls)
         self._parent = np.ascontiguousarray(parent, dtype=np.int64)
         h = ctypes.c_void_p()
-        opt = PlanOptions(selection=selection)
+        opt = PlanOptions(selection=selection, single_thread=int(bool(single_thread)))
         rc = L.rcr_lift_plan_create(self._parent.ctypes.data_as(_i64p), int(self._parent.shape[0]), int(n), int(m),
                                     ctypes.byref(opt), ctypes.byref(h))
         if rc != 0:
@@ -242,7 +242,8 @@ class Plan:
         return self
 
     @classmethod
-    def ragged(cls, parent, n_node, m_edge, selection: int = SELECT_GREEDY_INDEX) -> "Plan":
+    def ragged(cls, parent, n_node, m_edge, selection: int = SELECT_GREEDY_INDEX,
+               single_thread: bool = False) -> "Plan":
         """Plan of a tree with per-node state and per-edge control dimensions
         (rcr_ragged_plan_create); solve it with ragged_solve on packed arrays."""
         L = lib()
@@ -254,7 +255,7 @@ class Plan:
         if nn.shape != (self.N,) or mm.shape != (self.N,):
             raise ValueError("n_node and m_edge need one entry per node")
         h = ctypes.c_void_p()
-        opt = PlanOptions(selection=selection)
+        opt = PlanOptions(selection=selection, single_thread=int(bool(single_thread)))
         rc = L.rcr_ragged_plan_create(self._parent.ctypes.data_as(_i64p), self.N, nn.ctypes.data_as(_i32p),
                                       mm.ctypes.data_as(_i32p), ctypes.byref(opt), ctypes.byref(h))
         if rc != 0:
@@ -269,13 +270,13 @@ class Plan:
         self.ragged_offsets = {f: off[i * (self.N + 1):(i + 1) * (self.N + 1)] for i, f in enumerate(RAGGED_FIELDS)}
         return self
 
-    def __init__(self, parent, n: int, m: int, selection: int = SELECT_GREEDY_INDEX):
+    def __init__(self, parent, n: int, m: int, selection: int = SELECT_GREEDY_INDEX, single_thread: bool = False):
         L = lib()
         self._parent = np.ascontiguousarray(parent, dtype=np.int64)
         self.N = int(self._parent.shape[0])
         self.n, self.m = int(n), int(m)
         h = ctypes.c_void_p()
-        opt = PlanOptions(selection=selection)
+        opt = PlanOptions(selection=selection, single_thread=int(bool(single_thread)))
         rc = L.rcr_plan_create(self._parent.ctypes.data_as(_i64p), self.N, self.n, self.m, ctypes.byref(opt),
                                ctypes.byref(h))
         if rc != 0:
@@ -384,6 +385,12 @@ def _check(t, name, shape):
         raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
     if tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {shape}")
+
+
+def solution_shapes(N: int, n: int, m: int) -> dict:
+    """Shapes of the rcr_solution fields of an N-node problem."""
+    sh = _shapes(N, n, m)
+    return {k: sh[k] for k in SOLUTION_FIELDS}
 
 
 def alloc_solution(plan: Plan, device="cuda"):

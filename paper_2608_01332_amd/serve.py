@@ -19,7 +19,8 @@ problem data already resident on the device -- arrive over time.  The server
     running in the other slots;
   * completes a group when its stream's completion event has fired.
 
-Every request gets its own output buffers; its arithmetic is that of the same
+Every request gets its own output fields (views of one device block per
+group, see output_layout); its arithmetic is that of the same
 kernels on its own nodes, so the result does not depend on the group it ran
 in.  Latency runs from the request's arrival time to the host observing its
 completion event (planning on a plan-cache miss included).
@@ -79,14 +80,31 @@ def batch_staging_bytes(sizes, n: int, m: int) -> int:
     return stage + -(-32 * chunks // 256) * 256
 
 
+OUT_FIELD_ALIGN = 256  # bytes; every output field of a group's block starts on this boundary
+
+
+def output_layout(reqs):
+    """Byte offsets of the output fields (rcr_solution order) of each request in
+    the one device block that holds a group's outputs, and the block's size: the
+    fields packed on 256-byte boundaries, the total rounded up to a power of two
+    so that the blocks of a serving loop come in few distinct sizes and the ones
+    freed are reused rather than new device memory being mapped."""
+    offs, at = [], 0
+    for r in reqs:
+        t, s = r.m * r.n, r.n * r.n
+        o = {}
+        for k, w in zip(rcr.SOLUTION_FIELDS, (t, s, r.n, r.m, r.n)):
+            o[k] = at
+            at += -(-8 * w * r.N // OUT_FIELD_ALIGN) * OUT_FIELD_ALIGN
+        offs.append(o)
+    return offs, 1 << max(at - 1, 0).bit_length()
+
+
 def group_footprint(reqs, precision: int, ws_bytes: int, plan_bytes: int = 0) -> int:
     """HBM bytes a group holds while it runs: its workspace (ws_bytes, staging
-    included for a merged group), its outputs and the device copy of its plan
-    when that is not a cached plan's (plan_bytes)."""
-    n, m = reqs[0].n, reqs[0].m
-    N = sum(r.N for r in reqs)
-    w_in, w_out = io_words(N, n, m)
-    return ws_bytes + 8 * w_out + plan_bytes
+    included for a merged group), its output block and the device copy of its
+    plan when that is not a cached plan's (plan_bytes)."""
+    return ws_bytes + output_layout(reqs)[1] + plan_bytes
 
 
 def form_group(ready, free_bytes: int, max_nodes: int, ws_of, precision: int):
@@ -122,17 +140,20 @@ class _Slot:
         self.group = None
         self.keep = None
         self.bytes = 0
+        self.ws = None      # the slot's workspace, grown when a group needs more (never shrunk)
+        self.ws_target = 0  # its size as charged by admission
 
 
 class Server:
-    def __init__(self, device="cuda:0", slots: int = 4, hbm_budget: int = 64 << 30, max_group_nodes: int = 1 << 20,
+    def __init__(self, device="cuda:0", slots: int = 4, hbm_budget: int = 64 << 30, max_group_nodes: int = 1 << 18,
                  precision: int = rcr.MIXED32, refine_steps: int = 1, planner_threads: int = 8,
                  plan_cache: int = 512, batching: bool = True):
         import torch
         self.device = torch.device(device)
         self.slots = [_Slot(self.device) for _ in range(slots)]
         self.budget = int(hbm_budget)
-        self.in_use = 0
+        self.in_use = 0          # outputs and plan copies of the running groups
+        self.ws_held = 0         # the slots' workspaces (kept between groups)
         self.max_group_nodes = max_group_nodes if batching else 1
         self.precision = precision
         self.refine_steps = refine_steps
@@ -144,12 +165,13 @@ class Server:
         self.ready = collections.deque()
         self.done = []
         self.groups = 0
-        self.stats = {"plan_s": 0.0, "prep_s": 0.0, "launch_s": 0.0}
+        self.stats = {"plan_s": 0.0, "prep_s": 0.0, "launch_s": 0.0, "launch_max_s": 0.0, "ws_grow": 0}
 
     # ---- arrival and planning -------------------------------------------------
     def _plan(self, req: Request):
         t = time.perf_counter()
-        p = rcr.Plan(req.parent, req.n, req.m)
+        # the pool already builds plans side by side: no helper threads per plan
+        p = rcr.Plan(req.parent, req.n, req.m, single_thread=True)
         self.stats["plan_s"] += time.perf_counter() - t
         return p
 
@@ -234,13 +256,19 @@ class Server:
         self.stats["prep_s"] += time.perf_counter() - t
         return plan
 
-    def _dispatch(self, slot: _Slot, group, fp: int):
+    def _dispatch(self, slot: _Slot, group, fp: int, ws_charge: int, ws_target: int):
+        """Start a group on an idle slot.  fp is its footprint with the slot's
+        workspace counted at ws_charge = max(held workspace, group's need); the
+        workspace is grown to ws_target (>= ws_charge) if it is smaller."""
         now = time.perf_counter()
         for r in group:
             r.t_admit = now
             r.group_size = len(group)
-        slot.group, slot.bytes = group, fp
-        self.in_use += fp
+        cap = slot.ws.numel() if slot.ws is not None else 0
+        self.ws_held += ws_target - cap
+        slot.ws_target = ws_target
+        slot.group, slot.bytes = group, fp - ws_charge
+        self.in_use += fp - ws_charge
         self._pin(group, +1)
         self.groups += 1
         if len(group) == 1 and getattr(group[0].plan, "_uploaded", False):
@@ -248,20 +276,37 @@ class Server:
         else:
             slot.prep = self.pool.submit(self._prepare, group, slot.stream)
 
+    def _alloc_outputs(self, group):
+        """Views of one device block per group (output_layout): each request's
+        fields, shaped as rcr_solution.  A request that keeps its outputs keeps
+        the block alive."""
+        import torch
+        offs, total = output_layout(group)
+        block = torch.empty(total // 8, dtype=torch.float64, device=self.device)
+        outs = []
+        for r, o in zip(group, offs):
+            sh = rcr.solution_shapes(r.N, r.n, r.m)
+            outs.append({k: block[o[k] // 8:o[k] // 8 + int(np.prod(sh[k]))].view(sh[k]) for k in rcr.SOLUTION_FIELDS})
+        return outs
+
     def _launch(self, slot: _Slot, plan):
         import torch
         t = time.perf_counter()
         group = slot.group
         with torch.cuda.stream(slot.stream):
-            outs = [rcr.alloc_solution(r.plan, self.device) for r in group]
+            outs = self._alloc_outputs(group)
+            need = (plan.workspace_size(self.precision) if len(group) == 1
+                    else rcr.batch_workspace_size(plan, self.precision))
+            if slot.ws is None or slot.ws.numel() < slot.ws_target:  # the size admission charged
+                slot.ws = None  # the slot's stream is idle here: its previous group has completed
+                slot.ws = torch.empty(slot.ws_target, dtype=torch.uint8, device=self.device)
+                self.stats["ws_grow"] += 1
+            ws = slot.ws[:need]
             if len(group) == 1:
-                ws = torch.empty(plan.workspace_size(self.precision), dtype=torch.uint8, device=self.device)
                 rcr.solve(plan, group[0].prob, out=outs[0], precision=self.precision,
                           refine_steps=self.refine_steps, executor=rcr.EXEC_LEVELS, workspace=ws,
                           stream=slot.stream)
             else:
-                ws = torch.empty(rcr.batch_workspace_size(plan, self.precision), dtype=torch.uint8,
-                                 device=self.device)
                 rcr.batch_solve(plan, [r.prob for r in group], outs, precision=self.precision,
                                 refine_steps=self.refine_steps, executor=rcr.EXEC_LEVELS, workspace=ws,
                                 stream=slot.stream)
@@ -271,7 +316,9 @@ class Server:
             r.out = o
         slot.event = ev
         slot.keep = (plan if len(group) > 1 else None, ws)
-        self.stats["launch_s"] += time.perf_counter() - t
+        dt = time.perf_counter() - t
+        self.stats["launch_s"] += dt
+        self.stats["launch_max_s"] = max(self.stats["launch_max_s"], dt)
 
     def poll(self) -> int:
         """Advance the loop once; returns the number of requests completed."""
@@ -283,7 +330,11 @@ class Server:
                 if len(slot.group) == 1 and not getattr(plan, "_uploaded", False):
                     plan._uploaded = True  # its device copy stays with the plan
                     if self._is_cached(slot.group[0]):
-                        self.cached_plan_bytes += plan.device_bytes()
+                        # the copy is charged to the cache from here on, not to the group
+                        db = plan.device_bytes()
+                        self.cached_plan_bytes += db
+                        slot.bytes -= db
+                        self.in_use -= db
                 self._launch(slot, plan)
             if slot.event is not None and slot.event.query():
                 t = time.perf_counter()
@@ -299,34 +350,64 @@ class Server:
                 slot.group, slot.event, slot.keep, slot.bytes = None, None, None, 0
         if self.planning:
             self._collect_plans()
+        blocked = False
         for slot in self.slots:
             if slot.group is not None or not self.ready:
                 continue
             while True:
-                group, fp = form_group(self.ready, self.budget - self.in_use - self.cached_plan_bytes,
-                                       self.max_group_nodes, self._ws_of, self.precision)
-                if group or not self._evict_for_room():
+                cap = slot.ws.numel() if slot.ws is not None else 0
+
+                def ws_of(g, cap=cap):  # the group runs on this slot's workspace, grown if needed
+                    ws, plan_bytes = self._ws_of(g)
+                    return max(cap, ws), plan_bytes
+
+                free = self.budget - self.in_use - self.cached_plan_bytes - (self.ws_held - cap)
+                group, fp = form_group(self.ready, free, self.max_group_nodes, ws_of, self.precision)
+                if group or not self._evict_for_room(slot):
                     break
             if not group:
-                if not any(s_.group is not None or s_.prep is not None for s_ in self.slots):
-                    raise RuntimeError(f"request {self.ready[0].rid} does not fit the HBM budget of "
-                                       f"{self.budget} bytes on an idle device")
-                break
+                blocked = True
+                continue
             ids = {id(r) for r in group}
             self.ready = collections.deque(r for r in self.ready if id(r) not in ids)
-            self._dispatch(slot, group, fp)
+            charge = ws_of(group)[0]
+            # grow to a power of two when the budget allows: few distinct sizes,
+            # so the blocks a slot gives up are reused by the others
+            target = max(cap, 1 << max(charge - 1, 0).bit_length())
+            if fp - charge + target > free:
+                target = charge
+            self._dispatch(slot, group, fp, charge, target)
+        if blocked and self.ready and not any(s_.group is not None for s_ in self.slots):
+            raise RuntimeError(f"request {self.ready[0].rid} does not fit the HBM budget of "
+                               f"{self.budget} bytes on an idle device")
         self._evict()
         return finished
 
-    def _evict_for_room(self) -> bool:
-        """Release the device copy of the least recently used cached plan that no
-        running group uses (the head of the queue did not fit); False if none."""
+    def _evict_for_room(self, slot) -> bool:
+        """Make room for the head of the queue: release the device copy of the least
+        recently used cached plan that no running group uses, else the workspace
+        of another idle slot, else this slot's own; False if there is nothing
+        left to release."""
         for k, ent in self.cache.items():
             if ent[1] == 0 and getattr(ent[0], "_uploaded", False):
                 self.cached_plan_bytes -= ent[0].device_bytes()
                 del self.cache[k]
                 return True
+        for other in self.slots:
+            if other is not slot and other.group is None and other.ws is not None:
+                self.ws_held -= other.ws.numel()
+                other.ws = None
+                return True
+        if slot.ws is not None:  # last, the slot's own (larger than the head needs)
+            self.ws_held -= slot.ws.numel()
+            slot.ws = None
+            return True
         return False
+
+    def held(self) -> int:
+        """HBM the server holds: running groups' outputs and plan copies, the
+        slots' workspaces and the cached plans' device copies (<= hbm_budget)."""
+        return self.in_use + self.ws_held + self.cached_plan_bytes
 
     def busy(self) -> bool:
         return bool(self.planning or self.ready or any(s.group is not None for s in self.slots))

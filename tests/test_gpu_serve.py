@@ -112,8 +112,8 @@ def test_serve_tight_budget_stays_within_budget():
     peak = 0
     while srv.busy():
         srv.poll()
-        peak = max(peak, srv.in_use)
-        assert srv.in_use <= need
+        peak = max(peak, srv.held())
+        assert srv.held() <= need
     assert peak <= need and len(srv.done) == len(reqs)
     # the largest request needs the whole budget: it ran alone
     big = max(reqs, key=lambda r: r.N)

@@ -270,3 +270,18 @@ def test_plans_do_not_depend_on_earlier_plans_of_the_thread():
     for (s0, o0), (s1, o1) in zip(alone, seq):
         assert s0 == s1
         np.testing.assert_array_equal(o0, o1)
+
+
+def test_single_thread_build_equals_default():
+    """rcr_plan_options.single_thread builds on the calling thread only; the plan
+    (statistics and every schedule) is the one the default four-thread build of
+    a tree above the threading threshold gives."""
+    rng = np.random.default_rng(77)
+    for N, p in ((20000, 0.95), (70000, 0.8)):
+        par = w.tree_chainprob(N, p, rng)
+        for sel in (rcr.SELECT_GREEDY_INDEX, rcr.SELECT_LIST_RANK):
+            a = rcr.Plan(par, 8, 3, selection=sel)
+            b = rcr.Plan(par, 8, 3, selection=sel, single_thread=True)
+            assert a.stats() == b.stats()
+            np.testing.assert_array_equal(a.export_ops(), b.export_ops())
+            assert a.device_bytes() == b.device_bytes()

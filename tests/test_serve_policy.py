@@ -46,11 +46,31 @@ def test_group_node_cap_and_footprint():
     assert [r.rid for r in g] == [0, 2]
     g1, fp1 = serve.form_group(ready, 1 << 40, 100, _ws_of, rcr.MIXED32)
     assert [r.rid for r in g1] == [0]
-    w_in, w_out = serve.io_words(100, 4, 2)
-    assert fp1 == 1000 + 8 * w_out
-    w_in2, w_out2 = serve.io_words(130, 4, 2)
-    assert fp == 2000 + 8 * w_out2
+    assert fp1 == 1000 + serve.output_layout(g1)[1]
+    assert fp == 2000 + serve.output_layout(g)[1]
     assert serve.group_footprint(g, rcr.MIXED32, 2000, 77) == fp + 77
+
+
+def test_output_layout_packs_aligned_fields():
+    """Every output field of every request gets its own 256-byte aligned range
+    of the group's block, large enough for its shape; the block is the next
+    power of two at or above the packed total."""
+    g = [_req(0, 100, 4, 2), _req(1, 37, 4, 2), _req(2, 1, 4, 2)]
+    offs, total = serve.output_layout(g)
+    spans = []
+    for r, o in zip(g, offs):
+        sh = rcr.solution_shapes(r.N, r.n, r.m)
+        for k in rcr.SOLUTION_FIELDS:
+            assert o[k] % serve.OUT_FIELD_ALIGN == 0
+            spans.append((o[k], o[k] + 8 * int(np.prod(sh[k]))))
+    spans.sort()
+    assert all(a[1] <= b[0] for a, b in zip(spans, spans[1:]))
+    packed = sum(-(-(b - a) // 256) * 256 for a, b in spans)
+    assert total >= spans[-1][1] and total & (total - 1) == 0 and total < 2 * packed
+    # the outputs of one request are what io_words counts
+    w_in, w_out = serve.io_words(100, 4, 2)
+    sh = rcr.solution_shapes(100, 4, 2)
+    assert sum(int(np.prod(sh[k])) for k in rcr.SOLUTION_FIELDS) == w_out
 
 
 def test_group_respects_budget_and_blocks_when_head_does_not_fit():
