@@ -118,6 +118,29 @@ typedef struct {
 int rcr_plan_create(const int64_t *parent, int64_t N, int32_t n, int32_t m,
                     const rcr_plan_options *opt, rcr_plan **out);
 
+/* The same plan built on the GPU (the device-side planner, Sec. VII: the
+ * structural rounds with list ranking for the compress selection, the
+ * readiness-weighted sibling reductions of Lemma 3, earliest-start levels and
+ * static slots, by one workgroup of one CU, so that solves keep the rest of
+ * the device) from a DEVICE parent array (int64, N entries, root -1).  The
+ * result is byte-identical to rcr_plan_create with RCR_SELECT_LIST_RANK: opt
+ * may be NULL (meaning that selection); RCR_SELECT_GREEDY_INDEX, a sequential
+ * choice in node-id order, is rejected with RCR_BAD_OPTION.  The planner runs
+ * in the order of `stream` (a hipStream_t, NULL the default stream) and the
+ * call returns when the plan's schedules are back on the host; its working
+ * memory (about 0.5 KB per node) comes from the library's device pool and is
+ * released in stream order.  single_thread is ignored.  Errors: RCR_NULL_ARG,
+ * RCR_BAD_DIMS, RCR_INVALID_TREE, RCR_BAD_OPTION, RCR_OOM, RCR_NO_DEVICE,
+ * RCR_HIP_ERROR. */
+int rcr_plan_create_device(const int64_t *parent, int64_t N, int32_t n, int32_t m,
+                           const rcr_plan_options *opt, void *stream, rcr_plan **out);
+
+/* 64-bit FNV-1a hash of everything a plan holds (dimensions, statistics and
+ * every schedule and offset array, each preceded by its length), for checking
+ * that two plans are identical (tests, caches).  Host only.
+ * Errors: RCR_NULL_ARG. */
+int rcr_plan_digest(const rcr_plan *plan, uint64_t *digest);
+
 /* Summary of a plan (host only).  Errors: RCR_NULL_ARG. */
 int rcr_plan_info(const rcr_plan *plan, rcr_plan_stats *out);
 

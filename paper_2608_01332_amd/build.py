@@ -21,7 +21,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "-Wno-u
           "-Wno-unused-result"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
-SOURCES = ["plan.cpp", "api.cpp", "device.hip", "inst4.hip", "inst6.hip", "inst8.hip", "inst12.hip", "inst16.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "device.hip", "dplan.hip", "inst4.hip", "inst6.hip", "inst8.hip", "inst12.hip", "inst16.hip"]
 
 
 def _compile(src: str) -> str:

@@ -171,6 +171,67 @@ int rcr_plan_create(const int64_t *parent, int64_t N, int32_t n, int32_t m, cons
   return RCR_OK;
 }
 
+int rcr_plan_create_device(const int64_t *parent, int64_t N, int32_t n, int32_t m, const rcr_plan_options *opt,
+                           void *stream, rcr_plan **out) {
+  if (!parent || !out) return RCR_NULL_ARG;
+  *out = nullptr;
+  if (opt && opt->selection != RCR_SELECT_LIST_RANK) return RCR_BAD_OPTION;
+  if (!has_device()) return RCR_NO_DEVICE;
+  rcr_plan *p = new_plan();
+  if (!p) return RCR_OOM;
+  int rc;
+  try {
+    rc = rcr::device_plan(parent, N, n, m, (hipStream_t)stream, p->obj.host);
+  } catch (const std::bad_alloc &) {
+    rc = RCR_OOM;
+  }
+  if (rc) {
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return RCR_OK;
+}
+
+int rcr_plan_digest(const rcr_plan *plan, uint64_t *digest) {
+  if (!plan || !digest) return RCR_NULL_ARG;
+  const rcr::PlanHost &h = plan->obj.host;
+  uint64_t x = 1469598103934665603ull;
+  auto bytes = [&x](const void *p, size_t n) {
+    const unsigned char *c = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) {
+      x ^= c[i];
+      x *= 1099511628211ull;
+    }
+  };
+  auto word = [&](int64_t v) { bytes(&v, sizeof v); };
+  auto vec = [&](const auto &v) {
+    word((int64_t)v.size());
+    if (!v.empty()) bytes(v.data(), v.size() * sizeof(v[0]));
+  };
+  for (int64_t v : {h.N, (int64_t)h.n, (int64_t)h.m, h.root, (int64_t)h.selection, h.height, h.leaves, h.max_degree,
+                    h.rounds, h.n_rake, h.n_compress, h.n_combine, h.n_absorb, h.n_contrib, h.n_edge_slots, h.lift_N,
+                    (int64_t)h.lift_n})
+    word(v);
+  vec(h.ops);
+  vec(h.lvl_off);
+  vec(h.kind_off);
+  vec(h.exp_ops);
+  vec(h.exp_off);
+  vec(h.tc_ops);
+  vec(h.tc_off);
+  vec(h.sx_ops);
+  vec(h.sx_off);
+  vec(h.parent32);
+  vec(h.tree_off);
+  vec(h.lift_plus);
+  vec(h.rg_n);
+  vec(h.rg_m);
+  vec(h.rg_off);
+  *digest = x;
+  return RCR_OK;
+}
+
 int rcr_lift_plan_create(const int64_t *parent, int64_t N, int32_t n, int32_t m, const rcr_plan_options *opt,
                          rcr_plan **out) {
   if (!parent || !out) return RCR_NULL_ARG;

@@ -163,7 +163,7 @@ std::mutex pool_mu;
 hipMemPool_t pools[POOL_MAX_DEVICES] = {};
 }  // namespace
 
-static hipError_t dev_alloc(void **p, size_t bytes, hipStream_t st) {
+hipError_t dev_alloc(void **p, size_t bytes, hipStream_t st) {
   int dev = 0;
   hipError_t e = hipStreamGetDevice(st, &dev);
   if (e != hipSuccess) return e;

@@ -119,6 +119,14 @@ struct RhsIO {
 };
 
 int plan_upload(PlanObj &P, hipStream_t st);
+
+// Device memory of the library, from the calling GPU's stream-ordered pool
+// (released with hipFreeAsync).
+hipError_t dev_alloc(void **p, size_t bytes, hipStream_t st);
+
+// The plan of build_plan with the list-rank selection, computed on the device
+// from a device parent array (dplan.hip); the schedules are copied back into P.
+int device_plan(const int64_t *parent, int64_t N, int n, int m, hipStream_t st, PlanHost &P);
 // Bytes of a plan's device copy (its integer arrays), made by plan_upload.
 size_t plan_device_bytes(const PlanHost &h);
 void plan_release_device(PlanObj &P);

@@ -1,0 +1,881 @@
+// Device-side planner (Sec. VII): the plan of build_plan with the list-rank
+// selection, computed by one workgroup on the GPU.
+//
+// The same structural rounds as the host planner (rake every non-root leaf,
+// reduce each parent's new contributions by the readiness-weighted alphabetic
+// code of Lemma 3 and absorb the result, then compress alternate nodes of every
+// maximal path of non-root unary nodes), the same earliest-start levels
+// (eq. (earliest-level)), static slots and pass schedules, so the plan is the
+// host's byte for byte.  The rounds are sequential; inside a round every step
+// is data-parallel over the live nodes:
+//
+//   * the host orders a round's rakes by (parent, sibling key); here every node
+//     keeps the position of its edge in a stable children-by-parent array built
+//     once (a compression hands the removed node's position to its child, as
+//     the host hands over the sibling key), so that order is the order of
+//     positions: a scatter and a stable compaction;
+//   * the alternation along unary paths is the parity of each node's distance
+//     from the top of its path, found by pointer jumping (list ranking);
+//   * each sibling group's code tree is built by one thread, emitting its
+//     combinations in the host's order (post-order), at offsets known from the
+//     group's start (a group of k contributions makes k - 1 combinations and
+//     one absorption);
+//   * the four schedules are stable radix sorts of the round records by level.
+//
+// The program is written once against an executor X: X::each(f) runs f(t) for
+// every thread t and then synchronises the workgroup; bodies write memory only
+// (never the program's own scalars, which every thread derives identically
+// from collective results).  The GPU executor runs it on 1024 threads of one
+// workgroup; CpuExec runs the threads one after the other in a chosen order,
+// which checks that no phase depends on the order of its threads.
+#pragma once
+
+#include <cstdint>
+#include <cstring>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/rcr.h"
+#include "plan.hpp"
+
+namespace rcr {
+namespace dplan {
+
+constexpr int THREADS = 1024;
+
+// statistics words written by the program (int64)
+enum : int {
+  S_STATUS = 0, S_ROOT, S_HEIGHT, S_LEAVES, S_MAXDEG, S_ROUNDS, S_RAKE, S_COMPRESS, S_COMBINE, S_ABSORB,
+  S_CONTRIB, S_SLOTS, S_OPS, S_L, S_EXP, S_LE, S_TC, S_LT, S_SX, S_LX, S_COUNT
+};
+
+// Device (or, for the emulation, host) arrays of one planning run.
+struct Arena {
+  const int64_t *parent;
+  int64_t N;
+  int T;
+  // per node
+  int32_t *par32, *cnt, *up0, *up1, *dist0, *dist1, *cur_par, *lvlU, *lvlE, *edge_slot, *one_child, *alive, *sel,
+      *rem_slot, *rem_par, *comp_r, *comp_k, *rem_kind, *live0, *live1, *leaves, *sorted, *gstart, *elig, *comp, *pos,
+      *mark, *cout, *eP, *eX, *removal;
+  uint64_t *code_hi, *code_lo;  // per sorted rake: the code word r (128 bits)
+  int32_t *code_d;              // and its length
+  // per op / slot (2N)
+  int32_t *contrib_level, *lT;
+  OpRec *raw;
+  uint32_t *k0, *v0, *k1, *v1;  // sort buffers
+  int64_t *off4;                // bucket offsets of a schedule
+  // per thread
+  uint32_t *tcount, *hist;      // T and 16 T
+  // per round (N + 2)
+  int32_t *r_raw, *r_rem, *r_comp_rem, *r_comp_raw;
+  // outputs
+  OpRec *ops;
+  Op4 *exp_ops, *tc_ops, *sx_ops;
+  int64_t *lvl_off, *kind_off, *exp_off, *tc_off, *sx_off;
+  int64_t *stats;
+};
+
+// Lays the arrays out from `base` (every array 256-byte aligned) and returns
+// the total size; with base == nullptr only the size is computed.
+inline size_t carve(Arena &a, char *base, int64_t N, int T) {
+  size_t at = 0;
+  const size_t n1 = (size_t)N + 2, n2 = 2 * (size_t)N + 2;
+  auto take = [&](auto *&p, size_t count) {
+    using E = typename std::remove_reference<decltype(*p)>::type;
+    at = (at + 255) & ~size_t(255);
+    p = base ? reinterpret_cast<E *>(base + at) : nullptr;
+    at += count * sizeof(E);
+  };
+  int32_t **node[] = {&a.par32,   &a.cnt,    &a.up0,     &a.up1,      &a.dist0,  &a.dist1,    &a.cur_par, &a.lvlU,
+                      &a.lvlE,    &a.edge_slot, &a.one_child, &a.alive, &a.sel,    &a.rem_slot, &a.rem_par, &a.comp_r,
+                      &a.comp_k,  &a.rem_kind, &a.live0,  &a.live1,    &a.leaves, &a.sorted,   &a.gstart,  &a.elig,
+                      &a.comp,    &a.pos,    &a.mark,    &a.cout,     &a.eP,     &a.eX,       &a.removal, &a.code_d,
+                      &a.r_raw,   &a.r_rem,  &a.r_comp_rem, &a.r_comp_raw};
+  for (int32_t **p : node) take(*p, n1);
+  take(a.code_hi, n1);
+  take(a.code_lo, n1);
+  take(a.contrib_level, n2);
+  take(a.lT, n2);
+  take(a.raw, n2);
+  take(a.k0, n2);
+  take(a.v0, n2);
+  take(a.k1, n2);
+  take(a.v1, n2);
+  take(a.off4, 4 * n2 + 8);
+  take(a.tcount, (size_t)T);
+  take(a.hist, 16 * (size_t)T);
+  take(a.ops, n2);
+  take(a.exp_ops, n1);
+  take(a.tc_ops, n1);
+  take(a.sx_ops, n1);
+  take(a.lvl_off, n2);
+  take(a.kind_off, 5 * n2);
+  take(a.exp_off, n1);
+  take(a.tc_off, n1);
+  take(a.sx_off, n1);
+  take(a.stats, (size_t)S_COUNT);
+  a.N = N;
+  a.T = T;
+  return (at + 255) & ~size_t(255);
+}
+
+typedef unsigned __int128 u128;
+
+__host__ __device__ inline int bitlen(uint64_t v) {
+  int b = 0;
+  while (v) {
+    ++b;
+    v >>= 1;
+  }
+  return b;
+}
+
+// floor(num / den) for den < 2^63, by restoring long division.
+__host__ __device__ inline u128 div128(u128 num, uint64_t den) {
+  u128 q = 0;
+  uint64_t r = 0;
+  for (int i = 127; i >= 0; --i) {
+    r = (r << 1) | (uint64_t)((num >> i) & 1);
+    q <<= 1;
+    if (r >= den) {
+      r -= den;
+      q |= 1;
+    }
+  }
+  return q;
+}
+
+// Stable compaction of the indices i < n with pred(i), in increasing i:
+// write(i, o) for the o-th of them; returns their number.  Thread t takes the
+// contiguous chunk [t C, (t + 1) C).
+template <class X, class P, class W>
+__host__ __device__ uint32_t compact(X &x, const Arena &a, int64_t n, P pred, W write) {
+  const int T = a.T;
+  const int64_t C = (n + T - 1) / T;
+  x.each([&](int t) {
+    const int64_t b = t * C, e = b + C < n ? b + C : n;
+    uint32_t c = 0;
+    for (int64_t i = b; i < e; ++i) c += pred(i) ? 1u : 0u;
+    a.tcount[t] = c;
+  });
+  const uint32_t total = x.scan(a.tcount);
+  x.each([&](int t) {
+    const int64_t b = t * C, e = b + C < n ? b + C : n;
+    uint32_t o = a.tcount[t];
+    for (int64_t i = b; i < e; ++i)
+      if (pred(i)) write(i, o++);
+  });
+  return total;
+}
+
+// Stable least-significant-digit radix sort of (k[i], v[i]), i < n, on the low
+// `bits` bits of the keys, 4 bits per pass; the result is in (k, v) on return
+// (the pointers are swapped with the spare buffers as passes go).
+template <class X>
+__host__ __device__ void radix_sort(X &x, const Arena &a, int64_t n, int bits, uint32_t *&k, uint32_t *&v,
+                                    uint32_t *&k2, uint32_t *&v2) {
+  const int T = a.T;
+  const int64_t C = (n + T - 1) / T;
+  for (int sh = 0; sh < bits; sh += 4) {
+    uint32_t *kk = k, *vv = v, *kd = k2, *vd = v2;
+    x.each([&](int t) {
+      uint32_t h[16];
+      for (int d = 0; d < 16; ++d) h[d] = 0;
+      const int64_t b = t * C, e = b + C < n ? b + C : n;
+      for (int64_t i = b; i < e; ++i) h[(kk[i] >> sh) & 15]++;
+      for (int d = 0; d < 16; ++d) a.hist[(size_t)d * T + t] = h[d];
+    });
+    // exclusive scan of the digit-major histogram: thread t owns entries [16 t, 16 t + 16)
+    x.each([&](int t) {
+      uint32_t s = 0;
+      for (int j = 0; j < 16; ++j) {
+        const uint32_t c = a.hist[(size_t)16 * t + j];
+        a.hist[(size_t)16 * t + j] = s;
+        s += c;
+      }
+      a.tcount[t] = s;
+    });
+    x.scan(a.tcount);
+    x.each([&](int t) {
+      for (int j = 0; j < 16; ++j) a.hist[(size_t)16 * t + j] += a.tcount[t];
+    });
+    x.each([&](int t) {
+      uint32_t o[16];
+      for (int d = 0; d < 16; ++d) o[d] = a.hist[(size_t)d * T + t];
+      const int64_t b = t * C, e = b + C < n ? b + C : n;
+      for (int64_t i = b; i < e; ++i) {
+        const uint32_t p = o[(kk[i] >> sh) & 15]++;
+        kd[p] = kk[i];
+        vd[p] = vv[i];
+      }
+    });
+    k = kd;
+    v = vd;
+    k2 = kk;
+    v2 = vv;
+  }
+}
+
+// off[b] = the first q < n with key[q] >= b, for b = 0..B (n where none);
+// keys are sorted and below B.
+template <class X>
+__host__ __device__ void bucket_offsets(X &x, const Arena &a, const uint32_t *key, int64_t n, int64_t B, int64_t *off) {
+  x.each([&](int t) {
+    for (int64_t q = t; q <= n; q += a.T) {
+      const int64_t lo = q == 0 ? 0 : (int64_t)key[q - 1] + 1, hi = q == n ? B : (int64_t)key[q];
+      for (int64_t b = lo; b <= hi; ++b) off[b] = q;
+    }
+  });
+}
+
+// One sibling group (Lemma 3): the contributions at sorted positions [s0, s1)
+// of parent i; emits its k - 1 combinations and its absorption at raw[r0 ..]
+// with combination slots c0, c0 + 1, ... in the host's order, and updates
+// lvlU[i].
+__host__ __device__ inline void reduce_group(const Arena &a, int32_t s0, int32_t s1, int32_t r0, int32_t c0,
+                                             int32_t rnd) {
+  const int k = s1 - s0;
+  const int32_t i = a.cur_par[a.sorted[s0]];
+  int32_t agg, agg_lvl;
+  if (k == 1) {
+    agg = a.cout[a.sorted[s0]];
+    agg_lvl = a.contrib_level[agg];
+  } else {
+    int32_t lmin = a.contrib_level[a.cout[a.sorted[s0]]];
+    for (int j = 1; j < k; ++j) {
+      const int32_t l = a.contrib_level[a.cout[a.sorted[s0 + j]]];
+      lmin = l < lmin ? l : lmin;
+    }
+    int lg = 0;
+    while ((1LL << lg) < k) ++lg;
+    const int cap = 61 - lg;
+    u128 W = 0;
+    for (int j = 0; j < k; ++j) {
+      const int e = a.contrib_level[a.cout[a.sorted[s0 + j]]] - lmin;
+      W += (u128)1 << (e < cap ? e : cap);
+    }
+    u128 S = 0;
+    for (int j = 0; j < k; ++j) {
+      const int e0 = a.contrib_level[a.cout[a.sorted[s0 + j]]] - lmin;
+      const u128 w = (u128)1 << (e0 < cap ? e0 : cap);
+      int d = 0;
+      while ((w << d) < W) ++d;
+      d += 1;
+      const u128 r = div128((2 * S + w) << d, (uint64_t)(2 * W));
+      a.code_hi[s0 + j] = (uint64_t)(r >> 64);
+      a.code_lo[s0 + j] = (uint64_t)r;
+      a.code_d[s0 + j] = d;
+      S += w;
+    }
+    auto bit = [&](int j, int p) -> int {
+      const u128 r = ((u128)a.code_hi[s0 + j] << 64) | a.code_lo[s0 + j];
+      return (int)((r >> (a.code_d[s0 + j] - 1 - p)) & 1);
+    };
+    // the host's recursive build, as an explicit stack: frames of (range,
+    // depth, stage, left result); results return through (ret, ret_lvl)
+    struct Frame {
+      int lo, hi, depth, s, stage;
+      int32_t a, la;
+    };
+    Frame st[80];  // the code tree is at most 62 deep
+    int sp = 0;
+    st[sp++] = Frame{0, k - 1, 0, 0, 0, 0, 0};
+    int32_t ret = 0, ret_lvl = 0, emitted = 0;
+    while (sp > 0) {
+      Frame &f = st[sp - 1];
+      if (f.stage == 0) {
+        if (f.lo == f.hi) {
+          ret = a.cout[a.sorted[s0 + f.lo]];
+          ret_lvl = a.contrib_level[ret];
+          --sp;
+          continue;
+        }
+        int s = -1;
+        for (int j = f.lo; j <= f.hi; ++j)
+          if (bit(j, f.depth)) {
+            s = j;
+            break;
+          }
+        if (s < 0 || s == f.lo) {  // unary trie vertex: suppressed
+          ++f.depth;
+          continue;
+        }
+        f.s = s;
+        f.stage = 1;
+        st[sp++] = Frame{f.lo, s - 1, f.depth + 1, 0, 0, 0, 0};
+      } else if (f.stage == 1) {
+        f.a = ret;
+        f.la = ret_lvl;
+        f.stage = 2;
+        st[sp++] = Frame{f.s, f.hi, f.depth + 1, 0, 0, 0, 0};
+      } else {
+        const int32_t lv = 1 + (f.la > ret_lvl ? f.la : ret_lvl);
+        const int32_t out = c0 + emitted;
+        a.contrib_level[out] = lv;
+        a.raw[r0 + emitted] = OpRec{OP_COMBINE, rnd, lv, f.a, ret, out, i, 0};
+        ++emitted;
+        ret = out;
+        ret_lvl = lv;
+        --sp;
+      }
+    }
+    agg = ret;
+    agg_lvl = ret_lvl;
+  }
+  const int32_t lv = 1 + (a.lvlU[i] > agg_lvl ? a.lvlU[i] : agg_lvl);
+  a.raw[r0 + k - 1] = OpRec{OP_ABSORB, rnd, lv, i, agg, 0, 0, 0};
+  a.lvlU[i] = lv;
+}
+
+// The planner.  Returns 0 or a negative RCR_* status; the statistics and
+// schedules are in the arena's outputs.
+template <class X>
+__host__ __device__ int32_t program(X &x, Arena &a) {
+  const int64_t N = a.N;
+  const int T = a.T;
+  // ---- validation, degrees, the root
+  const bool bad = x.any([&](int t) {
+    bool b = false;
+    for (int64_t i = t; i < N; i += T) {
+      const int64_t p = a.parent[i];
+      if (p < 0) {
+        b |= p != -1;
+      } else {
+        b |= p >= N || p == i;
+      }
+      a.cnt[i] = 0;
+    }
+    return b;
+  });
+  if (bad) return RCR_INVALID_TREE;
+  const uint32_t roots = compact(
+      x, a, N, [&](int64_t i) { return a.parent[i] == -1; },
+      [&](int64_t i, uint32_t o) {
+        if (o == 0) a.stats[S_ROOT] = i;
+      });
+  if (roots != 1) return RCR_INVALID_TREE;
+  const int32_t root = (int32_t)a.stats[S_ROOT];
+  x.each([&](int t) {
+    for (int64_t i = t; i < N; i += T) {
+      const int32_t p = (int32_t)a.parent[i];
+      a.par32[i] = p;
+      if (p >= 0) x.atomic_add(&a.cnt[p], 1);
+      a.up0[i] = p < 0 ? (int32_t)i : p;
+      a.dist0[i] = p < 0 ? 0 : 1;
+    }
+  });
+  // ---- depths by pointer jumping; a node that never reaches the root lies on a cycle
+  {
+    int32_t *u = a.up0, *d = a.dist0, *u2 = a.up1, *d2 = a.dist1;
+    const int iters = bitlen((uint64_t)N) + 1;
+    for (int it = 0; it < iters; ++it) {
+      const bool ch = x.any([&](int t) {
+        bool c = false;
+        for (int64_t i = t; i < N; i += T) {
+          const int32_t w = u[i];
+          const int64_t s = (int64_t)d[i] + d[w];  // bounded: on a cycle it would grow without end
+          d2[i] = s > INT32_MAX ? INT32_MAX : (int32_t)s;
+          u2[i] = u[w];
+          c |= u2[i] != w;
+        }
+        return c;
+      });
+      int32_t *tu = u, *td = d;
+      u = u2;
+      d = d2;
+      u2 = tu;
+      d2 = td;
+      if (!ch) break;
+    }
+    const bool cyc = x.any([&](int t) {
+      bool c = false;
+      for (int64_t i = t; i < N; i += T) c |= u[i] != root;
+      return c;
+    });
+    if (cyc) return RCR_INVALID_TREE;
+    const int32_t h = x.maxall([&](int t) {
+      int32_t m = 0;
+      for (int64_t i = t; i < N; i += T) m = d[i] > m ? d[i] : m;
+      return m;
+    });
+    const int32_t maxdeg = x.maxall([&](int t) {
+      int32_t m = 0;
+      for (int64_t i = t; i < N; i += T) m = a.cnt[i] > m ? a.cnt[i] : m;
+      return m;
+    });
+    const uint32_t nleaf = compact(
+        x, a, N, [&](int64_t i) { return a.cnt[i] == 0; }, [&](int64_t, uint32_t) {});
+    x.each([&](int t) {
+      if (t == 0) {
+        a.stats[S_HEIGHT] = h;
+        a.stats[S_MAXDEG] = maxdeg;
+        a.stats[S_LEAVES] = nleaf;
+      }
+    });
+  }
+  // ---- edge positions: non-root nodes stably sorted by parent
+  {
+    uint32_t *k = a.k0, *v = a.v0, *k2 = a.k1, *v2 = a.v1;
+    const uint32_t n1 = compact(
+        x, a, N, [&](int64_t i) { return i != root; },
+        [&](int64_t i, uint32_t o) {
+          k[o] = (uint32_t)a.par32[i];
+          v[o] = (uint32_t)i;
+        });
+    radix_sort(x, a, n1, bitlen((uint64_t)(N - 1)), k, v, k2, v2);
+    x.each([&](int t) {
+      for (int64_t q = t; q < (int64_t)n1; q += T) a.pos[v[q]] = (int32_t)q;
+    });
+  }
+  // ---- rounds
+  x.each([&](int t) {
+    for (int64_t i = t; i < N; i += T) {
+      a.cur_par[i] = a.par32[i];
+      a.lvlU[i] = a.lvlE[i] = 0;
+      a.edge_slot[i] = (int32_t)i;
+      a.one_child[i] = -1;
+      a.alive[i] = 1;
+      a.sel[i] = 0;
+      a.rem_slot[i] = a.rem_par[i] = a.comp_r[i] = a.comp_k[i] = -1;
+      a.rem_kind[i] = 0;
+      a.live0[i] = (int32_t)i;
+      a.mark[i] = -1;
+      a.eP[i] = a.eX[i] = 0;
+    }
+  });
+  int32_t *live = a.live0, *live_next = a.live1;
+  int64_t live_n = N;
+  int32_t rnd = 0, next_slot = (int32_t)N, next_contrib = 0, raw_n = 0, rem_n = 0;
+  int64_t n_rake = 0, n_compress = 0, n_combine = 0, n_absorb = 0;
+  while (live_n > 1) {
+    ++rnd;
+    if (rnd > N) return RCR_INVALID_TREE;  // no progress: cannot happen on a tree (Lemma 2)
+    const int32_t round_raw = raw_n, round_rem = rem_n;
+    // rakes: every live non-root leaf, in increasing id
+    const uint32_t nl = compact(
+        x, a, live_n, [&](int64_t q) { return live[q] != root && a.cnt[live[q]] == 0; },
+        [&](int64_t q, uint32_t o) { a.leaves[o] = live[q]; });
+    x.each([&](int t) {
+      if (t == 0) {
+        a.r_raw[rnd] = round_raw;
+        a.r_rem[rnd] = round_rem;
+      }
+      for (int64_t q = t; q < (int64_t)nl; q += T) {
+        const int32_t j = a.leaves[q];
+        const int32_t lv = 1 + (a.lvlU[j] > a.lvlE[j] ? a.lvlU[j] : a.lvlE[j]);
+        const int32_t out = next_contrib + (int32_t)q;
+        a.contrib_level[out] = lv;
+        a.raw[raw_n + q] = OpRec{OP_RAKE, rnd, lv, j, a.edge_slot[j], out, a.cur_par[j], 0};
+        a.rem_kind[j] = 1;
+        a.rem_slot[j] = a.edge_slot[j];
+        a.rem_par[j] = a.cur_par[j];
+        a.removal[rem_n + q] = j;
+        a.cout[j] = out;
+        a.mark[a.pos[j]] = j;
+      }
+    });
+    n_rake += nl;
+    next_contrib += (int32_t)nl;
+    raw_n += (int32_t)nl;
+    rem_n += (int32_t)nl;
+    // the rakes in (parent, sibling) order: the order of their edge positions
+    compact(
+        x, a, N - 1, [&](int64_t q) { return a.mark[q] >= 0; },
+        [&](int64_t q, uint32_t o) {
+          a.sorted[o] = a.mark[q];
+          a.mark[q] = -1;
+        });
+    const uint32_t G = compact(
+        x, a, nl,
+        [&](int64_t q) { return q == 0 || a.cur_par[a.sorted[q]] != a.cur_par[a.sorted[q - 1]]; },
+        [&](int64_t q, uint32_t o) { a.gstart[o] = (int32_t)q; });
+    {
+      const int32_t r0 = raw_n, c0 = next_contrib;
+      x.each([&](int t) {
+        for (int64_t g = t; g < (int64_t)G; g += T) {
+          const int32_t s0 = a.gstart[g], s1 = g + 1 < (int64_t)G ? a.gstart[g + 1] : (int32_t)nl;
+          reduce_group(a, s0, s1, r0 + s0, c0 + (s0 - (int32_t)g), rnd);
+        }
+      });
+    }
+    raw_n += (int32_t)nl;
+    next_contrib += (int32_t)nl - (int32_t)G;
+    n_combine += nl - G;
+    n_absorb += G;
+    x.each([&](int t) {
+      for (int64_t q = t; q < (int64_t)nl; q += T) {
+        const int32_t j = a.leaves[q];
+        a.alive[j] = 0;
+        x.atomic_add(&a.cnt[a.cur_par[j]], -1);
+      }
+    });
+    // unary nodes of the post-rake tree and the single child of each
+    x.each([&](int t) {
+      for (int64_t q = t; q < live_n; q += T) {
+        const int32_t v = live[q];
+        if (a.alive[v] && v != root && a.cnt[a.cur_par[v]] == 1) a.one_child[a.cur_par[v]] = v;
+      }
+    });
+    const uint32_t ne = compact(
+        x, a, live_n,
+        [&](int64_t q) {
+          const int32_t v = live[q];
+          return a.alive[v] && v != root && a.cnt[v] == 1;
+        },
+        [&](int64_t q, uint32_t o) { a.elig[o] = live[q]; });
+    // list ranking: distance of every unary node from the top of its path
+    x.each([&](int t) {
+      for (int64_t q = t; q < (int64_t)ne; q += T) a.sel[a.elig[q]] = 2;
+    });
+    x.each([&](int t) {
+      for (int64_t q = t; q < (int64_t)ne; q += T) {
+        const int32_t v = a.elig[q], p = a.cur_par[v];
+        const bool up = a.sel[p] == 2;
+        a.up0[v] = up ? p : v;
+        a.dist0[v] = up ? 1 : 0;
+      }
+    });
+    {
+      int32_t *u = a.up0, *d = a.dist0, *u2 = a.up1, *d2 = a.dist1;
+      for (int it = 0; it < 64; ++it) {
+        const bool ch = x.any([&](int t) {
+          bool c = false;
+          for (int64_t q = t; q < (int64_t)ne; q += T) {
+            const int32_t v = a.elig[q], w = u[v];
+            d2[v] = d[v] + d[w];
+            u2[v] = u[w];
+            c |= u2[v] != w;
+          }
+          return c;
+        });
+        int32_t *tu = u, *td = d;
+        u = u2;
+        d = d2;
+        u2 = tu;
+        d2 = td;
+        if (!ch) break;
+      }
+      x.each([&](int t) {
+        for (int64_t q = t; q < (int64_t)ne; q += T) a.sel[a.elig[q]] = (d[a.elig[q]] & 1) == 0 ? 1 : 0;
+      });
+    }
+    // compressions of the selected nodes, in increasing id
+    const uint32_t nc = compact(
+        x, a, ne, [&](int64_t q) { return a.sel[a.elig[q]] == 1; },
+        [&](int64_t q, uint32_t o) { a.comp[o] = a.elig[q]; });
+    x.each([&](int t) {
+      if (t == 0) {
+        a.r_comp_rem[rnd] = rem_n;
+        a.r_comp_raw[rnd] = raw_n;
+      }
+      for (int64_t q = t; q < (int64_t)nc; q += T) {
+        const int32_t j = a.comp[q], i = a.cur_par[j], k = a.one_child[j];
+        int32_t lv = a.lvlU[j] > a.lvlE[k] ? a.lvlU[j] : a.lvlE[k];
+        lv = 1 + (a.lvlE[j] > lv ? a.lvlE[j] : lv);
+        const int32_t s = next_slot + (int32_t)q;
+        a.raw[raw_n + q] = OpRec{OP_COMPRESS, rnd, lv, j, a.edge_slot[j], a.edge_slot[k], s, k};
+        a.rem_kind[j] = 2;
+        a.rem_slot[j] = a.edge_slot[j];
+        a.rem_par[j] = i;
+        a.comp_r[j] = a.edge_slot[k];
+        a.comp_k[j] = k;
+        a.removal[rem_n + q] = j;
+        a.edge_slot[k] = s;
+        a.lvlE[k] = lv;
+        a.cur_par[k] = i;
+        a.pos[k] = a.pos[j];
+        a.alive[j] = 0;
+      }
+    });
+    next_slot += (int32_t)nc;
+    raw_n += (int32_t)nc;
+    rem_n += (int32_t)nc;
+    n_compress += nc;
+    x.each([&](int t) {
+      for (int64_t q = t; q < (int64_t)ne; q += T) a.sel[a.elig[q]] = 0;
+    });
+    live_n = compact(
+        x, a, live_n, [&](int64_t q) { return a.alive[live[q]] != 0; },
+        [&](int64_t q, uint32_t o) { live_next[o] = live[q]; });
+    int32_t *tl = live;
+    live = live_next;
+    live_next = tl;
+  }
+  const int32_t rounds = rnd;
+  x.each([&](int t) {
+    if (t == 0) {
+      a.r_raw[rounds + 1] = raw_n;
+      a.r_rem[rounds + 1] = rem_n;
+    }
+  });
+
+  // ---- contraction levels: ops by (level, kind), stable in creation order
+  uint32_t *k = a.k0, *v = a.v0, *k2 = a.k1, *v2 = a.v1;
+  const int32_t L = x.maxall([&](int t) {
+    int32_t m = 0;
+    for (int64_t i = t; i < raw_n; i += T) m = a.raw[i].level > m ? a.raw[i].level : m;
+    return m;
+  });
+  x.each([&](int t) {
+    for (int64_t i = t; i < raw_n; i += T) {
+      k[i] = (uint32_t)((a.raw[i].level - 1) * 4 + a.raw[i].kind);
+      v[i] = (uint32_t)i;
+    }
+  });
+  radix_sort(x, a, raw_n, bitlen((uint64_t)(4 * (int64_t)L)), k, v, k2, v2);
+  x.each([&](int t) {
+    for (int64_t q = t; q < raw_n; q += T) a.ops[q] = a.raw[v[q]];
+  });
+  bucket_offsets(x, a, k, raw_n, 4 * (int64_t)L, a.off4);
+  x.each([&](int t) {
+    for (int64_t l = t; l <= L; l += T) a.lvl_off[l] = a.off4[4 * l];
+    for (int64_t l = t; l < L; l += T)
+      for (int s = 0; s <= 4; ++s) a.kind_off[5 * l + s] = a.off4[4 * l + s];
+  });
+
+  // ---- expansion of compressions: level 1 + that of the child's value, stable in removal order
+  for (int32_t r = rounds; r >= 1; --r)
+    x.each([&](int t) {
+      for (int64_t q = a.r_comp_rem[r] + t; q < a.r_rem[r + 1]; q += T) {
+        const int32_t j = a.removal[q];
+        a.eP[j] = 1 + a.eP[a.comp_k[j]];
+      }
+    });
+  const int32_t LE = x.maxall([&](int t) {
+    int32_t m = 0;
+    for (int64_t i = t; i < N; i += T) m = a.eP[i] > m ? a.eP[i] : m;
+    return m;
+  });
+  const uint32_t n_exp = compact(
+      x, a, rem_n, [&](int64_t q) { return a.rem_kind[a.removal[q]] == 2; },
+      [&](int64_t q, uint32_t o) {
+        const int32_t j = a.removal[q];
+        k[o] = (uint32_t)(a.eP[j] - 1);
+        v[o] = (uint32_t)j;
+      });
+  radix_sort(x, a, n_exp, bitlen((uint64_t)LE), k, v, k2, v2);
+  x.each([&](int t) {
+    for (int64_t q = t; q < (int64_t)n_exp; q += T) {
+      const int32_t j = (int32_t)v[q];
+      a.exp_ops[q] = Op4{j, a.comp_r[j], a.comp_k[j], 0};
+    }
+  });
+  bucket_offsets(x, a, k, n_exp, LE, a.exp_off);
+
+  // ---- composition of edge maps along compressions, stable in creation order
+  x.each([&](int t) {
+    for (int64_t s = t; s < next_slot; s += T) a.lT[s] = 0;
+  });
+  for (int32_t r = 1; r <= rounds; ++r)
+    x.each([&](int t) {
+      for (int64_t q = a.r_comp_raw[r] + t; q < a.r_raw[r + 1]; q += T) {
+        const OpRec o = a.raw[q];
+        a.lT[o.d] = 1 + (a.lT[o.b] > a.lT[o.c] ? a.lT[o.b] : a.lT[o.c]);
+      }
+    });
+  const int32_t LT = x.maxall([&](int t) {
+    int32_t m = 0;
+    for (int64_t s = t; s < next_slot; s += T) m = a.lT[s] > m ? a.lT[s] : m;
+    return m;
+  });
+  const uint32_t n_tc = compact(
+      x, a, raw_n, [&](int64_t q) { return a.raw[q].kind == OP_COMPRESS; },
+      [&](int64_t q, uint32_t o) {
+        k[o] = (uint32_t)(a.lT[a.raw[q].d] - 1);
+        v[o] = (uint32_t)q;
+      });
+  radix_sort(x, a, n_tc, bitlen((uint64_t)LT), k, v, k2, v2);
+  x.each([&](int t) {
+    for (int64_t q = t; q < (int64_t)n_tc; q += T) {
+      const OpRec o = a.raw[v[q]];
+      a.tc_ops[q] = Op4{o.b, o.c, o.d, o.a};
+    }
+  });
+  bucket_offsets(x, a, k, n_tc, LT, a.tc_off);
+
+  // ---- state expansion: 1 + the level of the parent at removal, stable in removal order
+  for (int32_t r = rounds; r >= 1; --r) {
+    x.each([&](int t) {  // the round's compressions come after its rakes in removal order
+      for (int64_t q = a.r_comp_rem[r] + t; q < a.r_rem[r + 1]; q += T) {
+        const int32_t j = a.removal[q];
+        a.eX[j] = 1 + a.eX[a.rem_par[j]];
+      }
+    });
+    x.each([&](int t) {
+      for (int64_t q = a.r_rem[r] + t; q < a.r_comp_rem[r]; q += T) {
+        const int32_t j = a.removal[q];
+        a.eX[j] = 1 + a.eX[a.rem_par[j]];
+      }
+    });
+  }
+  const int32_t LX = x.maxall([&](int t) {
+    int32_t m = 0;
+    for (int64_t i = t; i < N; i += T) m = a.eX[i] > m ? a.eX[i] : m;
+    return m;
+  });
+  x.each([&](int t) {
+    for (int64_t q = t; q < rem_n; q += T) {
+      const int32_t j = a.removal[q];
+      k[q] = (uint32_t)(a.eX[j] - 1);
+      v[q] = (uint32_t)j;
+    }
+  });
+  radix_sort(x, a, rem_n, bitlen((uint64_t)LX), k, v, k2, v2);
+  x.each([&](int t) {
+    for (int64_t q = t; q < rem_n; q += T) {
+      const int32_t j = (int32_t)v[q];
+      a.sx_ops[q] = Op4{j, a.rem_slot[j], a.rem_par[j], 0};
+    }
+  });
+  bucket_offsets(x, a, k, rem_n, LX, a.sx_off);
+
+  x.each([&](int t) {
+    if (t == 0) {
+      a.stats[S_ROUNDS] = rounds;
+      a.stats[S_RAKE] = n_rake;
+      a.stats[S_COMPRESS] = n_compress;
+      a.stats[S_COMBINE] = n_combine;
+      a.stats[S_ABSORB] = n_absorb;
+      a.stats[S_CONTRIB] = next_contrib;
+      a.stats[S_SLOTS] = next_slot;
+      a.stats[S_OPS] = raw_n;
+      a.stats[S_L] = L;
+      a.stats[S_EXP] = n_exp;
+      a.stats[S_LE] = LE;
+      a.stats[S_TC] = n_tc;
+      a.stats[S_LT] = LT;
+      a.stats[S_SX] = rem_n;
+      a.stats[S_LX] = LX;
+    }
+  });
+  return 0;
+}
+
+// Sequential executor: the threads of each phase one after the other, in the
+// order `order` gives (0 increasing, 1 decreasing, 2 odd then even).
+struct CpuExec {
+  int T = THREADS, order = 0;
+  int tid(int k) const {
+    if (order == 1) return T - 1 - k;
+    if (order == 2) {
+      const int odd = T / 2;
+      return k < odd ? 2 * k + 1 : 2 * (k - odd);
+    }
+    return k;
+  }
+  template <class F>
+  void each(F f) {
+    for (int k = 0; k < T; ++k) f(tid(k));
+  }
+  template <class F>
+  bool any(F f) {
+    bool r = false;
+    for (int k = 0; k < T; ++k) r = f(tid(k)) || r;
+    return r;
+  }
+  template <class F>
+  int32_t maxall(F f) {
+    int32_t m = INT32_MIN;
+    for (int k = 0; k < T; ++k) {
+      const int32_t v = f(tid(k));
+      m = v > m ? v : m;
+    }
+    return m;
+  }
+  uint32_t scan(uint32_t *a) {
+    uint32_t s = 0;
+    for (int t = 0; t < T; ++t) {
+      const uint32_t c = a[t];
+      a[t] = s;
+      s += c;
+    }
+    return s;
+  }
+  void atomic_add(int32_t *p, int32_t v) { *p += v; }
+};
+
+// Copies a finished run's statistics and schedules (host copies of the arena's
+// outputs: `stats`, and the arrays at the sizes the statistics give) into a
+// plan.
+struct HostOut {
+  int64_t stats[S_COUNT];
+  std::vector<int32_t> par32;
+  std::vector<OpRec> ops;
+  std::vector<Op4> exp_ops, tc_ops, sx_ops;
+  std::vector<int64_t> lvl_off, kind_off, exp_off, tc_off, sx_off;
+};
+
+inline void fill_plan(const HostOut &h, int64_t N, int n, int m, PlanHost &P) {
+  P = PlanHost();
+  P.N = N;
+  P.n = n;
+  P.m = m;
+  P.selection = RCR_SELECT_LIST_RANK;
+  P.root = h.stats[S_ROOT];
+  P.height = h.stats[S_HEIGHT];
+  P.leaves = h.stats[S_LEAVES];
+  P.max_degree = h.stats[S_MAXDEG];
+  P.rounds = h.stats[S_ROUNDS];
+  P.n_rake = h.stats[S_RAKE];
+  P.n_compress = h.stats[S_COMPRESS];
+  P.n_combine = h.stats[S_COMBINE];
+  P.n_absorb = h.stats[S_ABSORB];
+  P.n_contrib = h.stats[S_CONTRIB];
+  P.n_edge_slots = h.stats[S_SLOTS];
+  P.parent32 = h.par32;
+  P.ops = h.ops;
+  P.lvl_off = h.lvl_off;
+  P.kind_off = h.kind_off;
+  P.exp_ops = h.exp_ops;
+  P.exp_off = h.exp_off;
+  P.tc_ops = h.tc_ops;
+  P.tc_off = h.tc_off;
+  P.sx_ops = h.sx_ops;
+  P.sx_off = h.sx_off;
+}
+
+// Element counts of the output arrays of a finished run.
+struct OutSizes {
+  size_t ops, lvl, kind, exp, exp_off, tc, tc_off, sx, sx_off;
+};
+inline OutSizes out_sizes(const int64_t *s) {
+  return OutSizes{(size_t)s[S_OPS], (size_t)s[S_L] + 1, 5 * (size_t)s[S_L], (size_t)s[S_EXP], (size_t)s[S_LE] + 1,
+                  (size_t)s[S_TC],  (size_t)s[S_LT] + 1, (size_t)s[S_SX], (size_t)s[S_LX] + 1};
+}
+
+// The planner run on the host by CpuExec over host arrays (the same program
+// the GPU runs), for checking the program itself without a GPU.
+inline int emulate(const int64_t *parent, int64_t N, int n, int m, int T, int order, PlanHost &P) {
+  if (!parent) return RCR_NULL_ARG;
+  if (N < 1 || n < 1 || m < 1 || n > RCR_MAX_DIM || m > RCR_MAX_DIM) return RCR_BAD_DIMS;
+  if (N > (int64_t)(INT32_MAX / 2 - 16)) return RCR_BAD_DIMS;
+  Arena a;
+  const size_t bytes = carve(a, nullptr, N, T);
+  std::vector<uint64_t> mem(bytes / 8 + 1);
+  carve(a, reinterpret_cast<char *>(mem.data()), N, T);
+  a.parent = parent;
+  CpuExec x;
+  x.T = T;
+  x.order = order;
+  const int32_t rc = program(x, a);
+  if (rc) return rc;
+  HostOut h;
+  memcpy(h.stats, a.stats, sizeof(h.stats));
+  const OutSizes z = out_sizes(a.stats);
+  h.par32.assign(a.par32, a.par32 + N);
+  h.ops.assign(a.ops, a.ops + z.ops);
+  h.lvl_off.assign(a.lvl_off, a.lvl_off + z.lvl);
+  h.kind_off.assign(a.kind_off, a.kind_off + z.kind);
+  h.exp_ops.assign(a.exp_ops, a.exp_ops + z.exp);
+  h.exp_off.assign(a.exp_off, a.exp_off + z.exp_off);
+  h.tc_ops.assign(a.tc_ops, a.tc_ops + z.tc);
+  h.tc_off.assign(a.tc_off, a.tc_off + z.tc_off);
+  h.sx_ops.assign(a.sx_ops, a.sx_ops + z.sx);
+  h.sx_off.assign(a.sx_off, a.sx_off + z.sx_off);
+  fill_plan(h, N, n, m, P);
+  return 0;
+}
+
+}  // namespace dplan
+}  // namespace rcr

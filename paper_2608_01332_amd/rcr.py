@@ -92,7 +92,7 @@ class SolveOptions(ctypes.Structure):
                 ("kernel_launches", ctypes.POINTER(ctypes.c_int32)), ("reserved", ctypes.c_int32 * 4)]
 
 
-EXPORTED = ("rcr_plan_create", "rcr_plan_info", "rcr_plan_device_bytes", "rcr_plan_export", "rcr_plan_destroy", "rcr_batch_plan_create",
+EXPORTED = ("rcr_plan_create", "rcr_plan_create_device", "rcr_plan_digest", "rcr_plan_info", "rcr_plan_device_bytes", "rcr_plan_export", "rcr_plan_destroy", "rcr_batch_plan_create",
             "rcr_plan_upload", "rcr_lift_plan_create", "rcr_lift_solve", "rcr_plan_set_launch",
             "rcr_plan_get_launch", "rcr_plan_tune",
             "rcr_workspace_size", "rcr_solve", "rcr_factor", "rcr_solve_rhs", "rcr_adjoint", "rcr_kkt_residual",
@@ -121,6 +121,12 @@ def lib():
             L.rcr_plan_create.restype = ctypes.c_int
             L.rcr_plan_create.argtypes = [_i64p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.POINTER(PlanOptions), ctypes.POINTER(ctypes.c_void_p)]
+            L.rcr_plan_create_device.restype = ctypes.c_int
+            L.rcr_plan_create_device.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                                 ctypes.POINTER(PlanOptions), ctypes.c_void_p,
+                                                 ctypes.POINTER(ctypes.c_void_p)]
+            L.rcr_plan_digest.restype = ctypes.c_int
+            L.rcr_plan_digest.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]
             L.rcr_plan_info.restype = ctypes.c_int
             L.rcr_plan_info.argtypes = [ctypes.c_void_p, ctypes.POINTER(PlanStats)]
             L.rcr_plan_device_bytes.restype = ctypes.c_int64
@@ -282,6 +288,37 @@ class Plan:
         if rc != 0:
             raise RcrError(rc, "rcr_plan_create")
         self._h = h
+
+    @classmethod
+    def from_device(cls, parent, n: int, m: int, stream=None) -> "Plan":
+        """rcr_plan_create_device: the plan built on the GPU from a device int64
+        parent tensor (list-rank selection; identical to
+        Plan(parent, n, m, selection=SELECT_LIST_RANK))."""
+        import torch
+        if not isinstance(parent, torch.Tensor) or not parent.is_cuda or parent.dtype != torch.int64 \
+                or not parent.is_contiguous() or parent.dim() != 1:
+            raise TypeError("parent must be a contiguous 1-D int64 CUDA tensor")
+        L = lib()
+        self = cls.__new__(cls)
+        self.N = int(parent.shape[0])
+        self.n, self.m = int(n), int(m)
+        st = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        opt = PlanOptions(selection=SELECT_LIST_RANK)
+        rc = L.rcr_plan_create_device(ctypes.c_void_p(parent.data_ptr()), self.N, self.n, self.m, ctypes.byref(opt),
+                                      ctypes.c_void_p(st.cuda_stream), ctypes.byref(h))
+        if rc != 0:
+            raise RcrError(rc, "rcr_plan_create_device")
+        self._h = h
+        return self
+
+    def digest(self) -> int:
+        """rcr_plan_digest: a hash of every array and statistic of the plan."""
+        d = ctypes.c_uint64()
+        rc = lib().rcr_plan_digest(self._h, ctypes.byref(d))
+        if rc != 0:
+            raise RcrError(rc, "rcr_plan_digest")
+        return int(d.value)
 
     def stats(self) -> dict:
         s = PlanStats()

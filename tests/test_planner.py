@@ -285,3 +285,18 @@ def test_single_thread_build_equals_default():
             assert a.stats() == b.stats()
             np.testing.assert_array_equal(a.export_ops(), b.export_ops())
             assert a.device_bytes() == b.device_bytes()
+
+
+def test_plan_digest_identifies_plans():
+    """rcr_plan_digest is equal for plans built alike and differs when any
+    schedule differs (another selection, another dimension, another tree)."""
+    rng = np.random.default_rng(5)
+    par = w.tree_chainprob(3000, 0.9, rng)
+    a = rcr.Plan(par, 6, 2, selection=rcr.SELECT_LIST_RANK)
+    b = rcr.Plan(par.copy(), 6, 2, selection=rcr.SELECT_LIST_RANK, single_thread=True)
+    assert a.digest() == b.digest()
+    assert rcr.Plan(par, 6, 2).digest() != a.digest()
+    assert rcr.Plan(par, 6, 3, selection=rcr.SELECT_LIST_RANK).digest() != a.digest()
+    par2 = par.copy()
+    par2[-1] = 0
+    assert rcr.Plan(par2, 6, 2, selection=rcr.SELECT_LIST_RANK).digest() != a.digest()
