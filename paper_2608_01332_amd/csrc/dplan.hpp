@@ -57,7 +57,7 @@ struct Arena {
   // per node
   int32_t *par32, *cnt, *up0, *up1, *dist0, *dist1, *cur_par, *lvlU, *lvlE, *edge_slot, *one_child, *alive, *sel,
       *rem_slot, *rem_par, *comp_r, *comp_k, *rem_kind, *live0, *live1, *leaves, *sorted, *gstart, *elig, *comp, *pos,
-      *mark, *cout, *eP, *eX, *removal;
+      *mark, *cout, *eP, *eX, *removal, *gslot, *glev;
   uint64_t *code_hi, *code_lo;  // per sorted rake: the code word r (128 bits)
   int32_t *code_d;              // and its length
   // per op / slot (2N)
@@ -91,6 +91,7 @@ inline size_t carve(Arena &a, char *base, int64_t N, int T) {
                       &a.lvlE,    &a.edge_slot, &a.one_child, &a.alive, &a.sel,    &a.rem_slot, &a.rem_par, &a.comp_r,
                       &a.comp_k,  &a.rem_kind, &a.live0,  &a.live1,    &a.leaves, &a.sorted,   &a.gstart,  &a.elig,
                       &a.comp,    &a.pos,    &a.mark,    &a.cout,     &a.eP,     &a.eX,       &a.removal, &a.code_d,
+                      &a.gslot,   &a.glev,
                       &a.r_raw,   &a.r_rem,  &a.r_comp_rem, &a.r_comp_raw};
   for (int32_t **p : node) take(*p, n1);
   take(a.code_hi, n1);
@@ -146,9 +147,13 @@ __host__ __device__ inline u128 div128(u128 num, uint64_t den) {
   return q;
 }
 
+// Items a thread handles together: their loads are issued before any of
+// their results is used, so up to this many memory round trips overlap.
+constexpr int BATCH = 8;
+
 // Stable compaction of the indices i < n with pred(i), in increasing i:
 // write(i, o) for the o-th of them; returns their number.  Thread t takes the
-// contiguous chunk [t C, (t + 1) C).
+// contiguous chunk [t C, (t + 1) C); pred must not depend on what write stores.
 template <class X, class P, class W>
 __host__ __device__ uint32_t compact(X &x, const Arena &a, int64_t n, P pred, W write) {
   const int T = a.T;
@@ -156,15 +161,27 @@ __host__ __device__ uint32_t compact(X &x, const Arena &a, int64_t n, P pred, W 
   x.each([&](int t) {
     const int64_t b = t * C, e = b + C < n ? b + C : n;
     uint32_t c = 0;
-    for (int64_t i = b; i < e; ++i) c += pred(i) ? 1u : 0u;
+    for (int64_t i0 = b; i0 < e; i0 += BATCH) {
+      bool f[BATCH];
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) f[u] = i0 + u < e && pred(i0 + u);
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) c += f[u] ? 1u : 0u;
+    }
     a.tcount[t] = c;
   });
   const uint32_t total = x.scan(a.tcount);
   x.each([&](int t) {
     const int64_t b = t * C, e = b + C < n ? b + C : n;
     uint32_t o = a.tcount[t];
-    for (int64_t i = b; i < e; ++i)
-      if (pred(i)) write(i, o++);
+    for (int64_t i0 = b; i0 < e; i0 += BATCH) {
+      bool f[BATCH];
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) f[u] = i0 + u < e && pred(i0 + u);
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u)
+        if (f[u]) write(i0 + u, o++);
+    }
   });
   return total;
 }
@@ -183,7 +200,14 @@ __host__ __device__ void radix_sort(X &x, const Arena &a, int64_t n, int bits, u
       uint32_t h[16];
       for (int d = 0; d < 16; ++d) h[d] = 0;
       const int64_t b = t * C, e = b + C < n ? b + C : n;
-      for (int64_t i = b; i < e; ++i) h[(kk[i] >> sh) & 15]++;
+      for (int64_t i0 = b; i0 < e; i0 += BATCH) {
+        uint32_t dg[BATCH];
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) dg[u] = i0 + u < e ? (kk[i0 + u] >> sh) & 15 : 16;
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u)
+          if (dg[u] < 16) h[dg[u]]++;
+      }
       for (int d = 0; d < 16; ++d) a.hist[(size_t)d * T + t] = h[d];
     });
     // exclusive scan of the digit-major histogram: thread t owns entries [16 t, 16 t + 16)
@@ -204,10 +228,20 @@ __host__ __device__ void radix_sort(X &x, const Arena &a, int64_t n, int bits, u
       uint32_t o[16];
       for (int d = 0; d < 16; ++d) o[d] = a.hist[(size_t)d * T + t];
       const int64_t b = t * C, e = b + C < n ? b + C : n;
-      for (int64_t i = b; i < e; ++i) {
-        const uint32_t p = o[(kk[i] >> sh) & 15]++;
-        kd[p] = kk[i];
-        vd[p] = vv[i];
+      for (int64_t i0 = b; i0 < e; i0 += BATCH) {
+        uint32_t kb[BATCH], vb[BATCH];
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) {
+          kb[u] = i0 + u < e ? kk[i0 + u] : 0;
+          vb[u] = i0 + u < e ? vv[i0 + u] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u)
+          if (i0 + u < e) {
+            const uint32_t p = o[(kb[u] >> sh) & 15]++;
+            kd[p] = kb[u];
+            vd[p] = vb[u];
+          }
       }
     });
     k = kd;
@@ -230,34 +264,32 @@ __host__ __device__ void bucket_offsets(X &x, const Arena &a, const uint32_t *ke
 }
 
 // One sibling group (Lemma 3): the contributions at sorted positions [s0, s1)
-// of parent i; emits its k - 1 combinations and its absorption at raw[r0 ..]
-// with combination slots c0, c0 + 1, ... in the host's order, and updates
-// lvlU[i].
+// of parent i (their slots and levels staged in gslot, glev); emits its k - 1
+// combinations and its absorption at raw[r0 ..] with combination slots c0,
+// c0 + 1, ... in the host's order, and updates lvlU[i].
 __host__ __device__ inline void reduce_group(const Arena &a, int32_t s0, int32_t s1, int32_t r0, int32_t c0,
                                              int32_t rnd) {
   const int k = s1 - s0;
   const int32_t i = a.cur_par[a.sorted[s0]];
+  const int32_t *gslot = a.gslot + s0, *glev = a.glev + s0;
   int32_t agg, agg_lvl;
   if (k == 1) {
-    agg = a.cout[a.sorted[s0]];
-    agg_lvl = a.contrib_level[agg];
+    agg = gslot[0];
+    agg_lvl = glev[0];
   } else {
-    int32_t lmin = a.contrib_level[a.cout[a.sorted[s0]]];
-    for (int j = 1; j < k; ++j) {
-      const int32_t l = a.contrib_level[a.cout[a.sorted[s0 + j]]];
-      lmin = l < lmin ? l : lmin;
-    }
+    int32_t lmin = glev[0];
+    for (int j = 1; j < k; ++j) lmin = glev[j] < lmin ? glev[j] : lmin;
     int lg = 0;
     while ((1LL << lg) < k) ++lg;
     const int cap = 61 - lg;
     u128 W = 0;
     for (int j = 0; j < k; ++j) {
-      const int e = a.contrib_level[a.cout[a.sorted[s0 + j]]] - lmin;
+      const int e = glev[j] - lmin;
       W += (u128)1 << (e < cap ? e : cap);
     }
     u128 S = 0;
     for (int j = 0; j < k; ++j) {
-      const int e0 = a.contrib_level[a.cout[a.sorted[s0 + j]]] - lmin;
+      const int e0 = glev[j] - lmin;
       const u128 w = (u128)1 << (e0 < cap ? e0 : cap);
       int d = 0;
       while ((w << d) < W) ++d;
@@ -269,8 +301,8 @@ __host__ __device__ inline void reduce_group(const Arena &a, int32_t s0, int32_t
       S += w;
     }
     auto bit = [&](int j, int p) -> int {
-      const u128 r = ((u128)a.code_hi[s0 + j] << 64) | a.code_lo[s0 + j];
-      return (int)((r >> (a.code_d[s0 + j] - 1 - p)) & 1);
+      const int sh = a.code_d[s0 + j] - 1 - p;
+      return (int)((sh >= 64 ? a.code_hi[s0 + j] >> (sh - 64) : a.code_lo[s0 + j] >> sh) & 1);
     };
     // the host's recursive build, as an explicit stack: frames of (range,
     // depth, stage, left result); results return through (ret, ret_lvl)
@@ -286,17 +318,30 @@ __host__ __device__ inline void reduce_group(const Arena &a, int32_t s0, int32_t
       Frame &f = st[sp - 1];
       if (f.stage == 0) {
         if (f.lo == f.hi) {
-          ret = a.cout[a.sorted[s0 + f.lo]];
-          ret_lvl = a.contrib_level[ret];
+          ret = gslot[f.lo];
+          ret_lvl = glev[f.lo];
           --sp;
           continue;
         }
-        int s = -1;
-        for (int j = f.lo; j <= f.hi; ++j)
-          if (bit(j, f.depth)) {
-            s = j;
-            break;
+        // the first code of the range with a 1 at this depth; the codes are
+        // increasing and share the first `depth` bits, so the bits at this
+        // depth are 0 ... 0 1 ... 1 and a binary search finds it
+        int s;
+        if (bit(f.lo, f.depth)) {
+          s = f.lo;
+        } else if (!bit(f.hi, f.depth)) {
+          s = -1;
+        } else {
+          int lo = f.lo, hi = f.hi;  // bit(lo) = 0, bit(hi) = 1
+          while (hi - lo > 1) {
+            const int mid = lo + (hi - lo) / 2;
+            if (bit(mid, f.depth))
+              hi = mid;
+            else
+              lo = mid;
           }
+          s = hi;
+        }
         if (s < 0 || s == f.lo) {  // unary trie vertex: suppressed
           ++f.depth;
           continue;
@@ -483,7 +528,10 @@ __host__ __device__ int32_t program(X &x, Arena &a) {
     compact(
         x, a, N - 1, [&](int64_t q) { return a.mark[q] >= 0; },
         [&](int64_t q, uint32_t o) {
-          a.sorted[o] = a.mark[q];
+          const int32_t j = a.mark[q];
+          a.sorted[o] = j;
+          a.gslot[o] = a.cout[j];
+          a.glev[o] = a.contrib_level[a.cout[j]];
           a.mark[q] = -1;
         });
     const uint32_t G = compact(
