@@ -2,8 +2,10 @@
 m = 2, FP64): the caterpillar (262,144-node trunk, 3 leaves per trunk node,
 height 262,143), the star-heavy tree (root with 10,000 chain children: a
 10,000-way sibling reduction) and the chain-probability tree.  One plan is
-reused for two re-solves with fresh data; every element of every result is
-checked against the FP64 oracle at 1e-9 relative."""
+reused for the eight re-solves of the workload, each with fresh data: every
+re-solve's KKT residual of eq. (kkt) is at most 1e-9 (a property that holds
+at any size), and every element of the first and the last re-solve is checked
+against the FP64 oracle at 1e-9 relative."""
 import numpy as np
 import pytest
 
@@ -20,13 +22,16 @@ def test_extreme_tree_fp64(kind):
     par = w.shape_extreme(kind)
     plan = rcr.Plan(par, 6, 2)
     out = None
-    for resolve in range(2):
+    for resolve in range(8):
         print(f"[gpu-extreme] {kind} resolve {resolve}", flush=True)
         d = w.lqr_data(par, w.DataSpec(6, 2), np.random.default_rng(w.config_seed(4, resolve, ["caterpillar", "star_heavy", "chainprob"].index(kind))))
         dev = rcr.to_device(d)
         out = rcr.solve(plan, dev, out=out, executor=rcr.EXEC_GRAPH, check=True, kkt_residual=True)
         torch.cuda.synchronize()
         assert out["kkt_residual"] < 1e-9
+        if resolve not in (0, 7):
+            del dev
+            continue
         ref = orc.tree_riccati(par, d)
         for k in rcr.SOLUTION_FIELDS:
             g = out[k].cpu().numpy()
