@@ -118,6 +118,104 @@ def bench_copy(args) -> dict:
             "launches": reps + 3, "ms_per_copy": ms, "copy_GBps": 2 * nbytes / (ms / 1e3) / 1e9}
 
 
+def _csvs(d: str, suffix: str):
+    import glob
+    return sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+
+
+def summarize_stats(d: str) -> str:
+    """Kernel statistics table from a rocprofv3 --kernel-trace --stats run
+    (its *kernel_stats.csv under directory d)."""
+    import csv
+    rows = []
+    for f in _csvs(d, "kernel_stats.csv"):
+        rows += list(csv.DictReader(open(f)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = ["name,calls,total_us,avg_us,min_us,max_us,percent"]
+    for r in rows:
+        out.append(f'{r["Name"]},{r["Calls"]},{float(r["TotalDurationNs"]) / 1e3:.1f},'
+                   f'{float(r["AverageNs"]) / 1e3:.2f},{float(r["MinNs"]) / 1e3:.2f},'
+                   f'{float(r["MaxNs"]) / 1e3:.2f},{float(r["Percentage"]):.2f}')
+    return "\n".join(out)
+
+
+def pmc_totals(d: str) -> dict:
+    """Per kernel name: dispatches and the sum of each counter over them, from
+    a rocprofv3 --pmc run (its *counter_collection.csv under directory d)."""
+    import csv
+    tot = {}
+    for f in _csvs(d, "counter_collection.csv"):
+        for r in csv.DictReader(open(f)):
+            e = tot.setdefault(r["Kernel_Name"], {"dispatches": set()})
+            e["dispatches"].add(r["Dispatch_Id"])
+            c = r["Counter_Name"]
+            e[c] = e.get(c, 0.0) + float(r["Counter_Value"])
+    return {k: dict(v, dispatches=len(v["dispatches"])) for k, v in tot.items()}
+
+
+# the dominant class: the first contraction level (fused with the condensation
+# when the plan allows) and the later per-level quadratic contraction launches
+DOMINANT_KERNELS = ("k_level1_wide<double, 12>", "k_quad_level_wide<double, 12>", "k_condense_wide<double, 12>")
+
+
+def _dominant(tot: dict):
+    sel = {k: v for k, v in tot.items() if any(x in k for x in DOMINANT_KERNELS)}
+    solves = max((v["dispatches"] for k, v in sel.items() if "k_level1_wide" in k or "k_condense_wide" in k),
+                 default=0)
+    launches = sum(v["dispatches"] for k, v in sel.items() if "k_condense_wide" not in k)
+    return sel, solves, launches
+
+
+def summarize_pmc(kind: str, runs: dict, copy_dirs: dict) -> str:
+    """Per-launch figures of the dominant kernel class from rocprofv3 --pmc runs:
+    kind "traffic": HBM bytes from FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
+    each scaled by what the counter reads for a plain copy of known size;
+    kind "flops": FP64 flops from the SQ instruction counters (64 lanes per VALU
+    instruction, an FMA counting 2; MFMA as 512 per MOPS unit).  runs maps a
+    quadratic tail setting q to {counter group: directory}."""
+    lines = []
+    if kind == "traffic":
+        cal = {}
+        for c, dirpath in copy_dirs.items():
+            t = pmc_totals(dirpath)
+            k = max(t, key=lambda x: t[x].get(c, 0.0) / max(t[x]["dispatches"], 1))
+            per = t[k][c] / t[k]["dispatches"] * 1024.0  # bytes per copy launch
+            known = float(os.environ.get("RCR_COPY_BYTES", 1 << 30))
+            cal[c] = known / per
+            lines.append(f"# copy: {c} reads {per / 1024:.0f} KiB for {known / 1024:.0f} KiB -> factor {cal[c]:.4f}")
+        lines.append(f"fetch_factor={cal['FETCH_SIZE']:.4f}")
+        lines.append(f"write_factor={cal['WRITE_SIZE']:.4f}")
+    for q, dirs in sorted(runs.items()):
+        tot = {}
+        for dirpath in dirs.values():
+            for k, v in pmc_totals(dirpath).items():
+                e = tot.setdefault(k, {"dispatches": v["dispatches"]})
+                e.update({c: x for c, x in v.items() if c != "dispatches"})
+        sel, solves, launches = _dominant(tot)
+        lpsolve = launches / max(solves, 1)
+        lines.append(f"# quad_tail_rounds={q}: {solves} solves, {launches} launches of the class; per launch:")
+        for k, v in sorted(sel.items()):
+            vals = " ".join(f"{c}={x / v['dispatches']:.4g}" for c, x in sorted(v.items()) if c != "dispatches")
+            lines.append(f"#   {k}: dispatches={v['dispatches']} {vals}")
+        if kind == "traffic":
+            fetch = sum(v.get("FETCH_SIZE", 0.0) for v in sel.values()) * 1024 * cal["FETCH_SIZE"] / max(launches, 1)
+            write = sum(v.get("WRITE_SIZE", 0.0) for v in sel.values()) * 1024 * cal["WRITE_SIZE"] / max(launches, 1)
+            lines += [f"qtr{q}.launches_per_solve={lpsolve:g}", f"qtr{q}.fetch_bytes_per_launch={fetch:.0f}",
+                      f"qtr{q}.write_bytes_per_launch={write:.0f}", f"qtr{q}.hbm_bytes_per_launch={fetch + write:.0f}"]
+        else:
+            def c_(name):
+                return sum(v.get(name, 0.0) for v in sel.values())
+            valu = 64 * (c_("SQ_INSTS_VALU_ADD_F64") + c_("SQ_INSTS_VALU_MUL_F64") + c_("SQ_INSTS_VALU_TRANS_F64")
+                         + 2 * c_("SQ_INSTS_VALU_FMA_F64"))
+            mfma = 512 * c_("SQ_INSTS_VALU_MFMA_MOPS_F64")
+            lines += [f"qtr{q}.launches_per_solve={lpsolve:g}",
+                      f"qtr{q}.valu_fp64_flops_per_launch={valu / max(launches, 1):.0f}",
+                      f"qtr{q}.mfma_fp64_flops_per_launch={mfma / max(launches, 1):.0f}",
+                      f"qtr{q}.fp64_flops_per_launch={(valu + mfma) / max(launches, 1):.0f}"]
+    lines.append(f"source_sha={kernel_source_sha()}")
+    return "\n".join(lines)
+
+
 def mapping_string(cfg) -> str:
     return ",".join(f"{k}={v}" for k, v in cfg.items()) if isinstance(cfg, dict) else "default"
 
@@ -208,6 +306,12 @@ def batch_record(args, steps: int, cpu_seconds: float) -> dict:
     torch.cuda.synchronize()
     batched_ms = e0.elapsed_time(e1) / steps
     # one solve per tree (each tree's own plan, launch sequence and buffers)
+    if getattr(args, "no_separate", False):
+        for p_ in plans:
+            p_.close()
+        return {"workload": f"{T} trees, n=8, m=3, MIXED32 + 1 refinement (merged only)", "trees": T,
+                "nodes": int(Ntot), "nodes_per_s": Ntot / (batched_ms / 1e3), "ms_per_batch": batched_ms,
+                "kkt_residual_batched": chk["kkt_residual"], "steps": steps}
     worst = 0.0
     for p_, pr, ou in zip(plans, probs, outs):
         r = rcr.solve(p_, pr, out=ou, check=True, kkt_residual=True, **kw)
@@ -277,6 +381,7 @@ def bench_extreme(args) -> dict:
         plan = rcr.Plan(par, 6, 2)
         plan_ms = (time.perf_counter() - t0) * 1e3
         prob, out, times, kkt = None, None, [], 0.0
+        print(f"[bench] extreme {kind}", file=sys.stderr, flush=True)
         for s_ in range(args.resolves):
             d = w.lqr_data(par, w.DataSpec(6, 2), np.random.default_rng(w.config_seed(4, s_, ti)))
             if prob is None:
@@ -554,12 +659,31 @@ def main() -> int:
     ap.add_argument("--no-serve", action="store_true", help="single workload: skip the serving sub-record")
     ap.add_argument("--serve-rate", type=float, default=1000.0, help="arrival rate of the serving sub-record")
     ap.add_argument("--serve-requests", type=int, default=10000, help="requests of the serving sub-record")
+    ap.add_argument("--no-separate", action="store_true", help="batch workload: merged solves only (for profiling)")
+    ap.add_argument("--summarize-stats", default="", help="print the kernel statistics of a rocprofv3 run directory")
+    ap.add_argument("--summarize-pmc", default="", choices=["", "traffic", "flops"],
+                    help="print the dominant class's per-launch figures from rocprofv3 --pmc run directories")
+    ap.add_argument("--pmc-run", action="append", default=[],
+                    help="Q:DIR, a --pmc run directory of the single workload at quad_tail_rounds=Q")
+    ap.add_argument("--pmc-copy", action="append", default=[],
+                    help="COUNTER:DIR, a --pmc run directory of the copy workload for that counter")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: measures one GPU only; --gpus {args.gpus} is not supported "
               "(independent trees shard across GPUs with no communication: each GPU runs its own plans)",
               file=sys.stderr)
         return 2
+    if args.summarize_stats:
+        print(summarize_stats(args.summarize_stats))
+        return 0
+    if args.summarize_pmc:
+        runs = {}
+        for spec in args.pmc_run:
+            q, dirpath = spec.split(":", 1)
+            runs.setdefault(int(q), {})[dirpath] = dirpath
+        copies = dict(x.split(":", 1) for x in args.pmc_copy)
+        print(summarize_pmc(args.summarize_pmc, runs, copies))
+        return 0
 
     import numpy as np
     import torch
