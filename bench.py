@@ -131,12 +131,15 @@ def summarize_stats(d: str) -> str:
     for f in _csvs(d, "kernel_stats.csv"):
         rows += list(csv.DictReader(open(f)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
-    out = ["name,calls,total_us,avg_us,min_us,max_us,percent"]
+    import io
+    buf = io.StringIO()
+    wr = csv.writer(buf, lineterminator="\n")
+    wr.writerow(["name", "calls", "total_us", "avg_us", "min_us", "max_us", "percent"])
     for r in rows:
-        out.append(f'{r["Name"]},{r["Calls"]},{float(r["TotalDurationNs"]) / 1e3:.1f},'
-                   f'{float(r["AverageNs"]) / 1e3:.2f},{float(r["MinNs"]) / 1e3:.2f},'
-                   f'{float(r["MaxNs"]) / 1e3:.2f},{float(r["Percentage"]):.2f}')
-    return "\n".join(out)
+        wr.writerow([r["Name"], r["Calls"], f'{float(r["TotalDurationNs"]) / 1e3:.1f}',
+                     f'{float(r["AverageNs"]) / 1e3:.2f}', f'{float(r["MinNs"]) / 1e3:.2f}',
+                     f'{float(r["MaxNs"]) / 1e3:.2f}', f'{float(r["Percentage"]):.2f}'])
+    return buf.getvalue().rstrip("\n")
 
 
 def pmc_totals(d: str) -> dict:
