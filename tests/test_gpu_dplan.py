@@ -85,3 +85,30 @@ def test_solve_on_device_plan_matches_host_plan(precision):
     for k in rcr.SOLUTION_FIELDS:
         assert torch.equal(a[k], b[k]), k
     assert a["kkt_residual"] <= 1e-8
+
+
+def test_device_plan_random_trees():
+    """40 random trees (five families, sizes from 1 to 40,000, labels permuted or
+    not), each device-built plan identical to the host planner's."""
+    rng = np.random.default_rng(w.config_seed(9, 1, 0))
+    for case in range(40):
+        fam = case % 5
+        N = int(rng.integers(1, 40000)) if case % 4 else int(rng.integers(1, 64))
+        if fam == 0:
+            par = w.tree_chainprob(N, float(rng.uniform(0.3, 0.999)), rng)
+        elif fam == 1:
+            par = w.tree_star(N)
+        elif fam == 2:
+            par = w.tree_balanced(N)
+        elif fam == 3:
+            par = w.tree_comb(max(N, 2))
+        else:
+            par = np.full(N, -1, dtype=np.int64)
+            par[1:] = [int(rng.integers(0, i)) for i in range(1, N)]  # uniform random recursive tree
+        if rng.random() < 0.5 and len(par) > 1:
+            par = w.permute_labels(par, rng)[0]
+        n, m = int(rng.integers(1, 17)), int(rng.integers(1, 17))
+        print(f"[gpu-dplan] random case {case} family {fam} N={len(par)} n={n} m={m}", flush=True)
+        dev = rcr.Plan.from_device(torch.from_numpy(np.ascontiguousarray(par, dtype=np.int64)).to("cuda:0"), n, m)
+        host = rcr.Plan(par, n, m, selection=rcr.SELECT_LIST_RANK)
+        assert dev.digest() == host.digest(), case
