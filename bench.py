@@ -385,8 +385,15 @@ def bench_extreme(args) -> dict:
         plan_ms = (time.perf_counter() - t0) * 1e3
         prob, out, times, kkt = None, None, [], 0.0
         print(f"[bench] extreme {kind}", file=sys.stderr, flush=True)
+        # the re-solves' data drawn ahead on host threads (numpy releases the
+        # interpreter lock in its array work), each from its own seed as before
+        import concurrent.futures as cf
+        with cf.ThreadPoolExecutor(max_workers=4) as gen_pool:
+            futs = [gen_pool.submit(w.lqr_data, par, w.DataSpec(6, 2),
+                                    np.random.default_rng(w.config_seed(4, s_, ti))) for s_ in range(args.resolves)]
         for s_ in range(args.resolves):
-            d = w.lqr_data(par, w.DataSpec(6, 2), np.random.default_rng(w.config_seed(4, s_, ti)))
+            d = futs[s_].result()
+            futs[s_] = None
             if prob is None:
                 prob = rcr.to_device(d, dev)
                 out = rcr.alloc_solution(plan, dev)
@@ -403,6 +410,7 @@ def bench_extreme(args) -> dict:
             times.append(e0.elapsed_time(e1))
             r = rcr.solve(plan, prob, out=out, executor=rcr.EXEC_GRAPH, kkt_residual=True)
             kkt = max(kkt, r["kkt_residual"])
+            del d
         st = plan.stats()
         res[kind] = {"nodes_per_s": len(par) / (float(np.median(times)) / 1e3), "median_ms": float(np.median(times)),
                      "max_ms": float(np.max(times)), "resolves": args.resolves, "kkt_residual_max": kkt,
@@ -663,6 +671,8 @@ def main() -> int:
     ap.add_argument("--serve-rate", type=float, default=1000.0, help="arrival rate of the serving sub-record")
     ap.add_argument("--serve-requests", type=int, default=10000, help="requests of the serving sub-record")
     ap.add_argument("--no-separate", action="store_true", help="batch workload: merged solves only (for profiling)")
+    ap.add_argument("--no-extreme", action="store_true", help="single workload: skip the shape-extreme sub-record")
+    ap.add_argument("--no-lift", action="store_true", help="single workload: skip the lifted sub-record")
     ap.add_argument("--summarize-stats", default="", help="print the kernel statistics of a rocprofv3 run directory")
     ap.add_argument("--summarize-pmc", default="", choices=["", "traffic", "flops"],
                     help="print the dominant class's per-launch figures from rocprofv3 --pmc run directories")
@@ -891,6 +901,24 @@ def main() -> int:
         row["data_pool_s"] = time.perf_counter() - t_gen - row["wall_s"]
         rec["serve"] = row
         del pool
+        torch.cuda.empty_cache()
+    if not args.no_extreme:
+        # the shape-extreme trees at 1,048,576 nodes: one plan each, eight re-solves with fresh data
+        print("[bench] shape-extreme workload", file=sys.stderr, flush=True)
+        ex_rec = bench_extreme(args)
+        rec["extreme"] = {"workload": ex_rec["config"]["workload"], "nodes_per_s": ex_rec["value"],
+                          "ms_per_solve": ex_rec["ms_per_step"], "resolves": args.resolves,
+                          "trees": {k: {kk: v[kk] for kk in ("median_ms", "max_ms", "kkt_residual_max", "plan_ms")}
+                                    for k, v in ex_rec["trees"].items()}}
+        torch.cuda.empty_cache()
+    if not args.no_lift:
+        print("[bench] lifted node-control workload", file=sys.stderr, flush=True)
+        lf = bench_lift(args)
+        rec["lift"] = {"workload": lf["config"]["workload"], "native_nodes_per_s": lf["value"],
+                       "ms_per_step_fp64": lf["precisions"]["fp64"]["ms_per_step"],
+                       "kkt_residual_fp64": lf["precisions"]["fp64"]["kkt_residual_lifted"],
+                       "ms_per_step_mixed32": lf["precisions"]["mixed32"]["ms_per_step"],
+                       "kkt_residual_mixed32": lf["precisions"]["mixed32"]["kkt_residual_lifted"]}
         torch.cuda.empty_cache()
     print(json.dumps(rec), flush=True)
     return 0
