@@ -68,6 +68,132 @@ struct GpuExec {
     return r;
   }
   __device__ void atomic_add(int32_t *p, int32_t v) { atomicAdd(p, v); }
+
+  // Wavefront w takes a contiguous range of the indices in steps of 64 (lane l
+  // the step's l-th index, so loads are coalesced) and ranks its lanes by
+  // ballot; U steps are loaded before any is ranked.
+  static constexpr int NW = THREADS / 64, U = 4;
+  __device__ static void wave_range(int64_t n, int64_t &b, int64_t &e) {
+    const int64_t steps = (n + 63) >> 6, per = (steps + NW - 1) / NW;
+    b = (int64_t)(threadIdx.x >> 6) * per * 64;
+    e = b + per * 64 < n ? b + per * 64 : n;
+  }
+
+  template <class P, class W>
+  __device__ uint32_t compact(const Arena &, int64_t n, P pred, W write) {
+    __shared__ uint32_t woff[NW + 1];
+    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+    const uint64_t lt = __lanemask_lt();
+    int64_t b, e;
+    wave_range(n, b, e);
+    uint32_t c = 0;
+    for (int64_t i0 = b; i0 < e; i0 += 64 * U) {
+      bool f[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = i0 + 64 * u + lane;
+        f[u] = i < e && pred(i);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) c += (uint32_t)__popcll(__ballot(f[u]));
+    }
+    if (lane == 0) woff[w] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t s = 0;
+      for (int k = 0; k < NW; ++k) {
+        const uint32_t v = woff[k];
+        woff[k] = s;
+        s += v;
+      }
+      woff[NW] = s;
+    }
+    __syncthreads();
+    uint32_t o = woff[w];
+    for (int64_t i0 = b; i0 < e; i0 += 64 * U) {
+      bool f[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = i0 + 64 * u + lane;
+        f[u] = i < e && pred(i);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint64_t m = __ballot(f[u]);
+        if (f[u]) write(i0 + 64 * u + lane, o + (uint32_t)__popcll(m & lt));
+        o += (uint32_t)__popcll(m);
+      }
+    }
+    const uint32_t total = woff[NW];
+    __syncthreads();
+    return total;
+  }
+
+  // One stable pass on digit (k >> sh) & 15: per-wavefront digit counts, a
+  // digit-major scan, then each step's lanes ranked among the lanes of the same
+  // digit (four ballots) and the group's offset advanced by its lowest lane.
+  __device__ void radix_pass(const Arena &, int64_t n, int sh, const uint32_t *kk, const uint32_t *vv, uint32_t *kd,
+                             uint32_t *vd) {
+    __shared__ uint32_t off[16 * NW];  // [digit][wavefront]
+    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+    const uint64_t lt = __lanemask_lt();
+    if (threadIdx.x < 16 * NW) off[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t b, e;
+    wave_range(n, b, e);
+    for (int64_t i0 = b; i0 < e; i0 += 64 * U) {
+      uint32_t dg[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = i0 + 64 * u + lane;
+        dg[u] = i < e ? (kk[i] >> sh) & 15 : 16;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (dg[u] < 16) atomicAdd(&off[dg[u] * NW + w], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t s = 0;
+      for (int k = 0; k < 16 * NW; ++k) {
+        const uint32_t v = off[k];
+        off[k] = s;
+        s += v;
+      }
+    }
+    __syncthreads();
+    for (int64_t i0 = b; i0 < e; i0 += 64 * U) {
+      uint32_t kb[U], vb[U];
+      bool act[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = i0 + 64 * u + lane;
+        act[u] = i < e;
+        kb[u] = act[u] ? kk[i] : 0;
+        vb[u] = act[u] ? vv[i] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t d = (kb[u] >> sh) & 15;
+        uint64_t peers = __ballot(act[u]);
+#pragma unroll
+        for (int bit = 0; bit < 4; ++bit) {
+          const bool one = (d >> bit) & 1;
+          const uint64_t bb = __ballot(act[u] && one);
+          peers &= one ? bb : ~bb;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt);
+        uint32_t base = 0;
+        if (act[u]) base = off[d * NW + w];
+        if (act[u]) {
+          kd[base + rank] = kb[u];
+          vd[base + rank] = vb[u];
+        }
+        if (act[u] && rank == 0) off[d * NW + w] = base + (uint32_t)__popcll(peers);
+      }
+    }
+    __syncthreads();
+  }
 };
 
 __global__ void __launch_bounds__(THREADS) k_device_plan(Arena a) {

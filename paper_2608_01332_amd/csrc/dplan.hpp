@@ -152,102 +152,27 @@ __host__ __device__ inline u128 div128(u128 num, uint64_t den) {
 constexpr int BATCH = 8;
 
 // Stable compaction of the indices i < n with pred(i), in increasing i:
-// write(i, o) for the o-th of them; returns their number.  Thread t takes the
-// contiguous chunk [t C, (t + 1) C); pred must not depend on what write stores.
+// write(i, o) for the o-th of them; returns their number (the executor's own
+// implementation; pred must not depend on what write stores).
 template <class X, class P, class W>
 __host__ __device__ uint32_t compact(X &x, const Arena &a, int64_t n, P pred, W write) {
-  const int T = a.T;
-  const int64_t C = (n + T - 1) / T;
-  x.each([&](int t) {
-    const int64_t b = t * C, e = b + C < n ? b + C : n;
-    uint32_t c = 0;
-    for (int64_t i0 = b; i0 < e; i0 += BATCH) {
-      bool f[BATCH];
-#pragma unroll
-      for (int u = 0; u < BATCH; ++u) f[u] = i0 + u < e && pred(i0 + u);
-#pragma unroll
-      for (int u = 0; u < BATCH; ++u) c += f[u] ? 1u : 0u;
-    }
-    a.tcount[t] = c;
-  });
-  const uint32_t total = x.scan(a.tcount);
-  x.each([&](int t) {
-    const int64_t b = t * C, e = b + C < n ? b + C : n;
-    uint32_t o = a.tcount[t];
-    for (int64_t i0 = b; i0 < e; i0 += BATCH) {
-      bool f[BATCH];
-#pragma unroll
-      for (int u = 0; u < BATCH; ++u) f[u] = i0 + u < e && pred(i0 + u);
-#pragma unroll
-      for (int u = 0; u < BATCH; ++u)
-        if (f[u]) write(i0 + u, o++);
-    }
-  });
-  return total;
+  return x.compact(a, n, pred, write);
 }
 
 // Stable least-significant-digit radix sort of (k[i], v[i]), i < n, on the low
-// `bits` bits of the keys, 4 bits per pass; the result is in (k, v) on return
-// (the pointers are swapped with the spare buffers as passes go).
+// `bits` bits of the keys, 4 bits per pass (the executor's radix_pass); the
+// result is in (k, v) on return (the pointers are swapped with the spare
+// buffers as passes go).
 template <class X>
 __host__ __device__ void radix_sort(X &x, const Arena &a, int64_t n, int bits, uint32_t *&k, uint32_t *&v,
                                     uint32_t *&k2, uint32_t *&v2) {
-  const int T = a.T;
-  const int64_t C = (n + T - 1) / T;
   for (int sh = 0; sh < bits; sh += 4) {
-    uint32_t *kk = k, *vv = v, *kd = k2, *vd = v2;
-    x.each([&](int t) {
-      uint32_t h[16];
-      for (int d = 0; d < 16; ++d) h[d] = 0;
-      const int64_t b = t * C, e = b + C < n ? b + C : n;
-      for (int64_t i0 = b; i0 < e; i0 += BATCH) {
-        uint32_t dg[BATCH];
-#pragma unroll
-        for (int u = 0; u < BATCH; ++u) dg[u] = i0 + u < e ? (kk[i0 + u] >> sh) & 15 : 16;
-#pragma unroll
-        for (int u = 0; u < BATCH; ++u)
-          if (dg[u] < 16) h[dg[u]]++;
-      }
-      for (int d = 0; d < 16; ++d) a.hist[(size_t)d * T + t] = h[d];
-    });
-    // exclusive scan of the digit-major histogram: thread t owns entries [16 t, 16 t + 16)
-    x.each([&](int t) {
-      uint32_t s = 0;
-      for (int j = 0; j < 16; ++j) {
-        const uint32_t c = a.hist[(size_t)16 * t + j];
-        a.hist[(size_t)16 * t + j] = s;
-        s += c;
-      }
-      a.tcount[t] = s;
-    });
-    x.scan(a.tcount);
-    x.each([&](int t) {
-      for (int j = 0; j < 16; ++j) a.hist[(size_t)16 * t + j] += a.tcount[t];
-    });
-    x.each([&](int t) {
-      uint32_t o[16];
-      for (int d = 0; d < 16; ++d) o[d] = a.hist[(size_t)d * T + t];
-      const int64_t b = t * C, e = b + C < n ? b + C : n;
-      for (int64_t i0 = b; i0 < e; i0 += BATCH) {
-        uint32_t kb[BATCH], vb[BATCH];
-#pragma unroll
-        for (int u = 0; u < BATCH; ++u) {
-          kb[u] = i0 + u < e ? kk[i0 + u] : 0;
-          vb[u] = i0 + u < e ? vv[i0 + u] : 0;
-        }
-#pragma unroll
-        for (int u = 0; u < BATCH; ++u)
-          if (i0 + u < e) {
-            const uint32_t p = o[(kb[u] >> sh) & 15]++;
-            kd[p] = kb[u];
-            vd[p] = vb[u];
-          }
-      }
-    });
-    k = kd;
-    v = vd;
-    k2 = kk;
-    v2 = vv;
+    x.radix_pass(a, n, sh, k, v, k2, v2);
+    uint32_t *tk = k, *tv = v;
+    k = k2;
+    v = v2;
+    k2 = tk;
+    v2 = tv;
   }
 }
 
@@ -267,6 +192,16 @@ __host__ __device__ void bucket_offsets(X &x, const Arena &a, const uint32_t *ke
 // of parent i (their slots and levels staged in gslot, glev); emits its k - 1
 // combinations and its absorption at raw[r0 ..] with combination slots c0,
 // c0 + 1, ... in the host's order, and updates lvlU[i].
+//
+// The host builds the code tree by descending one bit at a time: at depth p a
+// range splits at its first code with a 1 in bit p, and a range whose codes
+// all agree in bit p is a unary vertex (suppressed).  The same tree follows
+// from the common-prefix lengths L_j of neighbouring codes j - 1 and j: the
+// codes of a range agree in their first min L bits (min over the range's
+// inner neighbours), so the host descends to depth min L and splits at the
+// first j where L_j = min L (the codes increase, so bit min L flips there
+// from 0 to 1, once).  Weights are powers of two and 2 S + w < 2 W, so each
+// code word is at most 63 bits, found by a restoring division of d steps.
 __host__ __device__ inline void reduce_group(const Arena &a, int32_t s0, int32_t s1, int32_t r0, int32_t c0,
                                              int32_t rnd) {
   const int k = s1 - s0;
@@ -282,37 +217,48 @@ __host__ __device__ inline void reduce_group(const Arena &a, int32_t s0, int32_t
     int lg = 0;
     while ((1LL << lg) < k) ++lg;
     const int cap = 61 - lg;
-    u128 W = 0;
+    uint64_t W = 0;  // < k 2^cap <= 2^61
     for (int j = 0; j < k; ++j) {
       const int e = glev[j] - lmin;
-      W += (u128)1 << (e < cap ? e : cap);
+      W += (uint64_t)1 << (e < cap ? e : cap);
     }
-    u128 S = 0;
+    const int clW = bitlen(W - 1);  // smallest c with 2^c >= W
+    uint64_t *code = a.code_lo + s0;  // code words, left-aligned in 64 bits
+    int32_t *L = a.code_d + s0;       // L[j]: common-prefix length of codes j - 1 and j
+    uint64_t S = 0;
     for (int j = 0; j < k; ++j) {
-      const int e0 = glev[j] - lmin;
-      const u128 w = (u128)1 << (e0 < cap ? e0 : cap);
-      int d = 0;
-      while ((w << d) < W) ++d;
-      d += 1;
-      const u128 r = div128((2 * S + w) << d, (uint64_t)(2 * W));
-      a.code_hi[s0 + j] = (uint64_t)(r >> 64);
-      a.code_lo[s0 + j] = (uint64_t)r;
-      a.code_d[s0 + j] = d;
+      const int e0 = glev[j] - lmin, e = e0 < cap ? e0 : cap;
+      const uint64_t w = (uint64_t)1 << e;
+      // d_j = ceil(log2(W / w)) + 1, the leading d_j bits of (2 S + w) / (2 W)
+      const int d = (clW > e ? clW - e : 0) + 1;
+      const uint64_t D = 2 * W;
+      uint64_t rem = 2 * S + w, q = 0;  // rem < D
+      for (int b = 0; b < d; ++b) {
+        rem <<= 1;
+        q <<= 1;
+        if (rem >= D) {
+          rem -= D;
+          q |= 1;
+        }
+      }
+      code[j] = q << (64 - d);
+      if (j > 0) {
+        const uint64_t x = code[j - 1] ^ code[j];
+        int lz = 0;
+        while (!(x >> (63 - lz) & 1)) ++lz;  // codes are distinct: x != 0
+        L[j] = lz;
+      }
       S += w;
     }
-    auto bit = [&](int j, int p) -> int {
-      const int sh = a.code_d[s0 + j] - 1 - p;
-      return (int)((sh >= 64 ? a.code_hi[s0 + j] >> (sh - 64) : a.code_lo[s0 + j] >> sh) & 1);
-    };
     // the host's recursive build, as an explicit stack: frames of (range,
-    // depth, stage, left result); results return through (ret, ret_lvl)
+    // stage, split, left result); results return through (ret, ret_lvl)
     struct Frame {
-      int lo, hi, depth, s, stage;
+      int lo, hi, s, stage;
       int32_t a, la;
     };
     Frame st[80];  // the code tree is at most 62 deep
     int sp = 0;
-    st[sp++] = Frame{0, k - 1, 0, 0, 0, 0, 0};
+    st[sp++] = Frame{0, k - 1, 0, 0, 0, 0};
     int32_t ret = 0, ret_lvl = 0, emitted = 0;
     while (sp > 0) {
       Frame &f = st[sp - 1];
@@ -323,37 +269,17 @@ __host__ __device__ inline void reduce_group(const Arena &a, int32_t s0, int32_t
           --sp;
           continue;
         }
-        // the first code of the range with a 1 at this depth; the codes are
-        // increasing and share the first `depth` bits, so the bits at this
-        // depth are 0 ... 0 1 ... 1 and a binary search finds it
-        int s;
-        if (bit(f.lo, f.depth)) {
-          s = f.lo;
-        } else if (!bit(f.hi, f.depth)) {
-          s = -1;
-        } else {
-          int lo = f.lo, hi = f.hi;  // bit(lo) = 0, bit(hi) = 1
-          while (hi - lo > 1) {
-            const int mid = lo + (hi - lo) / 2;
-            if (bit(mid, f.depth))
-              hi = mid;
-            else
-              lo = mid;
-          }
-          s = hi;
-        }
-        if (s < 0 || s == f.lo) {  // unary trie vertex: suppressed
-          ++f.depth;
-          continue;
-        }
+        int s = f.lo + 1;
+        for (int j = f.lo + 2; j <= f.hi; ++j)
+          if (L[j] < L[s]) s = j;
         f.s = s;
         f.stage = 1;
-        st[sp++] = Frame{f.lo, s - 1, f.depth + 1, 0, 0, 0, 0};
+        st[sp++] = Frame{f.lo, s - 1, 0, 0, 0, 0};
       } else if (f.stage == 1) {
         f.a = ret;
         f.la = ret_lvl;
         f.stage = 2;
-        st[sp++] = Frame{f.s, f.hi, f.depth + 1, 0, 0, 0, 0};
+        st[sp++] = Frame{f.s, f.hi, 0, 0, 0, 0};
       } else {
         const int32_t lv = 1 + (f.la > ret_lvl ? f.la : ret_lvl);
         const int32_t out = c0 + emitted;
@@ -841,6 +767,62 @@ struct CpuExec {
     return s;
   }
   void atomic_add(int32_t *p, int32_t v) { *p += v; }
+
+  // Thread t takes the contiguous chunk [t C, (t + 1) C) of the indices.
+  template <class P, class W>
+  uint32_t compact(const Arena &a, int64_t n, P pred, W write) {
+    const int64_t C = (n + T - 1) / T;
+    each([&](int t) {
+      const int64_t b = t * C, e = b + C < n ? b + C : n;
+      uint32_t c = 0;
+      for (int64_t i = b; i < e; ++i) c += pred(i) ? 1u : 0u;
+      a.tcount[t] = c;
+    });
+    const uint32_t total = scan(a.tcount);
+    each([&](int t) {
+      const int64_t b = t * C, e = b + C < n ? b + C : n;
+      uint32_t o = a.tcount[t];
+      for (int64_t i = b; i < e; ++i)
+        if (pred(i)) write(i, o++);
+    });
+    return total;
+  }
+
+  // One stable pass on digit (k >> sh) & 15 from (kk, vv) into (kd, vd):
+  // per-thread digit counts over contiguous chunks, scanned digit-major.
+  void radix_pass(const Arena &a, int64_t n, int sh, const uint32_t *kk, const uint32_t *vv, uint32_t *kd,
+                  uint32_t *vd) {
+    const int64_t C = (n + T - 1) / T;
+    each([&](int t) {
+      uint32_t h[16] = {0};
+      const int64_t b = t * C, e = b + C < n ? b + C : n;
+      for (int64_t i = b; i < e; ++i) h[(kk[i] >> sh) & 15]++;
+      for (int d = 0; d < 16; ++d) a.hist[(size_t)d * T + t] = h[d];
+    });
+    each([&](int t) {  // thread t owns the digit-major entries [16 t, 16 t + 16)
+      uint32_t s = 0;
+      for (int j = 0; j < 16; ++j) {
+        const uint32_t c = a.hist[(size_t)16 * t + j];
+        a.hist[(size_t)16 * t + j] = s;
+        s += c;
+      }
+      a.tcount[t] = s;
+    });
+    scan(a.tcount);
+    each([&](int t) {
+      for (int j = 0; j < 16; ++j) a.hist[(size_t)16 * t + j] += a.tcount[t];
+    });
+    each([&](int t) {
+      uint32_t o[16];
+      for (int d = 0; d < 16; ++d) o[d] = a.hist[(size_t)d * T + t];
+      const int64_t b = t * C, e = b + C < n ? b + C : n;
+      for (int64_t i = b; i < e; ++i) {
+        const uint32_t p = o[(kk[i] >> sh) & 15]++;
+        kd[p] = kk[i];
+        vd[p] = vv[i];
+      }
+    });
+  }
 };
 
 // Copies a finished run's statistics and schedules (host copies of the arena's
