@@ -444,14 +444,15 @@ def _serve_pool(specs, dev):
 
 
 def run_serving(specs, pars, pool, dev, slots: int, batching: bool, budget: int, planner_threads: int,
-                sample_every: int = 0):
+                sample_every: int = 0, device_planner: bool = False):
     """Drive a Server with the stream's arrival times in real time; returns the
     completed requests (outputs kept only for every sample_every-th) and the
     wall time from the first arrival to the last completion."""
     import numpy as np
     import torch
     from paper_2608_01332_amd import serve
-    srv = serve.Server(dev, slots=slots, batching=batching, hbm_budget=budget, planner_threads=planner_threads)
+    srv = serve.Server(dev, slots=slots, batching=batching, hbm_budget=budget, planner_threads=planner_threads,
+                       device_planner=device_planner)
     # the planner and preparation threads run C code between short Python steps:
     # hand them the interpreter lock promptly
     old_switch = sys.getswitchinterval()
@@ -525,7 +526,8 @@ def serve_rate(rate: float, specs, pool, dev, args, mode: str = "continuous", sa
     if mode != "continuous":
         sample = 0
     reqs, wall, groups, hstats = run_serving(specs, pars, pool, dev, slots, batching, args.hbm_budget_gib << 30,
-                                             args.planner_threads, sample_every=sample)
+                                             args.planner_threads, sample_every=sample,
+                                             device_planner=getattr(args, "device_planner", False))
     lat = np.array([(r.t_done - r.arrival) * 1e3 for r in reqs])
     nodes = sum(r.N for r in reqs)
     row = {"rate_per_s": rate, "mode": mode, "slots": slots, "requests": len(reqs),
@@ -533,7 +535,8 @@ def serve_rate(rate: float, specs, pool, dev, args, mode: str = "continuous", sa
            "mean_ms": float(lat.mean()), "nodes_per_s": nodes / wall, "solves_per_s": len(reqs) / wall,
            "groups": groups, "mean_group": len(reqs) / max(groups, 1),
            "plan_cache_hits": float(np.mean([r.cache_hit for r in reqs])),
-           "host_s": {k: round(v, 3) for k, v in hstats.items()}, "wall_s": wall}
+           "host_s": {k: round(v, 3) for k, v in hstats.items()}, "wall_s": wall,
+           "planner": "device" if getattr(args, "device_planner", False) else "host"}
     if sample:
         torch.cuda.synchronize()
         torch.cuda.empty_cache()  # the run's cached group buffers
@@ -541,7 +544,8 @@ def serve_rate(rate: float, specs, pool, dev, args, mode: str = "continuous", sa
         for r in reqs:
             if not r.out:
                 continue
-            plan = rcr.Plan(r.parent, r.n, r.m)
+            sel = rcr.SELECT_LIST_RANK if getattr(args, "device_planner", False) else rcr.SELECT_GREEDY_INDEX
+            plan = rcr.Plan(r.parent, r.n, r.m, selection=sel)  # the selection the server's planner used
             alone = rcr.solve(plan, r.prob, precision=rcr.MIXED32, refine_steps=1, kkt_residual=True)
             for k in rcr.SOLUTION_FIELDS:
                 worst_diff = max(worst_diff, float((alone[k] - r.out[k]).abs().max()))
@@ -671,6 +675,7 @@ def main() -> int:
     ap.add_argument("--serve-rate", type=float, default=1000.0, help="arrival rate of the serving sub-record")
     ap.add_argument("--serve-requests", type=int, default=10000, help="requests of the serving sub-record")
     ap.add_argument("--no-separate", action="store_true", help="batch workload: merged solves only (for profiling)")
+    ap.add_argument("--device-planner", action="store_true", help="serve workload: plan cache misses on the GPU")
     ap.add_argument("--no-extreme", action="store_true", help="single workload: skip the shape-extreme sub-record")
     ap.add_argument("--no-lift", action="store_true", help="single workload: skip the lifted sub-record")
     ap.add_argument("--summarize-stats", default="", help="print the kernel statistics of a rocprofv3 run directory")

@@ -147,9 +147,14 @@ class _Slot:
 class Server:
     def __init__(self, device="cuda:0", slots: int = 4, hbm_budget: int = 64 << 30, max_group_nodes: int = 1 << 18,
                  precision: int = rcr.MIXED32, refine_steps: int = 1, planner_threads: int = 8,
-                 plan_cache: int = 512, batching: bool = True):
+                 plan_cache: int = 512, batching: bool = True, device_planner: bool = False):
+        import threading
         import torch
         self.device = torch.device(device)
+        # plan cache misses on the GPU (rcr_plan_create_device, list-rank selection),
+        # one planning stream per planner thread, instead of on the host
+        self.device_planner = device_planner
+        self._plan_local = threading.local()
         self.slots = [_Slot(self.device) for _ in range(slots)]
         self.budget = int(hbm_budget)
         self.in_use = 0          # outputs and plan copies of the running groups
@@ -170,6 +175,16 @@ class Server:
     # ---- arrival and planning -------------------------------------------------
     def _plan(self, req: Request):
         t = time.perf_counter()
+        if self.device_planner:
+            import torch
+            loc = self._plan_local
+            if not hasattr(loc, "stream"):
+                loc.stream = torch.cuda.Stream(device=self.device)
+            with torch.cuda.stream(loc.stream):
+                par = torch.from_numpy(np.ascontiguousarray(req.parent, dtype=np.int64)).to(self.device)
+                p = rcr.Plan.from_device(par, req.n, req.m, stream=loc.stream)
+            self.stats["plan_s"] += time.perf_counter() - t
+            return p
         # the pool already builds plans side by side: no helper threads per plan
         p = rcr.Plan(req.parent, req.n, req.m, single_thread=True)
         self.stats["plan_s"] += time.perf_counter() - t

@@ -151,3 +151,23 @@ def test_plan_shared_across_streams():
             assert torch.equal(o0[k], ref0[k]) and torch.equal(o1[k], ref1[k])
     plan.close()
     torch.cuda.synchronize()
+
+
+def test_serve_with_device_planner():
+    """Plan cache misses built on the GPU (rcr_plan_create_device): every served
+    result equals the same request solved alone on the host's list-rank plan of
+    its tree, bit for bit."""
+    print("[gpu-serve] device planner", flush=True)
+    reqs = _requests(60, seed=12, n_choices=(4, 8, 12), N_range=(300, 20000))
+    srv = serve.Server("cuda:0", slots=4, planner_threads=4, device_planner=True)
+    for r in reqs:
+        srv.submit(r)
+    srv.drain()
+    assert len(srv.done) == len(reqs)
+    for r in reqs:
+        plan = rcr.Plan(r.parent, r.n, r.m, selection=rcr.SELECT_LIST_RANK)
+        a = rcr.solve(plan, r.prob, precision=rcr.MIXED32, refine_steps=1, kkt_residual=True)
+        for k in rcr.SOLUTION_FIELDS:
+            assert torch.equal(a[k], r.out[k]), (r.rid, k)
+        assert a["kkt_residual"] <= 1e-8
+    srv.close()
