@@ -925,6 +925,22 @@ def main() -> int:
                        "ms_per_step_mixed32": lf["precisions"]["mixed32"]["ms_per_step"],
                        "kkt_residual_mixed32": lf["precisions"]["mixed32"]["kkt_residual_lifted"]}
         torch.cuda.empty_cache()
+    # the plan of the same tree built on the device (list-rank selection) against
+    # the host planner's with that selection on one host thread: median of 5 builds
+    par_d = torch.from_numpy(np.ascontiguousarray(parent, dtype=np.int64)).to(dev)
+    t_dev, t_host, same = [], [], True
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pd = rcr.Plan.from_device(par_d, n, m)
+        t_dev.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        ph = rcr.Plan(parent, n, m, selection=rcr.SELECT_LIST_RANK, single_thread=True)
+        t_host.append(time.perf_counter() - t0)
+        same = same and pd.digest() == ph.digest()
+    rec["device_planner"] = {"tree": f"N={N} chain-prob p=0.95 (the single workload's)",
+                             "device_ms": float(np.median(t_dev)) * 1e3, "host_ms": float(np.median(t_host)) * 1e3,
+                             "host_threads": 1, "identical_plans": bool(same)}
     print(json.dumps(rec), flush=True)
     return 0
 
