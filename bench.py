@@ -460,19 +460,21 @@ def run_serving(specs, pars, pool, dev, slots: int, batching: bool, budget: int,
     reqs = [serve.Request(rid=e["rid"], parent=pars[e["topo"]], n=e["n"], m=e["m"],
                           prob={k: v[:e["N"]] for k, v in pool[(e["n"], e["m"], e["variant"])].items()},
                           topo=e["topo"]) for e in specs]
-    # warm-up (not timed): a small request of every (n, m) class of the stream,
-    # alone and then in merged pairs, through the same server, so the code
-    # objects of every kernel the stream uses are loaded and the planner threads
-    # and staging buffers exist before the first timed arrival
+    # warm-up (not timed): a request of every (n, m) class of the stream, alone
+    # and then in merged pairs, through the same server, so every kernel the
+    # stream uses has been launched once (its code loaded) and the planner
+    # threads and staging buffers exist before the first timed arrival; the
+    # tree is large enough (WARM_N nodes) to need the per-level launches too
+    WARM_N = min([32768] + [int(v["Q"].shape[0]) for v in pool.values()])
     from paper_2608_01332_amd import workloads as w
     classes = sorted({(e["n"], e["m"], e["variant"]) for e in specs})
-    wpar = w.tree_chainprob(1024, 0.9, np.random.default_rng(7))
+    wpar = w.tree_chainprob(WARM_N, 0.9, np.random.default_rng(7))
     wid = -1
     for pair in (1, 2):
         for (n, m, var) in classes:
             for _ in range(pair):
                 srv.submit(serve.Request(rid=wid, parent=wpar, n=n, m=m,
-                                         prob={k: v[:1024] for k, v in pool[(n, m, var)].items()}))
+                                         prob={k: v[:WARM_N] for k, v in pool[(n, m, var)].items()}))
                 wid -= 1
         srv.drain()
     srv.done.clear()

@@ -116,19 +116,24 @@ static inline double *ws_resid(void *ws) { return reinterpret_cast<double *>(sta
 // Pinned staging buffers of plan uploads, reused across uploads: a fresh
 // pageable buffer per upload pays first-touch page faults on the host and a
 // staged pageable copy.  Every pooled buffer holds STAGE_BYTES; the pool grows
-// to the number of uploads that run at once and is never freed (freeing pinned
-// memory waits for the device, which would stall the solves on other streams).
-// A larger upload stages through ordinary heap memory.
+// to STAGE_MAX buffers and is never freed (freeing pinned memory waits for the
+// device, which would stall the solves on other streams).  Pinning a new
+// buffer takes tens of milliseconds and holds up other HIP calls of the
+// process, so beyond STAGE_MAX uploads at once, and for uploads larger than a
+// buffer, the upload stages through ordinary heap memory instead.
 namespace {
 constexpr size_t STAGE_BYTES = size_t(32) << 20;
+constexpr int STAGE_MAX = 4;
 struct StagePool {
   std::mutex mu;
   std::vector<char *> free_bufs;
+  int made = 0;
 };
 StagePool &stage_pool() {
   static StagePool *pool = new StagePool();
   return *pool;
 }
+// A pooled buffer, or nullptr when none is free and the pool is full.
 char *stage_take() {
   StagePool &sp = stage_pool();
   {
@@ -138,9 +143,15 @@ char *stage_take() {
       sp.free_bufs.pop_back();
       return b;
     }
+    if (sp.made >= STAGE_MAX) return nullptr;
+    ++sp.made;
   }
   void *b = nullptr;
-  if (hipHostMalloc(&b, STAGE_BYTES, hipHostMallocDefault) != hipSuccess) return nullptr;
+  if (hipHostMalloc(&b, STAGE_BYTES, hipHostMallocDefault) != hipSuccess) {
+    std::lock_guard<std::mutex> lock(sp.mu);
+    --sp.made;
+    return nullptr;
+  }
   return static_cast<char *>(b);
 }
 void stage_give(char *b) {
@@ -266,12 +277,10 @@ int plan_upload(PlanObj &P, hipStream_t st) {
   const int64_t NC = std::max<int64_t>(h.N, 1);
   size_t bytes[NP], at[NP];
   const size_t total = plan_pieces(h, bytes, at);
-  const bool pooled = total <= STAGE_BYTES;
+  char *stage = total <= STAGE_BYTES ? stage_take() : nullptr;
+  const bool pooled = stage != nullptr;
   std::unique_ptr<char[]> heap;
-  char *stage = nullptr;
-  if (pooled) {
-    stage = stage_take();
-  } else {
+  if (!pooled) {
     heap.reset(new (std::nothrow) char[total]);
     stage = heap.get();
   }
@@ -413,16 +422,44 @@ void drop_graphs(PlanObj &P) {
 
 size_t graph_cache_size(const PlanObj &P) { return P.graphs.size() + P.timed.size(); }
 
+// One stream of the library's own per GPU (non-blocking, default priority) on
+// which plans release their device memory after their last solve.  The legacy
+// default stream would order those frees with all other blocking work of the
+// process, and a serving loop releases a plan per completed group.
+namespace {
+std::mutex rel_mu;
+hipStream_t rel_streams[POOL_MAX_DEVICES] = {};
+}  // namespace
+
+static hipStream_t release_stream(int dev) {
+  if (dev < 0 || dev >= POOL_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(rel_mu);
+  if (!rel_streams[dev]) {
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return nullptr;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return nullptr;
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess) rel_streams[dev] = st;
+    if (cur != dev) (void)hipSetDevice(cur);
+  }
+  return rel_streams[dev];
+}
+
 void plan_release_device(PlanObj &P) {
   drop_graphs(P);
   for (hipEvent_t e : P.events) (void)hipEventDestroy(e);
   P.events.clear();
   // release after the last solve that used the plan (its completion event), in
-  // the order of the default stream, without blocking the host
+  // the order of the library's release stream, without blocking the host
   void *ptrs[] = {P.dev.base, P.ws[0], P.ws[1], P.resid_buf};
-  if (P.last_done) (void)hipStreamWaitEvent(nullptr, P.last_done, 0);
+  bool any = false;
+  for (void *p : ptrs) any = any || p;
+  int dev = P.dev.device;
+  if (any && dev < 0 && hipGetDevice(&dev) != hipSuccess) dev = -1;
+  hipStream_t rs = any ? release_stream(dev) : nullptr;
+  if (any && P.last_done) (void)hipStreamWaitEvent(rs, P.last_done, 0);
   for (void *p : ptrs)
-    if (p) (void)hipFreeAsync(p, nullptr);
+    if (p) (void)hipFreeAsync(p, rs);
   if (P.last_done) (void)hipEventDestroy(P.last_done);
   P.last_done = nullptr;
   P.dev = PlanDev();
