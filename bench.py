@@ -142,6 +142,37 @@ def summarize_stats(d: str) -> str:
     return buf.getvalue().rstrip("\n")
 
 
+def summarize_timeline(d: str, which: int) -> str:
+    """Per-launch timeline of one solve from a rocprofv3 --kernel-trace run (its
+    *kernel_trace.csv under directory d): solves are split at the first-level
+    kernel; for solve `which`, each launch's start (from the solve's first
+    launch), duration and idle gap before it, in microseconds."""
+    import csv
+    import re
+    rows = []
+    for f in _csvs(d, "kernel_trace.csv"):
+        rows += list(csv.DictReader(open(f)))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    starts = [i for i, r in enumerate(rows) if "k_level1_wide" in r["Kernel_Name"] or "k_condense_wide" in r["Kernel_Name"]]
+    i0, i1 = starts[which], starts[which + 1] if which + 1 < len(starts) else len(rows)
+    seq = rows[i0:i1]
+    t0 = int(seq[0]["Start_Timestamp"])
+    out = ["start_us,dur_us,gap_us,kernel"]
+    prev = None
+    busy = gaps = 0
+    for r in seq:
+        s_, e_ = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        gap = 0 if prev is None else max(0, s_ - prev)
+        name = re.sub(r"\(.*", "", r["Kernel_Name"]).replace("void ", "")
+        out.append(f"{(s_ - t0) / 1e3:.2f},{(e_ - s_) / 1e3:.2f},{gap / 1e3:.2f},\"{name}\"")
+        busy += e_ - s_
+        gaps += gap
+        prev = e_
+    out.append(f"# {len(seq)} launches: kernels {busy / 1e3:.1f} us, gaps {gaps / 1e3:.1f} us, "
+               f"span {(prev - t0) / 1e3:.1f} us (the last row starts the next solve's graph)")
+    return "\n".join(out)
+
+
 def pmc_totals(d: str) -> dict:
     """Per kernel name: dispatches and the sum of each counter over them, from
     a rocprofv3 --pmc run (its *counter_collection.csv under directory d)."""
@@ -681,6 +712,8 @@ def main() -> int:
     ap.add_argument("--no-extreme", action="store_true", help="single workload: skip the shape-extreme sub-record")
     ap.add_argument("--no-lift", action="store_true", help="single workload: skip the lifted sub-record")
     ap.add_argument("--summarize-stats", default="", help="print the kernel statistics of a rocprofv3 run directory")
+    ap.add_argument("--summarize-timeline", default="", help="print one solve's launches from a --kernel-trace run")
+    ap.add_argument("--timeline-solve", type=int, default=10, help="which solve of the trace --summarize-timeline prints")
     ap.add_argument("--summarize-pmc", default="", choices=["", "traffic", "flops"],
                     help="print the dominant class's per-launch figures from rocprofv3 --pmc run directories")
     ap.add_argument("--pmc-run", action="append", default=[],
@@ -695,6 +728,9 @@ def main() -> int:
         return 2
     if args.summarize_stats:
         print(summarize_stats(args.summarize_stats))
+        return 0
+    if args.summarize_timeline:
+        print(summarize_timeline(args.summarize_timeline, args.timeline_solve))
         return 0
     if args.summarize_pmc:
         runs = {}
