@@ -197,3 +197,37 @@ def test_graph_cache_stays_bounded():
         assert _rel(out["x"].cpu().numpy(), ref["x"]) <= 1e-9
         assert plan.stats()["graph_cache_entries"] <= rcr.GRAPH_CACHE_CAP
     assert plan.stats()["graph_cache_entries"] == rcr.GRAPH_CACHE_CAP
+
+
+def test_factor_rhs_and_adjoint_config2_full_size():
+    """The 65,536-node config-2 instance (n = 12, m = 4, rank-6 Delta): one factor,
+    four right-hand sides, each against the oracle at 1e-9; then the adjoint of
+    a random seed on the same factor against the oracle's adjoint at 1e-9."""
+    print("[gpu-factor] config 2 full size", flush=True)
+    par, d, spec = w.config_instance(2)
+    N, n, m = len(par), spec.n, spec.m
+    rng = np.random.default_rng(w.config_seed(2, 7, 0))
+    plan = rcr.Plan(par, n, m)
+    dev = rcr.to_device(d)
+    fac = rcr.factor(plan, dev, check=True)
+    rhs = _rhs(rng, N, n, m, 4)
+    res = rcr.solve_rhs(plan, dev, fac, [{k: _dev(v) for k, v in r_.items()} for r_ in rhs], check=True,
+                        kkt_residual=True)
+    torch.cuda.synchronize()
+    assert res["kkt_residual"] <= 1e-8
+    for i, r_ in enumerate(rhs):
+        di = dict(d)
+        di.update(r_)
+        ref = orc.tree_riccati(par, di)
+        for k in ("x", "u", "lam"):
+            assert _rel(res["solutions"][i][k].cpu().numpy(), ref[k]) <= 1e-9, (i, k)
+    fwd = rcr.solve(plan, dev, check=True)
+    fwd = {k: v.clone() for k, v in fwd.items()}
+    fac = rcr.factor(plan, dev, check=True)
+    fwd["K"], fwd["P"] = fac["K"], fac["P"]
+    seed = {"x": rng.standard_normal((N, n)), "u": rng.standard_normal((N, m)), "lam": rng.standard_normal((N, n))}
+    g = rcr.adjoint(plan, dev, fwd, {k: _dev(v) for k, v in seed.items()}, check=True)
+    torch.cuda.synchronize()
+    ref = oadj.adjoint(par, d, {k: fwd[k].cpu().numpy() for k in ("x", "u", "lam")}, seed)
+    for k in rcr.GRADIENT_FIELDS:
+        assert _rel(g[k].cpu().numpy(), ref[k]) <= 1e-9, (k, _rel(g[k].cpu().numpy(), ref[k]))

@@ -38,7 +38,7 @@ def _check(out, ref, par, nn, mm, tol):
 
 
 @pytest.mark.parametrize("N,nmax,mmax,nmin", [(300, 4, 2, 1), (2000, 8, 3, 2), (1500, 12, 4, 5), (800, 16, 4, 9),
-                                              (1, 6, 3, 6), (2, 3, 2, 1), (600, 5, 5, 1)])
+                                              (1, 6, 3, 6), (2, 3, 2, 1), (600, 5, 5, 1), (32768, 12, 4, 6)])
 def test_ragged_matches_oracle(N, nmax, mmax, nmin):
     print(f"[gpu-ragged] N={N} n<={nmax} m<={mmax}", flush=True)
     rng = np.random.default_rng(N * 7 + nmax)
