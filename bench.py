@@ -481,6 +481,7 @@ def run_serving(specs, pars, pool, dev, slots: int, batching: bool, budget: int,
     wall time from the first arrival to the last completion."""
     import numpy as np
     import torch
+    from paper_2608_01332_amd import rcr
     from paper_2608_01332_amd import serve
     srv = serve.Server(dev, slots=slots, batching=batching, hbm_budget=budget, planner_threads=planner_threads,
                        device_planner=device_planner)
@@ -500,6 +501,16 @@ def run_serving(specs, pars, pool, dev, slots: int, batching: bool, budget: int,
     from paper_2608_01332_amd import workloads as w
     classes = sorted({(e["n"], e["m"], e["variant"]) for e in specs})
     wpar = w.tree_chainprob(WARM_N, 0.9, np.random.default_rng(7))
+    # slot workspaces and output blocks at the size of the largest group the
+    # stream can form (a merged group of max_group_nodes of its largest class)
+    big_ws, big_out = 0, 0
+    for (n, m) in sorted({(c[0], c[1]) for c in classes}):
+        p_ = rcr.Plan(wpar, n, m, single_thread=True)
+        G = srv.max_group_nodes
+        big_ws = max(big_ws, int(p_.workspace_size(srv.precision) / WARM_N * G) + serve.batch_staging_bytes([G], n, m))
+        big_out = max(big_out, serve.io_words(G, n, m)[1] * 8)
+        p_.close()
+    srv.reserve(1 << max(big_ws - 1, 0).bit_length(), 1 << max(big_out - 1, 0).bit_length())
     wid = -1
     for pair in (1, 2):
         for (n, m, var) in classes:

@@ -398,6 +398,27 @@ class Server:
         self._evict()
         return finished
 
+    def reserve(self, ws_bytes: int, out_bytes: int):
+        """Grow every idle slot's workspace to ws_bytes (charged to the budget like
+        any held workspace) and let each slot's stream allocate and release one
+        output block of out_bytes, so that a serving stream does not map new
+        device memory when its first large group arrives (a new mapping holds up
+        the other threads of the process for tens of milliseconds)."""
+        import torch
+        for slot in self.slots:
+            if slot.group is not None:
+                continue
+            cap = slot.ws.numel() if slot.ws is not None else 0
+            with torch.cuda.stream(slot.stream):
+                if ws_bytes > cap and self.held() + ws_bytes - cap <= self.budget:
+                    slot.ws = None
+                    slot.ws = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
+                    self.ws_held += ws_bytes - cap
+                if out_bytes > 0:
+                    blk = torch.empty(out_bytes // 8, dtype=torch.float64, device=self.device)
+                    del blk
+        torch.cuda.synchronize(self.device)
+
     def _evict_for_room(self, slot) -> bool:
         """Make room for the head of the queue: release the device copy of the least
         recently used cached plan that no running group uses, else the workspace
