@@ -128,7 +128,7 @@ int rcr_plan_create(const int64_t *parent, int64_t N, int32_t n, int32_t m,
  * choice in node-id order, is rejected with RCR_BAD_OPTION.  The planner runs
  * in the order of `stream` (a hipStream_t, NULL the default stream) and the
  * call returns when the plan's schedules are back on the host; its working
- * memory (about 0.5 KB per node) comes from the library's device pool and is
+ * memory (about 0.65 KB per node) comes from the library's device pool and is
  * released in stream order.  single_thread is ignored.  Errors: RCR_NULL_ARG,
  * RCR_BAD_DIMS, RCR_INVALID_TREE, RCR_BAD_OPTION, RCR_OOM, RCR_NO_DEVICE,
  * RCR_HIP_ERROR. */

@@ -67,6 +67,35 @@ struct GpuExec {
     __syncthreads();
     return r;
   }
+  // scan() for 64-bit values.
+  __device__ uint64_t scan64(uint64_t *a) {
+    __shared__ uint64_t wsum[THREADS / 64];
+    __shared__ uint64_t tot;
+    const int t = (int)threadIdx.x, lane = t & 63, w = t >> 6;
+    const uint64_t v = a[t];
+    uint64_t s = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint64_t y = __shfl_up(s, (unsigned)o);
+      if (lane >= o) s += y;
+    }
+    if (lane == 63) wsum[w] = s;
+    __syncthreads();
+    if (t == 0) {
+      uint64_t acc = 0;
+      for (int i = 0; i < THREADS / 64; ++i) {
+        const uint64_t c = wsum[i];
+        wsum[i] = acc;
+        acc += c;
+      }
+      tot = acc;
+    }
+    __syncthreads();
+    a[t] = s - v + wsum[w];
+    const uint64_t r = tot;
+    __syncthreads();
+    return r;
+  }
   __device__ void atomic_add(int32_t *p, int32_t v) { atomicAdd(p, v); }
 
   // Wavefront w takes a contiguous range of the indices in steps of 64 (lane l

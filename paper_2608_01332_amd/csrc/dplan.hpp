@@ -19,7 +19,8 @@
 //   * each sibling group's code tree is built by one thread, emitting its
 //     combinations in the host's order (post-order), at offsets known from the
 //     group's start (a group of k contributions makes k - 1 combinations and
-//     one absorption);
+//     one absorption); a group of more than big_group contributions (a hub)
+//     is built by the whole workgroup instead (reduce_big_group);
 //   * the four schedules are stable radix sorts of the round records by level.
 //
 // The program is written once against an executor X: X::each(f) runs f(t) for
@@ -42,6 +43,9 @@ namespace rcr {
 namespace dplan {
 
 constexpr int THREADS = 1024;
+// Sibling groups of more contributions than this are built by the whole
+// workgroup (reduce_big_group), smaller ones by one thread each.
+constexpr int32_t BIG_GROUP = 128;
 
 // statistics words written by the program (int64)
 enum : int {
@@ -58,8 +62,12 @@ struct Arena {
   int32_t *par32, *cnt, *up0, *up1, *dist0, *dist1, *cur_par, *lvlU, *lvlE, *edge_slot, *one_child, *alive, *sel,
       *rem_slot, *rem_par, *comp_r, *comp_k, *rem_kind, *live0, *live1, *leaves, *sorted, *gstart, *elig, *comp, *pos,
       *mark, *cout, *eP, *eX, *removal, *gslot, *glev;
-  uint64_t *code_hi, *code_lo;  // per sorted rake: the code word r (128 bits)
-  int32_t *code_d;              // and its length
+  uint64_t *code_hi, *code_lo;  // per sorted rake: prefix weight sum, code word
+  int32_t *code_d;              // and the common-prefix length with the previous code
+  // a group built by the whole workgroup (reduce_big_group), per split position
+  int32_t *bg_A, *bg_R, *bg_par, *bg_lc, *bg_rc, *bg_left, *bg_dep, *bg_idx, *bg_val, *bg_p0, *bg_d0, *bg_p1,
+      *bg_d1, *bg_seg, *bigs;
+  int32_t big_group;  // groups above this size are built by the whole workgroup
   // per op / slot (2N)
   int32_t *contrib_level, *lT;
   OpRec *raw;
@@ -67,6 +75,7 @@ struct Arena {
   int64_t *off4;                // bucket offsets of a schedule
   // per thread
   uint32_t *tcount, *hist;      // T and 16 T
+  uint64_t *tsum;               // T
   // per round (N + 2)
   int32_t *r_raw, *r_rem, *r_comp_rem, *r_comp_raw;
   // outputs
@@ -91,7 +100,8 @@ inline size_t carve(Arena &a, char *base, int64_t N, int T) {
                       &a.lvlE,    &a.edge_slot, &a.one_child, &a.alive, &a.sel,    &a.rem_slot, &a.rem_par, &a.comp_r,
                       &a.comp_k,  &a.rem_kind, &a.live0,  &a.live1,    &a.leaves, &a.sorted,   &a.gstart,  &a.elig,
                       &a.comp,    &a.pos,    &a.mark,    &a.cout,     &a.eP,     &a.eX,       &a.removal, &a.code_d,
-                      &a.gslot,   &a.glev,
+                      &a.gslot,   &a.glev,   &a.bg_A,    &a.bg_R,     &a.bg_par, &a.bg_lc,    &a.bg_rc,   &a.bg_left,
+                      &a.bg_dep,  &a.bg_idx, &a.bg_val,  &a.bg_p0,    &a.bg_d0,  &a.bg_p1,    &a.bg_d1,   &a.bigs,
                       &a.r_raw,   &a.r_rem,  &a.r_comp_rem, &a.r_comp_raw};
   for (int32_t **p : node) take(*p, n1);
   take(a.code_hi, n1);
@@ -104,8 +114,10 @@ inline size_t carve(Arena &a, char *base, int64_t N, int T) {
   take(a.k1, n2);
   take(a.v1, n2);
   take(a.off4, 4 * n2 + 8);
+  take(a.bg_seg, 4 * n1);  // a segment tree over at most 2 N leaves
   take(a.tcount, (size_t)T);
   take(a.hist, 16 * (size_t)T);
+  take(a.tsum, (size_t)T);
   take(a.ops, n2);
   take(a.exp_ops, n1);
   take(a.tc_ops, n1);
@@ -118,6 +130,7 @@ inline size_t carve(Arena &a, char *base, int64_t N, int T) {
   take(a.stats, (size_t)S_COUNT);
   a.N = N;
   a.T = T;
+  a.big_group = BIG_GROUP;
   return (at + 255) & ~size_t(255);
 }
 
@@ -188,6 +201,28 @@ __host__ __device__ void bucket_offsets(X &x, const Arena &a, const uint32_t *ke
   });
 }
 
+// The code word of Lemma 3's alphabetic code for weight w = 2^e whose
+// predecessors in the group weigh S in all (W the group's total, clW the
+// smallest c with 2^c >= W): the leading d = ceil(log2(W / w)) + 1 bits of
+// (2 S + w) / (2 W), by restoring division, left-aligned in 64 bits.
+__host__ __device__ inline uint64_t code_word(uint64_t S, int e, uint64_t W, int clW) {
+  const uint64_t w = (uint64_t)1 << e, D = 2 * W;
+  const int d = (clW > e ? clW - e : 0) + 1;
+  uint64_t rem = 2 * S + w, q = 0;  // rem < D
+  for (int b = 0; b < d; ++b) {
+    rem <<= 1;
+    q <<= 1;
+    if (rem >= D) {
+      rem -= D;
+      q |= 1;
+    }
+  }
+  return q << (64 - d);
+}
+
+// Common-prefix length of two distinct left-aligned code words.
+__host__ __device__ inline int32_t lcp_bits(uint64_t a, uint64_t b) { return (int32_t)__builtin_clzll(a ^ b); }
+
 // One sibling group (Lemma 3): the contributions at sorted positions [s0, s1)
 // of parent i (their slots and levels staged in gslot, glev); emits its k - 1
 // combinations and its absorption at raw[r0 ..] with combination slots c0,
@@ -228,27 +263,9 @@ __host__ __device__ inline void reduce_group(const Arena &a, int32_t s0, int32_t
     uint64_t S = 0;
     for (int j = 0; j < k; ++j) {
       const int e0 = glev[j] - lmin, e = e0 < cap ? e0 : cap;
-      const uint64_t w = (uint64_t)1 << e;
-      // d_j = ceil(log2(W / w)) + 1, the leading d_j bits of (2 S + w) / (2 W)
-      const int d = (clW > e ? clW - e : 0) + 1;
-      const uint64_t D = 2 * W;
-      uint64_t rem = 2 * S + w, q = 0;  // rem < D
-      for (int b = 0; b < d; ++b) {
-        rem <<= 1;
-        q <<= 1;
-        if (rem >= D) {
-          rem -= D;
-          q |= 1;
-        }
-      }
-      code[j] = q << (64 - d);
-      if (j > 0) {
-        const uint64_t x = code[j - 1] ^ code[j];
-        int lz = 0;
-        while (!(x >> (63 - lz) & 1)) ++lz;  // codes are distinct: x != 0
-        L[j] = lz;
-      }
-      S += w;
+      code[j] = code_word(S, e, W, clW);
+      if (j > 0) L[j] = lcp_bits(code[j - 1], code[j]);  // codes are distinct
+      S += (uint64_t)1 << e;
     }
     // the host's recursive build, as an explicit stack: frames of (range,
     // stage, split, left result); results return through (ret, ret_lvl)
@@ -297,6 +314,202 @@ __host__ __device__ inline void reduce_group(const Arena &a, int32_t s0, int32_t
   const int32_t lv = 1 + (a.lvlU[i] > agg_lvl ? a.lvlU[i] : agg_lvl);
   a.raw[r0 + k - 1] = OpRec{OP_ABSORB, rnd, lv, i, agg, 0, 0, 0};
   a.lvlU[i] = lv;
+}
+
+// Segment trees over positions 0 .. P - 1 (P a power of two, leaves at
+// seg[P + q], node v over its children 2 v and 2 v + 1).
+// The largest position q < p whose leaf is <= x, 0 when there is none, in a
+// tree of minima.
+__host__ __device__ inline int32_t seg_last_le(const int32_t *seg, int32_t P, int32_t p, int32_t x) {
+  int32_t v = P + p;
+  for (; v > 1; v >>= 1) {
+    if ((v & 1) && seg[v - 1] <= x) {  // the left sibling's range holds one: its rightmost
+      v -= 1;
+      while (v < P) v = seg[2 * v + 1] <= x ? 2 * v + 1 : 2 * v;
+      return v - P;
+    }
+  }
+  return 0;
+}
+// The smallest position q > p whose leaf is < x, P when there is none, in a
+// tree of minima.
+__host__ __device__ inline int32_t seg_first_lt(const int32_t *seg, int32_t P, int32_t p, int32_t x) {
+  int32_t v = P + p;
+  for (; v > 1; v >>= 1) {
+    if (!(v & 1) && seg[v + 1] < x) {  // the right sibling's range holds one: its leftmost
+      v += 1;
+      while (v < P) v = seg[2 * v] < x ? 2 * v : 2 * v + 1;
+      return v - P;
+    }
+  }
+  return P;
+}
+// The largest leaf of positions lo .. hi in a tree of maxima.
+__host__ __device__ inline int32_t seg_max(const int32_t *seg, int32_t P, int32_t lo, int32_t hi) {
+  int32_t r = INT32_MIN;
+  for (int32_t l = lo + P, h = hi + P + 1; l < h; l >>= 1, h >>= 1) {
+    if (l & 1) r = seg[l] > r ? seg[l] : r, ++l;
+    if (h & 1) --h, r = seg[h] > r ? seg[h] : r;
+  }
+  return r;
+}
+
+// reduce_group for a large group, by the whole workgroup, with the same
+// output.  The code tree splits a range at the first minimum of its
+// common-prefix lengths, so it is the Cartesian tree of L_1 .. L_{k-1} with
+// ties going to the leftmost; its vertex p (a combination) covers the codes
+// A_p .. B_p, where A_p is the nearest q < p with L_q <= L_p (0 when none) and
+// B_p + 1 the nearest q > p with L_q < L_p (k when none), both found in a
+// segment tree of minima; its parent is whichever of the two has the larger L
+// (on a tie the right one, which lies below the left one).  In the host's
+// post-order the combination p comes after the k - 1 - (B_p - A_p) vertices
+// left of its codes' range minus those of them that are its ancestors, so
+// its index is B_p - 1 - (the number of ancestors left of p), which follows
+// the chain p -> A_p -> ... by pointer jumping.  Its level is 1 + the larger
+// of its operands' levels, that is the largest of (level of a code + its
+// depth below p) over the codes A_p .. B_p: depths by pointer jumping along
+// the parents, the maxima from a segment tree of maxima.
+template <class X>
+__host__ __device__ void reduce_big_group(X &x, const Arena &a, int32_t s0, int32_t s1, int32_t r0, int32_t c0,
+                                          int32_t rnd) {
+  const int T = a.T;
+  const int32_t k = s1 - s0, m = k - 1;  // codes 0 .. k - 1, split positions 1 .. m
+  const int32_t i = a.cur_par[a.sorted[s0]];
+  const int32_t *gslot = a.gslot + s0, *glev = a.glev + s0;
+  uint64_t *code = a.code_lo + s0, *S = a.code_hi + s0;
+  int32_t *L = a.code_d + s0;
+  const int32_t lmin = -x.maxall([&](int t) {
+    int32_t mm = INT32_MIN;
+    for (int32_t j = t; j < k; j += T) mm = -glev[j] > mm ? -glev[j] : mm;
+    return mm;
+  });
+  int lg = 0;
+  while ((1LL << lg) < k) ++lg;
+  const int cap = 61 - lg;
+  auto expo = [&](int32_t j) {
+    const int e = glev[j] - lmin;
+    return e < cap ? e : cap;
+  };
+  // prefix sums of the weights over contiguous chunks
+  const int32_t C = (k + T - 1) / T;
+  x.each([&](int t) {
+    uint64_t sum = 0;
+    for (int32_t j = t * C, e = (t + 1) * C < k ? (t + 1) * C : k; j < e; ++j) sum += (uint64_t)1 << expo(j);
+    a.tsum[t] = sum;
+  });
+  const uint64_t W = x.scan64(a.tsum);
+  x.each([&](int t) {
+    uint64_t sum = a.tsum[t];
+    for (int32_t j = t * C, e = (t + 1) * C < k ? (t + 1) * C : k; j < e; ++j) {
+      S[j] = sum;
+      sum += (uint64_t)1 << expo(j);
+    }
+  });
+  const int clW = bitlen(W - 1);
+  x.each([&](int t) {
+    for (int32_t j = t; j < k; j += T) code[j] = code_word(S[j], expo(j), W, clW);
+  });
+  x.each([&](int t) {
+    for (int32_t j = 1 + t; j < k; j += T) L[j] = lcp_bits(code[j - 1], code[j]);
+  });
+  // tree of minima over L (position 0 and those past m never match)
+  int32_t P = 1;
+  while (P < k) P <<= 1;
+  int32_t *seg = a.bg_seg;
+  x.each([&](int t) {
+    for (int32_t q = t; q < P; q += T) seg[P + q] = (q >= 1 && q <= m) ? L[q] : INT32_MAX;
+  });
+  for (int32_t h = P >> 1; h >= 1; h >>= 1)
+    x.each([&](int t) {
+      for (int32_t v = h + t; v < 2 * h; v += T) seg[v] = seg[2 * v] < seg[2 * v + 1] ? seg[2 * v] : seg[2 * v + 1];
+    });
+  x.each([&](int t) {
+    for (int32_t p = 1 + t; p <= m; p += T) {
+      const int32_t A = seg_last_le(seg, P, p, L[p]), f = seg_first_lt(seg, P, p, L[p]), R = f >= P ? k : f;
+      const bool hl = A >= 1, hr = R <= m;
+      a.bg_A[p] = A;
+      a.bg_R[p] = R;
+      a.bg_par[p] = hl && hr ? (L[A] > L[R] ? A : R) : (hl ? A : (hr ? R : 0));
+    }
+  });
+  x.each([&](int t) {
+    for (int32_t p = 1 + t; p <= m; p += T) {
+      const int32_t q = a.bg_par[p];
+      if (q && p < q) a.bg_lc[q] = p;
+      if (q && p > q) a.bg_rc[q] = p;
+    }
+  });
+  // the length of the chain p -> next(p) -> ... -> 0 for every split p, by
+  // pointer jumping (position 0 is the chains' common end)
+  auto chain = [&](const int32_t *next, int32_t *out) {
+    int32_t *p0 = a.bg_p0, *d0 = a.bg_d0, *p1 = a.bg_p1, *d1 = a.bg_d1;
+    x.each([&](int t) {
+      for (int32_t q = t; q <= m; q += T) {
+        const int32_t f = q ? next[q] : 0;
+        p0[q] = f;
+        d0[q] = f ? 1 : 0;
+      }
+    });
+    for (int it = 0; it < 64; ++it) {
+      const bool more = x.any([&](int t) {
+        bool c = false;
+        for (int32_t q = t; q <= m; q += T) {
+          const int32_t w = p0[q];
+          d1[q] = d0[q] + d0[w];
+          p1[q] = p0[w];
+          c |= p0[w] != 0;
+        }
+        return c;
+      });
+      int32_t *tp = p0, *td = d0;
+      p0 = p1;
+      d0 = d1;
+      p1 = tp;
+      d1 = td;
+      if (!more) break;
+    }
+    x.each([&](int t) {
+      for (int32_t q = t; q <= m; q += T) out[q] = d0[q];
+    });
+  };
+  chain(a.bg_A, a.bg_left);  // ancestors left of p
+  chain(a.bg_par, a.bg_dep);  // ancestors
+  // per code: its level + its depth (that of the deeper adjacent split, + 1)
+  x.each([&](int t) {
+    for (int32_t l = t; l < k; l += T) {
+      const bool hl = l >= 1, hr = l + 1 <= m;
+      const int32_t ps = hl && hr ? (L[l] > L[l + 1] ? l : l + 1) : (hl ? l : l + 1);
+      a.bg_val[l] = glev[l] + a.bg_dep[ps] + 1;
+    }
+  });
+  x.each([&](int t) {
+    for (int32_t q = t; q < P; q += T) seg[P + q] = q < k ? a.bg_val[q] : INT32_MIN;
+  });
+  for (int32_t h = P >> 1; h >= 1; h >>= 1)
+    x.each([&](int t) {
+      for (int32_t v = h + t; v < 2 * h; v += T) seg[v] = seg[2 * v] > seg[2 * v + 1] ? seg[2 * v] : seg[2 * v + 1];
+    });
+  x.each([&](int t) {  // post-order index and level of every combination
+    for (int32_t p = 1 + t; p <= m; p += T) {
+      const int32_t A = a.bg_A[p], B = a.bg_R[p] - 1;
+      a.bg_idx[p] = B - 1 - a.bg_left[p];
+      a.bg_val[p] = seg_max(seg, P, A, B) - a.bg_dep[p];
+    }
+  });
+  x.each([&](int t) {
+    for (int32_t p = 1 + t; p <= m; p += T) {
+      const int32_t A = a.bg_A[p], B = a.bg_R[p] - 1, lv = a.bg_val[p], id = a.bg_idx[p];
+      const int32_t lo = A == p - 1 ? gslot[p - 1] : c0 + a.bg_idx[a.bg_lc[p]];
+      const int32_t hi = B == p ? gslot[p] : c0 + a.bg_idx[a.bg_rc[p]];
+      a.contrib_level[c0 + id] = lv;
+      a.raw[r0 + id] = OpRec{OP_COMBINE, rnd, lv, lo, hi, c0 + id, i, 0};
+      if (a.bg_par[p] == 0) {  // the root: the group's aggregate, absorbed into i
+        const int32_t la = 1 + (a.lvlU[i] > lv ? a.lvlU[i] : lv);
+        a.raw[r0 + k - 1] = OpRec{OP_ABSORB, rnd, la, i, c0 + id, 0, 0, 0};
+        a.lvlU[i] = la;
+      }
+    }
+  });
 }
 
 // The planner.  Returns 0 or a negative RCR_* status; the statistics and
@@ -466,12 +679,25 @@ __host__ __device__ int32_t program(X &x, Arena &a) {
         [&](int64_t q, uint32_t o) { a.gstart[o] = (int32_t)q; });
     {
       const int32_t r0 = raw_n, c0 = next_contrib;
-      x.each([&](int t) {
+      auto group_end = [&](int64_t g) { return g + 1 < (int64_t)G ? a.gstart[g + 1] : (int32_t)nl; };
+      const bool any_big = x.any([&](int t) {
+        bool big = false;
         for (int64_t g = t; g < (int64_t)G; g += T) {
-          const int32_t s0 = a.gstart[g], s1 = g + 1 < (int64_t)G ? a.gstart[g + 1] : (int32_t)nl;
-          reduce_group(a, s0, s1, r0 + s0, c0 + (s0 - (int32_t)g), rnd);
+          const int32_t s0 = a.gstart[g], s1 = group_end(g);
+          if (s1 - s0 <= a.big_group)
+            reduce_group(a, s0, s1, r0 + s0, c0 + (s0 - (int32_t)g), rnd);
+          else
+            big = true;
         }
+        return big;
       });
+      const uint32_t nbig = !any_big ? 0 : compact(
+          x, a, G, [&](int64_t g) { return group_end(g) - a.gstart[g] > a.big_group; },
+          [&](int64_t g, uint32_t o) { a.bigs[o] = (int32_t)g; });
+      for (uint32_t b = 0; b < nbig; ++b) {
+        const int32_t g = a.bigs[b], s0 = a.gstart[g];
+        reduce_big_group(x, a, s0, group_end(g), r0 + s0, c0 + (s0 - g), rnd);
+      }
     }
     raw_n += (int32_t)nl;
     next_contrib += (int32_t)nl - (int32_t)G;
@@ -766,6 +992,15 @@ struct CpuExec {
     }
     return s;
   }
+  uint64_t scan64(uint64_t *a) {
+    uint64_t s = 0;
+    for (int t = 0; t < T; ++t) {
+      const uint64_t c = a[t];
+      a[t] = s;
+      s += c;
+    }
+    return s;
+  }
   void atomic_add(int32_t *p, int32_t v) { *p += v; }
 
   // Thread t takes the contiguous chunk [t C, (t + 1) C) of the indices.
@@ -875,8 +1110,10 @@ inline OutSizes out_sizes(const int64_t *s) {
 }
 
 // The planner run on the host by CpuExec over host arrays (the same program
-// the GPU runs), for checking the program itself without a GPU.
-inline int emulate(const int64_t *parent, int64_t N, int n, int m, int T, int order, PlanHost &P) {
+// the GPU runs), for checking the program itself without a GPU; big_group
+// sets the size above which sibling groups take the workgroup-wide build.
+inline int emulate(const int64_t *parent, int64_t N, int n, int m, int T, int order, PlanHost &P,
+                   int32_t big_group = BIG_GROUP) {
   if (!parent) return RCR_NULL_ARG;
   if (N < 1 || n < 1 || m < 1 || n > RCR_MAX_DIM || m > RCR_MAX_DIM) return RCR_BAD_DIMS;
   if (N > (int64_t)(INT32_MAX / 2 - 16)) return RCR_BAD_DIMS;
@@ -885,6 +1122,7 @@ inline int emulate(const int64_t *parent, int64_t N, int n, int m, int T, int or
   std::vector<uint64_t> mem(bytes / 8 + 1);
   carve(a, reinterpret_cast<char *>(mem.data()), N, T);
   a.parent = parent;
+  a.big_group = big_group;
   CpuExec x;
   x.T = T;
   x.order = order;

@@ -1,9 +1,10 @@
 // The device planner's program (dplan.hpp) run on the CPU by its sequential
 // executor, checked against the host planner (build_plan, list-rank
 // selection): every statistic and every schedule must be identical, for
-// thread counts 1024 (the GPU's) and others, and for three orders of the
+// thread counts 1024 (the GPU's) and others, for three orders of the
 // threads inside each phase (a phase whose result depended on that order would
-// race on the GPU).  Invalid trees must be rejected with the host's status.
+// race on the GPU), and with sibling groups built by one thread or by the
+// whole workgroup.  Invalid trees must be rejected with the host's status.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -36,11 +37,16 @@ static void compare(const std::string &name, const std::vector<int64_t> &parent)
   const int64_t N = (int64_t)parent.size();
   const int rh = build_plan(parent.data(), N, 6, 2, RCR_SELECT_LIST_RANK, host);
   const int Ts[] = {dplan::THREADS, 37, 1};
+  // every group through the one-thread build (above the largest group), then
+  // every group of two or more through the workgroup-wide build, then the
+  // default threshold
+  const int32_t bigs[] = {INT32_MAX, 1, dplan::BIG_GROUP};
+  for (int32_t big : bigs)
   for (int T : Ts)
     for (int order = 0; order < 3; ++order) {
       if (T == 1 && order) continue;
       PlanHost dev;
-      const int rd = dplan::emulate(parent.data(), N, 6, 2, T, order, dev);
+      const int rd = dplan::emulate(parent.data(), N, 6, 2, T, order, dev, big);
       CHECK(rd == rh, "status");
       if (rh) continue;
       CHECK(dev.root == host.root && dev.height == host.height && dev.leaves == host.leaves &&
@@ -136,6 +142,27 @@ int main() {
     for (int k = 0; k < 2000; ++k) hub.push_back(1 + (int64_t)(g() % 3000));
     for (int k = 0; k < 2000; ++k) hub.push_back((int64_t)hub.size() - 1);
     cases.push_back({"hubs", hub});
+  }
+  {  // a root with 700 chains of random lengths: large root groups of mixed levels, round after round
+    std::vector<int64_t> sc(1, -1);
+    for (int c = 0; c < 700; ++c) {
+      int64_t prev = 0;
+      const int len = 1 + (int)(g() % 40);
+      for (int l = 0; l < len; ++l) {
+        sc.push_back(prev);
+        prev = (int64_t)sc.size() - 1;
+      }
+    }
+    cases.push_back({"star_of_chains", sc});
+  }
+  {  // a root with 200 children of 200 leaves each
+    std::vector<int64_t> tl(1, -1);
+    for (int c = 0; c < 200; ++c) {
+      const int64_t v = (int64_t)tl.size();
+      tl.push_back(0);
+      for (int l = 0; l < 200; ++l) tl.push_back(v);
+    }
+    cases.push_back({"two_level_hubs", tl});
   }
   for (double p : {0.5, 0.8, 0.9, 0.95, 0.99}) {
     for (int64_t N : {100, 2500, 20000}) {

@@ -3,7 +3,8 @@ the CPU by its sequential executor (tests/native/dplan_emul.cpp), plain and
 under AddressSanitizer + UndefinedBehaviorSanitizer (host code only): every
 statistic and schedule equals the host planner's with the list-rank
 selection, for 1024 threads (the GPU's), 37 and 1, each in three orders of the
-threads within a phase, and invalid trees get the host's status."""
+threads within a phase, with sibling groups built by one thread each and by
+the whole workgroup, and invalid trees get the host's status."""
 import os
 import subprocess
 

@@ -2,7 +2,8 @@
 a device parent array are byte-identical to the host planner's with the
 list-rank selection (rcr_plan_digest over every array, plus the statistics
 and the exported ops), from one node to the 1,048,576-node shape-extreme
-trees and the 65,536-node config-2 tree, with labels in any order; invalid
+trees and the 65,536-node config-2 tree, with labels in any order (hubs
+whose sibling groups the whole workgroup builds among them); invalid
 trees and the greedy selection are rejected; a solve on the device-built plan
 equals the solve on the host-built one bit for bit."""
 import ctypes
@@ -30,6 +31,8 @@ def _trees():
         t = w.tree_chainprob(30000, p, rng)
         yield f"chainprob{p}", t
         yield f"permuted{p}", w.permute_labels(t, rng)[0]
+    # hubs: sibling groups of thousands of contributions of mixed levels, built by the whole workgroup
+    yield "star_of_chains", w.tree_star_heavy(3000, rng.integers(1, 60, size=3000))
     yield "config2", w.config_instance(2)[0]
     for kind in ("caterpillar", "star_heavy", "chainprob"):
         yield f"extreme_{kind}", w.shape_extreme(kind)
