@@ -287,13 +287,15 @@ int rcr_factor(const rcr_plan *plan, const rcr_problem *in, rcr_solution *out, c
 
 /* Solve k >= 1 right-hand sides rhs[0..k) on the factor made by rcr_factor
  * (same plan, precision and workspace; factor->K, factor->P are its outputs;
+ * rcr_solve leaves no factor for this: in float64 it does not store A^cl;
  * Delta and B of `in` are read, and in MIXED32 also Q, R, S, A for the
  * refinement's residual), writing sol[i] for rhs[i], one after the other on
  * `stream`.  MIXED32 refines each solution with opt->refine_steps correction
  * solves on the float64 KKT residual.  opt->kkt_residual receives the largest
  * residual over the k solutions.  Only the solve passes run: no factor-class
  * kernel is launched.  Errors: those of rcr_solve; RCR_BAD_OPTION when no
- * workspace is given and the plan has not factored in this precision. */
+ * workspace is given and the plan-owned workspace of this precision holds no
+ * factor (no rcr_factor yet, or an rcr_solve since). */
 int rcr_solve_rhs(const rcr_plan *plan, const rcr_problem *in, const rcr_solution *factor, int32_t k,
                   const rcr_rhs *rhs, rcr_rhs_solution *sol, const rcr_solve_options *opt, void *stream);
 

@@ -864,8 +864,8 @@ static int launch_sequence(PlanObj &P, const rcr_problem &in, const rcr_solution
   const RhsIO io{in.q, in.r, in.c, out.x, out.u, out.lam};
   if (opt.precision == RCR_FP64) {
     Bufs<double> bf = bufs_for<double>(P, L, ws, in, out.K, out.P, &io);
-    int rc = launch_phase<double>(P, bf, tm, st, 0 | RCR_PHASE_FIRST_RHS);
-    if (!rc) rc = launch_phase<double>(P, bf, tm, st, 1 | RCR_PHASE_FIRST_RHS);
+    int rc = launch_phase<double>(P, bf, tm, st, 0 | RCR_PHASE_FIRST_RHS | RCR_PHASE_ONE_RHS);
+    if (!rc) rc = launch_phase<double>(P, bf, tm, st, 1 | RCR_PHASE_FIRST_RHS | RCR_PHASE_ONE_RHS);
     return rc;
   }
   // MIXED32: float32 factor and solves; float64 R/G Cholesky and compress (I + C P)
@@ -1137,6 +1137,7 @@ int solve(PlanObj &P, const rcr_problem &in, rcr_solution &out, const rcr_solve_
   const WsLayout L = workspace_layout(P.host, prec);
   void *ws = nullptr;
   if ((rc = take_workspace(P, opt, L.total_bytes, total_workspace_bytes(P.host, prec), st, ws))) return rc;
+  if (ws == P.ws[prec]) P.ws_factor[prec] = false;  // a solve leaves no factor for rcr_solve_rhs
   Timer tm;
   tm.P = &P;
   tm.st = st;
@@ -1178,6 +1179,7 @@ int factor(PlanObj &P, const rcr_problem &in, double *K, double *Pm, const rcr_s
     rc = factor_sequence(P, in, K, Pm, prec, L, ws, tm, st);
   }
   if (rc) return rc;
+  if (ws == P.ws[prec]) P.ws_factor[prec] = true;
   rcr_solve_options o = opt;
   o.kkt_residual = nullptr;  // no iterate yet
   return finish_call(P, ws, o, tm, nullptr, {}, st);
@@ -1191,7 +1193,7 @@ int solve_rhs(PlanObj &P, const rcr_problem &in, const double *K, const double *
   const int prec = opt.precision;
   const WsLayout L = workspace_layout(P.host, prec);
   void *ws = opt.workspace ? opt.workspace : P.ws[prec];
-  if (!ws) return RCR_BAD_OPTION;  // no factor of this precision in the plan's workspace
+  if (!opt.workspace && !P.ws_factor[prec]) return RCR_BAD_OPTION;  // no factor of this precision in the plan's workspace
   if (opt.workspace && (size_t)opt.workspace_bytes < L.total_bytes) return RCR_SMALL_WORKSPACE;
   Timer tm;
   tm.P = &P;

@@ -18,6 +18,10 @@ namespace rcr {
 // Phase flag: the factor and the solve of one rcr_solve share its first
 // right-hand side, so the wide local factor may initialise that solve.
 constexpr int RCR_PHASE_FIRST_RHS = 4;
+// Phase flag (with RCR_PHASE_FIRST_RHS): that right-hand side is the factor's
+// only one (a float64 rcr_solve), so the local factor does not store A^cl,
+// which only the initialisation of later right-hand sides reads.
+constexpr int RCR_PHASE_ONE_RHS = 8;
 
 // Device copy of a plan's integer arrays.
 // The residual kernel sums a node's child terms in one team; a node with more
@@ -101,6 +105,7 @@ struct PlanObj {
   PlanDev dev;
   std::mutex mu;
   void *ws[2] = {nullptr, nullptr};  // plan-owned workspace per precision
+  bool ws_factor[2] = {false, false};  // it holds a factor made by rcr_factor
   size_t ws_bytes[2] = {0, 0};
   hipEvent_t last_done = nullptr;    // completion of the latest solve (stream-ordered release)
   std::map<GraphKey, GraphEntry> graphs;

@@ -425,7 +425,7 @@ struct LfLay {
 };
 
 template <typename T, int NB, int MB>
-__device__ __forceinline__ void local_factor_body(const Bufs<T> &bf, bool rhs) {
+__device__ __forceinline__ void local_factor_body(const Bufs<T> &bf, bool rhs, bool keep_acl) {
   // One team per node v:  F = I + Delta P, Finv, W = P F^-1; for v != root and
   // e = (parent, v):  WB = W B,  H^T = A^T WB + M,  G = R + B^T WB (float64
   // Cholesky),  K^T = -H^T G^-1,  G^-1,  A^cl = A + B K,  T = F^-1 A^cl.
@@ -629,7 +629,7 @@ __device__ __forceinline__ void local_factor_body(const Bufs<T> &bf, bool rhs) {
   lds_put(LA, tv, r);                  // A was last read for H^T
   team_sync();
   stage_store<PW, NB, NB>(bf.Finv, smt + Ly::Fi, TST, v0, cnt, n, n, lane);
-  stage_store<PW, NB, NB>(bf.Acl, smt + Ly::P, TST, v0, cnt, n, n, lane, noedge, TW);
+  if (keep_acl) stage_store<PW, NB, NB>(bf.Acl, smt + Ly::P, TST, v0, cnt, n, n, lane, noedge, TW);
   stage_store<PW, NB, NB>(bf.Tm, smt + Ly::A, TST, v0, cnt, n, n, lane, noedge, TW);
   stage_store<PW, MB, NB, true>(bf.Kw, smt + Ly::WB, TST, v0, cnt, m, n, lane);  // K = (K^T)^T, m x n
   if (rhs) {  // G's block is dead since the G^-1 rows, the pivot-row scratch since the elimination
@@ -649,13 +649,14 @@ __device__ __forceinline__ void local_factor_body(const Bufs<T> &bf, bool rhs) {
 
 template <typename T, int NB, int MB>
 __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(lf_waves_per_eu<NB>())))
-void k_local_factor(Bufs<T> bf, int rhs) {
+void k_local_factor(Bufs<T> bf, int flags) {  // flags as for k_local_factor_wide
+  const bool rhs = (flags & 1) != 0, keep_acl = (flags & 2) == 0;
   if (bf.n == NB && bf.m == MB)
-    local_factor_body<T, NB, MB>(exact_nm<NB, MB>(bf), rhs != 0);
+    local_factor_body<T, NB, MB>(exact_nm<NB, MB>(bf), rhs, keep_acl);
   else if (bf.n == NB)
-    local_factor_body<T, NB, MB>(exact_n<NB>(bf), rhs != 0);
+    local_factor_body<T, NB, MB>(exact_n<NB>(bf), rhs, keep_acl);
   else
-    local_factor_body<T, NB, MB>(bf, rhs != 0);
+    local_factor_body<T, NB, MB>(bf, rhs, keep_acl);
 }
 
 // Composite transition of one compression on a team: T_new = T_r T_l.

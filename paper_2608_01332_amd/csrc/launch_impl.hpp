@@ -166,6 +166,8 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
   constexpr int PWm = TeamW<NM>::PW;
   constexpr bool WIDE = MatLay<NB>::WIDE;  // one primitive per wavefront for the level kernels
   const bool fused_rhs = (phase_flags & RCR_PHASE_FIRST_RHS) != 0;
+  // local factor flags: 1 initialise the first right-hand side, 2 do not store A^cl
+  const int lf_flags = (fused_rhs ? 1 : 0) | (fused_rhs && (phase_flags & RCR_PHASE_ONE_RHS) ? 2 : 0);
   const size_t lds_cond = (size_t)PW * CondLay<NB, MB>::words * sizeof(double);
   const size_t lds_quad = (size_t)PW * lds_quad_words<T, NB>() * sizeof(T);
   const size_t lds_lf = (size_t)PW * LfLay<T, NB, MB>::words * sizeof(double);
@@ -278,9 +280,9 @@ int launch_phase_nb(PlanObj &P, Bufs<T> bf, Timer &tm, hipStream_t st, int phase
   tm.begin(RCR_K_LOCAL_FACTOR);
   if constexpr (WIDE) {
     allow_lds(k_local_factor_wide<T, NB, MB>, lds_lfw);
-    LAUNCH(tm, (k_local_factor_wide<T, NB, MB>), dim3((unsigned)h.N), dim3(64), lds_lfw, st, bf, fused_rhs ? 1 : 0);
+    LAUNCH(tm, (k_local_factor_wide<T, NB, MB>), dim3((unsigned)h.N), dim3(64), lds_lfw, st, bf, lf_flags);
   } else {
-    LAUNCH(tm, (k_local_factor<T, NB, MB>), dim3(NBk), dim3(64), lds_lf, st, bf, fused_rhs ? 1 : 0);
+    LAUNCH(tm, (k_local_factor<T, NB, MB>), dim3(NBk), dim3(64), lds_lf, st, bf, lf_flags);
   }
 
   // ---- composite transitions along compressions (with the first right-hand

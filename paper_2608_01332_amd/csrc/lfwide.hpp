@@ -81,7 +81,7 @@ __device__ __forceinline__ void chol_inv_regs(const double *LG, double (&Gi)[MB]
 }
 
 template <typename T, int NB, int MB>
-__device__ __forceinline__ void local_factor_wide(const Bufs<T> &bf, bool rhs) {
+__device__ __forceinline__ void local_factor_wide(const Bufs<T> &bf, bool rhs, bool keep_acl) {
   using Ly = LfwLay<T, NB, MB>;
   constexpr int CQ = WideCfg<NB>::CQ, TL = WideCfg<NB>::TILE, LD = Ly::LD, LW = Ly::LW, MBP = Ly::MBP;
   constexpr int TB = (NB * MB + 63) / 64;
@@ -269,7 +269,7 @@ __device__ __forceinline__ void local_factor_wide(const Bufs<T> &bf, bool rhs) {
       for (int c = 0; c < MB; ++c) s = fmat(LB[rr * MBP + c], LKt[j * MBP + c], s);
       acl[cc] = s;
     }
-    if (edge) wstore_piece<T, NB>(bf.Acl + v * nn, acl, n, true);
+    if (edge && keep_acl) wstore_piece<T, NB>(bf.Acl + v * nn, acl, n, true);
     wput_piece<T, NB>(LDe, LD, acl);
   }
   team_sync();
@@ -301,16 +301,18 @@ __device__ __forceinline__ void local_factor_wide(const Bufs<T> &bf, bool rhs) {
 
 // One node per wavefront; the body is specialised for n = NB (and m = MB)
 // when the blocks need no padding (exact_n, exact_nm).
-// With rhs set it also initialises the solve of the right-hand side that
-// Bufs carries (sq, sr, sc), which then skips its own initialisation.
+// With bit 1 of flags it also initialises the solve of the right-hand side
+// that Bufs carries (sq, sr, sc), which then skips its own initialisation;
+// with bit 2 it leaves A^cl unstored (no later right-hand side needs it).
 template <typename T, int NB, int MB>
-RCR_MAT_KERNEL(NB) void k_local_factor_wide(Bufs<T> bf, int rhs) {
+RCR_MAT_KERNEL(NB) void k_local_factor_wide(Bufs<T> bf, int flags) {
+  const bool rhs = (flags & 1) != 0, keep_acl = (flags & 2) == 0;
   if (bf.n == NB && bf.m == MB)
-    local_factor_wide<T, NB, MB>(exact_nm<NB, MB>(bf), rhs != 0);
+    local_factor_wide<T, NB, MB>(exact_nm<NB, MB>(bf), rhs, keep_acl);
   else if (bf.n == NB)
-    local_factor_wide<T, NB, MB>(exact_n<NB>(bf), rhs != 0);
+    local_factor_wide<T, NB, MB>(exact_n<NB>(bf), rhs, keep_acl);
   else
-    local_factor_wide<T, NB, MB>(bf, rhs != 0);
+    local_factor_wide<T, NB, MB>(bf, rhs, keep_acl);
 }
 
 }  // namespace rcr

@@ -92,6 +92,31 @@ def test_split_equals_solve_bitwise(n, m, ex):
             assert torch.equal(res["solutions"][0][k], one[k]), (rep, k)
 
 
+@pytest.mark.parametrize("n,m,prec", [(12, 4, rcr.FP64), (8, 3, rcr.FP64), (12, 4, rcr.MIXED32)])
+def test_solve_leaves_no_factor_for_rhs(n, m, prec):
+    """rcr_solve_rhs on the plan-owned workspace needs a factor from rcr_factor:
+    after an rcr_solve in the same precision it is refused (RCR_BAD_OPTION; a
+    float64 solve does not store A^cl), and a new rcr_factor makes it work again,
+    equal bit for bit to the first factor's solve."""
+    print(f"[gpu-split] refused after solve n={n} m={m} prec={prec}", flush=True)
+    par, d, rng = _instance(f"refuse{n}", 3000, n, m, cross=False)
+    plan = rcr.Plan(par, n, m)
+    dev = rcr.to_device(d)
+    rhs = [{k: _dev(v) for k, v in r_.items()} for r_ in _rhs(rng, 3000, n, m, 1)]
+    fac = rcr.factor(plan, dev, precision=prec, check=True)
+    first = rcr.solve_rhs(plan, dev, fac, rhs, precision=prec, check=True)["solutions"][0]
+    first = {k: v.clone() for k, v in first.items()}
+    rcr.solve(plan, dev, precision=prec, check=True)
+    with pytest.raises(rcr.RcrError) as ei:
+        rcr.solve_rhs(plan, dev, fac, rhs, precision=prec, check=True)
+    assert ei.value.status == rcr.ERR_BAD_OPTION
+    fac = rcr.factor(plan, dev, precision=prec, check=True)
+    again = rcr.solve_rhs(plan, dev, fac, rhs, precision=prec, check=True)["solutions"][0]
+    torch.cuda.synchronize()
+    for k in ("x", "u", "lam"):
+        assert torch.equal(again[k], first[k]), k
+
+
 def test_factor_then_rhs_mixed32():
     print("[gpu-factor-mixed]", flush=True)
     par, d, rng = _instance("facmix", 20000, 8, 3, cross=True)
