@@ -1,7 +1,7 @@
 // Local factor (eqs. (FW), (factor-local)) in the wide layout for NB in
 // {12, 16}: one node per 64-lane wavefront, lane (q, r) owning row r and
 // column quarter q of every NB x NB block (wide.hpp).  Per node v:
-//   F = I + Delta P,  Finv by Gauss-Jordan on [F | I],  W = P Finv;
+//   F = I + Delta P,  Finv by Gauss-Jordan in place (gj_inv_wide),  W = P Finv;
 //   for the edge e = (parent, v):  WB = W B,  H^T = A^T WB + M,
 //   G = R + B^T WB (float64 Cholesky),  K = -G^-1 H,  G^-1,
 //   A^cl = A + B K,  T = Finv A^cl;
@@ -18,10 +18,10 @@ namespace rcr {
 
 template <typename T, int NB, int MB>
 struct LfwLay {
-  static constexpr int LD = WideCfg<NB>::LD, BS = WideCfg<NB>::BS, W = 2 * NB, LW = W + 1, MBP = MB + 1;
-  // words of T: P (later W), Delta (later H^T in float64, then A^cl), A, the
-  // system [F | I], B, WB (later K^T) (NB x MB each, row stride MB + 1)
-  static constexpr int P = 0, D = BS, A = 2 * BS, M = 3 * BS, B = M + NB * LW, WB = B + NB * MBP, Kt = WB,
+  static constexpr int LD = WideCfg<NB>::LD, BS = WideCfg<NB>::BS, MBP = MB + 1;
+  // words of T: P (later W), Delta (later H^T in float64, then A^cl), A, F
+  // (inverted in place), B, WB (later K^T) (NB x MB each, row stride MB + 1)
+  static constexpr int P = 0, D = BS, A = 2 * BS, M = 3 * BS, B = M + BS, WB = B + NB * MBP, Kt = WB,
                        Cv = WB + NB * MBP, Rv = Cv + NB, tend = Rv + MB;  // c, r: the first right-hand side
   // doubles: H^T (NB x MB; over Delta where it fits), G and G^-1 (MB x MB)
   static constexpr bool HD = D * sizeof(T) % 8 == 0 && NB * MBP * 8 <= BS * (int)sizeof(T);
@@ -83,7 +83,7 @@ __device__ __forceinline__ void chol_inv_regs(const double *LG, double (&Gi)[MB]
 template <typename T, int NB, int MB>
 __device__ __forceinline__ void local_factor_wide(const Bufs<T> &bf, bool rhs, bool keep_acl) {
   using Ly = LfwLay<T, NB, MB>;
-  constexpr int CQ = WideCfg<NB>::CQ, TL = WideCfg<NB>::TILE, LD = Ly::LD, LW = Ly::LW, MBP = Ly::MBP;
+  constexpr int CQ = WideCfg<NB>::CQ, TL = WideCfg<NB>::TILE, LD = Ly::LD, MBP = Ly::MBP;
   constexpr int TB = (NB * MB + 63) / 64;
   extern __shared__ double smd[];
   T *L = reinterpret_cast<T *>(smd);
@@ -140,20 +140,16 @@ __device__ __forceinline__ void local_factor_wide(const Bufs<T> &bf, bool rhs, b
     }
   }
   team_sync();
-  {  // the system [F | I], F = I + Delta P
+  {  // F = I + Delta P
     const dv4 f = mf_mm<NB, false, false>(mf_ident(NB), LDe, LD, LP, LD);
-    mf_store(LM, LW, f, NB, NB);
-    if (r < NB) {
-#pragma unroll
-      for (int c = 0; c < CQ; ++c) LM[r * LW + NB + q * CQ + c] = (q * CQ + c == r) ? (T)1 : (T)0;
-    }
+    mf_store(LM, LD, f, NB, NB);
   }
   team_sync();
-  gj_wide<T, NB, 2 * NB>(LM, bf.status, true);
-  const T *LFi = LM + NB;  // Finv, row stride LW
+  gj_inv_wide<T, NB>(LM, bf.status, true);
+  const T *LFi = LM;  // Finv, row stride LD
   {
-    mf_store(bf.Finv + v * nn, n, mf_load(LFi, LW, NB, NB), n, n);
-    const dv4 w = mf_mm<NB, false, false>(mf_zero(), LP, LD, LFi, LW);  // W = P Finv
+    mf_store(bf.Finv + v * nn, n, mf_load(LFi, LD, NB, NB), n, n);
+    const dv4 w = mf_mm<NB, false, false>(mf_zero(), LP, LD, LFi, LD);  // W = P Finv
     mf_store(bf.W + v * nn, n, w, n, n);
     team_sync();  // the reads of P precede its replacement by W
     mf_store(LP, LD, w, NB, NB);
@@ -274,7 +270,7 @@ __device__ __forceinline__ void local_factor_wide(const Bufs<T> &bf, bool rhs, b
   }
   team_sync();
   {
-    const dv4 t = mf_mm<NB, false, false>(mf_zero(), LFi, LW, LDe, LD);  // T = Finv A^cl
+    const dv4 t = mf_mm<NB, false, false>(mf_zero(), LFi, LD, LDe, LD);  // T = Finv A^cl
     if (edge) mf_store(bf.Tm + v * nn, n, t, n, n);
   }
   if (rhs) {

@@ -120,8 +120,9 @@ __device__ __forceinline__ float readlane_t<float>(float v, int lane) {
   "1:\n\t"
 #define RCR_JT_TAIL "2:\n\ts_nop 1"
 #define RCR_FM(OP, I, P) OP " %" #I ", %" #I ", %[g] row_newbcast:" #P " row_mask:0xf bank_mask:0xf\n\t"
-#define RCR_C6(OP, P) \
-  RCR_FM(OP, 0, P) RCR_FM(OP, 1, P) RCR_FM(OP, 2, P) RCR_FM(OP, 3, P) RCR_FM(OP, 4, P) RCR_FM(OP, 5, P)
+#define RCR_C3(OP, P) RCR_FM(OP, 0, P) RCR_FM(OP, 1, P) RCR_FM(OP, 2, P)
+#define RCR_C4(OP, P) RCR_C3(OP, P) RCR_FM(OP, 3, P)
+#define RCR_C6(OP, P) RCR_C4(OP, P) RCR_FM(OP, 4, P) RCR_FM(OP, 5, P)
 #define RCR_C8(OP, P) RCR_C6(OP, P) RCR_FM(OP, 6, P) RCR_FM(OP, 7, P)
 #define RCR_C9(OP, P) RCR_C8(OP, P) RCR_FM(OP, 8, P)
 #define RCR_C12(OP, P) RCR_C9(OP, P) RCR_FM(OP, 9, P) RCR_FM(OP, 10, P) RCR_FM(OP, 11, P)
@@ -131,7 +132,9 @@ __device__ __forceinline__ float readlane_t<float>(float v, int lane) {
   RCR_CASE(C, OP, 5) RCR_CASE(C, OP, 6) RCR_CASE(C, OP, 7) RCR_CASE(C, OP, 8) RCR_CASE(C, OP, 9)            \
   RCR_CASE(C, OP, 10) RCR_CASE(C, OP, 11) RCR_CASE(C, OP, 12) RCR_CASE(C, OP, 13) RCR_CASE(C, OP, 14)       \
   RCR_CASE(C, OP, 15)
-#define RCR_OPS6(m) "+v"(m[0]), "+v"(m[1]), "+v"(m[2]), "+v"(m[3]), "+v"(m[4]), "+v"(m[5])
+#define RCR_OPS3(m) "+v"(m[0]), "+v"(m[1]), "+v"(m[2])
+#define RCR_OPS4(m) RCR_OPS3(m), "+v"(m[3])
+#define RCR_OPS6(m) RCR_OPS4(m), "+v"(m[4]), "+v"(m[5])
 #define RCR_OPS8(m) RCR_OPS6(m), "+v"(m[6]), "+v"(m[7])
 #define RCR_OPS9(m) RCR_OPS8(m), "+v"(m[8])
 #define RCR_OPS12(m) RCR_OPS9(m), "+v"(m[9]), "+v"(m[10]), "+v"(m[11])
@@ -143,13 +146,18 @@ __device__ __forceinline__ float readlane_t<float>(float v, int lane) {
 template <typename T, int WQ>
 __device__ __forceinline__ void row_rank1(T (&m)[WQ], T g, int p) {
   static_assert(sizeof(T) == 8 || sizeof(T) == 4, "float or double");
-  static_assert(WQ == 6 || WQ == 8 || WQ == 9 || WQ == 12, "row piece of 6, 8, 9 or 12 words");
+  static_assert(WQ == 3 || WQ == 4 || WQ == 6 || WQ == 8 || WQ == 9 || WQ == 12,
+                "row piece of 3, 4, 6, 8, 9 or 12 words");
   if constexpr (sizeof(T) == 8) {
+    if constexpr (WQ == 3) RCR_JT(3, 28, "v_fmac_f64_dpp");
+    if constexpr (WQ == 4) RCR_JT(4, 36, "v_fmac_f64_dpp");
     if constexpr (WQ == 6) RCR_JT(6, 52, "v_fmac_f64_dpp");
     if constexpr (WQ == 8) RCR_JT(8, 68, "v_fmac_f64_dpp");
     if constexpr (WQ == 9) RCR_JT(9, 76, "v_fmac_f64_dpp");
     if constexpr (WQ == 12) RCR_JT(12, 100, "v_fmac_f64_dpp");
   } else {
+    if constexpr (WQ == 3) RCR_JT(3, 28, "v_fmac_f32_dpp");
+    if constexpr (WQ == 4) RCR_JT(4, 36, "v_fmac_f32_dpp");
     if constexpr (WQ == 6) RCR_JT(6, 52, "v_fmac_f32_dpp");
     if constexpr (WQ == 8) RCR_JT(8, 68, "v_fmac_f32_dpp");
     if constexpr (WQ == 9) RCR_JT(9, 76, "v_fmac_f32_dpp");
@@ -161,12 +169,16 @@ __device__ __forceinline__ void row_rank1(T (&m)[WQ], T g, int p) {
 #undef RCR_OPS9
 #undef RCR_OPS8
 #undef RCR_OPS6
+#undef RCR_OPS4
+#undef RCR_OPS3
 #undef RCR_ALL
 #undef RCR_CASE
 #undef RCR_C12
 #undef RCR_C9
 #undef RCR_C8
 #undef RCR_C6
+#undef RCR_C4
+#undef RCR_C3
 #undef RCR_FM
 #undef RCR_JT_TAIL
 #undef RCR_JT_HEAD
@@ -214,6 +226,58 @@ __device__ __forceinline__ void gj_wide(T *LM, int *status, bool report) {
   if (r < NB) {
 #pragma unroll
     for (int c = 0; c < WQ; ++c) LM[step * LW + q * WQ + c] = m[c];
+  }
+  team_sync();
+}
+
+// In-place inverse of the NB x NB matrix staged in LDS (LM, row stride NB + 1)
+// by the elimination of gj_wide without the identity half.  Before the
+// rank-1 update of step k, column k, which the update would turn into the
+// pivot row's unit column, is set to e_p (p the pivot row): the identity half
+// of [F | I] holds e_p in its column p until that step, so the update leaves
+// in column k exactly the values (same operations, same bits) the identity
+// half's column p would hold, and later steps update it as they would have.
+// The result is the inverse in pivot order: row r of the elimination belongs
+// at the row of the step where r pivoted, column k at the column of step k's
+// pivot row; the final store puts both in place, so LM holds F^-1.
+template <typename T, int NB>
+__device__ __forceinline__ void gj_inv_wide(T *LM, int *status, bool report) {
+  constexpr int WQ = NB / 4, LW = NB + 1;
+  const int q = wq_of(), r = wr_of();
+  T m[WQ];
+  int col[WQ];  // the final column of each of this lane's entries
+#pragma unroll
+  for (int c = 0; c < WQ; ++c) {
+    m[c] = (r < NB) ? LM[r * LW + q * WQ + c] : (T)0;
+    col[c] = 0;
+  }
+  bool used = r >= NB, sing = false;
+  int step = 0;
+  static_for<NB>([&](auto kc) {
+    constexpr int k = decltype(kc)::value, qk = k / WQ, ck = k % WQ;
+    const T rc = rcp_nr(m[ck]);
+    const unsigned key = (unsigned)__builtin_amdgcn_readlane(
+        (int)team_umax<16>(piv_key(m[ck], r, !used && q == qk)), qk * 16);
+    const int p = piv_row(key);
+    sing = sing || piv_zero(key);
+    const T inv = readlane_t<T>(rc, qk * 16 + p);
+    const T f = row_bcast<qk>(m[ck]);
+    const T g = (r == p) ? inv - (T)1 : -f * inv;
+    if (q == qk) {
+      m[ck] = (r == p) ? (T)1 : (T)0;
+      col[ck] = p;
+    }
+    row_rank1(m, g, p);
+    if (r == p) {
+      used = true;
+      step = k;
+    }
+  });
+  if (report && (threadIdx.x & 63) == 0 && sing) atomicOr(status, ST_SINGULAR);
+  team_sync();  // every lane has read its row before any is overwritten
+  if (r < NB) {
+#pragma unroll
+    for (int c = 0; c < WQ; ++c) LM[step * LW + col[c]] = m[c];
   }
   team_sync();
 }
