@@ -13,7 +13,7 @@
 //     keeps the position of its edge in a stable children-by-parent array built
 //     once (a compression hands the removed node's position to its child, as
 //     the host hands over the sibling key), so that order is the order of
-//     positions: a scatter and a stable compaction;
+//     positions: a radix sort of the round's rakes by position;
 //   * the alternation along unary paths is the parity of each node's distance
 //     from the top of its path, found by pointer jumping (list ranking);
 //   * each sibling group's code tree is built by one thread, emitting its
@@ -61,7 +61,7 @@ struct Arena {
   // per node
   int32_t *par32, *cnt, *up0, *up1, *dist0, *dist1, *cur_par, *lvlU, *lvlE, *edge_slot, *one_child, *alive, *sel,
       *rem_slot, *rem_par, *comp_r, *comp_k, *rem_kind, *live0, *live1, *leaves, *sorted, *gstart, *elig, *comp, *pos,
-      *mark, *cout, *eP, *eX, *removal, *gslot, *glev;
+      *cout, *eP, *eX, *removal, *gslot, *glev;
   uint64_t *code_hi, *code_lo;  // per sorted rake: prefix weight sum, code word
   int32_t *code_d;              // and the common-prefix length with the previous code
   // a group built by the whole workgroup (reduce_big_group), per split position
@@ -99,7 +99,7 @@ inline size_t carve(Arena &a, char *base, int64_t N, int T) {
   int32_t **node[] = {&a.par32,   &a.cnt,    &a.up0,     &a.up1,      &a.dist0,  &a.dist1,    &a.cur_par, &a.lvlU,
                       &a.lvlE,    &a.edge_slot, &a.one_child, &a.alive, &a.sel,    &a.rem_slot, &a.rem_par, &a.comp_r,
                       &a.comp_k,  &a.rem_kind, &a.live0,  &a.live1,    &a.leaves, &a.sorted,   &a.gstart,  &a.elig,
-                      &a.comp,    &a.pos,    &a.mark,    &a.cout,     &a.eP,     &a.eX,       &a.removal, &a.code_d,
+                      &a.comp,    &a.pos,    &a.cout,     &a.eP,     &a.eX,       &a.removal, &a.code_d,
                       &a.gslot,   &a.glev,   &a.bg_A,    &a.bg_R,     &a.bg_par, &a.bg_lc,    &a.bg_rc,   &a.bg_left,
                       &a.bg_dep,  &a.bg_idx, &a.bg_val,  &a.bg_p0,    &a.bg_d0,  &a.bg_p1,    &a.bg_d1,   &a.bigs,
                       &a.r_raw,   &a.r_rem,  &a.r_comp_rem, &a.r_comp_raw};
@@ -624,7 +624,6 @@ __host__ __device__ int32_t program(X &x, Arena &a) {
       a.rem_slot[i] = a.rem_par[i] = a.comp_r[i] = a.comp_k[i] = -1;
       a.rem_kind[i] = 0;
       a.live0[i] = (int32_t)i;
-      a.mark[i] = -1;
       a.eP[i] = a.eX[i] = 0;
     }
   });
@@ -656,7 +655,8 @@ __host__ __device__ int32_t program(X &x, Arena &a) {
         a.rem_par[j] = a.cur_par[j];
         a.removal[rem_n + q] = j;
         a.cout[j] = out;
-        a.mark[a.pos[j]] = j;
+        a.k0[q] = (uint32_t)a.pos[j];
+        a.v0[q] = (uint32_t)j;
       }
     });
     n_rake += nl;
@@ -664,15 +664,19 @@ __host__ __device__ int32_t program(X &x, Arena &a) {
     raw_n += (int32_t)nl;
     rem_n += (int32_t)nl;
     // the rakes in (parent, sibling) order: the order of their edge positions
-    compact(
-        x, a, N - 1, [&](int64_t q) { return a.mark[q] >= 0; },
-        [&](int64_t q, uint32_t o) {
-          const int32_t j = a.mark[q];
-          a.sorted[o] = j;
-          a.gslot[o] = a.cout[j];
-          a.glev[o] = a.contrib_level[a.cout[j]];
-          a.mark[q] = -1;
-        });
+    // (distinct), by a radix sort of this round's rakes only
+    {
+      uint32_t *pk = a.k0, *pv = a.v0, *pk2 = a.k1, *pv2 = a.v1;
+      radix_sort(x, a, nl, bitlen((uint64_t)N), pk, pv, pk2, pv2);
+      x.each([&](int t) {
+        for (int64_t q = t; q < (int64_t)nl; q += T) {
+          const int32_t j = (int32_t)pv[q];
+          a.sorted[q] = j;
+          a.gslot[q] = a.cout[j];
+          a.glev[q] = a.contrib_level[a.cout[j]];
+        }
+      });
+    }
     const uint32_t G = compact(
         x, a, nl,
         [&](int64_t q) { return q == 0 || a.cur_par[a.sorted[q]] != a.cur_par[a.sorted[q - 1]]; },
