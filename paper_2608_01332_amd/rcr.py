@@ -539,8 +539,10 @@ def solve_rhs(plan: Plan, prob: dict, fac: dict, rhs: list, outs: list | None = 
               executor: int = EXEC_LEVELS, check: bool = False, kkt_residual: bool = False,
               kernel_ms: bool = False, refine_steps: int = -1, workspace=None, stream=None) -> dict:
     """rcr_solve_rhs: Steps 4-6 for each right-hand side dict (q, r, c) of `rhs`
-    on the factor of rcr_factor (fac holds its K, P).  Returns {'solutions': [...]}
-    with x, u, lam per right-hand side."""
+    on the factor of rcr_factor (fac holds its K, P; an rcr_solve in between on
+    the same workspace leaves none, and the plan-owned workspace then raises
+    RcrError ERR_BAD_OPTION).  Returns {'solutions': [...]} with x, u, lam per
+    right-hand side."""
     import torch
     sh = _shapes(plan.N, plan.n, plan.m)
     for k in MATRIX_FIELDS:
