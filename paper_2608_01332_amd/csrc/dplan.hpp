@@ -134,8 +134,6 @@ inline size_t carve(Arena &a, char *base, int64_t N, int T) {
   return (at + 255) & ~size_t(255);
 }
 
-typedef unsigned __int128 u128;
-
 __host__ __device__ inline int bitlen(uint64_t v) {
   int b = 0;
   while (v) {
@@ -144,25 +142,6 @@ __host__ __device__ inline int bitlen(uint64_t v) {
   }
   return b;
 }
-
-// floor(num / den) for den < 2^63, by restoring long division.
-__host__ __device__ inline u128 div128(u128 num, uint64_t den) {
-  u128 q = 0;
-  uint64_t r = 0;
-  for (int i = 127; i >= 0; --i) {
-    r = (r << 1) | (uint64_t)((num >> i) & 1);
-    q <<= 1;
-    if (r >= den) {
-      r -= den;
-      q |= 1;
-    }
-  }
-  return q;
-}
-
-// Items a thread handles together: their loads are issued before any of
-// their results is used, so up to this many memory round trips overlap.
-constexpr int BATCH = 8;
 
 // Stable compaction of the indices i < n with pred(i), in increasing i:
 // write(i, o) for the o-th of them; returns their number (the executor's own
